@@ -1,0 +1,189 @@
+/*
+ * schur_refine.h - C interface of the MI355X (gfx950) library for the iterative
+ * refinement of Schur decompositions (Bujanovic, Kressner, Schroder, "Iterative
+ * Refinement of Schur decompositions", arXiv 2203.10879).
+ *
+ * Problem (Section 2, Algorithm 1 and Algorithm 4): given A and a nearly unitary
+ * Q-hat such that Q-hat^H A Q-hat is nearly upper triangular, compute a unitary Q
+ * (to high precision, hp) with Q^H A Q upper triangular. Each pass evaluates
+ * That = Q^H A Q in hp, splits it into its upper part T and strictly lower part E,
+ * solves the triangular matrix equation stril(T L - L T) = -E (Section 2.1,
+ * eq. (7)) in low precision (lp), and applies the merged Newton-Schulz update
+ * Q <- 1/2 Q (2I + 2W - Y - YW + W^2 + W^3), W = L - L^H, Y = Q^H Q - I
+ * (Section 2.4, eq. (alg:eq:NSmerged)). Before the loop Q-hat is orthogonalised by
+ * one Newton-Schulz step (eq. (alg:eq:NS)).
+ *
+ * Tiers: hp = FP64 (native FP64 MFMA, optionally compensated accumulation, or an
+ * Ozaki-style split on INT8/BF16 MFMA) with lp = FP32; hp = double-double with
+ * lp = FP64 (schur_refine_dd).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are n x n, column-major, leading dimension n, complex128 stored as
+ *    interleaved (re, im) doubles (C99 double _Complex / hipDoubleComplex layout),
+ *    unless a parameter says complex64 (interleaved floats).
+ *  - Matrix pointers are DEVICE pointers owned by the caller; the library never
+ *    frees them. Host pointers are marked "host".
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream). Work is
+ *    enqueued on it; the refinement entry points synchronise it to read residuals.
+ *  - Return value: SR_OK (0) or a positive outcome code (the last iterate is still
+ *    written), or a negative error code (outputs untouched when validation fails).
+ *  - No exceptions cross the interface. Calls on different streams with different
+ *    workspaces may run concurrently; calls sharing a workspace must not overlap.
+ */
+#ifndef SCHUR_REFINE_H
+#define SCHUR_REFINE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SR_OK = 0,             /* relative stril residual reached tol                      */
+  SR_NOT_CONVERGED = 1,  /* `iters` passes done without reaching tol                 */
+  SR_STAGNATED = 2,      /* residual stopped decreasing at the hp accumulation floor */
+  SR_BREAKDOWN = 3,      /* non-finite value, or two equal diagonal entries of T
+                            (Theorem 1: the solve is then singular)                  */
+  SR_DIVERGED = 4,       /* residual rose on two consecutive passes                  */
+  SR_EINVAL = -1,        /* invalid argument                                         */
+  SR_EHIP = -2,          /* a HIP runtime call failed                                */
+  SR_ENOMEM = -3,        /* workspace too small or allocation failed                 */
+  SR_ENOSYS = -4         /* option not supported by this build                       */
+} sr_status;
+
+typedef enum {
+  SR_GEMM_FP64 = 0,       /* native FP64 MFMA                                         */
+  SR_GEMM_OZAKI_I8 = 1,   /* Ozaki split on INT8 MFMA, INT32 accumulation             */
+  SR_GEMM_OZAKI_BF16 = 2  /* Ozaki split on BF16 MFMA, FP32 accumulation              */
+} sr_gemm_mode;
+
+typedef struct {
+  int gemm;               /* sr_gemm_mode for the hp products                         */
+  int slices;             /* Ozaki slices for That and Y (0 = default)                */
+  int update_slices;      /* Ozaki slices for Q * Delta (0 = default)                 */
+  int compensated;        /* 1: chunked K accumulation with error-free (TwoSum)
+                             combination in the FP64 products P, That and Y            */
+  int gate_lp_terms;      /* 1: skip YW, W^2, W^3 whose Frobenius bound is below
+                             0.1 u_hp (Section 2.4 notes the high-order terms may
+                             fall below roundoff)                                      */
+  int trunc;              /* 1: zero any computed entry of L above 1e-5 in modulus
+                             (Example 4 device); 0: off                                */
+  int timing;             /* 1: time the hp products and the solve with HIP events on
+                             `stream` (fills the ms_* fields of sr_info)               */
+  void* workspace;        /* device workspace of >= sr_workspace_bytes(n, opts)
+                             bytes, or NULL to let the library allocate and cache one  */
+  size_t workspace_bytes;
+  void* stream;           /* hipStream_t                                               */
+} sr_opts;
+
+typedef struct {
+  int status;             /* sr_status of the call                                    */
+  int iters;              /* passes = evaluations of That (the paper's iterations)    */
+  int updates;            /* Q updates done (= iters - 1 when converged)              */
+  int hp_gemms;           /* hp products counted as in the paper: 2 + 4(iters-1) + 2  */
+  int lp_products;        /* lp products (YW, W^2, W^3) actually formed               */
+  double resid;           /* last ||stril(That)||_F / ||A||_F, computed in hp         */
+  double orth;            /* ||Q^H Q - I||_F of the last Y formed (0 if none)         */
+  double resid_hist[16];  /* residual of passes 1..min(iters,16)                      */
+  double norm_w_hist[16]; /* ||W||_F of updates 1..16                                 */
+  float ms_total;         /* device time of the call (HIP events)                     */
+  float ms_hp_gemm;       /* with opts.timing: summed time of the hp product launches  */
+  int hp_gemm_launches;   /* with opts.timing: number of hp product launches timed     */
+  float ms_solve;         /* with opts.timing: summed time of the triangular solves    */
+} sr_info;
+
+/* Default options: FP64 MFMA, compensated accumulation on, gating on, no trunc. */
+void sr_default_opts(sr_opts* opts);
+
+/* Bytes of device workspace schur_refine needs for size n under `opts`. */
+size_t sr_workspace_bytes(int n, const sr_opts* opts);
+
+/* Refine one Schur decomposition (Algorithm 4 from its second step).
+ *  A  (in,  device, complex128 n x n): the matrix, read only.
+ *  Q  (in/out, device, complex128 n x n): in: the start Q-hat (nearly unitary, e.g.
+ *     FP32 Schur vectors widened to complex128); out: the refined Q.
+ *  T  (out, device, complex128 n x n): triu(Q^H A Q) of the last pass; its strictly
+ *     lower part is set to zero.
+ *  n >= 1; iters >= 1: maximum number of passes; tol > 0: stop when
+ *  ||stril(Q^H A Q)||_F / ||A||_F <= tol (computed in hp).
+ *  opts may be NULL (defaults); info (host) may be NULL.
+ *  n = 1: T = A, Q = q / |q|, one pass. */
+int schur_refine(const void* A, void* Q, void* T, int n, int iters, double tol,
+                 const sr_opts* opts, sr_info* info);
+
+/* Refine `batch` independent decompositions of possibly different sizes.
+ *  n (host, int[batch]); A, Q, T (host arrays of `batch` device pointers), each
+ *  matrix laid out as in schur_refine. info (host, sr_info[batch]) may be NULL.
+ *  Returns the worst (largest) outcome over the batch, or a negative error. */
+int schur_refine_batched(int batch, const int* n, const void* const* A, void* const* Q,
+                         void* const* T, int iters, double tol, const sr_opts* opts,
+                         sr_info* info);
+
+/* Double-double tier: A = A_hi + A_lo, Q = Q_hi + Q_lo, T = T_hi + T_lo (all device,
+ * complex128 n x n). hp products are double-double, the solve runs in FP64. */
+int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, void* T_hi,
+                    void* T_lo, int n, int iters, double tol, const sr_opts* opts,
+                    sr_info* info);
+
+/* Static description of a status code. */
+const char* sr_status_string(int status);
+
+/* ---------------------------------------------------------------------------
+ * Stage entry points: the steps of one pass, callable on their own (a caller may
+ * drive the loop itself). All pointers are device pointers; `ws` is a workspace of
+ * at least sr_workspace_bytes(n, NULL) bytes; `stream` as above. They return SR_OK
+ * or a negative error code and do not synchronise the stream unless stated.
+ * ------------------------------------------------------------------------- */
+
+/* C = op(A) B (+ Cin), complex128, native FP64 MFMA (Section 2.4: the hp products).
+ * op(A) is m x k: opa = 0 uses A (m x k, leading dim lda), opa = 1 uses the
+ * conjugate transpose of A (k x m, leading dim lda). B is k x n (ldb), C is m x n
+ * (ldc). Cin (may be NULL) is added when given (ldcin). compensated = 1 selects
+ * chunked accumulation with error-free combination. C must not overlap A, B, Cin. */
+int sr_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+             const void* Cin, int ldcin, void* C, int ldc, int compensated, void* stream);
+
+/* C = A B, complex64, FP32 MFMA (the lp products YW, W^2, W^3 of Algorithm 4). */
+int sr_cgemm(int m, int n, int k, const void* A, int lda, const void* B, int ldb, void* C,
+             int ldc, void* stream);
+
+/* Residual products and split (Algorithm 4, the That, E and T steps):
+ * P = A Q, That = Q^H P; T (complex128) = triu(That) with zeros below;
+ * T_lp, E_lp (complex64 n x n) = triu(That), stril(That) rounded to FP32;
+ * eps (host, may be NULL) = ||stril(That)||_F / ||A||_F. Synchronises `stream` when
+ * eps is requested. */
+int sr_residual(const void* A, const void* Q, int n, void* T, void* T_lp, void* E_lp,
+                double* eps, int compensated, void* ws, void* stream);
+
+/* Triangular matrix equation stril(T L - L T) = -E (Section 2.1, eq. (7)) in FP32.
+ * T_lp: complex64, upper triangle (incl. diagonal) read; E_lp: complex64, strictly
+ * lower part read (the buffer is not modified); L_lp: complex64 out, strictly lower
+ * solution, zeros elsewhere. trunc > 0 zeroes computed entries above trunc in
+ * modulus. Returns SR_BREAKDOWN (after synchronising) if two diagonal entries of T
+ * coincide or a non-finite value appears; otherwise SR_OK without synchronising. */
+int sr_trisolve(const void* T_lp, const void* E_lp, void* L_lp, int n, float trunc,
+                void* ws, void* stream);
+
+/* Merged Newton-Schulz update (Algorithm 4, the W, Y, Sigma and Q steps) given L:
+ * W = L - L^H, Y = Q^H Q - I (hp), lp products (gated when gate != 0),
+ * Delta = 1/2 Sigma - I = W - Y/2 + (-YW + W^2 + W^3)/2, Q_out = Q + Q Delta.
+ * L_lp complex64; Q, Q_out complex128 (must not overlap). norms (host, may be NULL,
+ * double[2]) receives ||W||_F and ||Y||_F (synchronises). */
+int sr_update(const void* Q, const void* L_lp, void* Q_out, int n, int gate,
+              int compensated, double* norms, void* ws, void* stream);
+
+/* Newton-Schulz step Q = 1/2 Qh (3I - Qh^H Qh) = Qh + Qh (-(Qh^H Qh - I)/2)
+ * (Algorithm 4, before the loop). Qh, Q complex128, must not overlap. */
+int sr_ns_init(const void* Qh, void* Q, int n, int compensated, void* ws, void* stream);
+
+/* Diagnostic: one matrix-core instruction (kind 0: v_mfma_f64_16x16x4f64, kind 1:
+ * v_mfma_f32_16x16x4f32) on a 16x4 A and a 4x16 B (row-major, host), fed and read
+ * back with the lane layout the GEMM kernels assume; D (16x16 row-major, host)
+ * equals A B exactly for small integers when that layout is right. */
+int sr_diag_mfma(int kind, const double* A, const double* B, double* D);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,274 @@
+"""MI355X (gfx950) refinement of Schur decompositions: Python binding.
+
+A thin ctypes layer over libschurrefine.so (C interface in include/schur_refine.h).
+It marshals arguments only: every step of the refinement runs in the library's
+HIP kernels. PyTorch supplies device memory and the current stream.
+
+Matrices are torch tensors on the GPU in column-major storage: shape (m, n) with
+strides (1, m), the layout of `colmajor(x)` below (the transpose view of a
+row-major tensor). complex128 unless a function says complex64.
+
+Importing the package does not load the library; the first call does, and raises
+if libschurrefine.so has not been built (`python -m paper_2203_10879_amd.build`).
+There is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libschurrefine.so")
+_LIB = None
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "STAGNATED", 3: "BREAKDOWN", 4: "DIVERGED",
+          -1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "ENOSYS"}
+GEMM_MODES = {"fp64": 0, "ozaki_i8": 1, "ozaki_bf16": 2}
+
+
+class SrOpts(ctypes.Structure):
+    _fields_ = [("gemm", ctypes.c_int), ("slices", ctypes.c_int), ("update_slices", ctypes.c_int),
+                ("compensated", ctypes.c_int), ("gate_lp_terms", ctypes.c_int),
+                ("trunc", ctypes.c_int), ("timing", ctypes.c_int), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+
+
+class SrInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("updates", ctypes.c_int),
+                ("hp_gemms", ctypes.c_int), ("lp_products", ctypes.c_int),
+                ("resid", ctypes.c_double), ("orth", ctypes.c_double),
+                ("resid_hist", ctypes.c_double * 16), ("norm_w_hist", ctypes.c_double * 16),
+                ("ms_total", ctypes.c_float), ("ms_hp_gemm", ctypes.c_float),
+                ("hp_gemm_launches", ctypes.c_int), ("ms_solve", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        k = min(self.iters, 16)
+        u = min(self.updates, 16)
+        return {"status": STATUS.get(self.status, self.status), "iters": self.iters,
+                "updates": self.updates, "hp_gemms": self.hp_gemms,
+                "lp_products": self.lp_products, "resid": self.resid, "orth": self.orth,
+                "resid_hist": list(self.resid_hist[:k]), "norm_w_hist": list(self.norm_w_hist[:u]),
+                "ms_total": self.ms_total, "ms_hp_gemm": self.ms_hp_gemm,
+                "hp_gemm_launches": self.hp_gemm_launches, "ms_solve": self.ms_solve}
+
+
+# name -> (restype, argtypes); mirrors include/schur_refine.h
+_vp, _i, _d, _f, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_float, ctypes.c_size_t
+_SIGS = {
+    "sr_default_opts": (None, [ctypes.POINTER(SrOpts)]),
+    "sr_workspace_bytes": (_sz, [_i, ctypes.POINTER(SrOpts)]),
+    "schur_refine": (_i, [_vp, _vp, _vp, _i, _i, _d, ctypes.POINTER(SrOpts), ctypes.POINTER(SrInfo)]),
+    "schur_refine_batched": (_i, [_i, _vp, _vp, _vp, _vp, _i, _d, ctypes.POINTER(SrOpts),
+                                  ctypes.POINTER(SrInfo)]),
+    "schur_refine_dd": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _d, ctypes.POINTER(SrOpts),
+                             ctypes.POINTER(SrInfo)]),
+    "sr_status_string": (ctypes.c_char_p, [_i]),
+    "sr_zgemm": (_i, [_i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _vp]),
+    "sr_cgemm": (_i, [_i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp]),
+    "sr_residual": (_i, [_vp, _vp, _i, _vp, _vp, _vp, ctypes.POINTER(_d), _i, _vp, _vp]),
+    "sr_trisolve": (_i, [_vp, _vp, _vp, _i, _f, _vp, _vp]),
+    "sr_update": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.POINTER(_d), _vp, _vp]),
+    "sr_ns_init": (_i, [_vp, _vp, _i, _i, _vp, _vp]),
+    "sr_diag_mfma": (_i, [_i, _vp, _vp, _vp]),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def lib():
+    """Load libschurrefine.so (raises if it is missing)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError(f"{SO_PATH} is not built; run `python -m paper_2203_10879_amd.build`")
+        L = ctypes.CDLL(SO_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+# ------------------------------------------------------------------ helpers
+
+def colmajor(x, device="cuda"):
+    """A (m, n) torch tensor on `device` holding x in column-major storage."""
+    import torch
+
+    if isinstance(x, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(np.asarray(x).T))
+    else:
+        t = x.detach().T.contiguous()
+    return t.to(device).T
+
+
+def colmajor_empty(m, n, dtype=None, device="cuda"):
+    import torch
+
+    dtype = dtype or torch.complex128
+    return torch.zeros((n, m), dtype=dtype, device=device).T
+
+
+def to_numpy(t) -> np.ndarray:
+    """Host copy (column-major numpy array) of a column-major tensor."""
+    return np.asfortranarray(t.T.contiguous().cpu().numpy().T)
+
+
+def _mat(t, dtype_name: str, rows: int | None = None, cols: int | None = None):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA/HIP torch tensor")
+    want = {"c128": torch.complex128, "c64": torch.complex64}[dtype_name]
+    if t.dtype != want:
+        raise TypeError(f"expected {want}, got {t.dtype}")
+    if t.dim() != 2 or t.stride(0) != 1 or t.stride(1) < max(1, t.shape[0]):
+        raise ValueError("expected a column-major matrix (strides (1, ld))")
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError("row count mismatch")
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError("column count mismatch")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def make_opts(gemm="fp64", slices=0, update_slices=0, compensated=True, gate=True, trunc=False,
+              timing=False, workspace=None, stream=None) -> SrOpts:
+    o = SrOpts()
+    lib().sr_default_opts(ctypes.byref(o))
+    o.gemm = GEMM_MODES[gemm] if isinstance(gemm, str) else int(gemm)
+    o.slices = int(slices)
+    o.update_slices = int(update_slices)
+    o.compensated = int(bool(compensated))
+    o.gate_lp_terms = int(bool(gate))
+    o.trunc = int(bool(trunc))
+    o.timing = int(bool(timing))
+    if workspace is not None:
+        o.workspace = ctypes.c_void_p(workspace.data_ptr())
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    o.stream = _stream(stream)
+    return o
+
+
+def workspace(n: int, device="cuda"):
+    """A device workspace tensor large enough for size n."""
+    import torch
+
+    nbytes = lib().sr_workspace_bytes(int(n), None)
+    return torch.empty(max(1, nbytes), dtype=torch.uint8, device=device)
+
+
+def sr_workspace_bytes(n: int) -> int:
+    return int(lib().sr_workspace_bytes(int(n), None))
+
+
+def sr_status_string(code: int) -> str:
+    return lib().sr_status_string(int(code)).decode()
+
+
+# ------------------------------------------------------------ entry points
+
+def schur_refine(A, Q, T, iters: int = 6, tol: float = 1e-15, **kw) -> dict:
+    """Refine (Q, T) for A in place; returns the info record as a dict."""
+    n = A.shape[0]
+    a = _mat(A, "c128", n, n)
+    q = _mat(Q, "c128", n, n)
+    t = _mat(T, "c128", n, n)
+    o = make_opts(**kw)
+    info = SrInfo()
+    rc = lib().schur_refine(a, q, t, n, int(iters), float(tol), ctypes.byref(o), ctypes.byref(info))
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def schur_refine_batched(As, Qs, Ts, iters: int = 6, tol: float = 1e-15, **kw):
+    b = len(As)
+    ns = (ctypes.c_int * b)(*[int(a.shape[0]) for a in As])
+    pa = (ctypes.c_void_p * b)(*[_mat(a, "c128").value for a in As])
+    pq = (ctypes.c_void_p * b)(*[_mat(q, "c128").value for q in Qs])
+    pt = (ctypes.c_void_p * b)(*[_mat(t, "c128").value for t in Ts])
+    o = make_opts(**kw)
+    infos = (SrInfo * max(1, b))()
+    rc = lib().schur_refine_batched(b, ns, pa, pq, pt, int(iters), float(tol), ctypes.byref(o), infos)
+    return rc, [infos[i].as_dict() for i in range(b)]
+
+
+def schur_refine_dd(A_hi, A_lo, Q_hi, Q_lo, T_hi, T_lo, iters: int = 8, tol: float = 1e-28, **kw):
+    n = A_hi.shape[0]
+    args = [_mat(x, "c128", n, n) for x in (A_hi, A_lo, Q_hi, Q_lo, T_hi, T_lo)]
+    o = make_opts(**kw)
+    info = SrInfo()
+    rc = lib().schur_refine_dd(*args, n, int(iters), float(tol), ctypes.byref(o), ctypes.byref(info))
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def sr_zgemm(A, B, C, opa: int = 0, Cin=None, compensated: bool = False, stream=None) -> int:
+    m, n = C.shape
+    k = B.shape[0]
+    return lib().sr_zgemm(int(opa), m, n, k, _mat(A, "c128"), A.stride(1), _mat(B, "c128"),
+                          B.stride(1), _mat(Cin, "c128") if Cin is not None else None,
+                          Cin.stride(1) if Cin is not None else 0, _mat(C, "c128"), C.stride(1),
+                          int(bool(compensated)), _stream(stream))
+
+
+def sr_cgemm(A, B, C, stream=None) -> int:
+    m, n = C.shape
+    k = B.shape[0]
+    return lib().sr_cgemm(m, n, k, _mat(A, "c64"), A.stride(1), _mat(B, "c64"), B.stride(1),
+                          _mat(C, "c64"), C.stride(1), _stream(stream))
+
+
+def sr_residual(A, Q, T, T_lp, E_lp, ws, want_eps=True, compensated=True, stream=None):
+    n = A.shape[0]
+    eps = ctypes.c_double(0.0)
+    rc = lib().sr_residual(_mat(A, "c128", n, n), _mat(Q, "c128", n, n), n, _mat(T, "c128", n, n),
+                           _mat(T_lp, "c64", n, n), _mat(E_lp, "c64", n, n),
+                           ctypes.byref(eps) if want_eps else None, int(bool(compensated)),
+                           ctypes.c_void_p(ws.data_ptr()), _stream(stream))
+    return rc, eps.value
+
+
+def sr_trisolve(T_lp, E_lp, L_lp, ws, trunc: float = 0.0, stream=None) -> int:
+    n = T_lp.shape[0]
+    return lib().sr_trisolve(_mat(T_lp, "c64", n, n), _mat(E_lp, "c64", n, n),
+                             _mat(L_lp, "c64", n, n), n, float(trunc),
+                             ctypes.c_void_p(ws.data_ptr()), _stream(stream))
+
+
+def sr_update(Q, L_lp, Q_out, ws, gate=True, compensated=True, stream=None):
+    n = Q.shape[0]
+    norms = (ctypes.c_double * 2)()
+    rc = lib().sr_update(_mat(Q, "c128", n, n), _mat(L_lp, "c64", n, n), _mat(Q_out, "c128", n, n), n,
+                         int(bool(gate)), int(bool(compensated)), norms,
+                         ctypes.c_void_p(ws.data_ptr()), _stream(stream))
+    return rc, (norms[0], norms[1])
+
+
+def sr_ns_init(Qh, Q, ws, compensated=True, stream=None) -> int:
+    n = Qh.shape[0]
+    return lib().sr_ns_init(_mat(Qh, "c128", n, n), _mat(Q, "c128", n, n), n,
+                            int(bool(compensated)), ctypes.c_void_p(ws.data_ptr()), _stream(stream))
+
+
+def sr_diag_mfma(A: np.ndarray, B: np.ndarray, kind: int = 0) -> np.ndarray:
+    """kind 0: FP64 16x16x4 instruction, kind 1: FP32 16x16x4 instruction."""
+    a = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(B, dtype=np.float64)
+    d = np.zeros((16, 16), dtype=np.float64)
+    rc = lib().sr_diag_mfma(int(kind), a.ctypes.data_as(ctypes.c_void_p),
+                            b.ctypes.data_as(ctypes.c_void_p), d.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise RuntimeError(f"sr_diag_mfma failed: {rc}")
+    return d

@@ -1,0 +1,63 @@
+// Shared device/host definitions of the MI355X (gfx950) Schur-refinement library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sr {
+
+template <typename R>
+struct cplx {
+  R re, im;
+};
+using zc = cplx<double>;  // complex128, layout of C99 double _Complex
+using cc = cplx<float>;   // complex64
+
+template <typename R>
+__device__ __host__ inline cplx<R> mk(R re, R im) {
+  cplx<R> z;
+  z.re = re;
+  z.im = im;
+  return z;
+}
+template <typename R>
+__device__ inline cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return mk<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+// a += b * c
+template <typename R>
+__device__ inline void cfma(cplx<R>& a, cplx<R> b, cplx<R> c) {
+  a.re = fma(b.re, c.re, fma(-b.im, c.im, a.re));
+  a.im = fma(b.re, c.im, fma(b.im, c.re, a.im));
+}
+// a -= b * c
+template <typename R>
+__device__ inline void cfms(cplx<R>& a, cplx<R> b, cplx<R> c) {
+  a.re = fma(-b.re, c.re, fma(b.im, c.im, a.re));
+  a.im = fma(-b.re, c.im, fma(-b.im, c.re, a.im));
+}
+
+// Error-free sum s + e = a + b (Knuth).
+__device__ inline void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Device status bits written by kernels (OR-ed into a status word).
+enum : unsigned {
+  DEV_BREAKDOWN = 1u,  // t_ii == t_jj or a non-finite value in the solve
+};
+
+constexpr int kCUs = 256;  // MI355X compute units
+constexpr int kXCDs = 8;   // accelerator complex dies (one L2 each)
+
+__host__ __device__ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace sr
+
+#define SR_HIP_CHECK(expr)                   \
+  do {                                       \
+    hipError_t _e = (expr);                  \
+    if (_e != hipSuccess) return SR_EHIP;    \
+  } while (0)

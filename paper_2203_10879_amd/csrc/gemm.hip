@@ -1,0 +1,292 @@
+// Complex GEMM on CDNA4 matrix cores: FP64 MFMA (hp products of the refinement)
+// and FP32 MFMA (its lp products), with the pass's elementwise steps fused into
+// the epilogue.
+//
+// Tiling: a 256-thread block computes a 64 x 64 complex tile of C; its four
+// waves each own a 32 x 32 complex quadrant, i.e. 2 x 2 blocks of 16 x 16, with
+// separate real and imaginary accumulators. Every 16 x 16 x 4 step is four real
+// MFMAs: re += a_re b_re - a_im b_im, im += a_re b_im + a_im b_re. op(A) and B
+// tiles (K depth 16) are staged through LDS, double-buffered, with an XOR swizzle
+// so that both the transposing stores and the fragment loads avoid bank
+// conflicts. Complex values stay interleaved (re, im) so one 16-byte LDS read
+// yields both parts of an operand.
+//
+// Compensated mode (FP64 only): the MFMA accumulators are folded every
+// kChunk K-tiles into a (hi, lo) pair by an error-free TwoSum, so the rounding
+// error of a dot product of length K grows like sqrt(K * chunk) instead of K.
+#include "kernels.hpp"
+
+namespace sr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct MF;
+// Accumulator layout: element v of lane l holds D[row(l, v)][l % 16]. The FP64
+// instruction interleaves its rows (row = l/16 + 4v); the FP32 one stacks them
+// (row = 4 (l/16) + v). Both were confirmed with a one-instruction probe.
+template <>
+struct MF<double> {
+  using v4 = d4;
+  __device__ static inline v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct MF<float> {
+  using v4 = f4;
+  __device__ static inline v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+constexpr int GBM = 64, GBN = 64, GBK = 16, GNT = 256;
+constexpr int kChunk = 2;  // K-tiles (32 complex terms) per compensated fold
+
+// LDS column swizzle: row k of a [GBK][64] tile is permuted by XOR with 4 (k mod 16).
+__device__ inline int swz(int k, int m) { return m ^ ((k & 15) << 2); }
+
+// Operand layout of v_mfma_*_16x16x4 (one block): lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; accumulator element v of lane l is D[MF<R>::row(l, v)][l % 16].
+template <typename R, int OPA, int EPI, int COMP>
+__global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
+  using V = typename MF<R>::v4;
+  using C = cplx<R>;
+  __shared__ C As[2][GBK][GBM];
+  __shared__ C Bs[2][GBK][GBN];
+  __shared__ double red[GNT / 64];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+
+  // Blocks are dispatched round-robin over the XCDs (block b on XCD b mod 8):
+  // give each XCD a contiguous run of logical tiles, then walk tiles in groups of
+  // kGroup tile-rows so that concurrently running blocks share A rows and B columns
+  // in their XCD's L2.
+  const int ntiles = g.tiles_m * g.tiles_n;
+  const int bid = blockIdx.x;
+  int logical = bid;
+  {
+    const int per = ntiles / kXCDs;
+    if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
+  }
+  constexpr int kGroup = 4;
+  const int group = logical / (kGroup * g.tiles_n);
+  const int first_m = group * kGroup;
+  const int gsize = min(g.tiles_m - first_m, kGroup);
+  const int within = logical - group * kGroup * g.tiles_n;
+  const int tm = first_m + within % gsize;
+  const int tn = within / gsize;
+  const int m0 = tm * GBM, n0 = tn * GBN;
+
+  const C* __restrict__ Ap = (const C*)g.A;
+  const C* __restrict__ Bp = (const C*)g.B;
+
+  V acc_re[2][2], acc_im[2][2];
+  V hi_re[2][2], hi_im[2][2], lo_re[2][2], lo_im[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        acc_re[a][b][v] = 0;
+        acc_im[a][b][v] = 0;
+        hi_re[a][b][v] = 0;
+        hi_im[a][b][v] = 0;
+        lo_re[a][b][v] = 0;
+        lo_im[a][b][v] = 0;
+      }
+
+  C ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int idx = r * GNT + tid;
+      int mm, kk;
+      if (OPA == 0) {
+        mm = idx & 63;
+        kk = idx >> 6;
+      } else {
+        kk = idx & 15;
+        mm = idx >> 4;
+      }
+      const int gm = m0 + mm, gk = k0 + kk;
+      C v = mk<R>(0, 0);
+      if (gm < g.m && gk < g.k) {
+        v = OPA == 0 ? Ap[gm + (long)gk * g.lda] : Ap[gk + (long)gm * g.lda];
+        if (OPA) v.im = -v.im;
+      }
+      ra[r] = v;
+      const int bk = idx & 15, bn = idx >> 4;
+      const int gn = n0 + bn, gkb = k0 + bk;
+      C w = mk<R>(0, 0);
+      if (gn < g.n && gkb < g.k) w = Bp[gkb + (long)gn * g.ldb];
+      rb[r] = w;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int idx = r * GNT + tid;
+      int mm, kk;
+      if (OPA == 0) {
+        mm = idx & 63;
+        kk = idx >> 6;
+      } else {
+        kk = idx & 15;
+        mm = idx >> 4;
+      }
+      As[buf][kk][swz(kk, mm)] = ra[r];
+      const int bk = idx & 15, bn = idx >> 4;
+      Bs[buf][bk][swz(bk, bn)] = rb[r];
+    }
+  };
+  auto fold = [&]() {
+    if constexpr (COMP) {
+#pragma unroll
+      for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            double s, e;
+            two_sum(hi_re[a][b][v], acc_re[a][b][v], s, e);
+            hi_re[a][b][v] = s;
+            lo_re[a][b][v] += e;
+            two_sum(hi_im[a][b][v], acc_im[a][b][v], s, e);
+            hi_im[a][b][v] = s;
+            lo_im[a][b][v] += e;
+            acc_re[a][b][v] = 0;
+            acc_im[a][b][v] = 0;
+          }
+    }
+  };
+
+  const int KT = (g.k + GBK - 1) / GBK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < KT; kt++) {
+    const int cur = kt & 1;
+    if (kt + 1 < KT) gload((kt + 1) * GBK);
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 4) {
+      const int krow = kk + (lane >> 4);
+      R a_re[2], a_im[2], na_im[2], b_re[2], b_im[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; mi++) {
+        const C v = As[cur][krow][swz(krow, wm + mi * 16 + (lane & 15))];
+        a_re[mi] = v.re;
+        a_im[mi] = v.im;
+        na_im[mi] = -v.im;
+      }
+#pragma unroll
+      for (int ni = 0; ni < 2; ni++) {
+        const C v = Bs[cur][krow][swz(krow, wn + ni * 16 + (lane & 15))];
+        b_re[ni] = v.re;
+        b_im[ni] = v.im;
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; mi++)
+#pragma unroll
+        for (int ni = 0; ni < 2; ni++) {
+          acc_re[mi][ni] = MF<R>::op(a_re[mi], b_re[ni], acc_re[mi][ni]);
+          acc_im[mi][ni] = MF<R>::op(a_re[mi], b_im[ni], acc_im[mi][ni]);
+          acc_re[mi][ni] = MF<R>::op(na_im[mi], b_im[ni], acc_re[mi][ni]);
+          acc_im[mi][ni] = MF<R>::op(a_im[mi], b_re[ni], acc_im[mi][ni]);
+        }
+    }
+    if (COMP && ((kt + 1) % kChunk == 0 || kt + 1 == KT)) fold();
+    if (kt + 1 < KT) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue.
+  C* __restrict__ Cp = (C*)g.C;
+  const C* __restrict__ Cin = (const C*)g.Cin;
+  double part = 0;
+#pragma unroll
+  for (int mi = 0; mi < 2; mi++)
+#pragma unroll
+    for (int ni = 0; ni < 2; ni++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int i = m0 + wm + mi * 16 + MF<R>::row(lane, v);
+        const int j = n0 + wn + ni * 16 + (lane & 15);
+        C val;
+        if constexpr (COMP) {
+          val.re = hi_re[mi][ni][v] + lo_re[mi][ni][v];
+          val.im = hi_im[mi][ni][v] + lo_im[mi][ni][v];
+        } else {
+          val.re = acc_re[mi][ni][v];
+          val.im = acc_im[mi][ni][v];
+        }
+        if (i < g.m && j < g.n) {
+          const long o = i + (long)j * g.ldc;
+          if constexpr (EPI == EPI_STORE) {
+            Cp[o] = val;
+          } else if constexpr (EPI == EPI_ADD) {
+            const C c0 = Cin[i + (long)j * g.ldcin];
+            Cp[o] = mk<R>(c0.re + val.re, c0.im + val.im);
+          } else if constexpr (EPI == EPI_SPLIT) {
+            const long ol = i + (long)j * g.ldlp;
+            if (i <= j) {
+              Cp[o] = val;
+              g.Tlp[ol] = mk<float>((float)val.re, (float)val.im);
+              g.Elp[ol] = mk<float>(0.f, 0.f);
+            } else {
+              Cp[o] = mk<R>(0, 0);
+              g.Tlp[ol] = mk<float>(0.f, 0.f);
+              g.Elp[ol] = mk<float>((float)val.re, (float)val.im);
+              part += (double)val.re * val.re + (double)val.im * val.im;
+            }
+          } else {  // EPI_YDEF
+            if (i == j) val.re -= 1;
+            Cp[o] = val;
+            part += (double)val.re * val.re + (double)val.im * val.im;
+          }
+        }
+      }
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    if (tid == 0) g.partials[bid] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+int gemm_tiles(int m, int n) { return ceil_div(m, GBM) * ceil_div(n, GBN); }
+
+template <typename R, int OPA, int EPI, int COMP>
+static hipError_t launch(GemmArgs g, hipStream_t st) {
+  g.tiles_m = ceil_div(g.m, GBM);
+  g.tiles_n = ceil_div(g.n, GBN);
+  const int nt = g.tiles_m * g.tiles_n;
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL((gemm_kernel<R, OPA, EPI, COMP>), dim3(nt), dim3(GNT), 0, st, g);
+  return hipGetLastError();
+}
+
+hipError_t zgemm(int opa, int epi, int comp, const GemmArgs& g, hipStream_t st) {
+#define SR_Z(OPA, EPI)                                                     \
+  if (opa == OPA && epi == EPI) {                                          \
+    return comp ? launch<double, OPA, EPI, 1>(g, st) : launch<double, OPA, EPI, 0>(g, st); \
+  }
+  SR_Z(0, EPI_STORE)
+  SR_Z(0, EPI_ADD)
+  SR_Z(1, EPI_STORE)
+  SR_Z(1, EPI_ADD)
+  SR_Z(1, EPI_SPLIT)
+  SR_Z(1, EPI_YDEF)
+#undef SR_Z
+  return hipErrorInvalidValue;
+}
+
+hipError_t cgemm(const GemmArgs& g, hipStream_t st) { return launch<float, 0, EPI_STORE, 0>(g, st); }
+
+}  // namespace sr

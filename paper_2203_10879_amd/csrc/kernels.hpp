@@ -1,0 +1,61 @@
+// Internal launch interface between the host driver and the device kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace sr {
+
+// Epilogues of the complex GEMM.
+enum GemmEpi : int {
+  EPI_STORE = 0,  // C = acc
+  EPI_ADD = 1,    // C = Cin + acc
+  EPI_SPLIT = 2,  // That: C = triu(acc) (zeros below), Tlp = fp32 triu, Elp = fp32 stril,
+                  //       partials[block] = sum |stril(acc)|^2
+  EPI_YDEF = 3    // Y: C = acc - I, partials[block] = sum |acc - I|^2
+};
+
+struct GemmArgs {
+  int m, n, k;
+  const void* A;
+  long lda;
+  const void* B;
+  long ldb;
+  void* C;
+  long ldc;
+  const void* Cin;
+  long ldcin;
+  cc* Tlp;
+  cc* Elp;
+  long ldlp;
+  double* partials;
+  int tiles_m, tiles_n;
+};
+
+// Number of output tiles (= blocks, = partial sums written) of a GEMM launch.
+int gemm_tiles(int m, int n);
+
+// complex128 product on FP64 MFMA; opa: 0 = A, 1 = A^H; comp: compensated accumulation.
+hipError_t zgemm(int opa, int epi, int comp, const GemmArgs& g, hipStream_t st);
+// complex64 product on FP32 MFMA (C = A B).
+hipError_t cgemm(const GemmArgs& g, hipStream_t st);
+
+// Squared Frobenius norm partials of a complex128 array: writes `nparts` values.
+hipError_t fro2_partials(const zc* x, long count, double* partials, int nparts, hipStream_t st);
+// out[0] = sum of partials[0..np) in a fixed order (one block).
+hipError_t reduce_partials(const double* partials, int np, double* out, hipStream_t st);
+// W = L - L^H (complex64, strictly lower L), partials of ||W||_F^2; returns #partials.
+int form_w_parts(int n);
+hipError_t form_w(const cc* L, cc* W, int n, double* partials, hipStream_t st);
+// D = W - Y/2 + (W2 + W3 - YW)/2 with W = L - L^H (L may be NULL: W = 0; the
+// products may be NULL: absent).
+hipError_t form_delta(const cc* L, const zc* Y, const cc* W2, const cc* W3, const cc* YW, zc* D,
+                      int n, hipStream_t st);
+hipError_t to_c64(const zc* x, cc* y, long count, hipStream_t st);
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
+
+// Triangular matrix equation in FP32 (complex64).
+size_t trisolve_ws_bytes(int n);
+hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* ws,
+                    unsigned* status, hipStream_t st);
+
+}  // namespace sr

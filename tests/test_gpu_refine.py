@@ -1,0 +1,130 @@
+"""End-to-end GPU refinement (schur_refine through the C interface) against the
+binary128 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import U64, dev, empty, host, phase_align
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sr():
+    import torch
+
+    import paper_2203_10879_amd as m
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.lib()
+    return m
+
+
+def _refine(sr, a, qh, iters=6, tol=1e-15, **kw):
+    n = a.shape[0]
+    q, t = dev(qh), empty(n, n)
+    info = sr.schur_refine(dev(a), q, t, iters=iters, tol=tol, **kw)
+    return host(q), host(t), info
+
+
+def test_config0_n64_against_oracle_mirror(sr):
+    """n = 64, gaps 0.05, start = complex64 Schur form from the oracle's QR
+    algorithm; FP64 tier, tol 1e-15, at most 6 passes."""
+    g = synth.schur_test_matrix(64, seed=0)
+    a = g["A"]
+    z, _ = oracle.schur_qr(a.astype(np.complex64).astype(np.complex128), lp="float")
+    qh = np.asfortranarray(z.astype(np.complex64).astype(np.complex128))
+    q, t, info = _refine(sr, a, qh)
+    assert info["status"] == "OK" and info["iters"] <= 5, info
+    assert info["hp_gemms"] == 4 * info["iters"]
+    ev = oracle.evaluate(a, q, t)
+    assert ev["stril"] <= 1e-15 and ev["orth"] <= 1e-13 and ev["tdiff"] <= 1e-13 * ev["normA"]
+    # the (float lp, quad hp) oracle mirrors the iteration: same eps per pass
+    # while above the FP64 floor (within a factor 10)
+    ref = oracle.refine(a, qh, lp="float", maxit=6, tol=1e-15)
+    for k, (eg, eo) in enumerate(zip(info["resid_hist"], ref["hist"])):
+        if eo > 1e-14:
+            assert 0.1 * eo <= eg <= 10 * eo, (k, eg, eo)
+    # the Schur form itself: diag(T) recovers diag(T0), Q matches the oracle's
+    assert np.max(np.min(np.abs(np.diag(t)[:, None] - g["lam"][None, :]), axis=1)) <= 1e-12
+    qq = oracle.refine(a, qh, lp="quad", maxit=8, tol=1e-30)["Q"].to_c128()
+    assert np.linalg.norm(phase_align(q, qq) - qq) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [16, 64, 256])
+def test_exact_hadamard_schur_form(sr, n):
+    h = synth.hadamard_exact(n, seed=n + 1)
+    qh = synth.perturbed_start(h["Q0"], seed=2, delta=1e-6)
+    q, t, info = _refine(sr, h["A"], qh)
+    assert info["status"] == "OK", info
+    assert np.abs(np.diag(t) - h["lam"]).max() <= 1e-13
+    c = h["Q0"].real.T @ q  # must be diagonal unitary
+    assert np.abs(c - np.diag(np.diag(c))).max() <= 1e-13
+    assert np.abs(np.abs(np.diag(c)) - 1).max() <= 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 2, 17, 100, 257])
+def test_ragged_sizes_converge(sr, n):
+    g = synth.schur_test_matrix(n, seed=50 + n)
+    qh = synth.lp_schur_start(g["A"])
+    q, t, info = _refine(sr, g["A"], qh)
+    assert info["status"] == "OK", info
+    ev = oracle.evaluate(g["A"], q, t)
+    assert ev["stril"] <= 1e-15 and ev["orth"] <= 1e-12
+
+
+def test_config1_n1024_quad_rows(sr):
+    """n = 1024 (the benchmark workload): passes to 1e-15, quad error on 64 rows."""
+    g = synth.schur_test_matrix(1024, seed=1)
+    a = g["A"]
+    qh = synth.lp_schur_start(a)
+    q, t, info = _refine(sr, a, qh)
+    assert info["status"] == "OK" and info["iters"] <= 5, info
+    rows = np.random.default_rng(20001).choice(1024, 64, replace=False)
+    ev = oracle.evaluate_rows(a, q, rows)
+    assert ev["stril"] <= 1e-15, ev
+    assert ev["orth"] <= 4 * U64 * np.sqrt(1024) * 10, ev
+    assert np.max(np.min(np.abs(np.diag(t)[:, None] - g["lam"][None, :]), axis=1)) <= 1e-10
+
+
+def test_status_codes(sr):
+    g = synth.schur_test_matrix(40, seed=3)
+    qh = synth.lp_schur_start(g["A"])
+    _, _, info = _refine(sr, g["A"], qh, iters=1)
+    assert info["status"] == "NOT_CONVERGED" and info["iters"] == 1 and info["rc"] == 1
+    a = g["A"].copy()
+    a[5, 7] = np.nan
+    _, _, info = _refine(sr, a, qh)
+    assert info["status"] == "BREAKDOWN"
+    # invalid arguments are rejected without touching the outputs
+    q, t = dev(qh), empty(40, 40)
+    info = sr.schur_refine(dev(g["A"]), q, t, iters=0)
+    assert info["rc"] == -1
+    assert np.array_equal(host(q), qh)
+
+
+def test_resume_from_saved_iterate(sr):
+    """Checkpoint/resume: a second call from the first call's Q continues the
+    iteration (the method accepts any nearly unitary start)."""
+    g = synth.schur_test_matrix(128, seed=8)
+    qh = synth.lp_schur_start(g["A"])
+    q1, _, i1 = _refine(sr, g["A"], qh, iters=2, tol=1e-15)
+    q2, t2, i2 = _refine(sr, g["A"], q1, iters=4, tol=1e-15)
+    assert i1["status"] == "NOT_CONVERGED" and i2["status"] == "OK"
+    assert oracle.evaluate(g["A"], q2, t2)["stril"] <= 1e-15
+
+
+def test_batched_equals_single(sr):
+    sizes = [20, 50, 90]
+    mats = [synth.schur_test_matrix(n, seed=200 + n) for n in sizes]
+    starts = [synth.lp_schur_start(m["A"]) for m in mats]
+    As = [dev(m["A"]) for m in mats]
+    Qs = [dev(s) for s in starts]
+    Ts = [empty(n, n) for n in sizes]
+    rc, infos = sr.schur_refine_batched(As, Qs, Ts)
+    assert rc == 0
+    for m, s, qd, td, inf in zip(mats, starts, Qs, Ts, infos):
+        q1, t1, i1 = _refine(sr, m["A"], s)
+        assert inf["iters"] == i1["iters"]
+        assert np.array_equal(host(qd), q1) and np.array_equal(host(td), t1)
