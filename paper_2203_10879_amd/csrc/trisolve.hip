@@ -7,161 +7,242 @@
 // entries on one subdiagonal i - j = d are independent (the wavefront order the
 // paper mentions after Theorem 1).
 //
-// GPU schedule. L is cut into 32 x 32 tiles. For a tile (I, J), I >= J, the
+// GPU schedule. L is cut into TB x TB tiles (TB = 32). For a tile (I, J), I >= J, the
 // same algebra at tile level gives
 //   T_II X - X T_JJ = -R_IJ,  R_IJ = E_IJ + sum_{K>I} T_IK L_KJ - sum_{K<J} L_IK T_KJ
 // (for I = J only the strictly lower part, with X strictly lower): a tile depends
 // on the tiles below it in its tile column and left of it in its tile row, so the
-// tiles of one tile diagonal D = I - J are independent. One launch per tile
-// diagonal, D = nb-1 down to 0:
-//   1. the nb-1-D block products of every tile of the diagonal are split over
-//      S blocks (S chosen to fill the chip), each writing its partial sum;
-//   2. the last block of a tile to finish (arrival counter after a device fence;
-//      no block ever waits) adds E_IJ and the partials in a fixed order and
-//      solves the tile by substitution along its anti-diagonals (63 dependent
-//      steps; 31 for a diagonal tile), keeping T_II, T_JJ and X in LDS.
-// Small matrices (and the batched path) use one block that walks all tiles.
+// tiles of one tile diagonal D = I - J are independent, and L_KJ, L_IK of the sum
+// lie on tile diagonals > D. Only two of the block products of a tile touch
+// diagonal D + 1 (K = I + 1 and K = J - 1, the "near" products); the others touch
+// diagonals >= D + 2 ("far").
+//
+// One launch per tile diagonal D = nb-1 .. 0, with two kinds of blocks:
+//   - solve blocks (one per tile of diagonal D): R = E + the far partial sums
+//     computed by the previous launch + the two near products, then substitution
+//     inside the tile along its anti-diagonals (2 TB - 1 dependent steps; TB - 1 on
+//     the diagonal) with T_II and T_JJ in LDS and one thread per entry;
+//   - partial blocks for diagonal D - 1: its far products, split over S blocks per
+//     tile so that the launch fills the chip, written to a buffer selected by the
+//     parity of D.
+// No block waits on another and no device-scope fence is needed: all data a
+// launch reads were written by earlier launches. Small matrices (and the batched
+// path) use one block that walks all tiles.
 #include "kernels.hpp"
 
 namespace sr {
 
-constexpr int TB = 32;
-constexpr int TNT = 256;
-constexpr int TLD = TB + 1;
+#ifndef SR_TRI_TB
+#define SR_TRI_TB 32
+#endif
+constexpr int TB = SR_TRI_TB;
+constexpr int TNT = TB * TB;  // one thread per tile entry
+constexpr int TLD = TB + 1;   // LDS column stride (complex64 elements)
 constexpr int kTargetBlocks = 2 * kCUs;
+constexpr int kTileElems = TB * TB;
 
+// ok ? v : 0, component-wise (a struct-valued select would go through scratch).
+__device__ inline cc keep(bool ok, cc v) { return mk<float>(ok ? v.re : 0.f, ok ? v.im : 0.f); }
+
+// Column ownership (products, partial sums): thread t owns entry (t mod 32, t / 32).
 struct Own {
-  int q, p0;  // this thread owns entries (p0 + c, q), c = 0..3, of a tile
+  int p, q;
 };
 __device__ inline Own owner() {
   Own o;
-  o.q = threadIdx.x >> 3;
-  o.p0 = (threadIdx.x & 7) * 4;
+  o.p = threadIdx.x & (TB - 1);
+  o.q = threadIdx.x / TB;
   return o;
 }
 
-// LDS tile, column-major with padded stride: S[q * TLD + p] = G(I*TB + p, J*TB + q).
+// LDS tile, column-major with padded stride: S[q * TLD + p] = G(I*TB + p, J*TB + q),
+// zero outside the n x n matrix.
 __device__ inline void load_tile(cc* S, const cc* __restrict__ G, int n, int I, int J) {
-#pragma unroll
-  for (int r = 0; r < 4; r++) {
-    const int idx = r * TNT + threadIdx.x;
-    const int p = idx & (TB - 1), q = idx >> 5;
-    const int gi = I * TB + p, gj = J * TB + q;
-    S[q * TLD + p] = (gi < n && gj < n) ? G[gi + (long)gj * n] : mk<float>(0.f, 0.f);
-  }
+  const int p = threadIdx.x & (TB - 1), q = threadIdx.x / TB;
+  const int gi = I * TB + p, gj = J * TB + q;
+  const bool ok = gi < n && gj < n;
+  const cc v = G[ok ? gi + (long)gj * n : 0];
+  S[q * TLD + p] = keep(ok, v);
 }
 
 template <int SIGN>
-__device__ inline void tile_mac(cc acc[4], const cc* F, const cc* G, Own o) {
+__device__ inline void tile_mac(cc& acc, const cc* F, const cc* G, Own o) {
 #pragma unroll 8
   for (int k = 0; k < TB; k++) {
-    const cc b = G[o.q * TLD + k];
-#pragma unroll
-    for (int c = 0; c < 4; c++) {
-      const cc a = F[k * TLD + o.p0 + c];
-      if (SIGN > 0) cfma(acc[c], a, b);
-      else cfms(acc[c], a, b);
-    }
+    const cc a = F[k * TLD + o.p], b = G[o.q * TLD + k];
+    if (SIGN > 0) cfma(acc, a, b);
+    else cfms(acc, a, b);
   }
 }
 
-// acc += sum of block products number u0..u1-1 of tile (I, J): the first
-// nb-1-I are + T_IK L_KJ (K = I+1..nb-1), the rest - L_IK T_KJ (K = 0..J-1).
-__device__ void tile_products(cc acc[4], const cc* T, const cc* L, int n, int nb, int I, int J,
-                              int u0, int u1, cc* S1, cc* S2, Own o) {
-  const int mA = nb - 1 - I;
-  for (int u = u0; u < u1; u++) {
-    __syncthreads();
-    if (u < mA) {
-      const int K = I + 1 + u;
-      load_tile(S1, T, n, I, K);
-      load_tile(S2, L, n, K, J);
-    } else {
-      const int K = u - mA;
-      load_tile(S1, L, n, I, K);
-      load_tile(S2, T, n, K, J);
-    }
-    __syncthreads();
-    if (u < mA) tile_mac<+1>(acc, S1, S2, o);
-    else tile_mac<-1>(acc, S1, S2, o);
+// acc += one block product of tile (I, J): + T_IK L_KJ (typeA) or - L_IK T_KJ.
+__device__ inline void block_product(cc& acc, const cc* T, const cc* L, int n, int I, int J, int K,
+                                     bool typeA, cc* S1, cc* S2, Own o) {
+  __syncthreads();
+  if (typeA) {
+    load_tile(S1, T, n, I, K);
+    load_tile(S2, L, n, K, J);
+  } else {
+    load_tile(S1, L, n, I, K);
+    load_tile(S2, T, n, K, J);
+  }
+  __syncthreads();
+  if (typeA) tile_mac<+1>(acc, S1, S2, o);
+  else tile_mac<-1>(acc, S1, S2, o);
+}
+
+// All block products of tile (I, J) (K = I+1..nb-1 of type A, K = 0..J-1 of type B).
+__device__ void all_products(cc& acc, const cc* T, const cc* L, int n, int nb, int I, int J, cc* S1,
+                             cc* S2, Own o) {
+  for (int K = I + 1; K < nb; K++) block_product(acc, T, L, n, I, J, K, true, S1, S2, o);
+  for (int K = 0; K < J; K++) block_product(acc, T, L, n, I, J, K, false, S1, S2, o);
+}
+
+__device__ inline void add_e(cc& acc, const cc* __restrict__ E, int n, int I, int J, Own o) {
+  const int gi = I * TB + o.p, gj = J * TB + o.q;
+  const bool ok = gi < n && gj < n && gi > gj;
+  const cc v = E[ok ? gi + (long)gj * n : 0];
+  if (ok) {
+    acc.re += v.re;
+    acc.im += v.im;
   }
 }
 
-__device__ inline void add_e(cc acc[4], const cc* __restrict__ E, int n, int I, int J, Own o) {
-  const int gj = J * TB + o.q;
-#pragma unroll
-  for (int c = 0; c < 4; c++) {
-    const int gi = I * TB + o.p0 + c;
-    if (gi < n && gj < n && gi > gj) {
-      const cc e = E[gi + (long)gj * n];
-      acc[c].re += e.re;
-      acc[c].im += e.im;
-    }
+// Entry of rank r in anti-diagonal order (d = p - q from 31 down to -31, q
+// increasing within a diagonal). Diagonals d >= 0 hold ranks 0..527.
+__device__ inline void diag_rank(int r, int& p, int& q) {
+  const bool upper = r < (TB * (TB + 1)) / 2;
+  const int rr = upper ? r : TB * TB - 1 - r;
+  int k = (int)((sqrtf(8.f * rr + 1.f) - 1.f) * 0.5f);
+  while (k * (k + 1) / 2 > rr) k--;
+  while ((k + 1) * (k + 2) / 2 <= rr) k++;
+  const int i = rr - k * (k + 1) / 2;  // position within the diagonal
+  if (upper) {
+    const int d = TB - 1 - k;
+    q = i;
+    p = q + d;
+  } else {
+    const int d = -(TB - 1 - k);
+    q = TB - 1 - i;
+    p = q + d;
   }
 }
+
+// LDS layouts of the solve (complex64 elements):
+//   TaP: T_II column-major, 63 columns of stride TLD, columns 32..62 zero, so that
+//        Ta(p, q+s) is addressable for every q + s <= 62;
+//   TbP: T_JJ (T_II on a diagonal tile) column-major with stride 64 and a row
+//        offset of 31, rows -31..-1 zero, so that Tb(p-s, q) is addressable for
+//        every p - s >= -31;
+//   dv:  per step the finalized anti-diagonal by column, dv[32 + c] = X(c+s, c)
+//        (0 where that entry does not exist), dv[0..31] = 0, so that X(p, p-s)
+//        reads dv[32 + p - s] for every p - s >= -32.
+constexpr int kTaCols = 2 * TB - 1;
+constexpr int kTbLd = 2 * TB;
+constexpr int kSolveS1 = kTaCols * TLD;  // elements of the first LDS buffer
+constexpr int kSolveS2 = TB * kTbLd;     // elements of the second LDS buffer
 
 // Solve T_II X - X T_JJ = -R (I > J) or stril(T_II X - X T_II) = -stril(R) (I = J)
-// for the tile whose R is in acc; writes the tile of L.
-__device__ void tile_solve(cc acc[4], const cc* T, cc* L, int n, int I, int J, float trunc,
-                           unsigned* status, cc* Ta, cc* Tb, cc* X, Own o) {
+// for the tile whose R (column ownership) is in acc; writes the tile of L.
+//
+// Threads take the entries in anti-diagonal order, so the entries of a wave lie
+// on a few neighbouring anti-diagonals. Step s finalizes anti-diagonal p - q = s:
+// its entries write x = -r / (ta_pp - tb_qq) to L and to dv (double-buffered by
+// step parity); after one barrier every pending entry (p - q < s) adds the two
+// contributions of that diagonal,
+//   + Ta(p, q+s) X(q+s, q)   (entry below it in its column)
+//   - X(p, p-s) Tb(p-s, q)   (entry left of it in its row)
+// with operands that read as zero where the entry does not exist, and addresses
+// that move by a constant per step. Waves whose entries are all final skip the
+// update.
+__device__ void tile_solve(cc acc, const cc* T, cc* L, int n, int I, int J, float trunc,
+                           unsigned* status, cc* TaP, cc* TbP, cc* R, Own o) {
+  __shared__ cc dv[2][2 * TB];
+  __shared__ int wave_min_d[TNT / 64];
   const bool diag = (I == J);
+  const cc z = mk<float>(0.f, 0.f);
   __syncthreads();
-  load_tile(Ta, T, n, I, I);
-  if (!diag) load_tile(Tb, T, n, J, J);
-  for (int r = threadIdx.x; r < TB * TLD; r += TNT) X[r] = mk<float>(0.f, 0.f);
-  __syncthreads();
-  const cc* B = diag ? Ta : Tb;
-  const int q = o.q;
-  cc rd[4];
-  bool live[4];
-  bool bad = false;
-#pragma unroll
-  for (int c = 0; c < 4; c++) {
-    const int p = o.p0 + c;
-    live[c] = (I * TB + p < n) && (J * TB + q < n) && (!diag || p > q);
-    rd[c] = mk<float>(0.f, 0.f);
-    if (live[c]) {
-      const cc ta = Ta[p * TLD + p], tb = B[q * TLD + q];
-      const float dr = ta.re - tb.re, di = ta.im - tb.im;
-      const float den = dr * dr + di * di;
-      if (den == 0.f) bad = true;
-      rd[c] = mk<float>(dr / den, -di / den);
+  {
+    // TaP columns 0..31 from T_II, 32..62 zero
+    const int p = threadIdx.x & (TB - 1), c = threadIdx.x / TB;
+    const int gi = I * TB + p, gj = I * TB + c;
+    const bool ok = gi < n && gj < n;
+    const cc v = T[ok ? gi + (long)gj * n : 0];
+    TaP[c * TLD + p] = keep(ok, v);
+    if (c < TB - 1) TaP[(TB + c) * TLD + p] = z;
+    // TbP rows -31..31 of column c (offset 31), rows < 0 zero
+    const int K = diag ? I : J;
+    const int gk = K * TB + p, gc = K * TB + c;
+    const bool okb = gk < n && gc < n;
+    const cc w = T[okb ? gk + (long)gc * n : 0];
+    TbP[c * kTbLd + (TB - 1) + p] = keep(okb, w);
+    if (p < TB - 1) TbP[c * kTbLd + p] = z;
+    if (threadIdx.x < 2 * TB) {
+      dv[0][threadIdx.x] = z;
+      dv[1][threadIdx.x] = z;
     }
   }
-  const int smin = diag ? 1 : -(TB - 1);
-  for (int s = TB - 1; s >= smin; s--) {
+  R[o.q * TLD + o.p] = acc;
+  int p, q;
+  diag_rank(threadIdx.x, p, q);
+  const int d = p - q;
+  const bool live = (I * TB + p < n) && (J * TB + q < n) && (!diag || d > 0);
+  {
+    int md = d;
 #pragma unroll
-    for (int c = 0; c < 4; c++) {
-      const int p = o.p0 + c;
-      if (live[c] && p - q == s) {
-        cc x = cmul(acc[c], rd[c]);
+    for (int off = 32; off > 0; off >>= 1) md = min(md, __shfl_xor(md, off, 64));
+    if ((threadIdx.x & 63) == 0) wave_min_d[threadIdx.x >> 6] = md;
+  }
+  __syncthreads();
+  cc a = R[q * TLD + p];
+  const int wmin = wave_min_d[threadIdx.x >> 6];
+  bool bad = false;
+  cc rd = z;
+  {
+    const cc ta = TaP[p * TLD + p], tb = TbP[q * kTbLd + (TB - 1) + q];
+    const float dr = ta.re - tb.re, di = ta.im - tb.im;
+    const float den = dr * dr + di * di;
+    if (live && den == 0.f) bad = true;
+    if (live) rd = mk<float>(dr / den, -di / den);
+  }
+  const float trunc2 = trunc * trunc;
+  const int smin = diag ? 1 : -(TB - 1);
+  const long gaddr = (I * TB + p) + (long)(J * TB + q) * n;
+  // operand indices at s = TB - 1; per step: ta -= TLD, xb += 1, tb += 1
+  int ta_i = (q + TB - 1) * TLD + p;
+  int xb_i = TB + p - (TB - 1);
+  int tb_i = q * kTbLd + p;
+  const int r = threadIdx.x;  // column whose dv slot this thread clears when absent
+  cc xf = z;                  // this thread's entry of L once finalized
+  // The loop touches LDS only: a global store inside it would make every barrier
+  // (a workgroup release) wait for that store to complete.
+  for (int s = TB - 1; s >= smin; s--) {
+    cc* cur = dv[s & 1];
+    if (d == s) {
+      cc x = z;
+      if (live) {
+        x = cmul(a, rd);
         x.re = -x.re;
         x.im = -x.im;
-        if (!isfinite(x.re) || !isfinite(x.im)) bad = true;
-        if (trunc > 0.f && x.re * x.re + x.im * x.im > trunc * trunc) x = mk<float>(0.f, 0.f);
-        X[q * TLD + p] = x;
+        bad |= !isfinite(x.re) || !isfinite(x.im);
+        if (trunc2 > 0.f && x.re * x.re + x.im * x.im > trunc2) x = z;
       }
+      xf = x;
+      cur[TB + q] = x;
     }
+    if (r < TB && (r + s > TB - 1 || r + s < 0)) cur[TB + r] = z;
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 4; c++) {
-      const int p = o.p0 + c;
-      if (live[c] && p - q < s) {
-        const int p2 = q + s;  // finalized entry (p2, q) below in this column
-        if (p2 < TB && p2 > p) cfma(acc[c], Ta[p2 * TLD + p], X[q * TLD + p2]);
-        const int r = p - s;   // finalized entry (p, r) left in this row
-        if (r >= 0 && r < q) cfms(acc[c], X[r * TLD + p], B[q * TLD + r]);
-      }
+    if (wmin < s && d < s) {
+      const cc xa = cur[TB + q], xb = cur[xb_i];
+      const cc ta = TaP[ta_i], tb = TbP[tb_i];
+      cfma(a, ta, xa);
+      cfms(a, xb, tb);
     }
+    ta_i -= TLD;
+    xb_i += 1;
+    tb_i += 1;
   }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < 4; r++) {
-    const int idx = r * TNT + threadIdx.x;
-    const int p = idx & (TB - 1), qq = idx >> 5;
-    const int gi = I * TB + p, gj = J * TB + qq;
-    if (gi < n && gj < n) L[gi + (long)gj * n] = X[qq * TLD + p];
-  }
+  if (live) L[gaddr] = xf;
   if (bad) atomicOr(status, (unsigned)DEV_BREAKDOWN);
 }
 
@@ -169,55 +250,46 @@ struct TriLevelArgs {
   const cc* T;
   const cc* E;
   cc* L;
-  int n, nb, D, S;
-  cc* partial;
-  unsigned* counters;
+  int n, nb, D;
+  int S_cur;         // partial blocks per tile that wrote diagonal D's far sums
+  int S_next;        // partial blocks per tile for diagonal D - 1 (0: none)
+  const cc* part_cur;  // [tiles(D)][S_cur][TB*TB]
+  cc* part_next;       // [tiles(D-1)][S_next][TB*TB]
   unsigned* status;
   float trunc;
 };
 
 __global__ __launch_bounds__(TNT) void trisolve_level_kernel(TriLevelArgs a) {
-  __shared__ cc S1[TB * TLD], S2[TB * TLD], S3[TB * TLD];
-  __shared__ unsigned is_last;
-  const int t = blockIdx.x / a.S, s = blockIdx.x - (blockIdx.x / a.S) * a.S;
-  const int I = a.D + t, J = t;
+  __shared__ cc S1[kSolveS1], S2[kSolveS2], S3[TB * TLD];
   const Own o = owner();
-  const int m = a.nb - 1 - a.D;
-  cc acc[4];
-#pragma unroll
-  for (int c = 0; c < 4; c++) acc[c] = mk<float>(0.f, 0.f);
-  const int u0 = (int)((long)m * s / a.S), u1 = (int)((long)m * (s + 1) / a.S);
-  tile_products(acc, a.T, a.L, a.n, a.nb, I, J, u0, u1, S1, S2, o);
-  if (a.S > 1) {
-    cc* slot = a.partial + ((long)t * a.S + s) * (TB * TB);
-#pragma unroll
-    for (int c = 0; c < 4; c++) slot[(o.p0 + c) + o.q * TB] = acc[c];
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const unsigned prev = atomicAdd(&a.counters[t], 1u);
-      is_last = (prev == (unsigned)(a.S - 1)) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    if (threadIdx.x == 0) a.counters[t] = 0u;
-#pragma unroll
-    for (int c = 0; c < 4; c++) acc[c] = mk<float>(0.f, 0.f);
+  const int tiles = a.nb - a.D;
+  cc acc = mk<float>(0.f, 0.f);
+  if ((int)blockIdx.x < tiles) {
+    // solve block for tile (D + t, t)
+    const int t = blockIdx.x, I = a.D + t, J = t;
     add_e(acc, a.E, a.n, I, J, o);
-    for (int s2 = 0; s2 < a.S; s2++) {
-      const cc* sl = a.partial + ((long)t * a.S + s2) * (TB * TB);
-#pragma unroll
-      for (int c = 0; c < 4; c++) {
-        const cc v = sl[(o.p0 + c) + o.q * TB];
-        acc[c].re += v.re;
-        acc[c].im += v.im;
-      }
+    for (int s = 0; s < a.S_cur; s++) {
+      const cc v = a.part_cur[((long)t * a.S_cur + s) * kTileElems + o.p + o.q * TB];
+      acc.re += v.re;
+      acc.im += v.im;
     }
-  } else {
-    add_e(acc, a.E, a.n, I, J, o);
+    if (I + 1 < a.nb) block_product(acc, a.T, a.L, a.n, I, J, I + 1, true, S1, S2, o);
+    if (J >= 1) block_product(acc, a.T, a.L, a.n, I, J, J - 1, false, S1, S2, o);
+    tile_solve(acc, a.T, a.L, a.n, I, J, a.trunc, a.status, S1, S2, S3, o);
+    return;
   }
-  tile_solve(acc, a.T, a.L, a.n, I, J, a.trunc, a.status, S1, S2, S3, o);
+  // partial block for diagonal D - 1: tile t2 = (D - 1 + t2, t2), split s
+  const int b = blockIdx.x - tiles;
+  const int t2 = b / a.S_next, s = b - (b / a.S_next) * a.S_next;
+  const int I = a.D - 1 + t2, J = t2;
+  const int fa = max(0, a.nb - 2 - I), fb = max(0, J - 1);
+  const int m = fa + fb;
+  const int u0 = (int)((long)m * s / a.S_next), u1 = (int)((long)m * (s + 1) / a.S_next);
+  for (int u = u0; u < u1; u++) {
+    if (u < fa) block_product(acc, a.T, a.L, a.n, I, J, I + 2 + u, true, S1, S2, o);
+    else block_product(acc, a.T, a.L, a.n, I, J, u - fa, false, S1, S2, o);
+  }
+  a.part_next[((long)t2 * a.S_next + s) * kTileElems + o.p + o.q * TB] = acc;
 }
 
 struct TriMatrix {
@@ -231,28 +303,44 @@ struct TriMatrix {
 __global__ __launch_bounds__(TNT) void trisolve_single_kernel(const TriMatrix* __restrict__ mats,
                                                               TriMatrix one, unsigned* status,
                                                               float trunc) {
-  __shared__ cc S1[TB * TLD], S2[TB * TLD], S3[TB * TLD];
+  __shared__ cc S1[kSolveS1], S2[kSolveS2], S3[TB * TLD];
   const TriMatrix mt = mats ? mats[blockIdx.x] : one;
   const int n = mt.n, nb = (n + TB - 1) / TB;
   const Own o = owner();
   for (int D = nb - 1; D >= 0; D--) {
     for (int t = 0; t < nb - D; t++) {
       const int I = D + t, J = t;
-      cc acc[4];
-#pragma unroll
-      for (int c = 0; c < 4; c++) acc[c] = mk<float>(0.f, 0.f);
+      cc acc = mk<float>(0.f, 0.f);
       add_e(acc, mt.E, n, I, J, o);
-      tile_products(acc, mt.T, mt.L, n, nb, I, J, 0, nb - 1 - D, S1, S2, o);
+      all_products(acc, mt.T, mt.L, n, nb, I, J, S1, S2, o);
       tile_solve(acc, mt.T, mt.L, n, I, J, trunc, status, S1, S2, S3, o);
     }
   }
 }
 
+// Far products per tile on diagonal D (the most of any tile there).
+static int max_far(int nb, int D) {
+  if (D < 0) return 0;
+  const int m = nb - 1 - D;  // all products
+  if (nb - D == 1) return 0;
+  return m - 1;  // the first and last tile lack one near product
+}
+
+static int splits(int nb, int D) {
+  const int mf = max_far(nb, D);
+  if (mf <= 0) return 0;
+  int S = ceil_div(kTargetBlocks, nb - D);
+  if (S > mf) S = mf;
+  return S < 1 ? 1 : S;
+}
+
+static size_t part_bytes(int nb) {
+  return (size_t)(kTargetBlocks + nb) * kTileElems * sizeof(cc);
+}
+
 size_t trisolve_ws_bytes(int n) {
   const int nb = ceil_div(n, TB);
-  const size_t counters = ((size_t)nb * 4 + 255) / 256 * 256;
-  const size_t parts = (size_t)(kTargetBlocks + nb) * TB * TB * sizeof(cc);
-  return counters + parts;
+  return 2 * part_bytes(nb);
 }
 
 hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* ws,
@@ -267,20 +355,17 @@ hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* w
                        (const TriMatrix*)nullptr, one, status, trunc);
     return hipGetLastError();
   }
-  const size_t counters_bytes = ((size_t)nb * 4 + 255) / 256 * 256;
-  unsigned* counters = (unsigned*)ws;
-  cc* partial = (cc*)((char*)ws + counters_bytes);
-  e = fill_zero(counters, counters_bytes, st);
-  if (e != hipSuccess) return e;
+  cc* part[2] = {(cc*)ws, (cc*)((char*)ws + part_bytes(nb))};
+  int S_cur = 0;  // the top diagonal has no far products
   for (int D = nb - 1; D >= 0; D--) {
-    const int tiles = nb - D, m = nb - 1 - D;
-    int S = ceil_div(kTargetBlocks, tiles);
-    if (S > m) S = m;
-    if (S < 1) S = 1;
-    TriLevelArgs a{T, E, L, n, nb, D, S, partial, counters, status, trunc};
-    hipLaunchKernelGGL(trisolve_level_kernel, dim3(tiles * S), dim3(TNT), 0, st, a);
+    const int tiles = nb - D;
+    const int S_next = D >= 1 ? splits(nb, D - 1) : 0;
+    const int tiles_next = D >= 1 ? nb - D + 1 : 0;
+    TriLevelArgs a{T, E, L, n, nb, D, S_cur, S_next, part[D & 1], part[(D - 1) & 1], status, trunc};
+    hipLaunchKernelGGL(trisolve_level_kernel, dim3(tiles + tiles_next * S_next), dim3(TNT), 0, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    S_cur = S_next;
   }
   return hipSuccess;
 }
