@@ -2,18 +2,21 @@
 // and FP32 MFMA (its lp products), with the pass's elementwise steps fused into
 // the epilogue.
 //
-// Tiling: a 256-thread block computes a 64 x 64 complex tile of C; its four
-// waves each own a 32 x 32 complex quadrant, i.e. 2 x 2 blocks of 16 x 16, with
-// separate real and imaginary accumulators. Every 16 x 16 x 4 step is four real
+// Tiling: a 512-thread block computes a 64 x 64 complex tile of C; its eight
+// waves (2 along M x 4 along N) each own a 32 x 16 complex piece, i.e. 2 x 1
+// blocks of 16 x 16, with separate real and imaginary accumulators. Every 16 x 16 x 4 step is four real
 // MFMAs: re += a_re b_re - a_im b_im, im += a_re b_im + a_im b_re. op(A) and B
 // tiles (K depth 16) are staged through LDS, double-buffered, with an XOR swizzle
 // so that both the transposing stores and the fragment loads avoid bank
 // conflicts. Complex values stay interleaved (re, im) so one 16-byte LDS read
 // yields both parts of an operand.
 //
-// Compensated mode (FP64 only): the MFMA accumulators are folded every
-// kChunk K-tiles into a (hi, lo) pair by an error-free TwoSum, so the rounding
-// error of a dot product of length K grows like sqrt(K * chunk) instead of K.
+// Compensated mode (FP64 only): two-level summation. The MFMA accumulators hold
+// the sum of one chunk of kChunk K-tiles and are then added into a running total
+// and cleared. For random-sign terms the rounding error of a length-K dot product
+// drops from about u K / sqrt(2) to about u (K / sqrt(2 c) + sqrt(K c / 2)) with
+// c = 16 kChunk terms per chunk: 4-6x smaller for K = 1024..4096, which brings the
+// FP64 floor of ||stril(Q^H A Q)|| / ||A|| below 1e-15.
 #include "kernels.hpp"
 
 namespace sr {
@@ -43,8 +46,10 @@ struct MF<float> {
   __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-constexpr int GBM = 64, GBN = 64, GBK = 16, GNT = 256;
-constexpr int kChunk = 2;  // K-tiles (32 complex terms) per compensated fold
+constexpr int GBM = 64, GBN = 64, GBK = 16, GNT = 512;
+constexpr int WM = 2, WN = 1;  // 16 x 16 blocks per wave along M and N
+constexpr int kLoads = GBM * GBK / GNT;  // elements of each operand tile per thread
+constexpr int kChunk = 2;  // K-tiles (32 complex terms) per chunk of the two-level sum
 
 // LDS column swizzle: row k of a [GBK][64] tile is permuted by XOR with 4 (k mod 16).
 __device__ inline int swz(int k, int m) { return m ^ ((k & 15) << 2); }
@@ -60,7 +65,7 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
   __shared__ double red[GNT / 64];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int wm = (wave & 1) * (16 * WM), wn = (wave >> 1) * (16 * WN);
 
   // Blocks are dispatched round-robin over the XCDs (block b on XCD b mod 8):
   // give each XCD a contiguous run of logical tiles, then walk tiles in groups of
@@ -85,26 +90,24 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
   const C* __restrict__ Ap = (const C*)g.A;
   const C* __restrict__ Bp = (const C*)g.B;
 
-  V acc_re[2][2], acc_im[2][2];
-  V hi_re[2][2], hi_im[2][2], lo_re[2][2], lo_im[2][2];
+  V acc_re[WM][WN], acc_im[WM][WN];
+  V tot_re[WM][WN], tot_im[WM][WN];
 #pragma unroll
-  for (int a = 0; a < 2; a++)
+  for (int a = 0; a < WM; a++)
 #pragma unroll
-    for (int b = 0; b < 2; b++)
+    for (int b = 0; b < WN; b++)
 #pragma unroll
       for (int v = 0; v < 4; v++) {
         acc_re[a][b][v] = 0;
         acc_im[a][b][v] = 0;
-        hi_re[a][b][v] = 0;
-        hi_im[a][b][v] = 0;
-        lo_re[a][b][v] = 0;
-        lo_im[a][b][v] = 0;
+        tot_re[a][b][v] = 0;
+        tot_im[a][b][v] = 0;
       }
 
-  C ra[4], rb[4];
+  C ra[kLoads], rb[kLoads];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
+    for (int r = 0; r < kLoads; r++) {
       const int idx = r * GNT + tid;
       int mm, kk;
       if (OPA == 0) {
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
+    for (int r = 0; r < kLoads; r++) {
       const int idx = r * GNT + tid;
       int mm, kk;
       if (OPA == 0) {
@@ -148,21 +151,17 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
   auto fold = [&]() {
     if constexpr (COMP) {
 #pragma unroll
-      for (int a = 0; a < 2; a++)
+      for (int a = 0; a < WM; a++)
 #pragma unroll
-        for (int b = 0; b < 2; b++)
+        for (int b = 0; b < WN; b++) {
+          tot_re[a][b] += acc_re[a][b];
+          tot_im[a][b] += acc_im[a][b];
 #pragma unroll
           for (int v = 0; v < 4; v++) {
-            double s, e;
-            two_sum(hi_re[a][b][v], acc_re[a][b][v], s, e);
-            hi_re[a][b][v] = s;
-            lo_re[a][b][v] += e;
-            two_sum(hi_im[a][b][v], acc_im[a][b][v], s, e);
-            hi_im[a][b][v] = s;
-            lo_im[a][b][v] += e;
             acc_re[a][b][v] = 0;
             acc_im[a][b][v] = 0;
           }
+        }
     }
   };
 
@@ -176,26 +175,33 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 4) {
       const int krow = kk + (lane >> 4);
-      R a_re[2], a_im[2], na_im[2], b_re[2], b_im[2];
+      R a_re[WM], a_im[WM], na_im[WM], b_re[WN], b_im[WN];
 #pragma unroll
-      for (int mi = 0; mi < 2; mi++) {
+      for (int mi = 0; mi < WM; mi++) {
         const C v = As[cur][krow][swz(krow, wm + mi * 16 + (lane & 15))];
         a_re[mi] = v.re;
         a_im[mi] = v.im;
         na_im[mi] = -v.im;
       }
 #pragma unroll
-      for (int ni = 0; ni < 2; ni++) {
+      for (int ni = 0; ni < WN; ni++) {
         const C v = Bs[cur][krow][swz(krow, wn + ni * 16 + (lane & 15))];
         b_re[ni] = v.re;
         b_im[ni] = v.im;
       }
+      // The two products that accumulate into one register are issued 2 WM WN
+      // MFMAs apart, so a dependent MFMA does not wait for its predecessor.
 #pragma unroll
-      for (int mi = 0; mi < 2; mi++)
+      for (int mi = 0; mi < WM; mi++)
 #pragma unroll
-        for (int ni = 0; ni < 2; ni++) {
+        for (int ni = 0; ni < WN; ni++) {
           acc_re[mi][ni] = MF<R>::op(a_re[mi], b_re[ni], acc_re[mi][ni]);
           acc_im[mi][ni] = MF<R>::op(a_re[mi], b_im[ni], acc_im[mi][ni]);
+        }
+#pragma unroll
+      for (int mi = 0; mi < WM; mi++)
+#pragma unroll
+        for (int ni = 0; ni < WN; ni++) {
           acc_re[mi][ni] = MF<R>::op(na_im[mi], b_im[ni], acc_re[mi][ni]);
           acc_im[mi][ni] = MF<R>::op(a_im[mi], b_re[ni], acc_im[mi][ni]);
         }
@@ -210,17 +216,17 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
   const C* __restrict__ Cin = (const C*)g.Cin;
   double part = 0;
 #pragma unroll
-  for (int mi = 0; mi < 2; mi++)
+  for (int mi = 0; mi < WM; mi++)
 #pragma unroll
-    for (int ni = 0; ni < 2; ni++)
+    for (int ni = 0; ni < WN; ni++)
 #pragma unroll
       for (int v = 0; v < 4; v++) {
         const int i = m0 + wm + mi * 16 + MF<R>::row(lane, v);
         const int j = n0 + wn + ni * 16 + (lane & 15);
         C val;
         if constexpr (COMP) {
-          val.re = hi_re[mi][ni][v] + lo_re[mi][ni][v];
-          val.im = hi_im[mi][ni][v] + lo_im[mi][ni][v];
+          val.re = tot_re[mi][ni][v];
+          val.im = tot_im[mi][ni][v];
         } else {
           val.re = acc_re[mi][ni][v];
           val.im = acc_im[mi][ni][v];
@@ -231,7 +237,12 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
             Cp[o] = val;
           } else if constexpr (EPI == EPI_ADD) {
             const C c0 = Cin[i + (long)j * g.ldcin];
-            Cp[o] = mk<R>(c0.re + val.re, c0.im + val.im);
+            const C r = mk<R>(c0.re + val.re, c0.im + val.im);
+            Cp[o] = r;
+            // optional conjugate transpose of the result; in this accumulator
+            // layout lanes 16 apart hold consecutive columns j, so the transposed
+            // store still writes runs of 16 consecutive elements
+            if (g.CH) ((C*)g.CH)[j + (long)i * g.ldch] = mk<R>(r.re, -r.im);
           } else if constexpr (EPI == EPI_SPLIT) {
             const long ol = i + (long)j * g.ldlp;
             if (i <= j) {
@@ -256,7 +267,12 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
     if (lane == 0) red[wave] = part;
     __syncthreads();
-    if (tid == 0) g.partials[bid] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (tid == 0) {
+      double t = 0;
+#pragma unroll
+      for (int w = 0; w < GNT / 64; w++) t += red[w];
+      g.partials[bid] = t;
+    }
   }
 }
 
@@ -279,6 +295,8 @@ hipError_t zgemm(int opa, int epi, int comp, const GemmArgs& g, hipStream_t st) 
   }
   SR_Z(0, EPI_STORE)
   SR_Z(0, EPI_ADD)
+  SR_Z(0, EPI_SPLIT)
+  SR_Z(0, EPI_YDEF)
   SR_Z(1, EPI_STORE)
   SR_Z(1, EPI_ADD)
   SR_Z(1, EPI_SPLIT)

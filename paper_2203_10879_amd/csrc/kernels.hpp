@@ -8,7 +8,7 @@ namespace sr {
 // Epilogues of the complex GEMM.
 enum GemmEpi : int {
   EPI_STORE = 0,  // C = acc
-  EPI_ADD = 1,    // C = Cin + acc
+  EPI_ADD = 1,    // C = Cin + acc (and CH = C^H when CH is set)
   EPI_SPLIT = 2,  // That: C = triu(acc) (zeros below), Tlp = fp32 triu, Elp = fp32 stril,
                   //       partials[block] = sum |stril(acc)|^2
   EPI_YDEF = 3    // Y: C = acc - I, partials[block] = sum |acc - I|^2
@@ -24,6 +24,8 @@ struct GemmArgs {
   long ldc;
   const void* Cin;
   long ldcin;
+  void* CH;  // EPI_ADD: optional conjugate transpose of C
+  long ldch;
   cc* Tlp;
   cc* Elp;
   long ldlp;

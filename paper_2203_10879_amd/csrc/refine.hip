@@ -36,7 +36,7 @@ int partial_slots(int n) {
 }
 
 struct Work {
-  zc *Qa, *P, *Y;
+  zc *Qa, *QH, *P, *Y;
   cc *Tlp, *Elp, *Llp, *W, *W2, *W3, *YW, *Ylp;
   double* partials;
   double* scal;
@@ -56,6 +56,7 @@ Work carve(void* base, int n) {
     return r;
   };
   w.Qa = (zc*)take(z);
+  w.QH = (zc*)take(z);
   w.P = (zc*)take(z);
   w.Y = (zc*)take(z);
   w.Tlp = (cc*)take(c);
@@ -167,8 +168,9 @@ struct Timer {
     (tm)->count[c]++;     \
   }
 
-// Newton-Schulz start into Qout: Y0 = Qh^H Qh - I, Qout = Qh + Qh (-Y0/2).
-int ns_init(const zc* Qh, zc* Qout, int n, int comp, const Work& w, hipStream_t st,
+// Newton-Schulz start into Qout: Y0 = Qh^H Qh - I, Qout = Qh + Qh (-Y0/2);
+// QHout (may be NULL) receives Qout^H.
+int ns_init(const zc* Qh, zc* Qout, zc* QHout, int n, int comp, const Work& w, hipStream_t st,
             Timer* tm = nullptr) {
   GemmArgs g = gargs(n, n, n, Qh, n, Qh, n, w.Y, n);
   g.partials = w.partials;
@@ -179,6 +181,8 @@ int ns_init(const zc* Qh, zc* Qout, int n, int comp, const Work& w, hipStream_t 
   GemmArgs u = gargs(n, n, n, Qh, n, w.P, n, Qout, n);
   u.Cin = Qh;
   u.ldcin = n;
+  u.CH = QHout;
+  u.ldch = n;
   TIC(tm, 0);
   CK(zgemm(0, EPI_ADD, 0, u, st));
   TOC(tm, 0);
@@ -186,30 +190,32 @@ int ns_init(const zc* Qh, zc* Qout, int n, int comp, const Work& w, hipStream_t 
 }
 
 // P = A Q, That = Q^H P with the split epilogue, scal[1] = ||stril(That)||_F^2.
-int residual(const zc* A, const zc* Q, zc* T, int n, int comp, const Work& w, hipStream_t st,
-             Timer* tm = nullptr) {
+// With QH (= Q^H) given, That is formed as the plain product QH P.
+int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, const Work& w,
+             hipStream_t st, Timer* tm = nullptr) {
   GemmArgs g = gargs(n, n, n, A, n, Q, n, w.P, n);
   TIC(tm, 0);
   CK(zgemm(0, EPI_STORE, comp, g, st));
   TOC(tm, 0);
-  GemmArgs s = gargs(n, n, n, Q, n, w.P, n, T, n);
+  GemmArgs s = gargs(n, n, n, QH ? QH : Q, n, w.P, n, T, n);
   s.Tlp = w.Tlp;
   s.Elp = w.Elp;
   s.ldlp = n;
   s.partials = w.partials;
   TIC(tm, 0);
-  CK(zgemm(1, EPI_SPLIT, comp, s, st));
+  CK(zgemm(QH ? 0 : 1, EPI_SPLIT, comp, s, st));
   TOC(tm, 0);
   CK(reduce_partials(w.partials, gemm_tiles(n, n), w.scal + 1, st));
   return SR_OK;
 }
 
 // Y = Q^H Q - I (scal[2] = ||Y||^2), W = L - L^H (scal[3] = ||W||^2).
-int defects(const zc* Q, int n, int comp, const Work& w, hipStream_t st, Timer* tm = nullptr) {
-  GemmArgs g = gargs(n, n, n, Q, n, Q, n, w.Y, n);
+int defects(const zc* Q, const zc* QH, int n, int comp, const Work& w, hipStream_t st,
+            Timer* tm = nullptr) {
+  GemmArgs g = gargs(n, n, n, QH ? QH : Q, n, Q, n, w.Y, n);
   g.partials = w.partials;
   TIC(tm, 0);
-  CK(zgemm(1, EPI_YDEF, comp, g, st));
+  CK(zgemm(QH ? 0 : 1, EPI_YDEF, comp, g, st));
   TOC(tm, 0);
   CK(reduce_partials(w.partials, gemm_tiles(n, n), w.scal + 2, st));
   CK(form_w(w.Llp, w.W, n, w.partials, st));
@@ -221,9 +227,9 @@ struct Gate {
   bool w2, w3, yw;
 };
 
-// lp products, Delta, and Qout = Q + Q Delta.
-int apply_update(const zc* Q, zc* Qout, int n, Gate gt, const Work& w, hipStream_t st, int* nprod,
-                 Timer* tm = nullptr) {
+// lp products, Delta, and Qout = Q + Q Delta (QHout, if given, receives Qout^H).
+int apply_update(const zc* Q, zc* Qout, zc* QHout, int n, Gate gt, const Work& w, hipStream_t st,
+                 int* nprod, Timer* tm = nullptr) {
   int np = 0;
   if (gt.w2 || gt.w3) {
     CK(cgemm(gargs(n, n, n, w.W, n, w.W, n, w.W2, n), st));
@@ -243,6 +249,8 @@ int apply_update(const zc* Q, zc* Qout, int n, Gate gt, const Work& w, hipStream
   GemmArgs u = gargs(n, n, n, Q, n, w.P, n, Qout, n);
   u.Cin = Q;
   u.ldcin = n;
+  u.CH = QHout;
+  u.ldch = n;
   TIC(tm, 0);
   CK(zgemm(0, EPI_ADD, 0, u, st));
   TOC(tm, 0);
@@ -395,10 +403,10 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   double eps = 0, eps1 = -1, eps2 = -1, orth = 0;
   zc* cur = w.Qa;
   zc* other = Q;
-  if ((rc = ns_init(Q, w.Qa, n, comp, w, st, tm)) != SR_OK) return rc;
+  if ((rc = ns_init(Q, w.Qa, w.QH, n, comp, w, st, tm)) != SR_OK) return rc;
 
   for (int p = 0; p < iters; p++) {
-    if ((rc = residual(A, cur, T, n, comp, w, st, tm)) != SR_OK) return rc;
+    if ((rc = residual(A, cur, w.QH, T, n, comp, w, st, tm)) != SR_OK) return rc;
     double s[2];
     unsigned dst = 0;
     if ((rc = read_back(st, w, 2, s, &dst)) != SR_OK) return rc;
@@ -428,7 +436,7 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
     TIC(tm, 1);
     CK(trisolve(w.Tlp, w.Elp, w.Llp, n, o.trunc ? 1e-5f : 0.f, w.tri, w.status, st));
     TOC(tm, 1);
-    if ((rc = defects(cur, n, comp, w, st, tm)) != SR_OK) return rc;
+    if ((rc = defects(cur, w.QH, n, comp, w, st, tm)) != SR_OK) return rc;
     double nrm[4];
     if ((rc = read_back(st, w, 4, nrm, &dst)) != SR_OK) return rc;
     if (dst & DEV_BREAKDOWN) {
@@ -443,7 +451,7 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
       break;
     }
     const Gate gt = gate_terms(o.gate_lp_terms != 0, nw, ny);
-    if ((rc = apply_update(cur, other, n, gt, w, st, &nprod, tm)) != SR_OK) return rc;
+    if ((rc = apply_update(cur, other, w.QH, n, gt, w, st, &nprod, tm)) != SR_OK) return rc;
     zc* t = cur;
     cur = other;
     other = t;
@@ -525,7 +533,7 @@ int sr_residual(const void* A, const void* Q, int n, void* T, void* T_lp, void* 
   Work w = carve(ws, n);
   w.Tlp = (cc*)T_lp;
   w.Elp = (cc*)E_lp;
-  int rc = residual((const zc*)A, (const zc*)Q, (zc*)T, n, compensated ? 1 : 0, w, st);
+  int rc = residual((const zc*)A, (const zc*)Q, nullptr, (zc*)T, n, compensated ? 1 : 0, w, st);
   if (rc != SR_OK) return rc;
   if (eps) {
     CK(fro2_partials((const zc*)A, (long)n * n, w.partials, 1024, st));
@@ -558,7 +566,7 @@ int sr_update(const void* Q, const void* L_lp, void* Q_out, int n, int gate, int
   hipStream_t st = (hipStream_t)stream;
   Work w = carve(ws, n);
   CK(hipMemcpyAsync(w.Llp, L_lp, (size_t)n * n * sizeof(cc), hipMemcpyDeviceToDevice, st));
-  int rc = defects((const zc*)Q, n, compensated ? 1 : 0, w, st);
+  int rc = defects((const zc*)Q, nullptr, n, compensated ? 1 : 0, w, st);
   if (rc != SR_OK) return rc;
   double nrm[4] = {0, 0, 0, 0};
   Gate gt = gate_terms(false, 0, 0);
@@ -571,13 +579,13 @@ int sr_update(const void* Q, const void* L_lp, void* Q_out, int n, int gate, int
       norms[1] = sqrt(nrm[2]);
     }
   }
-  return apply_update((const zc*)Q, (zc*)Q_out, n, gt, w, st, nullptr);
+  return apply_update((const zc*)Q, (zc*)Q_out, nullptr, n, gt, w, st, nullptr);
 }
 
 int sr_ns_init(const void* Qh, void* Q, int n, int compensated, void* ws, void* stream) {
   if (!Qh || !Q || !ws || n < 1 || Qh == Q) return SR_EINVAL;
   Work w = carve(ws, n);
-  return ns_init((const zc*)Qh, (zc*)Q, n, compensated ? 1 : 0, w, (hipStream_t)stream);
+  return ns_init((const zc*)Qh, (zc*)Q, nullptr, n, compensated ? 1 : 0, w, (hipStream_t)stream);
 }
 
 }  // extern "C"
