@@ -177,6 +177,18 @@ int sr_update(const void* Q, const void* L_lp, void* Q_out, int n, int gate,
  * (Algorithm 4, before the loop). Qh, Q complex128, must not overlap. */
 int sr_ns_init(const void* Qh, void* Q, int n, int compensated, void* ws, void* stream);
 
+/* Ozaki split product (the hp products of Section 4 built from an Ozaki-scheme
+ * splitting) on INT8 MFMA: C = op(A) B (+ Cin), complex128, arguments as sr_zgemm.
+ * op(A) is split into slices_a 7-bit slices per row, B into slices_b per column
+ * (each with a power-of-two scale per row / column); slice pairs (s, t) with
+ * s + t <= dmax are multiplied exactly in int32 and combined in FP64. dmax =
+ * slices_a + slices_b keeps every pair. Requires pairs-per-diagonal * k * 127^2 <
+ * 2^31 (SR_EINVAL otherwise). ws: device workspace of >= sr_ozaki_ws_bytes(...). */
+size_t sr_ozaki_ws_bytes(int m, int n, int k, int slices_a, int slices_b);
+int sr_ozaki_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+                   const void* Cin, int ldcin, void* C, int ldc, int slices_a, int slices_b,
+                   int dmax, void* ws, size_t ws_bytes, void* stream);
+
 /* Diagnostic: one matrix-core instruction (kind 0: v_mfma_f64_16x16x4f64, kind 1:
  * v_mfma_f32_16x16x4f32) on a 16x4 A and a 4x16 B (row-major, host), fed and read
  * back with the lane layout the GEMM kernels assume; D (16x16 row-major, host)

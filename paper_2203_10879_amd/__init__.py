@@ -71,6 +71,8 @@ _SIGS = {
     "sr_trisolve": (_i, [_vp, _vp, _vp, _i, _f, _vp, _vp]),
     "sr_update": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.POINTER(_d), _vp, _vp]),
     "sr_ns_init": (_i, [_vp, _vp, _i, _i, _vp, _vp]),
+    "sr_ozaki_ws_bytes": (_sz, [_i, _i, _i, _i, _i]),
+    "sr_ozaki_zgemm": (_i, [_i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _i, _i, _vp, _sz, _vp]),
     "sr_diag_mfma": (_i, [_i, _vp, _vp, _vp]),
 }
 EXPORTS = tuple(_SIGS)
@@ -221,6 +223,24 @@ def sr_zgemm(A, B, C, opa: int = 0, Cin=None, compensated: bool = False, stream=
                           B.stride(1), _mat(Cin, "c128") if Cin is not None else None,
                           Cin.stride(1) if Cin is not None else 0, _mat(C, "c128"), C.stride(1),
                           int(bool(compensated)), _stream(stream))
+
+
+def sr_ozaki_zgemm(A, B, C, opa: int = 0, slices_a: int = 8, slices_b: int = 8, dmax=None, Cin=None,
+                   ws=None, stream=None) -> int:
+    """Ozaki split product on INT8 MFMA (see include/schur_refine.h)."""
+    import torch
+
+    m, n = C.shape
+    k = B.shape[0]
+    need = int(lib().sr_ozaki_ws_bytes(m, n, k, int(slices_a), int(slices_b)))
+    if ws is None:
+        ws = torch.empty(max(1, need), dtype=torch.uint8, device=C.device)
+    d = int(dmax) if dmax is not None else int(slices_a) + int(slices_b)
+    return lib().sr_ozaki_zgemm(int(opa), m, n, k, _mat(A, "c128"), A.stride(1), _mat(B, "c128"),
+                                B.stride(1), _mat(Cin, "c128") if Cin is not None else None,
+                                Cin.stride(1) if Cin is not None else 0, _mat(C, "c128"), C.stride(1),
+                                int(slices_a), int(slices_b), d, ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel() * ws.element_size(), _stream(stream))
 
 
 def sr_cgemm(A, B, C, stream=None) -> int:

@@ -1,0 +1,62 @@
+// Per-element epilogues shared by the complex GEMM kernels (FP64 MFMA and the
+// Ozaki INT8 split product): they fuse the elementwise steps of a refinement
+// pass into the store of a product.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace sr {
+
+// Store one element (i, j) of a product; `part` accumulates the squared norm the
+// SPLIT and YDEF epilogues report.
+template <int EPI, typename R>
+__device__ inline void epi_element(const GemmArgs& g, int i, int j, cplx<R> val, double& part) {
+  using C = cplx<R>;
+  C* __restrict__ Cp = (C*)g.C;
+  const long o = i + (long)j * g.ldc;
+  if constexpr (EPI == EPI_STORE) {
+    Cp[o] = val;
+  } else if constexpr (EPI == EPI_ADD) {
+    const C c0 = ((const C*)g.Cin)[i + (long)j * g.ldcin];
+    const C r = mk<R>(c0.re + val.re, c0.im + val.im);
+    Cp[o] = r;
+    // optional conjugate transpose of the result; in the MFMA accumulator layouts
+    // lanes 16 apart hold consecutive columns j, so the transposed store still
+    // writes runs of 16 consecutive elements
+    if (g.CH) ((C*)g.CH)[j + (long)i * g.ldch] = mk<R>(r.re, -r.im);
+  } else if constexpr (EPI == EPI_SPLIT) {
+    const long ol = i + (long)j * g.ldlp;
+    if (i <= j) {
+      Cp[o] = val;
+      g.Tlp[ol] = mk<float>((float)val.re, (float)val.im);
+      g.Elp[ol] = mk<float>(0.f, 0.f);
+    } else {
+      Cp[o] = mk<R>(0, 0);
+      g.Tlp[ol] = mk<float>(0.f, 0.f);
+      g.Elp[ol] = mk<float>((float)val.re, (float)val.im);
+      part += (double)val.re * val.re + (double)val.im * val.im;
+    }
+  } else {  // EPI_YDEF
+    if (i == j) val.re -= 1;
+    Cp[o] = val;
+    part += (double)val.re * val.re + (double)val.im * val.im;
+  }
+}
+
+// Block reduction of `part` into g.partials[slot] (fixed order).
+template <int NT>
+__device__ inline void epi_reduce(const GemmArgs& g, double part, double* red, int slot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+  if (lane == 0) red[wave] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; w++) t += red[w];
+    g.partials[slot] = t;
+  }
+}
+
+}  // namespace sr

@@ -17,7 +17,7 @@
 // drops from about u K / sqrt(2) to about u (K / sqrt(2 c) + sqrt(K c / 2)) with
 // c = 16 kChunk terms per chunk: 4-6x smaller for K = 1024..4096, which brings the
 // FP64 floor of ||stril(Q^H A Q)|| / ||A|| below 1e-15.
-#include "kernels.hpp"
+#include "epilogue.hpp"
 
 namespace sr {
 
@@ -212,8 +212,6 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
   }
 
   // Epilogue.
-  C* __restrict__ Cp = (C*)g.C;
-  const C* __restrict__ Cin = (const C*)g.Cin;
   double part = 0;
 #pragma unroll
   for (int mi = 0; mi < WM; mi++)
@@ -231,49 +229,9 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
           val.re = acc_re[mi][ni][v];
           val.im = acc_im[mi][ni][v];
         }
-        if (i < g.m && j < g.n) {
-          const long o = i + (long)j * g.ldc;
-          if constexpr (EPI == EPI_STORE) {
-            Cp[o] = val;
-          } else if constexpr (EPI == EPI_ADD) {
-            const C c0 = Cin[i + (long)j * g.ldcin];
-            const C r = mk<R>(c0.re + val.re, c0.im + val.im);
-            Cp[o] = r;
-            // optional conjugate transpose of the result; in this accumulator
-            // layout lanes 16 apart hold consecutive columns j, so the transposed
-            // store still writes runs of 16 consecutive elements
-            if (g.CH) ((C*)g.CH)[j + (long)i * g.ldch] = mk<R>(r.re, -r.im);
-          } else if constexpr (EPI == EPI_SPLIT) {
-            const long ol = i + (long)j * g.ldlp;
-            if (i <= j) {
-              Cp[o] = val;
-              g.Tlp[ol] = mk<float>((float)val.re, (float)val.im);
-              g.Elp[ol] = mk<float>(0.f, 0.f);
-            } else {
-              Cp[o] = mk<R>(0, 0);
-              g.Tlp[ol] = mk<float>(0.f, 0.f);
-              g.Elp[ol] = mk<float>((float)val.re, (float)val.im);
-              part += (double)val.re * val.re + (double)val.im * val.im;
-            }
-          } else {  // EPI_YDEF
-            if (i == j) val.re -= 1;
-            Cp[o] = val;
-            part += (double)val.re * val.re + (double)val.im * val.im;
-          }
-        }
+        if (i < g.m && j < g.n) epi_element<EPI, R>(g, i, j, val, part);
       }
-  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-    if (lane == 0) red[wave] = part;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0;
-#pragma unroll
-      for (int w = 0; w < GNT / 64; w++) t += red[w];
-      g.partials[bid] = t;
-    }
-  }
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<GNT>(g, part, red, bid);
 }
 
 int gemm_tiles(int m, int n) { return ceil_div(m, GBM) * ceil_div(n, GBN); }

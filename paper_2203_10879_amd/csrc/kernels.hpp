@@ -55,6 +55,16 @@ hipError_t form_delta(const cc* L, const zc* Y, const cc* W2, const cc* W3, cons
 hipError_t to_c64(const zc* x, cc* y, long count, hipStream_t st);
 hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
 
+// Ozaki split products on INT8 MFMA (complex128 operands, FP64 output).
+size_t oz_slice_bytes(int rows, int K, int S);
+hipError_t oz_split_cols(const zc* X, const zc* Xlo, long ld, int K, int ncols, int S, int8_t* out,
+                         int* exps, hipStream_t st);
+hipError_t oz_split_rows(const zc* X, const zc* Xlo, long ld, int M, int K, int S, int8_t* out,
+                         int* exps, hipStream_t st);
+int oz_gemm_tiles(int m, int n);
+hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t* B, const int* eb,
+                   int SB, int conjA, int dmax, GemmArgs g, hipStream_t st);
+
 // Triangular matrix equation in FP32 (complex64).
 size_t trisolve_ws_bytes(int n);
 hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* ws,

@@ -1,0 +1,416 @@
+// Ozaki-style split product on CDNA4 INT8 matrix cores: the high-precision
+// products of the refinement (the paper's Section 4 obtains them from an
+// Ozaki-scheme toolbox) computed from 8-bit slices with exact 32-bit integer
+// accumulation.
+//
+// Splitting. For an operand role, every row of op(A) (every column of B) gets a
+// power-of-two scale 2^e with max |re|, |im| < 2^e over the row (column). A value
+// x is written as 2^e sum_{s=1..S} d_s 2^{-7 s} with integer digits
+// d_s in [-127, 127], taken by truncation toward zero: r = x 2^-e; d = trunc(128 r);
+// r = 128 r - d. Each step is exact in FP64 (double-double inputs are split the
+// same way with an exact double-double remainder), so the retained digits
+// reproduce x up to 2^(e - 7 S).
+//
+// Product. C_ij = 2^(e_i + f_j) sum_{s,t} 2^{-7(s+t)} (A_s B_t)_ij. The slice
+// pairs are grouped by d = s + t; within one d every pair has the same scale, so
+// their products are summed exactly in int32 (|sum| <= pairs * 2 K * 127^2 <
+// 2^31 for the sizes the host admits) with v_mfma_i32_16x16x64_i8, and the int32
+// sums are folded into FP64 accumulators with scale 2^{-7 d} once d is done.
+// Pairs with s + t > dmax are dropped (their weight is below 2^{-7 dmax}). A
+// complex product keeps four real accumulators (re*re, im*im, re*im, im*re) so
+// that op(A) = conj(A slices) only changes signs at the fold.
+//
+// Tiling: a 512-thread block computes a 128 x 64 complex tile; its eight waves
+// (4 along M x 2 along N) each own 2 x 2 blocks of 16 x 16. Per step the block
+// stages one K-tile (64) of one slice of op(A) (both parts) and one slice of B in
+// LDS, double-buffered; LDS rows are padded to 80 bytes, which makes the 16-byte
+// fragment reads of 16 consecutive rows conflict-free.
+#include "epilogue.hpp"
+
+namespace sr {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int OBM = 128, OBN = 64, OBK = 64, ONT = 512, OLD = 80;
+constexpr int kSplitNT = 256;
+
+__host__ __device__ inline int oz_kp(int K) { return (K + OBK - 1) / OBK * OBK; }
+
+size_t oz_slice_bytes(int rows, int K, int S) { return (size_t)S * 2 * rows * oz_kp(K); }
+
+// ------------------------------------------------------------------- splitting
+
+__device__ inline int scale_exponent(double m) {
+  if (!(m > 0)) return 0;
+  int e;
+  frexp(m, &e);  // m = f 2^e, f in [0.5, 1): m < 2^e
+  return e;
+}
+
+// One digit of x in (-128, 128) given as a double-double (yh, yl): truncation
+// toward zero of the exact value, and the exact remainder.
+__device__ inline int dd_digit(double& rh, double& rl) {
+  const double yh = rh * 128.0, yl = rl * 128.0;
+  double d = trunc(yh);
+  if (d == yh && yl != 0.0 && ((yl < 0.0) != (yh < 0.0)) && yh != 0.0) d -= (yh > 0.0 ? 1.0 : -1.0);
+  const double t = yh - d;  // exact: |yh - d| <= 1
+  two_sum(t, yl, rh, rl);
+  return (int)d;
+}
+
+__device__ inline int fp_digit(double& r) {
+  const double y = r * 128.0;
+  const double d = trunc(y);
+  r = y - d;  // exact fractional part
+  return (int)d;
+}
+
+// Slices of the columns of X (K x ncols, leading dim ld): out[(s*2+part)*ncols + c][k].
+// These serve as B, and as op(A) = X^H when the product applies the conjugation.
+__global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __restrict__ X,
+                                                                 const zc* __restrict__ Xlo, long ld,
+                                                                 int K, int ncols, int S, int Kp,
+                                                                 int8_t* __restrict__ out,
+                                                                 int* __restrict__ exps) {
+  __shared__ double red[kSplitNT / 64];
+  __shared__ int e_sh;
+  const int col = blockIdx.x;
+  const zc* x = X + (long)col * ld;
+  const zc* xl = Xlo ? Xlo + (long)col * ld : nullptr;
+  double m = 0;
+  for (int k = threadIdx.x; k < K; k += kSplitNT) m = fmax(m, fmax(fabs(x[k].re), fabs(x[k].im)));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < kSplitNT / 64; w++) t = fmax(t, red[w]);
+    e_sh = scale_exponent(t);
+    exps[col] = e_sh;
+  }
+  __syncthreads();
+  const int e = e_sh;
+  const long stride = 2L * ncols * Kp;  // slice s -> s+1
+  int8_t* o_re = out + (long)col * Kp;
+  int8_t* o_im = out + ((long)ncols + col) * Kp;
+  for (int k = threadIdx.x; k < Kp; k += kSplitNT) {
+    if (k < K) {
+      const zc v = x[k];
+      if (xl) {
+        const zc w = xl[k];
+        double rh = ldexp(v.re, -e), rl = ldexp(w.re, -e);
+        double ih = ldexp(v.im, -e), il = ldexp(w.im, -e);
+        for (int s = 0; s < S; s++) {
+          o_re[s * stride + k] = (int8_t)dd_digit(rh, rl);
+          o_im[s * stride + k] = (int8_t)dd_digit(ih, il);
+        }
+      } else {
+        double r = ldexp(v.re, -e), i = ldexp(v.im, -e);
+        for (int s = 0; s < S; s++) {
+          o_re[s * stride + k] = (int8_t)fp_digit(r);
+          o_im[s * stride + k] = (int8_t)fp_digit(i);
+        }
+      }
+    } else {
+      for (int s = 0; s < S; s++) {
+        o_re[s * stride + k] = 0;
+        o_im[s * stride + k] = 0;
+      }
+    }
+  }
+}
+
+// Scale exponents of the rows of X (M x K, leading dim ld), computed over K-chunks
+// of 256 in parallel and combined with an integer atomic max on the exponent
+// (which is monotone in the maximum; an all-zero chunk contributes INT_MIN).
+constexpr int kNoExp = -2147483647 - 1;
+
+__global__ void oz_exp_init_kernel(int* __restrict__ exps, int M) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < M) exps[r] = kNoExp;
+}
+
+__global__ __launch_bounds__(kSplitNT) void oz_rowmax_kernel(const zc* __restrict__ X, long ld, int M,
+                                                             int K, int* __restrict__ exps) {
+  __shared__ double red[4][64];
+  const int r = blockIdx.x * 64 + (threadIdx.x & 63), c = threadIdx.x >> 6;
+  const int k0 = blockIdx.y * 256, k1 = min(K, k0 + 256);
+  double m = 0;
+  if (r < M)
+    for (int k = k0 + c; k < k1; k += 4) {
+      const zc v = X[r + (long)k * ld];
+      m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
+    }
+  red[c][threadIdx.x & 63] = m;
+  __syncthreads();
+  if (c == 0 && r < M) {
+    const double t = fmax(fmax(red[0][threadIdx.x], red[1][threadIdx.x]), fmax(red[2][threadIdx.x], red[3][threadIdx.x]));
+    if (t > 0) atomicMax(&exps[r], scale_exponent(t));
+  }
+}
+
+__global__ void oz_exp_fix_kernel(int* __restrict__ exps, int M) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < M && exps[r] == kNoExp) exps[r] = 0;
+}
+
+// Slices of the rows of X: out[(s*2+part)*M + i][k]; one block per 32 x 32 tile,
+// staged through LDS so that reads follow the columns and writes the rows.
+__global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __restrict__ X,
+                                                                 const zc* __restrict__ Xlo, long ld,
+                                                                 int M, int K, int S, int Kp,
+                                                                 const int* __restrict__ exps,
+                                                                 int8_t* __restrict__ out) {
+  __shared__ zc t[32][33];
+  __shared__ zc tl[32][33];
+  const int i0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    const int idx = r * kSplitNT + threadIdx.x;
+    const int row = idx & 31, kk = idx >> 5;
+    const int gi = i0 + row, gk = k0 + kk;
+    const bool ok = gi < M && gk < K;
+    const long o = ok ? gi + (long)gk * ld : 0;
+    const zc v = X[o];
+    t[kk][row] = mk<double>(ok ? v.re : 0.0, ok ? v.im : 0.0);
+    if (Xlo) {
+      const zc w = Xlo[o];
+      tl[kk][row] = mk<double>(ok ? w.re : 0.0, ok ? w.im : 0.0);
+    }
+  }
+  __syncthreads();
+  const int row = threadIdx.x >> 3, kg = (threadIdx.x & 7) * 4;
+  const int gi = i0 + row;
+  if (gi >= M) return;
+  const int e = exps[gi];
+  double rh[4], rl[4], ih[4], il[4];
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    const zc v = t[kg + c][row];
+    rh[c] = ldexp(v.re, -e);
+    ih[c] = ldexp(v.im, -e);
+    if (Xlo) {
+      const zc w = tl[kg + c][row];
+      rl[c] = ldexp(w.re, -e);
+      il[c] = ldexp(w.im, -e);
+    } else {
+      rl[c] = il[c] = 0;
+    }
+  }
+  const long stride = 2L * M * Kp;
+  int* o_re = (int*)(out + (long)gi * Kp + k0 + kg);
+  int* o_im = (int*)(out + ((long)M + gi) * Kp + k0 + kg);
+  for (int s = 0; s < S; s++) {
+    unsigned pr = 0, pi = 0;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const int dr = Xlo ? dd_digit(rh[c], rl[c]) : fp_digit(rh[c]);
+      const int di = Xlo ? dd_digit(ih[c], il[c]) : fp_digit(ih[c]);
+      pr |= (unsigned)(dr & 0xff) << (8 * c);
+      pi |= (unsigned)(di & 0xff) << (8 * c);
+    }
+    o_re[s * stride / 4] = (int)pr;
+    o_im[s * stride / 4] = (int)pi;
+  }
+}
+
+hipError_t oz_split_cols(const zc* X, const zc* Xlo, long ld, int K, int ncols, int S, int8_t* out,
+                         int* exps, hipStream_t st) {
+  if (ncols == 0) return hipSuccess;
+  hipLaunchKernelGGL(oz_split_cols_kernel, dim3(ncols), dim3(kSplitNT), 0, st, X, Xlo, ld, K, ncols, S,
+                     oz_kp(K), out, exps);
+  return hipGetLastError();
+}
+
+hipError_t oz_split_rows(const zc* X, const zc* Xlo, long ld, int M, int K, int S, int8_t* out,
+                         int* exps, hipStream_t st) {
+  if (M == 0) return hipSuccess;
+  hipLaunchKernelGGL(oz_exp_init_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, st, exps, M);
+  hipLaunchKernelGGL(oz_rowmax_kernel, dim3(ceil_div(M, 64), max(1, ceil_div(K, 256))), dim3(kSplitNT), 0,
+                     st, X, ld, M, K, exps);
+  hipLaunchKernelGGL(oz_exp_fix_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, st, exps, M);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int Kp = oz_kp(K);
+  hipLaunchKernelGGL(oz_split_rows_kernel, dim3(ceil_div(M, 32), Kp / 32), dim3(kSplitNT), 0, st, X, Xlo,
+                     ld, M, K, S, Kp, exps, out);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------------- product
+
+struct OzArgs {
+  const int8_t* A;  // op(A) slices: [SA][2][m][Kp]
+  const int* ea;
+  const int8_t* B;  // B slices: [SB][2][n][Kp]
+  const int* eb;
+  int SA, SB, dmax, conjA, Kp;
+  GemmArgs g;  // sizes, output and epilogue
+};
+
+template <int EPI>
+__global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
+  __shared__ __align__(16) int8_t As[2][2][OBM][OLD];
+  __shared__ __align__(16) int8_t Bs[2][2][OBN][OLD];
+  __shared__ double red[ONT / 64];
+  const GemmArgs& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 3) * 32, wn = (wave >> 2) * 32;
+
+  // XCD-aware grouped tile order (as in the FP64 kernel).
+  const int ntiles = g.tiles_m * g.tiles_n;
+  const int bid = blockIdx.x;
+  int logical = bid;
+  {
+    const int per = ntiles / kXCDs;
+    if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
+  }
+  constexpr int kGroup = 4;
+  const int group = logical / (kGroup * g.tiles_n);
+  const int first_m = group * kGroup;
+  const int gsize = min(g.tiles_m - first_m, kGroup);
+  const int within = logical - group * kGroup * g.tiles_n;
+  const int m0 = (first_m + within % gsize) * OBM, n0 = (within / gsize) * OBN;
+
+  const int KT = a.Kp / OBK;
+  const long sA = 2L * g.m * a.Kp, sB = 2L * g.n * a.Kp;  // bytes per slice
+
+  double out_re[2][2][4], out_im[2][2][4];
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) out_re[x][y][v] = out_im[x][y][v] = 0;
+
+  // staging: 2 chunks of A (16 B) and 1 of B per thread and step
+  v4i ra[2], rb;
+  auto gload = [&](int s, int t, int kt) {
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int idx = r * ONT + tid;  // 0..1023: part(1) row(128) chunk(4)
+      const int part = idx >> 9, row = (idx >> 2) & 127, ch = idx & 3;
+      const int gi = m0 + row;
+      v4i v = {0, 0, 0, 0};
+      if (gi < g.m)
+        v = *(const v4i*)(a.A + (long)(s - 1) * sA + ((long)part * g.m + gi) * a.Kp + kt * OBK + ch * 16);
+      ra[r] = v;
+    }
+    {
+      const int part = tid >> 8, col = (tid >> 2) & 63, ch = tid & 3;
+      const int gj = n0 + col;
+      v4i v = {0, 0, 0, 0};
+      if (gj < g.n)
+        v = *(const v4i*)(a.B + (long)(t - 1) * sB + ((long)part * g.n + gj) * a.Kp + kt * OBK + ch * 16);
+      rb = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int idx = r * ONT + tid;
+      const int part = idx >> 9, row = (idx >> 2) & 127, ch = idx & 3;
+      *(v4i*)&As[buf][part][row][ch * 16] = ra[r];
+    }
+    const int part = tid >> 8, col = (tid >> 2) & 63, ch = tid & 3;
+    *(v4i*)&Bs[buf][part][col][ch * 16] = rb;
+  };
+
+  for (int d = 2; d <= a.dmax; d++) {
+    const int s_lo = max(1, d - a.SB), s_hi = min(a.SA, d - 1);
+    if (s_lo > s_hi) continue;
+    const int steps = (s_hi - s_lo + 1) * KT;
+    v4i rr[2][2], ii[2][2], ri[2][2], ir[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; x++)
+#pragma unroll
+      for (int y = 0; y < 2; y++) rr[x][y] = ii[x][y] = ri[x][y] = ir[x][y] = v4i{0, 0, 0, 0};
+    __syncthreads();  // LDS of the previous diagonal no longer read
+    gload(s_lo, d - s_lo, 0);
+    sstore(0);
+    __syncthreads();
+    for (int st = 0; st < steps; st++) {
+      const int cur = st & 1;
+      if (st + 1 < steps) {
+        const int s = s_lo + (st + 1) / KT, kt = (st + 1) % KT;
+        gload(s, d - s, kt);
+      }
+      const int kq = 16 * (lane >> 4);
+      v4i far[2], fai[2], fbr[2], fbi[2];
+#pragma unroll
+      for (int x = 0; x < 2; x++) {
+        const int row = wm + x * 16 + (lane & 15);
+        far[x] = *(const v4i*)&As[cur][0][row][kq];
+        fai[x] = *(const v4i*)&As[cur][1][row][kq];
+      }
+#pragma unroll
+      for (int y = 0; y < 2; y++) {
+        const int col = wn + y * 16 + (lane & 15);
+        fbr[y] = *(const v4i*)&Bs[cur][0][col][kq];
+        fbi[y] = *(const v4i*)&Bs[cur][1][col][kq];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; x++)
+#pragma unroll
+        for (int y = 0; y < 2; y++) {
+          rr[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(far[x], fbr[y], rr[x][y], 0, 0, 0);
+          ii[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fai[x], fbi[y], ii[x][y], 0, 0, 0);
+          ri[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(far[x], fbi[y], ri[x][y], 0, 0, 0);
+          ir[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fai[x], fbr[y], ir[x][y], 0, 0, 0);
+        }
+      if (st + 1 < steps) sstore(cur ^ 1);
+      __syncthreads();
+    }
+    // fold diagonal d: scale 2^{-7 d}
+    const double sc = ldexp(1.0, -7 * d);
+    const double sg = a.conjA ? 1.0 : -1.0;  // re = rr + sg ii, im = ri - sg ir
+#pragma unroll
+    for (int x = 0; x < 2; x++)
+#pragma unroll
+      for (int y = 0; y < 2; y++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          out_re[x][y][v] += ((double)rr[x][y][v] + sg * (double)ii[x][y][v]) * sc;
+          out_im[x][y][v] += ((double)ri[x][y][v] - sg * (double)ir[x][y][v]) * sc;
+        }
+  }
+
+  double part = 0;
+#pragma unroll
+  for (int x = 0; x < 2; x++)
+#pragma unroll
+    for (int y = 0; y < 2; y++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int i = m0 + wm + x * 16 + 4 * (lane >> 4) + v;  // i32 accumulator rows
+        const int j = n0 + wn + y * 16 + (lane & 15);
+        if (i < g.m && j < g.n) {
+          const int e = a.ea[i] + a.eb[j];
+          zc val = mk<double>(ldexp(out_re[x][y][v], e), ldexp(out_im[x][y][v], e));
+          epi_element<EPI, double>(g, i, j, val, part);
+        }
+      }
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<ONT>(g, part, red, bid);
+}
+
+int oz_gemm_tiles(int m, int n) { return ceil_div(m, OBM) * ceil_div(n, OBN); }
+
+hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t* B, const int* eb,
+                   int SB, int conjA, int dmax, GemmArgs g, hipStream_t st) {
+  g.tiles_m = ceil_div(g.m, OBM);
+  g.tiles_n = ceil_div(g.n, OBN);
+  const int nt = g.tiles_m * g.tiles_n;
+  if (nt == 0) return hipSuccess;
+  OzArgs a{A, ea, B, eb, SA, SB, dmax, conjA, oz_kp(g.k), g};
+  switch (epi) {
+    case EPI_STORE: hipLaunchKernelGGL(oz_gemm_kernel<EPI_STORE>, dim3(nt), dim3(ONT), 0, st, a); break;
+    case EPI_ADD: hipLaunchKernelGGL(oz_gemm_kernel<EPI_ADD>, dim3(nt), dim3(ONT), 0, st, a); break;
+    case EPI_SPLIT: hipLaunchKernelGGL(oz_gemm_kernel<EPI_SPLIT>, dim3(nt), dim3(ONT), 0, st, a); break;
+    case EPI_YDEF: hipLaunchKernelGGL(oz_gemm_kernel<EPI_YDEF>, dim3(nt), dim3(ONT), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sr

@@ -516,6 +516,45 @@ int sr_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B
   return SR_OK;
 }
 
+size_t sr_ozaki_ws_bytes(int m, int n, int k, int slices_a, int slices_b) {
+  if (m < 0 || n < 0 || k < 0 || slices_a < 1 || slices_b < 1) return 0;
+  return align256(oz_slice_bytes(m, k, slices_a)) + align256(oz_slice_bytes(n, k, slices_b)) +
+         align256((size_t)(m + n) * sizeof(int));
+}
+
+// Largest slice-pair count on one diagonal times k must keep int32 sums exact.
+static bool oz_exact_ok(int k, int sa, int sb) {
+  const long pairs = sa < sb ? sa : sb;
+  const long kp = (k + 63) / 64 * 64;
+  return pairs * kp * 127L * 127L < 2147483647L;
+}
+
+int sr_ozaki_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+                   const void* Cin, int ldcin, void* C, int ldc, int slices_a, int slices_b, int dmax,
+                   void* ws, size_t ws_bytes, void* stream) {
+  if (m < 0 || n < 0 || k < 0 || (opa != 0 && opa != 1) || !C) return SR_EINVAL;
+  if (slices_a < 1 || slices_b < 1 || slices_a > 32 || slices_b > 32 || dmax < 2) return SR_EINVAL;
+  if (m == 0 || n == 0) return SR_OK;
+  if (k > 0 && (!A || !B)) return SR_EINVAL;
+  if (lda < (opa ? (k > 1 ? k : 1) : (m > 1 ? m : 1)) || ldb < (k > 1 ? k : 1) || ldc < m) return SR_EINVAL;
+  if (Cin && ldcin < m) return SR_EINVAL;
+  if (!oz_exact_ok(k, slices_a, slices_b)) return SR_EINVAL;
+  if (!ws || ws_bytes < sr_ozaki_ws_bytes(m, n, k, slices_a, slices_b)) return SR_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int8_t* qa = (int8_t*)ws;
+  int8_t* qb = qa + align256(oz_slice_bytes(m, k, slices_a));
+  int* ea = (int*)(qb + align256(oz_slice_bytes(n, k, slices_b)));
+  int* eb = ea + m;
+  if (opa == 0) CK(oz_split_rows((const zc*)A, nullptr, lda, m, k, slices_a, qa, ea, st));
+  else CK(oz_split_cols((const zc*)A, nullptr, lda, k, m, slices_a, qa, ea, st));
+  CK(oz_split_cols((const zc*)B, nullptr, ldb, k, n, slices_b, qb, eb, st));
+  GemmArgs g = gargs(m, n, k, nullptr, 0, nullptr, 0, C, ldc);
+  g.Cin = Cin;
+  g.ldcin = ldcin;
+  CK(oz_gemm(Cin ? EPI_ADD : EPI_STORE, qa, ea, slices_a, qb, eb, slices_b, opa, dmax, g, st));
+  return SR_OK;
+}
+
 int sr_cgemm(int m, int n, int k, const void* A, int lda, const void* B, int ldb, void* C, int ldc,
              void* stream) {
   if (m < 0 || n < 0 || k < 0 || !C) return SR_EINVAL;

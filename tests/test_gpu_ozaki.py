@@ -1,0 +1,79 @@
+"""GPU parity of the Ozaki split product (INT8 MFMA) against exact arithmetic and
+the binary128 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import U64, dev, empty, gemm_bound, host, rand_c
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sr():
+    import torch
+
+    import paper_2203_10879_amd as m
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.lib()
+    return m
+
+
+def _gauss_int(rng, shape, lim=256):
+    return np.asfortranarray(rng.integers(-lim, lim + 1, shape) + 1j * rng.integers(-lim, lim + 1, shape))
+
+
+@pytest.mark.parametrize("opa", [0, 1])
+@pytest.mark.parametrize("shape", [(130, 97, 75), (64, 64, 64), (1, 1, 1), (200, 33, 129)])
+def test_ozaki_exact_on_integers(sr, opa, shape):
+    # 9-bit integers fit in two 7-bit digits; with every slice pair kept the
+    # product is exact and so is its FP64 combination
+    m, n, k = shape
+    rng = np.random.default_rng(m + 7 * n + 13 * k)
+    a = _gauss_int(rng, (k, m) if opa else (m, k))
+    b = _gauss_int(rng, (k, n))
+    c = empty(m, n)
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=2, slices_b=2, dmax=4) == 0
+    ref = (a.conj().T if opa else a) @ b
+    assert np.array_equal(host(c), ref)
+
+
+@pytest.mark.parametrize("opa", [0, 1])
+def test_ozaki_fp64_faithful_with_8_slices(sr, opa):
+    rng = np.random.default_rng(21 + opa)
+    m, n, k = 150, 131, 260
+    a = rand_c(rng, (k, m) if opa else (m, k))
+    b = rand_c(rng, (k, n))
+    c = empty(m, n)
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=8, slices_b=8, dmax=9) == 0
+    chi, clo = oracle.gemm(a, b, opa=opa).to_dd()
+    err = np.abs((host(c) - chi) - clo)
+    aa = np.abs(a.conj().T if opa else a)
+    assert np.all(err <= gemm_bound(aa, np.abs(b), k, U64))
+
+
+def test_ozaki_error_decreases_with_slices(sr):
+    rng = np.random.default_rng(5)
+    n = 256
+    a, b = rand_c(rng, (n, n)), rand_c(rng, (n, n))
+    chi, clo = oracle.gemm(a, b).to_dd()
+    scale = np.linalg.norm(np.abs(a) @ np.abs(b))
+    errs = []
+    for s in (3, 4, 5, 6):
+        c = empty(n, n)
+        assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, slices_a=s, slices_b=s, dmax=s + 1) == 0
+        errs.append(np.linalg.norm((host(c) - chi) - clo) / scale)
+    for e_prev, e_next in zip(errs[:-1], errs[1:]):
+        assert e_next < e_prev / 30  # about 7 bits per slice
+    assert errs[0] < 2.0 ** -(7 * 3 - 6)
+
+
+def test_ozaki_add_epilogue_and_validation(sr):
+    rng = np.random.default_rng(3)
+    m, n, k = 70, 90, 40
+    a, b, c0 = _gauss_int(rng, (m, k)), _gauss_int(rng, (k, n)), _gauss_int(rng, (m, n))
+    c = empty(m, n)
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, slices_a=2, slices_b=2, dmax=4, Cin=dev(c0)) == 0
+    assert np.array_equal(host(c), c0 + a @ b)
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, slices_a=0, slices_b=2) == -1
