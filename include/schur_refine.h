@@ -54,14 +54,20 @@ typedef enum {
 
 typedef enum {
   SR_GEMM_FP64 = 0,       /* native FP64 MFMA                                         */
-  SR_GEMM_OZAKI_I8 = 1,   /* Ozaki split on INT8 MFMA, INT32 accumulation             */
-  SR_GEMM_OZAKI_BF16 = 2  /* Ozaki split on BF16 MFMA, FP32 accumulation              */
+  SR_GEMM_OZAKI_I8 = 1,   /* Ozaki split on INT8 MFMA, INT32 accumulation, for P = A Q,
+                             the start's Newton-Schulz products and Q * Delta; That and
+                             Y = Q^H Q - I stay native FP64 (their cancellation needs it) */
+  SR_GEMM_OZAKI_BF16 = 2  /* Ozaki split on BF16 MFMA: not built (SR_ENOSYS); INT8
+                             digits give the same exactness at twice the MFMA rate    */
 } sr_gemm_mode;
 
 typedef struct {
   int gemm;               /* sr_gemm_mode for the hp products                         */
-  int slices;             /* Ozaki slices for That and Y (0 = default)                */
-  int update_slices;      /* Ozaki slices for Q * Delta (0 = default)                 */
+  int slices;             /* SR_GEMM_OZAKI_I8: 7-bit digits per operand of P = A Q and
+                             of the start's Gram matrix, slice pairs up to s + t =
+                             slices + 1 (0 = default 8, at most 16)                   */
+  int update_slices;      /* SR_GEMM_OZAKI_I8: digits per operand of Q * Delta
+                             (0 = chosen per update from ||Delta||_F, 2..8)           */
   int compensated;        /* 1: chunked K accumulation with error-free (TwoSum)
                              combination in the FP64 products P, That and Y            */
   int gate_lp_terms;      /* 1: skip YW, W^2, W^3 whose Frobenius bound is below
@@ -91,6 +97,8 @@ typedef struct {
   float ms_hp_gemm;       /* with opts.timing: summed time of the hp product launches  */
   int hp_gemm_launches;   /* with opts.timing: number of hp product launches timed     */
   float ms_solve;         /* with opts.timing: summed time of the triangular solves    */
+  int update_slices_hist[16]; /* SR_GEMM_OZAKI_I8: digits used by the Newton-Schulz start
+                             (entry 0) and by updates 1..15                           */
 } sr_info;
 
 /* Default options: FP64 MFMA, compensated accumulation on, gating on, no trunc. */
@@ -120,11 +128,28 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
                          void* const* T, int iters, double tol, const sr_opts* opts,
                          sr_info* info);
 
-/* Double-double tier: A = A_hi + A_lo, Q = Q_hi + Q_lo, T = T_hi + T_lo (all device,
- * complex128 n x n). hp products are double-double, the solve runs in FP64. */
+/* Double-double tier (Section 4 refines to higher than working precision the same
+ * way): A = A_hi + A_lo, Q = Q_hi + Q_lo, T = T_hi + T_lo (all device, complex128
+ * n x n, each pair a double-double matrix). Every hp product (P = A Q, That, Y, the
+ * Newton-Schulz start and Q Delta) is an Ozaki split product of the double-double
+ * operands on INT8 MFMA with double-double accumulation; the solve and the lp
+ * products YW, W^2, W^3 run in FP64, gated against 0.1 * 2^-104.
+ *  opts->slices: digits per operand of the hp products (0 = 15, at most 32). The
+ *    digits of a row or column are relative to its largest entry, so a matrix
+ *    whose rows or columns span many orders of magnitude needs more digits to keep
+ *    its small entries to double-double accuracy (15 digits cover 105 bits);
+ *  opts->update_slices: digits of Q Delta: 0 = the same as opts->slices (the digits
+ *    of Q are relative to its row maxima, and the Schur vectors of a badly scaled
+ *    matrix have entries far below them); -1 = chosen from ||Delta|| (2..16, for
+ *    well-scaled matrices); otherwise the count given (at most 32);
+ *  opts->gemm and opts->compensated are ignored. The stagnation floor is
+ *  100 * 2^-104 * sqrt(n). Outputs and statuses as for schur_refine. */
 int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, void* T_hi,
                     void* T_lo, int n, int iters, double tol, const sr_opts* opts,
                     sr_info* info);
+
+/* Bytes of device workspace schur_refine_dd needs for size n under `opts`. */
+size_t sr_workspace_bytes_dd(int n, const sr_opts* opts);
 
 /* Static description of a status code. */
 const char* sr_status_string(int status);
@@ -165,6 +190,10 @@ int sr_residual(const void* A, const void* Q, int n, void* T, void* T_lp, void* 
 int sr_trisolve(const void* T_lp, const void* E_lp, void* L_lp, int n, float trunc,
                 void* ws, void* stream);
 
+/* The same equation in FP64 (the solve of the double-double tier): T, E, L are
+ * complex128 with the roles above; no truncation. Same outcomes. */
+int sr_trisolve64(const void* T, const void* E, void* L, int n, void* ws, void* stream);
+
 /* Merged Newton-Schulz update (Algorithm 4, the W, Y, Sigma and Q steps) given L:
  * W = L - L^H, Y = Q^H Q - I (hp), lp products (gated when gate != 0),
  * Delta = 1/2 Sigma - I = W - Y/2 + (-YW + W^2 + W^3)/2, Q_out = Q + Q Delta.
@@ -188,6 +217,18 @@ size_t sr_ozaki_ws_bytes(int m, int n, int k, int slices_a, int slices_b);
 int sr_ozaki_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
                    const void* Cin, int ldcin, void* C, int ldc, int slices_a, int slices_b,
                    int dmax, void* ws, size_t ws_bytes, void* stream);
+
+/* Double-double operands and result: C_hi + C_lo = op(A_hi + A_lo) (B_hi + B_lo)
+ * (+ Cin_hi + Cin_lo), each pair stored as two complex128 matrices with a shared
+ * leading dimension. The digits are taken from the exact double-double values, the
+ * pair sums are exact in int32 and are accumulated in double-double, so with 16
+ * digits per operand and dmax = 17 the result carries about 2^-105 relative to the
+ * row and column scales. A_lo, B_lo, Cin_lo may be NULL (zero). ws as above. */
+int sr_ozaki_zgemm_dd(int opa, int m, int n, int k, const void* A_hi, const void* A_lo, int lda,
+                      const void* B_hi, const void* B_lo, int ldb, const void* Cin_hi,
+                      const void* Cin_lo, int ldcin, void* C_hi, void* C_lo, int ldc,
+                      int slices_a, int slices_b, int dmax, void* ws, size_t ws_bytes,
+                      void* stream);
 
 /* Diagnostic: one matrix-core instruction (kind 0: v_mfma_f64_16x16x4f64, kind 1:
  * v_mfma_f32_16x16x4f32) on a 16x4 A and a 4x16 B (row-major, host), fed and read

@@ -41,7 +41,8 @@ class SrInfo(ctypes.Structure):
                 ("resid", ctypes.c_double), ("orth", ctypes.c_double),
                 ("resid_hist", ctypes.c_double * 16), ("norm_w_hist", ctypes.c_double * 16),
                 ("ms_total", ctypes.c_float), ("ms_hp_gemm", ctypes.c_float),
-                ("hp_gemm_launches", ctypes.c_int), ("ms_solve", ctypes.c_float)]
+                ("hp_gemm_launches", ctypes.c_int), ("ms_solve", ctypes.c_float),
+                ("update_slices_hist", ctypes.c_int * 16)]
 
     def as_dict(self) -> dict:
         k = min(self.iters, 16)
@@ -51,7 +52,8 @@ class SrInfo(ctypes.Structure):
                 "lp_products": self.lp_products, "resid": self.resid, "orth": self.orth,
                 "resid_hist": list(self.resid_hist[:k]), "norm_w_hist": list(self.norm_w_hist[:u]),
                 "ms_total": self.ms_total, "ms_hp_gemm": self.ms_hp_gemm,
-                "hp_gemm_launches": self.hp_gemm_launches, "ms_solve": self.ms_solve}
+                "hp_gemm_launches": self.hp_gemm_launches, "ms_solve": self.ms_solve,
+                "update_slices_hist": list(self.update_slices_hist[:min(u + 1, 16)])}
 
 
 # name -> (restype, argtypes); mirrors include/schur_refine.h
@@ -69,10 +71,14 @@ _SIGS = {
     "sr_cgemm": (_i, [_i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp]),
     "sr_residual": (_i, [_vp, _vp, _i, _vp, _vp, _vp, ctypes.POINTER(_d), _i, _vp, _vp]),
     "sr_trisolve": (_i, [_vp, _vp, _vp, _i, _f, _vp, _vp]),
+    "sr_trisolve64": (_i, [_vp, _vp, _vp, _i, _vp, _vp]),
     "sr_update": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.POINTER(_d), _vp, _vp]),
     "sr_ns_init": (_i, [_vp, _vp, _i, _i, _vp, _vp]),
     "sr_ozaki_ws_bytes": (_sz, [_i, _i, _i, _i, _i]),
     "sr_ozaki_zgemm": (_i, [_i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _i, _i, _vp, _sz, _vp]),
+    "sr_ozaki_zgemm_dd": (_i, [_i, _i, _i, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i,
+                               _i, _i, _i, _vp, _sz, _vp]),
+    "sr_workspace_bytes_dd": (_sz, [_i, ctypes.POINTER(SrOpts)]),
     "sr_diag_mfma": (_i, [_i, _vp, _vp, _vp]),
 }
 EXPORTS = tuple(_SIGS)
@@ -126,13 +132,21 @@ def _mat(t, dtype_name: str, rows: int | None = None, cols: int | None = None):
     want = {"c128": torch.complex128, "c64": torch.complex64}[dtype_name]
     if t.dtype != want:
         raise TypeError(f"expected {want}, got {t.dtype}")
-    if t.dim() != 2 or t.stride(0) != 1 or t.stride(1) < max(1, t.shape[0]):
+    if t.dim() != 2 or (t.shape[0] > 1 and t.stride(0) != 1) or (t.shape[1] > 1 and t.stride(1) < t.shape[0]):
         raise ValueError("expected a column-major matrix (strides (1, ld))")
     if rows is not None and t.shape[0] != rows:
         raise ValueError("row count mismatch")
     if cols is not None and t.shape[1] != cols:
         raise ValueError("column count mismatch")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _ld(t) -> int:
+    """Leading dimension of a column-major tensor (strides of size-1 dimensions are
+    arbitrary in torch)."""
+    if t is None:
+        return 0
+    return int(t.stride(1)) if t.shape[1] > 1 else max(1, int(t.shape[0]))
 
 
 def _stream(stream):
@@ -161,11 +175,13 @@ def make_opts(gemm="fp64", slices=0, update_slices=0, compensated=True, gate=Tru
     return o
 
 
-def workspace(n: int, device="cuda"):
-    """A device workspace tensor large enough for size n."""
+def workspace(n: int, device="cuda", **kw):
+    """A device workspace tensor large enough for size n under the options `kw`
+    (as for make_opts)."""
     import torch
 
-    nbytes = lib().sr_workspace_bytes(int(n), None)
+    o = make_opts(**kw) if kw else None
+    nbytes = lib().sr_workspace_bytes(int(n), ctypes.byref(o) if o is not None else None)
     return torch.empty(max(1, nbytes), dtype=torch.uint8, device=device)
 
 
@@ -205,7 +221,17 @@ def schur_refine_batched(As, Qs, Ts, iters: int = 6, tol: float = 1e-15, **kw):
     return rc, [infos[i].as_dict() for i in range(b)]
 
 
+def workspace_dd(n: int, device="cuda", **kw):
+    """A device workspace tensor for schur_refine_dd at size n under `kw`."""
+    import torch
+
+    o = make_opts(**kw)
+    return torch.empty(max(1, int(lib().sr_workspace_bytes_dd(int(n), ctypes.byref(o)))),
+                       dtype=torch.uint8, device=device)
+
+
 def schur_refine_dd(A_hi, A_lo, Q_hi, Q_lo, T_hi, T_lo, iters: int = 8, tol: float = 1e-28, **kw):
+    """Double-double refinement of (Q_hi + Q_lo, T_hi + T_lo) for A_hi + A_lo, in place."""
     n = A_hi.shape[0]
     args = [_mat(x, "c128", n, n) for x in (A_hi, A_lo, Q_hi, Q_lo, T_hi, T_lo)]
     o = make_opts(**kw)
@@ -219,9 +245,9 @@ def schur_refine_dd(A_hi, A_lo, Q_hi, Q_lo, T_hi, T_lo, iters: int = 8, tol: flo
 def sr_zgemm(A, B, C, opa: int = 0, Cin=None, compensated: bool = False, stream=None) -> int:
     m, n = C.shape
     k = B.shape[0]
-    return lib().sr_zgemm(int(opa), m, n, k, _mat(A, "c128"), A.stride(1), _mat(B, "c128"),
-                          B.stride(1), _mat(Cin, "c128") if Cin is not None else None,
-                          Cin.stride(1) if Cin is not None else 0, _mat(C, "c128"), C.stride(1),
+    return lib().sr_zgemm(int(opa), m, n, k, _mat(A, "c128"), _ld(A), _mat(B, "c128"),
+                          _ld(B), _mat(Cin, "c128") if Cin is not None else None,
+                          _ld(Cin), _mat(C, "c128"), _ld(C),
                           int(bool(compensated)), _stream(stream))
 
 
@@ -236,18 +262,39 @@ def sr_ozaki_zgemm(A, B, C, opa: int = 0, slices_a: int = 8, slices_b: int = 8, 
     if ws is None:
         ws = torch.empty(max(1, need), dtype=torch.uint8, device=C.device)
     d = int(dmax) if dmax is not None else int(slices_a) + int(slices_b)
-    return lib().sr_ozaki_zgemm(int(opa), m, n, k, _mat(A, "c128"), A.stride(1), _mat(B, "c128"),
-                                B.stride(1), _mat(Cin, "c128") if Cin is not None else None,
-                                Cin.stride(1) if Cin is not None else 0, _mat(C, "c128"), C.stride(1),
+    return lib().sr_ozaki_zgemm(int(opa), m, n, k, _mat(A, "c128"), _ld(A), _mat(B, "c128"),
+                                _ld(B), _mat(Cin, "c128") if Cin is not None else None,
+                                _ld(Cin), _mat(C, "c128"), _ld(C),
                                 int(slices_a), int(slices_b), d, ctypes.c_void_p(ws.data_ptr()),
                                 ws.numel() * ws.element_size(), _stream(stream))
+
+
+def sr_ozaki_zgemm_dd(A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, opa: int = 0, slices_a: int = 16,
+                      slices_b: int = 16, dmax=None, Cin_hi=None, Cin_lo=None, ws=None,
+                      stream=None) -> int:
+    """Double-double Ozaki split product (see include/schur_refine.h)."""
+    import torch
+
+    m, n = C_hi.shape
+    k = B_hi.shape[0]
+    need = int(lib().sr_ozaki_ws_bytes(m, n, k, int(slices_a), int(slices_b)))
+    if ws is None:
+        ws = torch.empty(max(1, need), dtype=torch.uint8, device=C_hi.device)
+    d = int(dmax) if dmax is not None else int(slices_a) + 1
+    opt = lambda x: _mat(x, "c128") if x is not None else None
+    return lib().sr_ozaki_zgemm_dd(
+        int(opa), m, n, k, _mat(A_hi, "c128"), opt(A_lo), _ld(A_hi), _mat(B_hi, "c128"),
+        opt(B_lo), _ld(B_hi), opt(Cin_hi), opt(Cin_lo),
+        _ld(Cin_hi), _mat(C_hi, "c128"), _mat(C_lo, "c128"),
+        _ld(C_hi), int(slices_a), int(slices_b), d, ctypes.c_void_p(ws.data_ptr()),
+        ws.numel() * ws.element_size(), _stream(stream))
 
 
 def sr_cgemm(A, B, C, stream=None) -> int:
     m, n = C.shape
     k = B.shape[0]
-    return lib().sr_cgemm(m, n, k, _mat(A, "c64"), A.stride(1), _mat(B, "c64"), B.stride(1),
-                          _mat(C, "c64"), C.stride(1), _stream(stream))
+    return lib().sr_cgemm(m, n, k, _mat(A, "c64"), _ld(A), _mat(B, "c64"), _ld(B),
+                          _mat(C, "c64"), _ld(C), _stream(stream))
 
 
 def sr_residual(A, Q, T, T_lp, E_lp, ws, want_eps=True, compensated=True, stream=None):
@@ -265,6 +312,12 @@ def sr_trisolve(T_lp, E_lp, L_lp, ws, trunc: float = 0.0, stream=None) -> int:
     return lib().sr_trisolve(_mat(T_lp, "c64", n, n), _mat(E_lp, "c64", n, n),
                              _mat(L_lp, "c64", n, n), n, float(trunc),
                              ctypes.c_void_p(ws.data_ptr()), _stream(stream))
+
+
+def sr_trisolve64(T, E, L, ws, stream=None) -> int:
+    n = T.shape[0]
+    return lib().sr_trisolve64(_mat(T, "c128", n, n), _mat(E, "c128", n, n), _mat(L, "c128", n, n), n,
+                               ctypes.c_void_p(ws.data_ptr()), _stream(stream))
 
 
 def sr_update(Q, L_lp, Q_out, ws, gate=True, compensated=True, stream=None):

@@ -44,6 +44,26 @@ __device__ inline void two_sum(double a, double b, double& s, double& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
+// Double-double arithmetic (Dekker, Knuth): a value is hi + lo with |lo| <= ulp(hi)/2.
+__device__ inline void fast_two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  e = b - (s - a);
+}
+// (h, l) += x
+__device__ inline void dd_add(double& h, double& l, double x) {
+  double s, e;
+  two_sum(h, x, s, e);
+  e += l;
+  fast_two_sum(s, e, h, l);
+}
+// (h, l) += (bh, bl)
+__device__ inline void dd_add(double& h, double& l, double bh, double bl) {
+  double s, e;
+  two_sum(h, bh, s, e);
+  e += l + bl;
+  fast_two_sum(s, e, h, l);
+}
+
 // Device status bits written by kernels (OR-ed into a status word).
 enum : unsigned {
   DEV_BREAKDOWN = 1u,  // t_ii == t_jj or a non-finite value in the solve

@@ -62,8 +62,11 @@ int form_w_parts(int n) {
   return nb * nb;
 }
 
-__global__ __launch_bounds__(ENT) void form_w_kernel(const cc* __restrict__ L, cc* __restrict__ W,
-                                                     int n, double* __restrict__ partials) {
+template <typename R>
+__global__ __launch_bounds__(ENT) void form_w_kernel(const cplx<R>* __restrict__ L,
+                                                     cplx<R>* __restrict__ W, int n,
+                                                     double* __restrict__ partials) {
+  using cc = cplx<R>;
   __shared__ cc lt[ET][ET + 1];
   __shared__ double red[ENT / 64];
   const int nb = ceil_div(n, ET);
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(ENT) void form_w_kernel(const cc* __restrict__ L, c
   for (int r = threadIdx.x; r < ET * ET; r += ENT) {
     const int a = r & (ET - 1), b = r >> 5;
     const int gi = bj * ET + a, gj = bi * ET + b;
-    cc v = mk<float>(0.f, 0.f);
+    cc v = mk<R>(0, 0);
     if (gi < n && gj < n && gi > gj) v = L[gi + (long)gj * n];
     lt[a][b] = v;
   }
@@ -82,12 +85,12 @@ __global__ __launch_bounds__(ENT) void form_w_kernel(const cc* __restrict__ L, c
     const int a = r & (ET - 1), b = r >> 5;
     const int i = bi * ET + a, j = bj * ET + b;
     if (i < n && j < n) {
-      cc w = mk<float>(0.f, 0.f);
+      cc w = mk<R>(0, 0);
       if (i > j) {
         w = L[i + (long)j * n];
       } else if (i < j) {
         const cc u = lt[b][a];  // L(j, i)
-        w = mk<float>(-u.re, u.im);
+        w = mk<R>(-u.re, u.im);
       }
       W[i + (long)j * n] = w;
       s += (double)w.re * w.re + (double)w.im * w.im;
@@ -98,7 +101,82 @@ __global__ __launch_bounds__(ENT) void form_w_kernel(const cc* __restrict__ L, c
 }
 
 hipError_t form_w(const cc* L, cc* W, int n, double* partials, hipStream_t st) {
-  hipLaunchKernelGGL(form_w_kernel, dim3(form_w_parts(n)), dim3(ENT), 0, st, L, W, n, partials);
+  hipLaunchKernelGGL(form_w_kernel<float>, dim3(form_w_parts(n)), dim3(ENT), 0, st, L, W, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t form_w64(const zc* L, zc* W, int n, double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(form_w_kernel<double>, dim3(form_w_parts(n)), dim3(ENT), 0, st, L, W, n, partials);
+  return hipGetLastError();
+}
+
+// Double-double tier: D = W - Y/2 + (W2 + W3 - YW)/2 with W = L - L^H (FP64, exact
+// in double-double), Y = Yhi + Ylo and the lp products in FP64.
+__global__ __launch_bounds__(ENT) void form_delta_dd_kernel(
+    const zc* __restrict__ L, const zc* __restrict__ Yhi, const zc* __restrict__ Ylo,
+    const zc* __restrict__ W2, const zc* __restrict__ W3, const zc* __restrict__ YW,
+    zc* __restrict__ Dhi, zc* __restrict__ Dlo, int n) {
+  __shared__ zc lt[ET][ET + 1];
+  const int nb = ceil_div(n, ET);
+  const int bi = blockIdx.x % nb, bj = blockIdx.x / nb;
+  if (L) {
+    for (int r = threadIdx.x; r < ET * ET; r += ENT) {
+      const int a = r & (ET - 1), b = r >> 5;
+      const int gi = bj * ET + a, gj = bi * ET + b;
+      zc v = mk<double>(0, 0);
+      if (gi < n && gj < n && gi > gj) v = L[gi + (long)gj * n];
+      lt[a][b] = v;
+    }
+    __syncthreads();
+  }
+  for (int r = threadIdx.x; r < ET * ET; r += ENT) {
+    const int a = r & (ET - 1), b = r >> 5;
+    const int i = bi * ET + a, j = bj * ET + b;
+    if (i < n && j < n) {
+      const long o = i + (long)j * n;
+      double wr = 0, wi = 0;
+      if (L) {
+        if (i > j) {
+          const zc u = L[o];
+          wr = u.re;
+          wi = u.im;
+        } else if (i < j) {
+          const zc u = lt[b][a];
+          wr = -u.re;
+          wi = u.im;
+        }
+      }
+      double pr = 0, pi = 0;
+      if (W2) {
+        pr += W2[o].re;
+        pi += W2[o].im;
+      }
+      if (W3) {
+        pr += W3[o].re;
+        pi += W3[o].im;
+      }
+      if (YW) {
+        pr -= YW[o].re;
+        pi -= YW[o].im;
+      }
+      const zc yh = Yhi[o], yl = Ylo[o];
+      // (-Y/2) in double-double, then + W and + (lp terms)/2
+      double rh = -0.5 * yh.re, rl = -0.5 * yl.re, ih = -0.5 * yh.im, il = -0.5 * yl.im;
+      dd_add(rh, rl, wr);
+      dd_add(ih, il, wi);
+      dd_add(rh, rl, 0.5 * pr);
+      dd_add(ih, il, 0.5 * pi);
+      Dhi[o] = mk<double>(rh, ih);
+      Dlo[o] = mk<double>(rl, il);
+    }
+  }
+}
+
+hipError_t form_delta_dd(const zc* L, const zc* Yhi, const zc* Ylo, const zc* W2, const zc* W3,
+                         const zc* YW, zc* Dhi, zc* Dlo, int n, hipStream_t st) {
+  const int nb = ceil_div(n, ET);
+  hipLaunchKernelGGL(form_delta_dd_kernel, dim3(nb * nb), dim3(ENT), 0, st, L, Yhi, Ylo, W2, W3, YW,
+                     Dhi, Dlo, n);
   return hipGetLastError();
 }
 

@@ -43,6 +43,47 @@ __device__ inline void epi_element(const GemmArgs& g, int i, int j, cplx<R> val,
   }
 }
 
+// Double-double variant: the product value is hi + lo (complex128 each).
+template <int EPI>
+__device__ inline void epi_element_dd(const GemmArgs& g, int i, int j, zc hi, zc lo, double& part) {
+  zc* __restrict__ Ch = (zc*)g.C;
+  zc* __restrict__ Cl = (zc*)g.Clo;
+  const long o = i + (long)j * g.ldc;
+  if constexpr (EPI == EPI_STORE) {
+    Ch[o] = hi;
+    Cl[o] = lo;
+  } else if constexpr (EPI == EPI_ADD) {
+    const long oi = i + (long)j * g.ldcin;
+    const zc ah = ((const zc*)g.Cin)[oi], al = ((const zc*)g.Cinlo)[oi];
+    double rh = ah.re, rl = al.re, ih = ah.im, il = al.im;
+    dd_add(rh, rl, hi.re, lo.re);
+    dd_add(ih, il, hi.im, lo.im);
+    Ch[o] = mk<double>(rh, ih);
+    Cl[o] = mk<double>(rl, il);
+  } else if constexpr (EPI == EPI_SPLIT) {
+    const long ol = i + (long)j * g.ldlp;
+    const zc z = mk<double>(0, 0);
+    if (i <= j) {
+      Ch[o] = hi;
+      Cl[o] = lo;
+      g.Tlp64[ol] = hi;
+      g.Elp64[ol] = z;
+    } else {
+      Ch[o] = z;
+      Cl[o] = z;
+      g.Tlp64[ol] = z;
+      g.Elp64[ol] = hi;
+      part += hi.re * hi.re + hi.im * hi.im;
+    }
+  } else {  // EPI_YDEF
+    double rh = hi.re, rl = lo.re;
+    if (i == j) dd_add(rh, rl, -1.0);
+    Ch[o] = mk<double>(rh, hi.im);
+    Cl[o] = mk<double>(rl, lo.im);
+    part += rh * rh + hi.im * hi.im;
+  }
+}
+
 // Block reduction of `part` into g.partials[slot] (fixed order).
 template <int NT>
 __device__ inline void epi_reduce(const GemmArgs& g, double part, double* red, int slot) {

@@ -31,6 +31,12 @@ struct GemmArgs {
   long ldlp;
   double* partials;
   int tiles_m, tiles_n;
+  // double-double outputs (Ozaki product with DD accumulation): low parts of C and
+  // Cin (same leading dimensions), and the FP64 lp split of That
+  void* Clo;
+  const void* Cinlo;
+  zc* Tlp64;
+  zc* Elp64;
 };
 
 // Number of output tiles (= blocks, = partial sums written) of a GEMM launch.
@@ -53,6 +59,12 @@ hipError_t form_w(const cc* L, cc* W, int n, double* partials, hipStream_t st);
 hipError_t form_delta(const cc* L, const zc* Y, const cc* W2, const cc* W3, const cc* YW, zc* D,
                       int n, hipStream_t st);
 hipError_t to_c64(const zc* x, cc* y, long count, hipStream_t st);
+// Double-double tier: W = L - L^H in FP64 (partials of ||W||^2), and
+// D = W - Y/2 + (W2 + W3 - YW)/2 with Y = Yhi + Ylo and D = Dhi + Dlo in
+// double-double (L and the lp products may be NULL: absent).
+hipError_t form_w64(const zc* L, zc* W, int n, double* partials, hipStream_t st);
+hipError_t form_delta_dd(const zc* L, const zc* Yhi, const zc* Ylo, const zc* W2, const zc* W3,
+                         const zc* YW, zc* Dhi, zc* Dlo, int n, hipStream_t st);
 hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
 
 // Ozaki split products on INT8 MFMA (complex128 operands, FP64 output).
@@ -61,13 +73,21 @@ hipError_t oz_split_cols(const zc* X, const zc* Xlo, long ld, int K, int ncols, 
                          int* exps, hipStream_t st);
 hipError_t oz_split_rows(const zc* X, const zc* Xlo, long ld, int M, int K, int S, int8_t* out,
                          int* exps, hipStream_t st);
-int oz_gemm_tiles(int m, int n);
+// Output tiles (= partial sums written) of a product; dd selects the kernel with
+// double-double accumulation, which serves every size.
+int oz_gemm_tiles(int m, int n, bool dd = false);
+// Bytes of scratch the product of an m x n output needs (0 for small FP64 outputs).
+size_t oz_gemm_scratch_bytes(int m, int n, bool dd = false);
 hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t* B, const int* eb,
-                   int SB, int conjA, int dmax, GemmArgs g, hipStream_t st);
+                   int SB, int conjA, int dmax, GemmArgs g, void* scratch, hipStream_t st,
+                   bool dd = false);
 
-// Triangular matrix equation in FP32 (complex64).
+// Triangular matrix equation in FP32 (complex64) and in FP64 (complex128); the
+// workspace size serves both.
 size_t trisolve_ws_bytes(int n);
 hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* ws,
                     unsigned* status, hipStream_t st);
+hipError_t trisolve64(const zc* T, const zc* E, zc* L, int n, void* ws, unsigned* status,
+                      hipStream_t st);
 
 }  // namespace sr

@@ -14,14 +14,15 @@
 // Product. C_ij = 2^(e_i + f_j) sum_{s,t} 2^{-7(s+t)} (A_s B_t)_ij. The slice
 // pairs are grouped by d = s + t; within one d every pair has the same scale, so
 // their products are summed exactly in int32 (|sum| <= pairs * 2 K * 127^2 <
-// 2^31 for the sizes the host admits) with v_mfma_i32_16x16x64_i8, and the int32
+// 2^31 for the sizes the host admits) with v_mfma_i32_32x32x32_i8 (the INT8 form
+// that runs at the full matrix rate; the 16 x 16 x 64 form runs at half), and the int32
 // sums are folded into FP64 accumulators with scale 2^{-7 d} once d is done.
 // Pairs with s + t > dmax are dropped (their weight is below 2^{-7 dmax}). A
 // complex product keeps four real accumulators (re*re, im*im, re*im, im*re) so
 // that op(A) = conj(A slices) only changes signs at the fold.
 //
 // Tiling: a 512-thread block computes a 128 x 64 complex tile; its eight waves
-// (4 along M x 2 along N) each own 2 x 2 blocks of 16 x 16. Per step the block
+// (4 along M x 2 along N) each own one 32 x 32 block. Per step the block
 // stages one K-tile (64) of one slice of op(A) (both parts) and one slice of B in
 // LDS, double-buffered; LDS rows are padded to 80 bytes, which makes the 16-byte
 // fragment reads of 16 consecutive rows conflict-free.
@@ -30,6 +31,7 @@
 namespace sr {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int OBM = 128, OBN = 64, OBK = 64, ONT = 512, OLD = 80;
 constexpr int kSplitNT = 256;
@@ -246,7 +248,8 @@ struct OzArgs {
   const int8_t* B;  // B slices: [SB][2][n][Kp]
   const int* eb;
   int SA, SB, dmax, conjA, Kp;
-  GemmArgs g;  // sizes, output and epilogue
+  GemmArgs g;          // sizes, output and epilogue
+  double2* scratch;    // large-tile kernel: FP64 partial sums between folds
 };
 
 template <int EPI>
@@ -276,13 +279,9 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
   const int KT = a.Kp / OBK;
   const long sA = 2L * g.m * a.Kp, sB = 2L * g.n * a.Kp;  // bytes per slice
 
-  double out_re[2][2][4], out_im[2][2][4];
+  double out_re[16], out_im[16];
 #pragma unroll
-  for (int x = 0; x < 2; x++)
-#pragma unroll
-    for (int y = 0; y < 2; y++)
-#pragma unroll
-      for (int v = 0; v < 4; v++) out_re[x][y][v] = out_im[x][y][v] = 0;
+  for (int v = 0; v < 16; v++) out_re[v] = out_im[v] = 0;
 
   // staging: 2 chunks of A (16 B) and 1 of B per thread and step
   v4i ra[2], rb;
@@ -321,11 +320,7 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
     const int s_lo = max(1, d - a.SB), s_hi = min(a.SA, d - 1);
     if (s_lo > s_hi) continue;
     const int steps = (s_hi - s_lo + 1) * KT;
-    v4i rr[2][2], ii[2][2], ri[2][2], ir[2][2];
-#pragma unroll
-    for (int x = 0; x < 2; x++)
-#pragma unroll
-      for (int y = 0; y < 2; y++) rr[x][y] = ii[x][y] = ri[x][y] = ir[x][y] = v4i{0, 0, 0, 0};
+    v16i rr = {}, ii = {}, ri = {}, ir = {};
     __syncthreads();  // LDS of the previous diagonal no longer read
     gload(s_lo, d - s_lo, 0);
     sstore(0);
@@ -336,29 +331,19 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
         const int s = s_lo + (st + 1) / KT, kt = (st + 1) % KT;
         gload(s, d - s, kt);
       }
-      const int kq = 16 * (lane >> 4);
-      v4i far[2], fai[2], fbr[2], fbi[2];
+      const int row = wm + (lane & 31), col = wn + (lane & 31);
 #pragma unroll
-      for (int x = 0; x < 2; x++) {
-        const int row = wm + x * 16 + (lane & 15);
-        far[x] = *(const v4i*)&As[cur][0][row][kq];
-        fai[x] = *(const v4i*)&As[cur][1][row][kq];
+      for (int kh = 0; kh < 2; kh++) {
+        const int kq = 32 * kh + 16 * (lane >> 5);
+        const v4i far = *(const v4i*)&As[cur][0][row][kq];
+        const v4i fai = *(const v4i*)&As[cur][1][row][kq];
+        const v4i fbr = *(const v4i*)&Bs[cur][0][col][kq];
+        const v4i fbi = *(const v4i*)&Bs[cur][1][col][kq];
+        rr = __builtin_amdgcn_mfma_i32_32x32x32_i8(far, fbr, rr, 0, 0, 0);
+        ii = __builtin_amdgcn_mfma_i32_32x32x32_i8(fai, fbi, ii, 0, 0, 0);
+        ri = __builtin_amdgcn_mfma_i32_32x32x32_i8(far, fbi, ri, 0, 0, 0);
+        ir = __builtin_amdgcn_mfma_i32_32x32x32_i8(fai, fbr, ir, 0, 0, 0);
       }
-#pragma unroll
-      for (int y = 0; y < 2; y++) {
-        const int col = wn + y * 16 + (lane & 15);
-        fbr[y] = *(const v4i*)&Bs[cur][0][col][kq];
-        fbi[y] = *(const v4i*)&Bs[cur][1][col][kq];
-      }
-#pragma unroll
-      for (int x = 0; x < 2; x++)
-#pragma unroll
-        for (int y = 0; y < 2; y++) {
-          rr[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(far[x], fbr[y], rr[x][y], 0, 0, 0);
-          ii[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fai[x], fbi[y], ii[x][y], 0, 0, 0);
-          ri[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(far[x], fbi[y], ri[x][y], 0, 0, 0);
-          ir[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fai[x], fbr[y], ir[x][y], 0, 0, 0);
-        }
       if (st + 1 < steps) sstore(cur ^ 1);
       __syncthreads();
     }
@@ -366,43 +351,297 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
     const double sc = ldexp(1.0, -7 * d);
     const double sg = a.conjA ? 1.0 : -1.0;  // re = rr + sg ii, im = ri - sg ir
 #pragma unroll
-    for (int x = 0; x < 2; x++)
-#pragma unroll
-      for (int y = 0; y < 2; y++)
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-          out_re[x][y][v] += ((double)rr[x][y][v] + sg * (double)ii[x][y][v]) * sc;
-          out_im[x][y][v] += ((double)ri[x][y][v] - sg * (double)ir[x][y][v]) * sc;
-        }
+    for (int v = 0; v < 16; v++) {
+      out_re[v] += ((double)rr[v] + sg * (double)ii[v]) * sc;
+      out_im[v] += ((double)ri[v] - sg * (double)ir[v]) * sc;
+    }
   }
 
   double part = 0;
 #pragma unroll
-  for (int x = 0; x < 2; x++)
-#pragma unroll
-    for (int y = 0; y < 2; y++)
-#pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int i = m0 + wm + x * 16 + 4 * (lane >> 4) + v;  // i32 accumulator rows
-        const int j = n0 + wn + y * 16 + (lane & 15);
-        if (i < g.m && j < g.n) {
-          const int e = a.ea[i] + a.eb[j];
-          zc val = mk<double>(ldexp(out_re[x][y][v], e), ldexp(out_im[x][y][v], e));
-          epi_element<EPI, double>(g, i, j, val, part);
-        }
-      }
+  for (int v = 0; v < 16; v++) {
+    const int i = m0 + wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);  // i32 32x32 accumulator rows
+    const int j = n0 + wn + (lane & 31);
+    if (i < g.m && j < g.n) {
+      const int e = a.ea[i] + a.eb[j];
+      zc val = mk<double>(ldexp(out_re[v], e), ldexp(out_im[v], e));
+      epi_element<EPI, double>(g, i, j, val, part);
+    }
+  }
   if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<ONT>(g, part, red, bid);
 }
 
-int oz_gemm_tiles(int m, int n) { return ceil_div(m, OBM) * ceil_div(n, OBN); }
+
+// ------------------------------------------------------- large-tile product
+//
+// For products with at least one 128 x 128 tile per CU. A 256-thread block (one
+// wave per SIMD) computes a 128 x 128 complex tile; each wave owns 64 x 64 as
+// 2 x 2 blocks of 32 x 32. Only two int32 accumulators per output are kept: with
+// the negated imaginary digits of op(A) staged beside the real and imaginary
+// ones, re = Ar Br + (-Ai) Bi and im = Ar Bi + Ai Br (conjugated op(A):
+// re = Ar Br + Ai Bi, im = Ar Bi + (-Ai) Br), all summed exactly in int32
+// (|sum| <= 2 * steps * 64 * 127^2, so a diagonal is folded at least every
+// kSeg steps). The FP64 partial sums live between folds in a per-tile scratch
+// laid out in the waves' register order (coalesced), not in registers, so the
+// register file holds the large wave tile.
+constexpr int PBM = 128, PBN = 128, PNT = 256, PLD = 80, kSeg = 1024;
+
+__device__ inline v4i neg_bytes(v4i x) {
+  // per-byte two's-complement negation (digits lie in [-127, 127])
+  v4i r;
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    const unsigned n = ~(unsigned)x[c];
+    r[c] = (int)(((n & 0x7f7f7f7fu) + 0x01010101u) ^ (n & 0x80808080u));
+  }
+  return r;
+}
+
+template <int EPI, bool DD>
+__global__ __launch_bounds__(PNT, 1) void oz_gemm2_kernel(OzArgs a) {
+  __shared__ __align__(16) int8_t As[2][3][PBM][PLD];
+  __shared__ __align__(16) int8_t Bs[2][2][PBN][PLD];
+  __shared__ double red[PNT / 64];
+  const GemmArgs& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+
+  const int ntiles = g.tiles_m * g.tiles_n;
+  const int bid = blockIdx.x;
+  int logical = bid;
+  {
+    const int per = ntiles / kXCDs;
+    if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
+  }
+  constexpr int kGroup = 4;
+  const int group = logical / (kGroup * g.tiles_n);
+  const int first_m = group * kGroup;
+  const int gsize = min(g.tiles_m - first_m, kGroup);
+  const int within = logical - group * kGroup * g.tiles_n;
+  const int m0 = (first_m + within % gsize) * PBM, n0 = (within / gsize) * PBN;
+
+  const int KT = a.Kp / OBK;
+  const long sA = 2L * g.m * a.Kp, sB = 2L * g.n * a.Kp;
+  const int pa2 = a.conjA ? 1 : 2, pa3 = a.conjA ? 2 : 1;
+  // per wave 4096 (x, y, v, lane) partial sums; the double-double product keeps
+  // each as a three-term expansion (see the fold)
+  constexpr int kWave = 16 * 4 * 64;
+  double2* sp = a.scratch ? a.scratch + ((long)bid * 4 + wave) * (DD ? 3 * kWave : kWave) + lane : nullptr;
+
+  v4i sa[2][2], sb[2][2];  // staged chunks: [pair][part]
+  auto gload = [&](int s, int t, int kt) {
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int q = r * PNT + tid, row = q >> 2, ch = q & 3;
+      const int gi = m0 + row, gj = n0 + row;
+#pragma unroll
+      for (int part = 0; part < 2; part++) {
+        v4i v = {0, 0, 0, 0}, w = {0, 0, 0, 0};
+        if (gi < g.m)
+          v = *(const v4i*)(a.A + (long)(s - 1) * sA + ((long)part * g.m + gi) * a.Kp + kt * OBK + ch * 16);
+        if (gj < g.n)
+          w = *(const v4i*)(a.B + (long)(t - 1) * sB + ((long)part * g.n + gj) * a.Kp + kt * OBK + ch * 16);
+        sa[r][part] = v;
+        sb[r][part] = w;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int q = r * PNT + tid, row = q >> 2, ch = q & 3;
+      *(v4i*)&As[buf][0][row][ch * 16] = sa[r][0];
+      *(v4i*)&As[buf][1][row][ch * 16] = sa[r][1];
+      *(v4i*)&As[buf][2][row][ch * 16] = neg_bytes(sa[r][1]);
+      *(v4i*)&Bs[buf][0][row][ch * 16] = sb[r][0];
+      *(v4i*)&Bs[buf][1][row][ch * 16] = sb[r][1];
+    }
+  };
+
+  v16i acc_re[2][2], acc_im[2][2];
+  double part = 0;
+  bool first = true;
+  const int d_last = min(a.dmax, a.SA + a.SB);
+  for (int d = 2; d <= d_last; d++) {
+    const int s_lo = max(1, d - a.SB), s_hi = min(a.SA, d - 1);
+    if (s_lo > s_hi) continue;
+    const int total = (s_hi - s_lo + 1) * KT;
+    for (int seg0 = 0; seg0 < total; seg0 += kSeg) {
+      const int steps = min(kSeg, total - seg0);
+      const bool last = d == d_last && seg0 + steps == total;
+#pragma unroll
+      for (int x = 0; x < 2; x++)
+#pragma unroll
+        for (int y = 0; y < 2; y++) acc_re[x][y] = acc_im[x][y] = v16i{};
+      __syncthreads();  // LDS of the previous segment no longer read
+      {
+        const int s = s_lo + seg0 / KT;
+        gload(s, d - s, seg0 % KT);
+      }
+      sstore(0);
+      __syncthreads();
+      for (int st = 0; st < steps; st++) {
+        const int cur = st & 1;
+        if (st + 1 < steps) {
+          const int q = seg0 + st + 1, s = s_lo + q / KT;
+          gload(s, d - s, q % KT);
+        }
+#pragma unroll
+        for (int kh = 0; kh < 2; kh++) {
+          const int kq = 32 * kh + 16 * (lane >> 5);
+          v4i fb0[2], fb1[2], fa0[2], fa2[2], fa3[2];
+#pragma unroll
+          for (int y = 0; y < 2; y++) {
+            const int col = wn + y * 32 + (lane & 31);
+            fb0[y] = *(const v4i*)&Bs[cur][0][col][kq];
+            fb1[y] = *(const v4i*)&Bs[cur][1][col][kq];
+          }
+#pragma unroll
+          for (int x = 0; x < 2; x++) {
+            const int row = wm + x * 32 + (lane & 31);
+            fa0[x] = *(const v4i*)&As[cur][0][row][kq];
+            fa2[x] = *(const v4i*)&As[cur][pa2][row][kq];
+            fa3[x] = *(const v4i*)&As[cur][pa3][row][kq];
+          }
+#pragma unroll
+          for (int x = 0; x < 2; x++)
+#pragma unroll
+            for (int y = 0; y < 2; y++)
+              acc_re[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa0[x], fb0[y], acc_re[x][y], 0, 0, 0);
+#pragma unroll
+          for (int x = 0; x < 2; x++)
+#pragma unroll
+            for (int y = 0; y < 2; y++)
+              acc_im[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa0[x], fb1[y], acc_im[x][y], 0, 0, 0);
+#pragma unroll
+          for (int x = 0; x < 2; x++)
+#pragma unroll
+            for (int y = 0; y < 2; y++)
+              acc_re[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa2[x], fb1[y], acc_re[x][y], 0, 0, 0);
+#pragma unroll
+          for (int x = 0; x < 2; x++)
+#pragma unroll
+            for (int y = 0; y < 2; y++)
+              acc_im[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa3[x], fb0[y], acc_im[x][y], 0, 0, 0);
+        }
+        if (st + 1 < steps) sstore(cur ^ 1);
+        __syncthreads();
+      }
+      // fold: partial = previous partial + acc 2^{-7 d} (acc 2^{-7 d} is exact in FP64)
+      const double sc = ldexp(1.0, -7 * d);
+#pragma unroll
+      for (int x = 0; x < 2; x++)
+#pragma unroll
+        for (int y = 0; y < 2; y++)
+#pragma unroll
+          for (int v = 0; v < 16; v++) {
+            const int o = ((x * 2 + y) * 16 + v) * 64;
+            double re = (double)acc_re[x][y][v] * sc, im = (double)acc_im[x][y][v] * sc;
+            // double-double: the partial sum is a0 + a1 + a2, extended with two exact
+            // TwoSum steps per fold; the partial sums can exceed the final value by
+            // the ratio of the row/column scales to it, which a two-term sum would
+            // turn into error of the final value
+            double rm = 0, im_m = 0, rl = 0, il = 0;
+            if (!first) {
+              const double2 pv = sp[o];
+              if constexpr (DD) {
+                const double2 pm = sp[o + kWave], pl = sp[o + 2 * kWave];
+                double s0, e0, s1, e1;
+                two_sum(pv.x, re, s0, e0);
+                two_sum(pm.x, e0, s1, e1);
+                re = s0;
+                rm = s1;
+                rl = pl.x + e1;
+                two_sum(pv.y, im, s0, e0);
+                two_sum(pm.y, e0, s1, e1);
+                im = s0;
+                im_m = s1;
+                il = pl.y + e1;
+              } else {
+                re = pv.x + re;
+                im = pv.y + im;
+              }
+            }
+            if (!last) {
+              sp[o] = make_double2(re, im);
+              if constexpr (DD) {
+                sp[o + kWave] = make_double2(rm, im_m);
+                sp[o + 2 * kWave] = make_double2(rl, il);
+              }
+            } else {
+              if constexpr (DD) {
+                // to double-double: (re + rm) exactly, then the third term
+                double h, e;
+                two_sum(re, rm, h, e);
+                e += rl;
+                fast_two_sum(h, e, re, rl);
+                two_sum(im, im_m, h, e);
+                e += il;
+                fast_two_sum(h, e, im, il);
+              }
+              const int i = m0 + wm + x * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+              const int j = n0 + wn + y * 32 + (lane & 31);
+              if (i < g.m && j < g.n) {
+                const int e = a.ea[i] + a.eb[j];
+                if constexpr (DD)
+                  epi_element_dd<EPI>(g, i, j, mk<double>(ldexp(re, e), ldexp(im, e)),
+                                      mk<double>(ldexp(rl, e), ldexp(il, e)), part);
+                else
+                  epi_element<EPI, double>(g, i, j, mk<double>(ldexp(re, e), ldexp(im, e)), part);
+              }
+            }
+          }
+      first = false;
+    }
+  }
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<PNT>(g, part, red, bid);
+}
+
+// The large-tile kernel is used when it still gives every CU a tile, and for
+// every double-double product.
+static bool use_large_tiles(int m, int n, bool dd) {
+  return dd || ceil_div(m, PBM) * ceil_div(n, PBN) >= kCUs;
+}
+
+size_t oz_gemm_scratch_bytes(int m, int n, bool dd) {
+  if (!use_large_tiles(m, n, dd)) return 0;
+  return (size_t)ceil_div(m, PBM) * ceil_div(n, PBN) * PBM * PBN * sizeof(double2) * (dd ? 3 : 1);
+}
+
+int oz_gemm_tiles(int m, int n, bool dd) {
+  if (use_large_tiles(m, n, dd)) return ceil_div(m, PBM) * ceil_div(n, PBN);
+  return ceil_div(m, OBM) * ceil_div(n, OBN);
+}
+
+template <int EPI>
+static void launch_large(bool dd, int nt, const OzArgs& a, hipStream_t st) {
+  if (dd) oz_gemm2_kernel<EPI, true><<<dim3(nt), dim3(PNT), 0, st>>>(a);
+  else oz_gemm2_kernel<EPI, false><<<dim3(nt), dim3(PNT), 0, st>>>(a);
+}
 
 hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t* B, const int* eb,
-                   int SB, int conjA, int dmax, GemmArgs g, hipStream_t st) {
+                   int SB, int conjA, int dmax, GemmArgs g, void* scratch, hipStream_t st,
+                   bool dd) {
+  if (g.m == 0 || g.n == 0) return hipSuccess;
+  if (use_large_tiles(g.m, g.n, dd)) {
+    if (!scratch) return hipErrorInvalidValue;
+    g.tiles_m = ceil_div(g.m, PBM);
+    g.tiles_n = ceil_div(g.n, PBN);
+    const int nt = g.tiles_m * g.tiles_n;
+    OzArgs a{A, ea, B, eb, SA, SB, dmax, conjA, oz_kp(g.k), g, (double2*)scratch};
+    switch (epi) {
+      case EPI_STORE: launch_large<EPI_STORE>(dd, nt, a, st); break;
+      case EPI_ADD: launch_large<EPI_ADD>(dd, nt, a, st); break;
+      case EPI_SPLIT: launch_large<EPI_SPLIT>(dd, nt, a, st); break;
+      case EPI_YDEF: launch_large<EPI_YDEF>(dd, nt, a, st); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   g.tiles_m = ceil_div(g.m, OBM);
   g.tiles_n = ceil_div(g.n, OBN);
   const int nt = g.tiles_m * g.tiles_n;
-  if (nt == 0) return hipSuccess;
-  OzArgs a{A, ea, B, eb, SA, SB, dmax, conjA, oz_kp(g.k), g};
+  OzArgs a{A, ea, B, eb, SA, SB, dmax, conjA, oz_kp(g.k), g, nullptr};
   switch (epi) {
     case EPI_STORE: hipLaunchKernelGGL(oz_gemm_kernel<EPI_STORE>, dim3(nt), dim3(ONT), 0, st, a); break;
     case EPI_ADD: hipLaunchKernelGGL(oz_gemm_kernel<EPI_ADD>, dim3(nt), dim3(ONT), 0, st, a); break;

@@ -35,6 +35,11 @@ int partial_slots(int n) {
   return m > 1024 ? m : 1024;
 }
 
+// Ozaki mode: slice counts. P = A Q and the Gram matrix of the start take
+// kOzSlices digits per operand (56 bits) with pairs up to s + t = kOzSlices + 1;
+// the products Q Delta take between kOzMinUpd and kOzMaxUpd, chosen from ||Delta||.
+constexpr int kOzSlices = 8, kOzMinUpd = 2, kOzMaxUpd = 8;
+
 struct Work {
   zc *Qa, *QH, *P, *Y;
   cc *Tlp, *Elp, *Llp, *W, *W2, *W3, *YW, *Ylp;
@@ -42,10 +47,20 @@ struct Work {
   double* scal;
   unsigned* status;
   void* tri;
+  // Ozaki mode only (NULL otherwise): row slices of A, column slices of Q, row
+  // slices of Q and column slices of Delta, with their exponents.
+  int8_t *sA, *sQc, *sQr, *sD;
+  int *eA, *eQc, *eQr, *eD;
+  void* oz_scratch;  // FP64 partial sums of the large-tile product (may be NULL)
+  int oz_s;
   size_t bytes;
 };
 
-Work carve(void* base, int n) {
+int oz_main_slices(const sr_opts* o) {
+  return (o && o->slices > 0) ? o->slices : kOzSlices;
+}
+
+Work carve(void* base, int n, const sr_opts* o = nullptr) {
   Work w;
   uintptr_t p = (uintptr_t)base;
   const size_t z = align256((size_t)n * n * sizeof(zc));
@@ -71,6 +86,25 @@ Work carve(void* base, int n) {
   w.scal = (double*)take(256);
   w.status = (unsigned*)take(256);
   w.tri = take(align256(trisolve_ws_bytes(n)));
+  w.sA = w.sQc = w.sQr = w.sD = nullptr;
+  w.eA = w.eQc = w.eQr = w.eD = nullptr;
+  w.oz_scratch = nullptr;
+  w.oz_s = 0;
+  if (o && o->gemm == SR_GEMM_OZAKI_I8) {
+    const int S = oz_main_slices(o);
+    const int Su = o->update_slices > 0 ? o->update_slices : kOzMaxUpd;
+    w.oz_s = S;
+    w.sA = (int8_t*)take(align256(oz_slice_bytes(n, n, S)));
+    w.sQc = (int8_t*)take(align256(oz_slice_bytes(n, n, S)));
+    w.sQr = (int8_t*)take(align256(oz_slice_bytes(n, n, Su)));
+    w.sD = (int8_t*)take(align256(oz_slice_bytes(n, n, Su)));
+    w.eA = (int*)take(align256((size_t)n * sizeof(int)));
+    w.eQc = (int*)take(align256((size_t)n * sizeof(int)));
+    w.eQr = (int*)take(align256((size_t)n * sizeof(int)));
+    w.eD = (int*)take(align256((size_t)n * sizeof(int)));
+    const size_t scr = oz_gemm_scratch_bytes(n, n);
+    if (scr) w.oz_scratch = take(align256(scr));
+  }
   w.bytes = (size_t)(p - (uintptr_t)base);
   return w;
 }
@@ -170,8 +204,57 @@ struct Timer {
 
 // Newton-Schulz start into Qout: Y0 = Qh^H Qh - I, Qout = Qh + Qh (-Y0/2);
 // QHout (may be NULL) receives Qout^H.
+// Ozaki mode: Qout = Q + Q D (QHout = Qout^H if given) from Su slices per operand.
+int oz_update(const zc* Q, const zc* D, zc* Qout, zc* QHout, int n, int Su, const Work& w,
+              hipStream_t st) {
+  CK(oz_split_rows(Q, nullptr, n, n, n, Su, w.sQr, w.eQr, st));
+  CK(oz_split_cols(D, nullptr, n, n, n, Su, w.sD, w.eD, st));
+  GemmArgs u = gargs(n, n, n, nullptr, 0, nullptr, 0, Qout, n);
+  u.Cin = Q;
+  u.ldcin = n;
+  u.CH = QHout;
+  u.ldch = n;
+  CK(oz_gemm(EPI_ADD, w.sQr, w.eQr, Su, w.sD, w.eD, Su, 0, Su + 1, u, w.oz_scratch, st));
+  return SR_OK;
+}
+
+// Digits per operand of Q Delta: the dropped part of each operand is below
+// 2^(-7 Su) of its row or column scale, so Su is taken with 2^(-7 Su) ||Delta||_F
+// under 0.05 u (plus one digit for the pairs dropped beyond Su + 1).
+int update_slices(const sr_opts& o, double norm_delta) {
+  if (o.update_slices > 0) return o.update_slices;
+  if (!(norm_delta > 0)) return kOzMinUpd;
+  const double bits = log2(norm_delta / (0.05 * kU64));
+  int s = (int)ceil(bits / 7.0) + 1;
+  if (s < kOzMinUpd) s = kOzMinUpd;
+  if (s > kOzMaxUpd) s = kOzMaxUpd;
+  return s;
+}
+
 int ns_init(const zc* Qh, zc* Qout, zc* QHout, int n, int comp, const Work& w, hipStream_t st,
-            Timer* tm = nullptr) {
+            Timer* tm = nullptr, const sr_opts* o = nullptr, int* su_used = nullptr) {
+  if (w.oz_s) {
+    // The Gram matrix Qh^H Qh from the column slices of Qh, used for both operands.
+    const int S = w.oz_s;
+    TIC(tm, 0);
+    CK(oz_split_cols(Qh, nullptr, n, n, n, S, w.sQc, w.eQc, st));
+    GemmArgs g = gargs(n, n, n, nullptr, 0, nullptr, 0, w.Y, n);
+    g.partials = w.partials;
+    CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, S, w.sQc, w.eQc, S, 1, S + 1, g, w.oz_scratch, st));
+    TOC(tm, 0);
+    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n), w.scal + 2, st));
+    double nrm[3];
+    unsigned dst = 0;
+    int rc = read_back(st, w, 3, nrm, &dst);
+    if (rc != SR_OK) return rc;
+    CK(form_delta(nullptr, w.Y, nullptr, nullptr, nullptr, w.P, n, st));
+    const int Su = update_slices(*o, 0.5 * sqrt(nrm[2]));
+    if (su_used) *su_used = Su;
+    TIC(tm, 0);
+    if ((rc = oz_update(Qh, w.P, Qout, QHout, n, Su, w, st)) != SR_OK) return rc;
+    TOC(tm, 0);
+    return SR_OK;
+  }
   GemmArgs g = gargs(n, n, n, Qh, n, Qh, n, w.Y, n);
   g.partials = w.partials;
   TIC(tm, 0);
@@ -195,7 +278,14 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
              hipStream_t st, Timer* tm = nullptr) {
   GemmArgs g = gargs(n, n, n, A, n, Q, n, w.P, n);
   TIC(tm, 0);
-  CK(zgemm(0, EPI_STORE, comp, g, st));
+  if (w.oz_s) {
+    // Ozaki mode: P from the row slices of A (split once per call) and the column
+    // slices of Q; That and Y stay native FP64.
+    CK(oz_split_cols(Q, nullptr, n, n, n, w.oz_s, w.sQc, w.eQc, st));
+    CK(oz_gemm(EPI_STORE, w.sA, w.eA, w.oz_s, w.sQc, w.eQc, w.oz_s, 0, w.oz_s + 1, g, w.oz_scratch, st));
+  } else {
+    CK(zgemm(0, EPI_STORE, comp, g, st));
+  }
   TOC(tm, 0);
   GemmArgs s = gargs(n, n, n, QH ? QH : Q, n, w.P, n, T, n);
   s.Tlp = w.Tlp;
@@ -229,7 +319,7 @@ struct Gate {
 
 // lp products, Delta, and Qout = Q + Q Delta (QHout, if given, receives Qout^H).
 int apply_update(const zc* Q, zc* Qout, zc* QHout, int n, Gate gt, const Work& w, hipStream_t st,
-                 int* nprod, Timer* tm = nullptr) {
+                 int* nprod, Timer* tm = nullptr, int Su = 0) {
   int np = 0;
   if (gt.w2 || gt.w3) {
     CK(cgemm(gargs(n, n, n, w.W, n, w.W, n, w.W2, n), st));
@@ -246,13 +336,18 @@ int apply_update(const zc* Q, zc* Qout, zc* QHout, int n, Gate gt, const Work& w
   }
   CK(form_delta(w.Llp, w.Y, gt.w2 ? w.W2 : nullptr, gt.w3 ? w.W3 : nullptr,
                 gt.yw ? w.YW : nullptr, w.P, n, st));
-  GemmArgs u = gargs(n, n, n, Q, n, w.P, n, Qout, n);
-  u.Cin = Q;
-  u.ldcin = n;
-  u.CH = QHout;
-  u.ldch = n;
   TIC(tm, 0);
-  CK(zgemm(0, EPI_ADD, 0, u, st));
+  if (w.oz_s) {
+    const int rc = oz_update(Q, w.P, Qout, QHout, n, Su, w, st);
+    if (rc != SR_OK) return rc;
+  } else {
+    GemmArgs u = gargs(n, n, n, Q, n, w.P, n, Qout, n);
+    u.Cin = Q;
+    u.ldcin = n;
+    u.CH = QHout;
+    u.ldch = n;
+    CK(zgemm(0, EPI_ADD, 0, u, st));
+  }
   TOC(tm, 0);
   if (nprod) *nprod += np;
   return SR_OK;
@@ -318,9 +413,8 @@ void sr_default_opts(sr_opts* o) {
 }
 
 size_t sr_workspace_bytes(int n, const sr_opts* opts) {
-  (void)opts;
   if (n < 1) return 0;
-  return carve(nullptr, n).bytes + 256;
+  return carve(nullptr, n, opts).bytes + 256;
 }
 
 const char* sr_status_string(int s) {
@@ -348,9 +442,15 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   sr_opts o;
   if (opts_in) o = *opts_in;
   else sr_default_opts(&o);
-  if (o.gemm != SR_GEMM_FP64) {
-    if (info) info->status = SR_ENOSYS;
-    return SR_ENOSYS;
+  if (o.gemm != SR_GEMM_FP64 && o.gemm != SR_GEMM_OZAKI_I8) {
+    if (info) info->status = o.gemm == SR_GEMM_OZAKI_BF16 ? SR_ENOSYS : SR_EINVAL;
+    return o.gemm == SR_GEMM_OZAKI_BF16 ? SR_ENOSYS : SR_EINVAL;
+  }
+  if (o.gemm == SR_GEMM_OZAKI_I8 &&
+      (o.slices < 0 || o.slices > 16 || o.update_slices < 0 || o.update_slices > kOzMaxUpd ||
+       (long)oz_main_slices(&o) * ((n + 63) / 64 * 64) * 127L * 127L >= 2147483647L)) {
+    if (info) info->status = SR_EINVAL;
+    return SR_EINVAL;
   }
   hipStream_t st = (hipStream_t)o.stream;
   const zc* A = (const zc*)A_;
@@ -384,7 +484,7 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
     if (info) info->status = rc;
     return rc;
   }
-  const Work w = carve(base, n);
+  const Work w = carve(base, n, &o);
   const int comp = o.compensated ? 1 : 0;
 
   Timer timer;
@@ -403,7 +503,10 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   double eps = 0, eps1 = -1, eps2 = -1, orth = 0;
   zc* cur = w.Qa;
   zc* other = Q;
-  if ((rc = ns_init(Q, w.Qa, w.QH, n, comp, w, st, tm)) != SR_OK) return rc;
+  if (w.oz_s) CK(oz_split_rows(A, nullptr, n, n, n, w.oz_s, w.sA, w.eA, st));
+  int su = 0;
+  if ((rc = ns_init(Q, w.Qa, w.QH, n, comp, w, st, tm, &o, &su)) != SR_OK) return rc;
+  if (info) info->update_slices_hist[0] = su;
 
   for (int p = 0; p < iters; p++) {
     if ((rc = residual(A, cur, w.QH, T, n, comp, w, st, tm)) != SR_OK) return rc;
@@ -451,7 +554,9 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
       break;
     }
     const Gate gt = gate_terms(o.gate_lp_terms != 0, nw, ny);
-    if ((rc = apply_update(cur, other, w.QH, n, gt, w, st, &nprod, tm)) != SR_OK) return rc;
+    su = w.oz_s ? update_slices(o, nw + 0.5 * ny) : 0;
+    if (info && updates + 1 < 16) info->update_slices_hist[updates + 1] = su;
+    if ((rc = apply_update(cur, other, w.QH, n, gt, w, st, &nprod, tm, su)) != SR_OK) return rc;
     zc* t = cur;
     cur = other;
     other = t;
@@ -495,11 +600,387 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
   return worst;
 }
 
-int schur_refine_dd(const void*, const void*, void*, void*, void*, void*, int, int, double,
-                    const sr_opts*, sr_info* info) {
+}  // extern "C"
+
+namespace {
+// ------------------------------------------------------------------------
+// Double-double tier: hp = double-double (every hp product is an Ozaki split
+// product of double-double operands with double-double accumulation), lp = FP64
+// (the solve and the lp products).
+
+constexpr double kUDD = 4.930380657631324e-32;  // 2^-104
+constexpr int kDDSlices = 15, kDDMaxUpd = 16;
+
+struct DDWork {
+  zc *Qh, *Ql, *Ph, *Pl, *Yh, *Yl, *Dh, *Dl;
+  zc *Tlp, *Elp, *L, *W, *W2, *W3, *YW;
+  int8_t *sA, *sQc, *sP, *sQr, *sD;
+  int *eA, *eQc, *eP, *eQr, *eD;
+  void* scratch;
+  double* partials;
+  double* scal;
+  unsigned* status;
+  void* tri;
+  int S;
+  size_t bytes;
+};
+
+int dd_main_slices(const sr_opts* o) { return (o && o->slices > 0) ? o->slices : kDDSlices; }
+
+// Host double-double helpers for the n = 1 case (Dekker's product via fma).
+struct HDD {
+  double h, l;
+};
+HDD hdd_add(HDD a, HDD b) {
+  const double s = a.h + b.h, bb = s - a.h;
+  double e = (a.h - (s - bb)) + (b.h - bb) + a.l + b.l;
+  const double r = s + e;
+  return {r, e - (r - s)};
+}
+HDD hdd_mul(HDD a, HDD b) {
+  const double p = a.h * b.h;
+  const double e = fma(a.h, b.h, -p) + a.h * b.l + a.l * b.h;
+  const double r = p + e;
+  return {r, e - (r - p)};
+}
+HDD hdd_div(HDD a, HDD b) {
+  const double q1 = a.h / b.h;
+  const HDD r = hdd_add(a, hdd_mul({-q1, 0.0}, b));
+  const double q2 = r.h / b.h;
+  const double s = q1 + q2;
+  return {s, q2 - (s - q1)};
+}
+HDD hdd_sqrt(HDD a) {
+  if (!(a.h > 0)) return {0.0, 0.0};
+  const double r0 = sqrt(a.h);
+  const HDD d = hdd_add(a, hdd_mul({-r0, 0.0}, {r0, 0.0}));
+  const double c = d.h / (2.0 * r0);
+  const double s = r0 + c;
+  return {s, c - (s - r0)};
+}
+
+DDWork carve_dd(void* base, int n, const sr_opts* o) {
+  DDWork w;
+  uintptr_t p = (uintptr_t)base;
+  auto take = [&](size_t b) {
+    void* r = (void*)p;
+    p += align256(b);
+    return r;
+  };
+  const size_t z = (size_t)n * n * sizeof(zc);
+  w.Qh = (zc*)take(z);
+  w.Ql = (zc*)take(z);
+  w.Ph = (zc*)take(z);
+  w.Pl = (zc*)take(z);
+  w.Yh = (zc*)take(z);
+  w.Yl = (zc*)take(z);
+  w.Dh = (zc*)take(z);
+  w.Dl = (zc*)take(z);
+  w.Tlp = (zc*)take(z);
+  w.Elp = (zc*)take(z);
+  w.L = (zc*)take(z);
+  w.W = (zc*)take(z);
+  w.W2 = (zc*)take(z);
+  w.W3 = (zc*)take(z);
+  w.YW = (zc*)take(z);
+  w.S = dd_main_slices(o);
+  int Su = w.S > kDDMaxUpd ? w.S : kDDMaxUpd;
+  if (o && o->update_slices > 0) Su = o->update_slices;
+  w.sA = (int8_t*)take(oz_slice_bytes(n, n, w.S));
+  w.sQc = (int8_t*)take(oz_slice_bytes(n, n, w.S));
+  w.sP = (int8_t*)take(oz_slice_bytes(n, n, w.S));
+  w.sQr = (int8_t*)take(oz_slice_bytes(n, n, Su));
+  w.sD = (int8_t*)take(oz_slice_bytes(n, n, Su));
+  w.eA = (int*)take(n * sizeof(int));
+  w.eQc = (int*)take(n * sizeof(int));
+  w.eP = (int*)take(n * sizeof(int));
+  w.eQr = (int*)take(n * sizeof(int));
+  w.eD = (int*)take(n * sizeof(int));
+  w.scratch = take(oz_gemm_scratch_bytes(n, n, true));
+  int np = oz_gemm_tiles(n, n, true);
+  if (form_w_parts(n) > np) np = form_w_parts(n);
+  if (np < 1024) np = 1024;
+  w.partials = (double*)take((size_t)np * sizeof(double));
+  w.scal = (double*)take(256);
+  w.status = (unsigned*)take(256);
+  w.tri = take(trisolve_ws_bytes(n));
+  w.bytes = (size_t)(p - (uintptr_t)base);
+  return w;
+}
+
+int read_back_dd(hipStream_t st, const DDWork& w, int count, double* out, unsigned* status) {
+  Work v;
+  memset(&v, 0, sizeof(v));
+  v.scal = w.scal;
+  v.status = w.status;
+  return read_back(st, v, count, out, status);
+}
+
+// Digits per operand of Q Delta in the double-double tier. By default the same as
+// the other hp products: the digits of Q are relative to its row maxima, and the
+// Schur vectors of a badly scaled matrix have entries far below them, which need
+// the full count. update_slices = -1 takes the count from ||Delta|| as in the FP64
+// tier (for the unit roundoff 2^-104), which suffices for well-scaled matrices.
+int dd_update_slices(const sr_opts& o, int S, double norm_delta) {
+  if (o.update_slices > 0) return o.update_slices;
+  if (o.update_slices == 0) return S;
+  if (!(norm_delta > 0)) return 2;
+  int s = (int)ceil(log2(norm_delta / (0.05 * kUDD)) / 7.0) + 1;
+  if (s < 2) s = 2;
+  if (s > kDDMaxUpd) s = kDDMaxUpd;
+  return s;
+}
+
+GemmArgs dd_args(int n, zc* Ch, zc* Cl) {
+  GemmArgs g = gargs(n, n, n, nullptr, 0, nullptr, 0, Ch, n);
+  g.Clo = Cl;
+  return g;
+}
+
+// Qout = Q + Q D in double-double from Su digits per operand.
+int dd_update(const zc* Qh, const zc* Ql, zc* Oh, zc* Ol, int n, int Su, const DDWork& w,
+              hipStream_t st) {
+  CK(oz_split_rows(Qh, Ql, n, n, n, Su, w.sQr, w.eQr, st));
+  CK(oz_split_cols(w.Dh, w.Dl, n, n, n, Su, w.sD, w.eD, st));
+  GemmArgs u = dd_args(n, Oh, Ol);
+  u.Cin = Qh;
+  u.Cinlo = Ql;
+  u.ldcin = n;
+  CK(oz_gemm(EPI_ADD, w.sQr, w.eQr, Su, w.sD, w.eD, Su, 0, Su + 1, u, w.scratch, st, true));
+  return SR_OK;
+}
+
+// Y = Q^H Q - I (DD) from the column slices of Q in w.sQc; scal[2] = ||Y||^2.
+int dd_ydef(int n, const DDWork& w, hipStream_t st) {
+  GemmArgs g = dd_args(n, w.Yh, w.Yl);
+  g.partials = w.partials;
+  CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, w.S, w.sQc, w.eQc, w.S, 1, w.S + 1, g, w.scratch, st, true));
+  CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, true), w.scal + 2, st));
+  return SR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, void* T_hi,
+                    void* T_lo, int n, int iters, double tol, const sr_opts* opts_in,
+                    sr_info* info) {
   info_init(info);
-  if (info) info->status = SR_ENOSYS;
-  return SR_ENOSYS;
+  if (!A_hi || !A_lo || !Q_hi || !Q_lo || !T_hi || !T_lo || n < 1 || iters < 1 || !(tol > 0)) {
+    if (info) info->status = SR_EINVAL;
+    return SR_EINVAL;
+  }
+  sr_opts o;
+  if (opts_in) o = *opts_in;
+  else sr_default_opts(&o);
+  if (o.slices < 0 || o.slices > 32 || o.update_slices < -1 || o.update_slices > 32) {
+    if (info) info->status = SR_EINVAL;
+    return SR_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)o.stream;
+  const zc* Ah = (const zc*)A_hi;
+  const zc* Al = (const zc*)A_lo;
+  zc* Th = (zc*)T_hi;
+  zc* Tl = (zc*)T_lo;
+  if (n == 1) {
+    // T = A, Q = q / |q| in double-double arithmetic on the host
+    zc v[4];
+    CK(hipMemcpyAsync(&v[0], Ah, sizeof(zc), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(&v[1], Al, sizeof(zc), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(&v[2], Q_hi, sizeof(zc), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(&v[3], Q_lo, sizeof(zc), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    const HDD qr = hdd_add({v[2].re, 0.0}, {v[3].re, 0.0});
+    const HDD qi = hdd_add({v[2].im, 0.0}, {v[3].im, 0.0});
+    const HDD m = hdd_sqrt(hdd_add(hdd_mul(qr, qr), hdd_mul(qi, qi)));
+    if (!(m.h > 0) || !isfinite(m.h) || !isfinite(v[0].re) || !isfinite(v[0].im)) {
+      if (info) info->status = SR_BREAKDOWN;
+      return SR_BREAKDOWN;
+    }
+    const HDD ur = hdd_div(qr, m), ui = hdd_div(qi, m);
+    zc out[2] = {mk<double>(ur.h, ui.h), mk<double>(ur.l, ui.l)};
+    CK(hipMemcpyAsync(T_hi, &v[0], sizeof(zc), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(T_lo, &v[1], sizeof(zc), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(Q_hi, &out[0], sizeof(zc), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(Q_lo, &out[1], sizeof(zc), hipMemcpyHostToDevice, st));
+    CK(hipStreamSynchronize(st));
+    if (info) {
+      info->status = SR_OK;
+      info->iters = 1;
+    }
+    return SR_OK;
+  }
+  void* base = nullptr;
+  int rc = get_ws(o, sr_workspace_bytes_dd(n, &o), &base);
+  if (rc != SR_OK) {
+    if (info) info->status = rc;
+    return rc;
+  }
+  const DDWork w = carve_dd(base, n, &o);
+  const int S = w.S;
+
+  Timer timer;
+  timer.st = st;
+  Timer* tm = o.timing ? &timer : nullptr;
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  CK(hipEventRecord(e0, st));
+  CK(fill_zero(w.status, 256, st));
+  CK(fro2_partials(Ah, (long)n * n, w.partials, 1024, st));
+  CK(reduce_partials(w.partials, 1024, w.scal, st));
+  CK(oz_split_rows(Ah, Al, n, n, n, S, w.sA, w.eA, st));
+
+  // Newton-Schulz start from Q-hat = (Q_hi, Q_lo)
+  zc* curh = w.Qh;
+  zc* curl = w.Ql;
+  zc* othh = (zc*)Q_hi;
+  zc* othl = (zc*)Q_lo;
+  TIC(tm, 0);
+  CK(oz_split_cols(othh, othl, n, n, n, S, w.sQc, w.eQc, st));
+  if ((rc = dd_ydef(n, w, st)) != SR_OK) return rc;
+  TOC(tm, 0);
+  double nrm[4] = {0, 0, 0, 0};
+  unsigned dst = 0;
+  if ((rc = read_back_dd(st, w, 3, nrm, &dst)) != SR_OK) return rc;
+  CK(form_delta_dd(nullptr, w.Yh, w.Yl, nullptr, nullptr, nullptr, w.Dh, w.Dl, n, st));
+  int su = dd_update_slices(o, S, 0.5 * sqrt(nrm[2]));
+  if (info) info->update_slices_hist[0] = su;
+  TIC(tm, 0);
+  if ((rc = dd_update(othh, othl, curh, curl, n, su, w, st)) != SR_OK) return rc;
+  TOC(tm, 0);
+
+  int status = SR_NOT_CONVERGED, passes = 0, updates = 0, nprod = 0;
+  double eps = 0, eps1 = -1, eps2 = -1, orth = 0;
+  for (int p = 0; p < iters; p++) {
+    TIC(tm, 0);
+    CK(oz_split_cols(curh, curl, n, n, n, S, w.sQc, w.eQc, st));
+    {
+      GemmArgs g = dd_args(n, w.Ph, w.Pl);
+      CK(oz_gemm(EPI_STORE, w.sA, w.eA, S, w.sQc, w.eQc, S, 0, S + 1, g, w.scratch, st, true));
+    }
+    TOC(tm, 0);
+    TIC(tm, 0);
+    CK(oz_split_cols(w.Ph, w.Pl, n, n, n, S, w.sP, w.eP, st));
+    {
+      GemmArgs g = dd_args(n, Th, Tl);
+      g.Tlp64 = w.Tlp;
+      g.Elp64 = w.Elp;
+      g.ldlp = n;
+      g.partials = w.partials;
+      CK(oz_gemm(EPI_SPLIT, w.sQc, w.eQc, S, w.sP, w.eP, S, 1, S + 1, g, w.scratch, st, true));
+    }
+    TOC(tm, 0);
+    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, true), w.scal + 1, st));
+    double s2[2];
+    if ((rc = read_back_dd(st, w, 2, s2, &dst)) != SR_OK) return rc;
+    eps = sqrt(s2[1]) / sqrt(s2[0]);
+    passes = p + 1;
+    if (info && p < 16) info->resid_hist[p] = eps;
+    if (!isfinite(eps)) {
+      status = SR_BREAKDOWN;
+      break;
+    }
+    if (eps <= tol) {
+      status = SR_OK;
+      break;
+    }
+    if (eps2 >= 0 && eps > eps1 && eps1 > eps2) {
+      status = SR_DIVERGED;
+      break;
+    }
+    if (eps1 >= 0 && eps > 0.5 * eps1 && eps < 100.0 * kUDD * sqrt((double)n)) {
+      status = SR_STAGNATED;
+      break;
+    }
+    eps2 = eps1;
+    eps1 = eps;
+    if (p == iters - 1) break;
+
+    TIC(tm, 1);
+    CK(trisolve64(w.Tlp, w.Elp, w.L, n, w.tri, w.status, st));
+    TOC(tm, 1);
+    TIC(tm, 0);
+    if ((rc = dd_ydef(n, w, st)) != SR_OK) return rc;
+    TOC(tm, 0);
+    CK(form_w64(w.L, w.W, n, w.partials, st));
+    CK(reduce_partials(w.partials, form_w_parts(n), w.scal + 3, st));
+    if ((rc = read_back_dd(st, w, 4, nrm, &dst)) != SR_OK) return rc;
+    if (dst & DEV_BREAKDOWN) {
+      status = SR_BREAKDOWN;
+      break;
+    }
+    const double ny = sqrt(nrm[2]), nw = sqrt(nrm[3]);
+    orth = ny;
+    if (info && updates < 16) info->norm_w_hist[updates] = nw;
+    if (!isfinite(ny) || !isfinite(nw)) {
+      status = SR_BREAKDOWN;
+      break;
+    }
+    // lp products in FP64, gated against the double-double roundoff
+    const double thr = 0.1 * kUDD;
+    const bool gw2 = !o.gate_lp_terms || nw * nw > thr;
+    const bool gw3 = !o.gate_lp_terms || nw * nw * nw > thr;
+    const bool gyw = !o.gate_lp_terms || ny * nw > thr;
+    if (gw2 || gw3) {
+      CK(zgemm(0, EPI_STORE, 0, gargs(n, n, n, w.W, n, w.W, n, w.W2, n), st));
+      nprod++;
+    }
+    if (gw3) {
+      CK(zgemm(0, EPI_STORE, 0, gargs(n, n, n, w.W2, n, w.W, n, w.W3, n), st));
+      nprod++;
+    }
+    if (gyw) {
+      CK(zgemm(0, EPI_STORE, 0, gargs(n, n, n, w.Yh, n, w.W, n, w.YW, n), st));
+      nprod++;
+    }
+    CK(form_delta_dd(w.L, w.Yh, w.Yl, gw2 ? w.W2 : nullptr, gw3 ? w.W3 : nullptr,
+                     gyw ? w.YW : nullptr, w.Dh, w.Dl, n, st));
+    su = dd_update_slices(o, S, nw + 0.5 * ny);
+    if (info && updates + 1 < 16) info->update_slices_hist[updates + 1] = su;
+    TIC(tm, 0);
+    if ((rc = dd_update(curh, curl, othh, othl, n, su, w, st)) != SR_OK) return rc;
+    TOC(tm, 0);
+    zc* t = curh;
+    curh = othh;
+    othh = t;
+    t = curl;
+    curl = othl;
+    othl = t;
+    updates++;
+  }
+  if (curh != (zc*)Q_hi) {
+    CK(hipMemcpyAsync(Q_hi, curh, (size_t)n * n * sizeof(zc), hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(Q_lo, curl, (size_t)n * n * sizeof(zc), hipMemcpyDeviceToDevice, st));
+  }
+  CK(hipEventRecord(e1, st));
+  CK(hipEventSynchronize(e1));
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (info) {
+    info->status = status;
+    info->iters = passes;
+    info->updates = updates;
+    info->hp_gemms = 2 + 4 * updates + 2 * (passes - updates);
+    info->lp_products = nprod;
+    info->resid = eps;
+    info->orth = orth;
+    info->ms_total = ms;
+    if (tm) {
+      info->ms_hp_gemm = timer.total(0);
+      info->hp_gemm_launches = timer.count[0];
+      info->ms_solve = timer.total(1);
+    }
+  }
+  return status;
+}
+
+size_t sr_workspace_bytes_dd(int n, const sr_opts* opts) {
+  if (n < 1) return 0;
+  return carve_dd(nullptr, n, opts).bytes + 256;
 }
 
 int sr_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
@@ -519,10 +1000,12 @@ int sr_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B
 size_t sr_ozaki_ws_bytes(int m, int n, int k, int slices_a, int slices_b) {
   if (m < 0 || n < 0 || k < 0 || slices_a < 1 || slices_b < 1) return 0;
   return align256(oz_slice_bytes(m, k, slices_a)) + align256(oz_slice_bytes(n, k, slices_b)) +
-         align256((size_t)(m + n) * sizeof(int));
+         align256((size_t)(m + n) * sizeof(int)) + align256(oz_gemm_scratch_bytes(m, n, true));
 }
 
 // Largest slice-pair count on one diagonal times k must keep int32 sums exact.
+// (the large-tile kernel sums two products per accumulator and folds long
+// diagonals in segments, so it only needs 2 * 64 K-steps per segment bounded).
 static bool oz_exact_ok(int k, int sa, int sb) {
   const long pairs = sa < sb ? sa : sb;
   const long kp = (k + 63) / 64 * 64;
@@ -545,13 +1028,55 @@ int sr_ozaki_zgemm(int opa, int m, int n, int k, const void* A, int lda, const v
   int8_t* qb = qa + align256(oz_slice_bytes(m, k, slices_a));
   int* ea = (int*)(qb + align256(oz_slice_bytes(n, k, slices_b)));
   int* eb = ea + m;
+  void* scr = (int8_t*)ea + align256((size_t)(m + n) * sizeof(int));
   if (opa == 0) CK(oz_split_rows((const zc*)A, nullptr, lda, m, k, slices_a, qa, ea, st));
   else CK(oz_split_cols((const zc*)A, nullptr, lda, k, m, slices_a, qa, ea, st));
   CK(oz_split_cols((const zc*)B, nullptr, ldb, k, n, slices_b, qb, eb, st));
   GemmArgs g = gargs(m, n, k, nullptr, 0, nullptr, 0, C, ldc);
   g.Cin = Cin;
   g.ldcin = ldcin;
-  CK(oz_gemm(Cin ? EPI_ADD : EPI_STORE, qa, ea, slices_a, qb, eb, slices_b, opa, dmax, g, st));
+  CK(oz_gemm(Cin ? EPI_ADD : EPI_STORE, qa, ea, slices_a, qb, eb, slices_b, opa, dmax, g, scr, st));
+  return SR_OK;
+}
+
+int sr_ozaki_zgemm_dd(int opa, int m, int n, int k, const void* A_hi, const void* A_lo, int lda,
+                      const void* B_hi, const void* B_lo, int ldb, const void* Cin_hi,
+                      const void* Cin_lo, int ldcin, void* C_hi, void* C_lo, int ldc,
+                      int slices_a, int slices_b, int dmax, void* ws, size_t ws_bytes,
+                      void* stream) {
+  if (m < 0 || n < 0 || k < 0 || (opa != 0 && opa != 1) || !C_hi || !C_lo) return SR_EINVAL;
+  if (slices_a < 1 || slices_b < 1 || slices_a > 32 || slices_b > 32 || dmax < 2) return SR_EINVAL;
+  if (m == 0 || n == 0) return SR_OK;
+  if (k > 0 && (!A_hi || !B_hi)) return SR_EINVAL;
+  if (lda < (opa ? (k > 1 ? k : 1) : (m > 1 ? m : 1)) || ldb < (k > 1 ? k : 1) || ldc < m) return SR_EINVAL;
+  if (Cin_hi && ldcin < m) return SR_EINVAL;
+  if (Cin_hi && !Cin_lo && ldcin != ldc) return SR_EINVAL;
+  if (!ws || ws_bytes < sr_ozaki_ws_bytes(m, n, k, slices_a, slices_b)) return SR_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int8_t* qa = (int8_t*)ws;
+  int8_t* qb = qa + align256(oz_slice_bytes(m, k, slices_a));
+  int* ea = (int*)(qb + align256(oz_slice_bytes(n, k, slices_b)));
+  int* eb = ea + m;
+  void* scr = (int8_t*)ea + align256((size_t)(m + n) * sizeof(int));
+  if (opa == 0) CK(oz_split_rows((const zc*)A_hi, (const zc*)A_lo, lda, m, k, slices_a, qa, ea, st));
+  else CK(oz_split_cols((const zc*)A_hi, (const zc*)A_lo, lda, k, m, slices_a, qa, ea, st));
+  CK(oz_split_cols((const zc*)B_hi, (const zc*)B_lo, ldb, k, n, slices_b, qb, eb, st));
+  GemmArgs g = gargs(m, n, k, nullptr, 0, nullptr, 0, C_hi, ldc);
+  g.Clo = C_lo;
+  const zc* zero_lo = nullptr;
+  if (Cin_hi) {
+    g.Cin = Cin_hi;
+    g.ldcin = ldcin;
+    if (!Cin_lo) {
+      // a zero low part: C_lo itself, cleared (each element is read before the
+      // same thread overwrites it)
+      CK(fill_zero(C_lo, (size_t)ldc * n * sizeof(zc), st));
+      zero_lo = (const zc*)C_lo;
+    }
+    g.Cinlo = Cin_lo ? Cin_lo : zero_lo;
+  }
+  CK(oz_gemm(Cin_hi ? EPI_ADD : EPI_STORE, qa, ea, slices_a, qb, eb, slices_b, opa, dmax, g, scr, st,
+             true));
   return SR_OK;
 }
 
@@ -592,6 +1117,19 @@ int sr_trisolve(const void* T_lp, const void* E_lp, void* L_lp, int n, float tru
   Work w = carve(ws, n);
   CK(fill_zero(w.status, 256, st));
   CK(trisolve((const cc*)T_lp, (const cc*)E_lp, (cc*)L_lp, n, trunc, w.tri, w.status, st));
+  double s[1];
+  unsigned d = 0;
+  int rc = read_back(st, w, 1, s, &d);
+  if (rc != SR_OK) return rc;
+  return (d & DEV_BREAKDOWN) ? SR_BREAKDOWN : SR_OK;
+}
+
+int sr_trisolve64(const void* T, const void* E, void* L, int n, void* ws, void* stream) {
+  if (!T || !E || !L || !ws || n < 1) return SR_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  Work w = carve(ws, n);
+  CK(fill_zero(w.status, 256, st));
+  CK(trisolve64((const zc*)T, (const zc*)E, (zc*)L, n, w.tri, w.status, st));
   double s[1];
   unsigned d = 0;
   int rc = read_back(st, w, 1, s, &d);

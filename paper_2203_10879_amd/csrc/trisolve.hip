@@ -1,5 +1,7 @@
-// Triangular matrix equation stril(T L - L T) = -E in FP32 (Section 2.1,
-// eqs. (7)-(10)): the low-precision solve of every refinement pass.
+// Triangular matrix equation stril(T L - L T) = -E (Section 2.1, eqs. (7)-(10)):
+// the low-precision solve of every refinement pass, in FP32 (complex64) for the
+// FP64 tier and in FP64 (complex128) for the double-double tier. The code below is
+// written once for both element types.
 //
 // Entry (i, j), i > j, reads
 //   l_ij = -( e_ij + sum_{k>i} t_ik l_kj - sum_{k<j} l_ik t_kj ) / (t_ii - t_jj),
@@ -37,12 +39,15 @@ namespace sr {
 #endif
 constexpr int TB = SR_TRI_TB;
 constexpr int TNT = TB * TB;  // one thread per tile entry
-constexpr int TLD = TB + 1;   // LDS column stride (complex64 elements)
+constexpr int TLD = TB + 1;   // LDS column stride (elements)
 constexpr int kTargetBlocks = 2 * kCUs;
 constexpr int kTileElems = TB * TB;
 
 // ok ? v : 0, component-wise (a struct-valued select would go through scratch).
-__device__ inline cc keep(bool ok, cc v) { return mk<float>(ok ? v.re : 0.f, ok ? v.im : 0.f); }
+template <typename R>
+__device__ inline cplx<R> keep(bool ok, cplx<R> v) {
+  return mk<R>(ok ? v.re : R(0), ok ? v.im : R(0));
+}
 
 // Column ownership (products, partial sums): thread t owns entry (t mod 32, t / 32).
 struct Own {
@@ -57,27 +62,29 @@ __device__ inline Own owner() {
 
 // LDS tile, column-major with padded stride: S[q * TLD + p] = G(I*TB + p, J*TB + q),
 // zero outside the n x n matrix.
-__device__ inline void load_tile(cc* S, const cc* __restrict__ G, int n, int I, int J) {
+template <typename C>
+__device__ inline void load_tile(C* S, const C* __restrict__ G, int n, int I, int J) {
   const int p = threadIdx.x & (TB - 1), q = threadIdx.x / TB;
   const int gi = I * TB + p, gj = J * TB + q;
   const bool ok = gi < n && gj < n;
-  const cc v = G[ok ? gi + (long)gj * n : 0];
+  const C v = G[ok ? gi + (long)gj * n : 0];
   S[q * TLD + p] = keep(ok, v);
 }
 
-template <int SIGN>
-__device__ inline void tile_mac(cc& acc, const cc* F, const cc* G, Own o) {
+template <int SIGN, typename C>
+__device__ inline void tile_mac(C& acc, const C* F, const C* G, Own o) {
 #pragma unroll 8
   for (int k = 0; k < TB; k++) {
-    const cc a = F[k * TLD + o.p], b = G[o.q * TLD + k];
+    const C a = F[k * TLD + o.p], b = G[o.q * TLD + k];
     if (SIGN > 0) cfma(acc, a, b);
     else cfms(acc, a, b);
   }
 }
 
 // acc += one block product of tile (I, J): + T_IK L_KJ (typeA) or - L_IK T_KJ.
-__device__ inline void block_product(cc& acc, const cc* T, const cc* L, int n, int I, int J, int K,
-                                     bool typeA, cc* S1, cc* S2, Own o) {
+template <typename C>
+__device__ inline void block_product(C& acc, const C* T, const C* L, int n, int I, int J, int K,
+                                     bool typeA, C* S1, C* S2, Own o) {
   __syncthreads();
   if (typeA) {
     load_tile(S1, T, n, I, K);
@@ -92,16 +99,18 @@ __device__ inline void block_product(cc& acc, const cc* T, const cc* L, int n, i
 }
 
 // All block products of tile (I, J) (K = I+1..nb-1 of type A, K = 0..J-1 of type B).
-__device__ void all_products(cc& acc, const cc* T, const cc* L, int n, int nb, int I, int J, cc* S1,
-                             cc* S2, Own o) {
+template <typename C>
+__device__ void all_products(C& acc, const C* T, const C* L, int n, int nb, int I, int J, C* S1,
+                             C* S2, Own o) {
   for (int K = I + 1; K < nb; K++) block_product(acc, T, L, n, I, J, K, true, S1, S2, o);
   for (int K = 0; K < J; K++) block_product(acc, T, L, n, I, J, K, false, S1, S2, o);
 }
 
-__device__ inline void add_e(cc& acc, const cc* __restrict__ E, int n, int I, int J, Own o) {
+template <typename C>
+__device__ inline void add_e(C& acc, const C* __restrict__ E, int n, int I, int J, Own o) {
   const int gi = I * TB + o.p, gj = J * TB + o.q;
   const bool ok = gi < n && gj < n && gi > gj;
-  const cc v = E[ok ? gi + (long)gj * n : 0];
+  const C v = E[ok ? gi + (long)gj * n : 0];
   if (ok) {
     acc.re += v.re;
     acc.im += v.im;
@@ -128,7 +137,7 @@ __device__ inline void diag_rank(int r, int& p, int& q) {
   }
 }
 
-// LDS layouts of the solve (complex64 elements):
+// LDS layouts of the solve (elements):
 //   TaP: T_II column-major, 63 columns of stride TLD, columns 32..62 zero, so that
 //        Ta(p, q+s) is addressable for every q + s <= 62;
 //   TbP: T_JJ (T_II on a diagonal tile) column-major with stride 64 and a row
@@ -155,26 +164,29 @@ constexpr int kSolveS2 = TB * kTbLd;     // elements of the second LDS buffer
 // with operands that read as zero where the entry does not exist, and addresses
 // that move by a constant per step. Waves whose entries are all final skip the
 // update.
-__device__ void tile_solve(cc acc, const cc* T, cc* L, int n, int I, int J, float trunc,
-                           unsigned* status, cc* TaP, cc* TbP, cc* R, Own o) {
-  __shared__ cc dv[2][2 * TB];
+template <typename Rl>
+__device__ void tile_solve(cplx<Rl> acc, const cplx<Rl>* T, cplx<Rl>* L, int n, int I, int J,
+                           float trunc, unsigned* status, cplx<Rl>* TaP, cplx<Rl>* TbP,
+                           cplx<Rl>* R, Own o) {
+  using C = cplx<Rl>;
+  __shared__ C dv[2][2 * TB];
   __shared__ int wave_min_d[TNT / 64];
   const bool diag = (I == J);
-  const cc z = mk<float>(0.f, 0.f);
+  const C z = mk<Rl>(0, 0);
   __syncthreads();
   {
     // TaP columns 0..31 from T_II, 32..62 zero
     const int p = threadIdx.x & (TB - 1), c = threadIdx.x / TB;
     const int gi = I * TB + p, gj = I * TB + c;
     const bool ok = gi < n && gj < n;
-    const cc v = T[ok ? gi + (long)gj * n : 0];
+    const C v = T[ok ? gi + (long)gj * n : 0];
     TaP[c * TLD + p] = keep(ok, v);
     if (c < TB - 1) TaP[(TB + c) * TLD + p] = z;
     // TbP rows -31..31 of column c (offset 31), rows < 0 zero
     const int K = diag ? I : J;
     const int gk = K * TB + p, gc = K * TB + c;
     const bool okb = gk < n && gc < n;
-    const cc w = T[okb ? gk + (long)gc * n : 0];
+    const C w = T[okb ? gk + (long)gc * n : 0];
     TbP[c * kTbLd + (TB - 1) + p] = keep(okb, w);
     if (p < TB - 1) TbP[c * kTbLd + p] = z;
     if (threadIdx.x < 2 * TB) {
@@ -194,18 +206,18 @@ __device__ void tile_solve(cc acc, const cc* T, cc* L, int n, int I, int J, floa
     if ((threadIdx.x & 63) == 0) wave_min_d[threadIdx.x >> 6] = md;
   }
   __syncthreads();
-  cc a = R[q * TLD + p];
+  C a = R[q * TLD + p];
   const int wmin = wave_min_d[threadIdx.x >> 6];
   bool bad = false;
-  cc rd = z;
+  C rd = z;
   {
-    const cc ta = TaP[p * TLD + p], tb = TbP[q * kTbLd + (TB - 1) + q];
-    const float dr = ta.re - tb.re, di = ta.im - tb.im;
-    const float den = dr * dr + di * di;
-    if (live && den == 0.f) bad = true;
-    if (live) rd = mk<float>(dr / den, -di / den);
+    const C ta = TaP[p * TLD + p], tb = TbP[q * kTbLd + (TB - 1) + q];
+    const Rl dr = ta.re - tb.re, di = ta.im - tb.im;
+    const Rl den = dr * dr + di * di;
+    if (live && den == Rl(0)) bad = true;
+    if (live) rd = mk<Rl>(dr / den, -di / den);
   }
-  const float trunc2 = trunc * trunc;
+  const Rl trunc2 = (Rl)trunc * (Rl)trunc;
   const int smin = diag ? 1 : -(TB - 1);
   const long gaddr = (I * TB + p) + (long)(J * TB + q) * n;
   // operand indices at s = TB - 1; per step: ta -= TLD, xb += 1, tb += 1
@@ -213,19 +225,19 @@ __device__ void tile_solve(cc acc, const cc* T, cc* L, int n, int I, int J, floa
   int xb_i = TB + p - (TB - 1);
   int tb_i = q * kTbLd + p;
   const int r = threadIdx.x;  // column whose dv slot this thread clears when absent
-  cc xf = z;                  // this thread's entry of L once finalized
+  C xf = z;                   // this thread's entry of L once finalized
   // The loop touches LDS only: a global store inside it would make every barrier
   // (a workgroup release) wait for that store to complete.
   for (int s = TB - 1; s >= smin; s--) {
-    cc* cur = dv[s & 1];
+    C* cur = dv[s & 1];
     if (d == s) {
-      cc x = z;
+      C x = z;
       if (live) {
         x = cmul(a, rd);
         x.re = -x.re;
         x.im = -x.im;
         bad |= !isfinite(x.re) || !isfinite(x.im);
-        if (trunc2 > 0.f && x.re * x.re + x.im * x.im > trunc2) x = z;
+        if (trunc2 > Rl(0) && x.re * x.re + x.im * x.im > trunc2) x = z;
       }
       xf = x;
       cur[TB + q] = x;
@@ -233,8 +245,8 @@ __device__ void tile_solve(cc acc, const cc* T, cc* L, int n, int I, int J, floa
     if (r < TB && (r + s > TB - 1 || r + s < 0)) cur[TB + r] = z;
     __syncthreads();
     if (wmin < s && d < s) {
-      const cc xa = cur[TB + q], xb = cur[xb_i];
-      const cc ta = TaP[ta_i], tb = TbP[tb_i];
+      const C xa = cur[TB + q], xb = cur[xb_i];
+      const C ta = TaP[ta_i], tb = TbP[tb_i];
       cfma(a, ta, xa);
       cfms(a, xb, tb);
     }
@@ -246,30 +258,33 @@ __device__ void tile_solve(cc acc, const cc* T, cc* L, int n, int I, int J, floa
   if (bad) atomicOr(status, (unsigned)DEV_BREAKDOWN);
 }
 
+template <typename Rl>
 struct TriLevelArgs {
-  const cc* T;
-  const cc* E;
-  cc* L;
+  const cplx<Rl>* T;
+  const cplx<Rl>* E;
+  cplx<Rl>* L;
   int n, nb, D;
   int S_cur;         // partial blocks per tile that wrote diagonal D's far sums
   int S_next;        // partial blocks per tile for diagonal D - 1 (0: none)
-  const cc* part_cur;  // [tiles(D)][S_cur][TB*TB]
-  cc* part_next;       // [tiles(D-1)][S_next][TB*TB]
+  const cplx<Rl>* part_cur;  // [tiles(D)][S_cur][TB*TB]
+  cplx<Rl>* part_next;       // [tiles(D-1)][S_next][TB*TB]
   unsigned* status;
   float trunc;
 };
 
-__global__ __launch_bounds__(TNT) void trisolve_level_kernel(TriLevelArgs a) {
-  __shared__ cc S1[kSolveS1], S2[kSolveS2], S3[TB * TLD];
+template <typename Rl>
+__global__ __launch_bounds__(TNT) void trisolve_level_kernel(TriLevelArgs<Rl> a) {
+  using C = cplx<Rl>;
+  __shared__ C S1[kSolveS1], S2[kSolveS2], S3[TB * TLD];
   const Own o = owner();
   const int tiles = a.nb - a.D;
-  cc acc = mk<float>(0.f, 0.f);
+  C acc = mk<Rl>(0, 0);
   if ((int)blockIdx.x < tiles) {
     // solve block for tile (D + t, t)
     const int t = blockIdx.x, I = a.D + t, J = t;
     add_e(acc, a.E, a.n, I, J, o);
     for (int s = 0; s < a.S_cur; s++) {
-      const cc v = a.part_cur[((long)t * a.S_cur + s) * kTileElems + o.p + o.q * TB];
+      const C v = a.part_cur[((long)t * a.S_cur + s) * kTileElems + o.p + o.q * TB];
       acc.re += v.re;
       acc.im += v.im;
     }
@@ -292,25 +307,28 @@ __global__ __launch_bounds__(TNT) void trisolve_level_kernel(TriLevelArgs a) {
   a.part_next[((long)t2 * a.S_next + s) * kTileElems + o.p + o.q * TB] = acc;
 }
 
+template <typename Rl>
 struct TriMatrix {
-  const cc* T;
-  const cc* E;
-  cc* L;
+  const cplx<Rl>* T;
+  const cplx<Rl>* E;
+  cplx<Rl>* L;
   int n;
 };
 
 // One block per matrix walks every tile diagonal; used for small n and batches.
-__global__ __launch_bounds__(TNT) void trisolve_single_kernel(const TriMatrix* __restrict__ mats,
-                                                              TriMatrix one, unsigned* status,
+template <typename Rl>
+__global__ __launch_bounds__(TNT) void trisolve_single_kernel(const TriMatrix<Rl>* __restrict__ mats,
+                                                              TriMatrix<Rl> one, unsigned* status,
                                                               float trunc) {
-  __shared__ cc S1[kSolveS1], S2[kSolveS2], S3[TB * TLD];
-  const TriMatrix mt = mats ? mats[blockIdx.x] : one;
+  using C = cplx<Rl>;
+  __shared__ C S1[kSolveS1], S2[kSolveS2], S3[TB * TLD];
+  const TriMatrix<Rl> mt = mats ? mats[blockIdx.x] : one;
   const int n = mt.n, nb = (n + TB - 1) / TB;
   const Own o = owner();
   for (int D = nb - 1; D >= 0; D--) {
     for (int t = 0; t < nb - D; t++) {
       const int I = D + t, J = t;
-      cc acc = mk<float>(0.f, 0.f);
+      C acc = mk<Rl>(0, 0);
       add_e(acc, mt.E, n, I, J, o);
       all_products(acc, mt.T, mt.L, n, nb, I, J, S1, S2, o);
       tile_solve(acc, mt.T, mt.L, n, I, J, trunc, status, S1, S2, S3, o);
@@ -334,8 +352,9 @@ static int splits(int nb, int D) {
   return S < 1 ? 1 : S;
 }
 
+// Partial-sum buffer of one parity, sized for complex128 (complex64 uses half).
 static size_t part_bytes(int nb) {
-  return (size_t)(kTargetBlocks + nb) * kTileElems * sizeof(cc);
+  return (size_t)(kTargetBlocks + nb) * kTileElems * sizeof(zc);
 }
 
 size_t trisolve_ws_bytes(int n) {
@@ -343,31 +362,43 @@ size_t trisolve_ws_bytes(int n) {
   return 2 * part_bytes(nb);
 }
 
-hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* ws,
-                    unsigned* status, hipStream_t st) {
-  if (n <= 1) return fill_zero(L, (size_t)n * n * sizeof(cc), st);
+template <typename Rl>
+static hipError_t trisolve_t(const cplx<Rl>* T, const cplx<Rl>* E, cplx<Rl>* L, int n, float trunc,
+                             void* ws, unsigned* status, hipStream_t st) {
+  using C = cplx<Rl>;
+  if (n <= 1) return fill_zero(L, (size_t)n * n * sizeof(C), st);
   const int nb = ceil_div(n, TB);
-  hipError_t e = fill_zero(L, (size_t)n * n * sizeof(cc), st);
+  hipError_t e = fill_zero(L, (size_t)n * n * sizeof(C), st);
   if (e != hipSuccess) return e;
   if (nb <= 2) {
-    TriMatrix one{T, E, L, n};
-    hipLaunchKernelGGL(trisolve_single_kernel, dim3(1), dim3(TNT), 0, st,
-                       (const TriMatrix*)nullptr, one, status, trunc);
+    TriMatrix<Rl> one{T, E, L, n};
+    hipLaunchKernelGGL(trisolve_single_kernel<Rl>, dim3(1), dim3(TNT), 0, st,
+                       (const TriMatrix<Rl>*)nullptr, one, status, trunc);
     return hipGetLastError();
   }
-  cc* part[2] = {(cc*)ws, (cc*)((char*)ws + part_bytes(nb))};
+  C* part[2] = {(C*)ws, (C*)((char*)ws + part_bytes(nb))};
   int S_cur = 0;  // the top diagonal has no far products
   for (int D = nb - 1; D >= 0; D--) {
     const int tiles = nb - D;
     const int S_next = D >= 1 ? splits(nb, D - 1) : 0;
     const int tiles_next = D >= 1 ? nb - D + 1 : 0;
-    TriLevelArgs a{T, E, L, n, nb, D, S_cur, S_next, part[D & 1], part[(D - 1) & 1], status, trunc};
-    hipLaunchKernelGGL(trisolve_level_kernel, dim3(tiles + tiles_next * S_next), dim3(TNT), 0, st, a);
+    TriLevelArgs<Rl> a{T, E, L, n, nb, D, S_cur, S_next, part[D & 1], part[(D - 1) & 1], status, trunc};
+    hipLaunchKernelGGL(trisolve_level_kernel<Rl>, dim3(tiles + tiles_next * S_next), dim3(TNT), 0, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     S_cur = S_next;
   }
   return hipSuccess;
+}
+
+hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* ws,
+                    unsigned* status, hipStream_t st) {
+  return trisolve_t<float>(T, E, L, n, trunc, ws, status, st);
+}
+
+hipError_t trisolve64(const zc* T, const zc* E, zc* L, int n, void* ws, unsigned* status,
+                      hipStream_t st) {
+  return trisolve_t<double>(T, E, L, n, 0.f, ws, status, st);
 }
 
 }  // namespace sr

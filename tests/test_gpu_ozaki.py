@@ -77,3 +77,51 @@ def test_ozaki_add_epilogue_and_validation(sr):
     assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, slices_a=2, slices_b=2, dmax=4, Cin=dev(c0)) == 0
     assert np.array_equal(host(c), c0 + a @ b)
     assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, slices_a=0, slices_b=2) == -1
+
+
+# Outputs with at least one 128 x 128 tile per CU (256 tiles) take the
+# large-tile kernel (two int32 accumulators per output, FP64 partial sums in
+# scratch between folds).
+
+@pytest.mark.parametrize("opa", [0, 1])
+def test_ozaki_large_tiles_exact_on_integers(sr, opa):
+    m, n, k = 2085, 2048, 130  # ragged rows, a ragged K-tile
+    rng = np.random.default_rng(90 + opa)
+    a = _gauss_int(rng, (k, m) if opa else (m, k))
+    b = _gauss_int(rng, (k, n))
+    c0 = _gauss_int(rng, (m, n))
+    c = empty(m, n)
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=2, slices_b=2, dmax=4, Cin=dev(c0)) == 0
+    ref = c0 + (a.conj().T if opa else a) @ b
+    assert np.array_equal(host(c), ref)
+
+
+def test_ozaki_large_tiles_segmented_diagonal(sr):
+    # k = 8256 gives 129 K-steps; the diagonal s + t = 9 of 8 x 8 slices then
+    # has 8 * 129 > 1024 steps and is folded in two segments
+    m = n = 2048
+    k = 8256
+    rng = np.random.default_rng(17)
+    a = _gauss_int(rng, (m, k))
+    b = _gauss_int(rng, (k, n))
+    c = empty(m, n)
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, slices_a=8, slices_b=8, dmax=9) == 0
+    rows = np.random.default_rng(3).choice(m, 48, replace=False)
+    assert np.array_equal(host(c)[rows], a[rows] @ b)
+
+
+@pytest.mark.parametrize("opa", [0, 1])
+def test_ozaki_large_tiles_fp64_faithful(sr, opa):
+    m = n = 2048
+    k = 192
+    rng = np.random.default_rng(40 + opa)
+    a = rand_c(rng, (k, m) if opa else (m, k))
+    b = rand_c(rng, (k, n))
+    c = empty(m, n)
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=8, slices_b=8, dmax=9) == 0
+    rows = np.random.default_rng(4).choice(m, 32, replace=False)
+    asub = np.asfortranarray(a[:, rows] if opa else a[rows])
+    chi, clo = oracle.gemm(asub, b, opa=opa).to_dd()
+    err = np.abs((host(c)[rows] - chi) - clo)
+    aa = np.abs(asub.conj().T if opa else asub)
+    assert np.all(err <= gemm_bound(aa, np.abs(b), k, U64))

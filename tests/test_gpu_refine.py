@@ -128,3 +128,67 @@ def test_batched_equals_single(sr):
         q1, t1, i1 = _refine(sr, m["A"], s)
         assert inf["iters"] == i1["iters"]
         assert np.array_equal(host(qd), q1) and np.array_equal(host(td), t1)
+
+
+@pytest.mark.parametrize("n", [64, 257])
+def test_ozaki_mode_converges(sr, n):
+    """Ozaki mode (P = A Q, the start's products and Q Delta on INT8 digits; That
+    and Y native FP64) reaches the same tolerance in the same number of passes."""
+    g = synth.schur_test_matrix(n, seed=300 + n)
+    qh = synth.lp_schur_start(g["A"])
+    q, t, info = _refine(sr, g["A"], qh, gemm="ozaki_i8")
+    _, _, ref = _refine(sr, g["A"], qh)
+    assert info["status"] == "OK", info
+    assert abs(info["iters"] - ref["iters"]) <= 1, (info, ref)
+    ev = oracle.evaluate(g["A"], q, t)
+    assert ev["stril"] <= 1e-15 and ev["orth"] <= 1e-12, ev
+    su = info["update_slices_hist"]
+    assert all(2 <= s <= 8 for s in su[: info["updates"] + 1]), su
+    # later updates need fewer digits (Delta shrinks quadratically)
+    assert su[info["updates"]] <= su[0], su
+
+
+def test_ozaki_mode_exact_hadamard(sr):
+    h = synth.hadamard_exact(256, seed=9)
+    qh = synth.perturbed_start(h["Q0"], seed=4, delta=1e-6)
+    q, t, info = _refine(sr, h["A"], qh, gemm="ozaki_i8", update_slices=4)
+    assert info["status"] == "OK", info
+    assert np.abs(np.diag(t) - h["lam"]).max() <= 1e-13
+    c = h["Q0"].real.T @ q
+    assert np.abs(c - np.diag(np.diag(c))).max() <= 1e-13
+
+
+def test_ozaki_mode_n1024_quad_rows(sr):
+    g = synth.schur_test_matrix(1024, seed=1)
+    a = g["A"]
+    qh = synth.lp_schur_start(a)
+    q, t, info = _refine(sr, a, qh, gemm="ozaki_i8")
+    assert info["status"] == "OK" and info["iters"] <= 5, info
+    rows = np.random.default_rng(20001).choice(1024, 64, replace=False)
+    ev = oracle.evaluate_rows(a, q, rows)
+    assert ev["stril"] <= 1e-15, ev
+    assert ev["orth"] <= 4 * U64 * np.sqrt(1024) * 10, ev
+
+
+def test_gemm_mode_validation(sr):
+    g = synth.schur_test_matrix(32, seed=5)
+    qh = synth.lp_schur_start(g["A"])
+    q, t = dev(qh), empty(32, 32)
+    assert sr.schur_refine(dev(g["A"]), q, t, gemm="ozaki_bf16")["rc"] == -4
+    assert sr.schur_refine(dev(g["A"]), q, t, gemm=7)["rc"] == -1
+    assert sr.schur_refine(dev(g["A"]), q, t, gemm="ozaki_i8", slices=17)["rc"] == -1
+    assert sr.schur_refine(dev(g["A"]), q, t, gemm="ozaki_i8", update_slices=9)["rc"] == -1
+    assert np.array_equal(host(q), qh)
+
+
+def test_ozaki_mode_n2048_large_tiles(sr):
+    """n = 2048: every Ozaki product takes the large-tile kernel."""
+    g = synth.schur_test_matrix(2048, seed=6, gap=0.01)
+    a = g["A"]
+    qh = synth.lp_schur_start(a)
+    q, t, info = _refine(sr, a, qh, gemm="ozaki_i8")
+    assert info["status"] == "OK" and info["iters"] <= 6, info
+    rows = np.random.default_rng(20002).choice(2048, 24, replace=False)
+    ev = oracle.evaluate_rows(a, q, rows)
+    assert ev["stril"] <= 1e-15, ev
+    assert ev["orth"] <= 4 * U64 * np.sqrt(2048) * 10, ev
