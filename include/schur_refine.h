@@ -120,13 +120,29 @@ size_t sr_workspace_bytes(int n, const sr_opts* opts);
 int schur_refine(const void* A, void* Q, void* T, int n, int iters, double tol,
                  const sr_opts* opts, sr_info* info);
 
-/* Refine `batch` independent decompositions of possibly different sizes.
+/* Refine `batch` independent decompositions of possibly different sizes (the
+ * FP64 tier of schur_refine on each).
  *  n (host, int[batch]); A, Q, T (host arrays of `batch` device pointers), each
- *  matrix laid out as in schur_refine. info (host, sr_info[batch]) may be NULL.
+ *  matrix laid out as in schur_refine. info (host, sr_info[batch]) may be NULL
+ *  (the ms_* fields are not filled).
+ *  Each pass runs as one fixed sequence of grouped launches over the whole batch
+ *  (persistent tile-table products, one block per matrix for the solve and the
+ *  elementwise steps) with device-side loop control; two passes are captured in a
+ *  HIP graph and replayed. The tile edge (64 or 32) of each size bucket is chosen
+ *  by timing both on the first batch that contains the bucket (kept for the
+ *  process). opts->gemm must be SR_GEMM_FP64. The work is ordered after the
+ *  caller's stream, and the call returns after it completed.
  *  Returns the worst (largest) outcome over the batch, or a negative error. */
 int schur_refine_batched(int batch, const int* n, const void* const* A, void* const* Q,
                          void* const* T, int iters, double tol, const sr_opts* opts,
                          sr_info* info);
+
+/* Bytes of device workspace schur_refine_batched needs (opts->workspace; when it
+ * is NULL the call allocates and frees its own). */
+size_t sr_workspace_bytes_batched(int batch, const int* n, const sr_opts* opts);
+
+/* Tile edge the batched autotuner chose for matrices of size n (-1: not tuned). */
+int sr_batched_tile_edge(int n);
 
 /* Double-double tier (Section 4 refines to higher than working precision the same
  * way): A = A_hi + A_lo, Q = Q_hi + Q_lo, T = T_hi + T_lo (all device, complex128

@@ -79,6 +79,8 @@ _SIGS = {
     "sr_ozaki_zgemm_dd": (_i, [_i, _i, _i, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i,
                                _i, _i, _i, _vp, _sz, _vp]),
     "sr_workspace_bytes_dd": (_sz, [_i, ctypes.POINTER(SrOpts)]),
+    "sr_workspace_bytes_batched": (_sz, [_i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SrOpts)]),
+    "sr_batched_tile_edge": (_i, [_i]),
     "sr_diag_mfma": (_i, [_i, _vp, _vp, _vp]),
 }
 EXPORTS = tuple(_SIGS)
@@ -207,6 +209,17 @@ def schur_refine(A, Q, T, iters: int = 6, tol: float = 1e-15, **kw) -> dict:
     d = info.as_dict()
     d["rc"] = rc
     return d
+
+
+def workspace_batched(sizes, device="cuda", **kw):
+    """A device workspace tensor for schur_refine_batched over matrices of `sizes`."""
+    import torch
+
+    b = len(sizes)
+    ns = (ctypes.c_int * max(1, b))(*[int(x) for x in sizes])
+    o = make_opts(**kw)
+    nbytes = int(lib().sr_workspace_bytes_batched(b, ns, ctypes.byref(o)))
+    return torch.empty(max(1, nbytes), dtype=torch.uint8, device=device)
 
 
 def schur_refine_batched(As, Qs, Ts, iters: int = 6, tol: float = 1e-15, **kw):

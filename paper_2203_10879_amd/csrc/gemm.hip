@@ -47,45 +47,38 @@ struct MF<float> {
 };
 
 constexpr int GBM = 64, GBN = 64, GBK = 16, GNT = 512;
-constexpr int WM = 2, WN = 1;  // 16 x 16 blocks per wave along M and N
-constexpr int kLoads = GBM * GBK / GNT;  // elements of each operand tile per thread
 constexpr int kChunk = 2;  // K-tiles (32 complex terms) per chunk of the two-level sum
 
-// LDS column swizzle: row k of a [GBK][64] tile is permuted by XOR with 4 (k mod 16).
-__device__ inline int swz(int k, int m) { return m ^ ((k & 15) << 2); }
+// Tile shapes: 64 x 64 with 512 threads (8 waves of 32 x 16) for the single
+// products; the grouped products of a batch also have 32 x 32 with 256 threads
+// (4 waves of 16 x 16) for small matrices.
+template <int BM>
+struct Shape {
+  static constexpr int NT = BM == 64 ? 512 : 256;
+  static constexpr int WM = BM == 64 ? 2 : 1;  // 16 x 16 blocks per wave along M
+  static constexpr int WN = 1;                 // and along N
+  static constexpr int LOADS = BM * GBK / NT;  // elements of each operand tile per thread
+};
 
+// LDS column swizzle: row k of a [GBK][BM] tile is permuted by XOR with 4 (k mod 16)
+// (k mod 8 for 32 columns), which keeps the XOR inside the row.
+template <int BM>
+__device__ inline int swz(int k, int m) {
+  return BM == 64 ? (m ^ ((k & 15) << 2)) : (m ^ ((k & 7) << 2));
+}
+
+// One output tile (m0, n0) of g; `slot` is the partial-sum slot of SPLIT / YDEF.
 // Operand layout of v_mfma_*_16x16x4 (one block): lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16]; accumulator element v of lane l is D[MF<R>::row(l, v)][l % 16].
-template <typename R, int OPA, int EPI, int COMP>
-__global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
+template <typename R, int OPA, int EPI, int COMP, int BM>
+__device__ inline void gemm_tile(const GemmArgs& g, int m0, int n0, int slot,
+                                 cplx<R> (*As)[GBK][BM], cplx<R> (*Bs)[GBK][BM], double* red) {
   using V = typename MF<R>::v4;
   using C = cplx<R>;
-  __shared__ C As[2][GBK][GBM];
-  __shared__ C Bs[2][GBK][GBN];
-  __shared__ double red[GNT / 64];
-
+  using S = Shape<BM>;
+  constexpr int WM = S::WM, WN = S::WN, NT = S::NT, kLoads = S::LOADS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * (16 * WM), wn = (wave >> 1) * (16 * WN);
-
-  // Blocks are dispatched round-robin over the XCDs (block b on XCD b mod 8):
-  // give each XCD a contiguous run of logical tiles, then walk tiles in groups of
-  // kGroup tile-rows so that concurrently running blocks share A rows and B columns
-  // in their XCD's L2.
-  const int ntiles = g.tiles_m * g.tiles_n;
-  const int bid = blockIdx.x;
-  int logical = bid;
-  {
-    const int per = ntiles / kXCDs;
-    if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
-  }
-  constexpr int kGroup = 4;
-  const int group = logical / (kGroup * g.tiles_n);
-  const int first_m = group * kGroup;
-  const int gsize = min(g.tiles_m - first_m, kGroup);
-  const int within = logical - group * kGroup * g.tiles_n;
-  const int tm = first_m + within % gsize;
-  const int tn = within / gsize;
-  const int m0 = tm * GBM, n0 = tn * GBN;
 
   const C* __restrict__ Ap = (const C*)g.A;
   const C* __restrict__ Bp = (const C*)g.B;
@@ -108,11 +101,11 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
   auto gload = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < kLoads; r++) {
-      const int idx = r * GNT + tid;
+      const int idx = r * NT + tid;
       int mm, kk;
       if (OPA == 0) {
-        mm = idx & 63;
-        kk = idx >> 6;
+        mm = idx & (BM - 1);
+        kk = idx / BM;
       } else {
         kk = idx & 15;
         mm = idx >> 4;
@@ -134,18 +127,18 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < kLoads; r++) {
-      const int idx = r * GNT + tid;
+      const int idx = r * NT + tid;
       int mm, kk;
       if (OPA == 0) {
-        mm = idx & 63;
-        kk = idx >> 6;
+        mm = idx & (BM - 1);
+        kk = idx / BM;
       } else {
         kk = idx & 15;
         mm = idx >> 4;
       }
-      As[buf][kk][swz(kk, mm)] = ra[r];
+      As[buf][kk][swz<BM>(kk, mm)] = ra[r];
       const int bk = idx & 15, bn = idx >> 4;
-      Bs[buf][bk][swz(bk, bn)] = rb[r];
+      Bs[buf][bk][swz<BM>(bk, bn)] = rb[r];
     }
   };
   auto fold = [&]() {
@@ -178,14 +171,14 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
       R a_re[WM], a_im[WM], na_im[WM], b_re[WN], b_im[WN];
 #pragma unroll
       for (int mi = 0; mi < WM; mi++) {
-        const C v = As[cur][krow][swz(krow, wm + mi * 16 + (lane & 15))];
+        const C v = As[cur][krow][swz<BM>(krow, wm + mi * 16 + (lane & 15))];
         a_re[mi] = v.re;
         a_im[mi] = v.im;
         na_im[mi] = -v.im;
       }
 #pragma unroll
       for (int ni = 0; ni < WN; ni++) {
-        const C v = Bs[cur][krow][swz(krow, wn + ni * 16 + (lane & 15))];
+        const C v = Bs[cur][krow][swz<BM>(krow, wn + ni * 16 + (lane & 15))];
         b_re[ni] = v.re;
         b_im[ni] = v.im;
       }
@@ -231,7 +224,52 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
         }
         if (i < g.m && j < g.n) epi_element<EPI, R>(g, i, j, val, part);
       }
-  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<GNT>(g, part, red, bid);
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<NT>(g, part, red, slot);
+}
+
+template <typename R, int OPA, int EPI, int COMP>
+__global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
+  __shared__ cplx<R> As[2][GBK][GBM];
+  __shared__ cplx<R> Bs[2][GBK][GBN];
+  __shared__ double red[GNT / 64];
+  // Blocks are dispatched round-robin over the XCDs (block b on XCD b mod 8):
+  // give each XCD a contiguous run of logical tiles, then walk tiles in groups of
+  // kGroup tile-rows so that concurrently running blocks share A rows and B columns
+  // in their XCD's L2.
+  const int ntiles = g.tiles_m * g.tiles_n;
+  const int bid = blockIdx.x;
+  int logical = bid;
+  {
+    const int per = ntiles / kXCDs;
+    if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
+  }
+  constexpr int kGroup = 4;
+  const int group = logical / (kGroup * g.tiles_n);
+  const int first_m = group * kGroup;
+  const int gsize = min(g.tiles_m - first_m, kGroup);
+  const int within = logical - group * kGroup * g.tiles_n;
+  const int tm = first_m + within % gsize;
+  const int tn = within / gsize;
+  gemm_tile<R, OPA, EPI, COMP, GBM>(g, tm * GBM, tn * GBN, bid, As, Bs, red);
+}
+
+// Grouped product over many matrices: a persistent grid walks a table of output
+// tiles (matrix, m0, n0, partial slot); tiles of matrices whose `active` flag is 0
+// are skipped, so a captured sequence can keep running while matrices finish.
+template <typename R, int OPA, int EPI, int COMP, int BM>
+__global__ __launch_bounds__(Shape<BM>::NT) void gemm_grouped_kernel(const GemmArgs* __restrict__ args,
+                                                                     const GTile* __restrict__ tiles,
+                                                                     int ntiles,
+                                                                     const int* __restrict__ active) {
+  __shared__ cplx<R> As[2][GBK][BM];
+  __shared__ cplx<R> Bs[2][GBK][BM];
+  __shared__ double red[Shape<BM>::NT / 64];
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const GTile d = tiles[t];
+    if (active && !active[d.mat]) continue;
+    const GemmArgs g = args[d.mat];
+    gemm_tile<R, OPA, EPI, COMP, BM>(g, d.m0, d.n0, d.slot, As, Bs, red);
+  }
 }
 
 int gemm_tiles(int m, int n) { return ceil_div(m, GBM) * ceil_div(n, GBN); }
@@ -264,5 +302,42 @@ hipError_t zgemm(int opa, int epi, int comp, const GemmArgs& g, hipStream_t st) 
 }
 
 hipError_t cgemm(const GemmArgs& g, hipStream_t st) { return launch<float, 0, EPI_STORE, 0>(g, st); }
+
+template <typename R, int OPA, int EPI, int COMP, int BM>
+static hipError_t launch_grouped(const GemmArgs* args, const GTile* tiles, int ntiles,
+                                 const int* active, int grid, hipStream_t st) {
+  if (ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL((gemm_grouped_kernel<R, OPA, EPI, COMP, BM>), dim3(grid), dim3(Shape<BM>::NT), 0, st,
+                     args, tiles, ntiles, active);
+  return hipGetLastError();
+}
+
+hipError_t zgemm_grouped(int opa, int epi, int comp, int bm, const GemmArgs* args, const GTile* tiles,
+                         int ntiles, const int* active, int grid, hipStream_t st) {
+#define SR_G(OPA, EPI, BM)                                                                  \
+  if (opa == OPA && epi == EPI && bm == BM) {                                               \
+    return comp ? launch_grouped<double, OPA, EPI, 1, BM>(args, tiles, ntiles, active, grid, st) \
+                : launch_grouped<double, OPA, EPI, 0, BM>(args, tiles, ntiles, active, grid, st); \
+  }
+  SR_G(0, EPI_STORE, 64)
+  SR_G(0, EPI_ADD, 64)
+  SR_G(0, EPI_SPLIT, 64)
+  SR_G(0, EPI_YDEF, 64)
+  SR_G(1, EPI_YDEF, 64)
+  SR_G(0, EPI_STORE, 32)
+  SR_G(0, EPI_ADD, 32)
+  SR_G(0, EPI_SPLIT, 32)
+  SR_G(0, EPI_YDEF, 32)
+  SR_G(1, EPI_YDEF, 32)
+#undef SR_G
+  return hipErrorInvalidValue;
+}
+
+hipError_t cgemm_grouped(int bm, const GemmArgs* args, const GTile* tiles, int ntiles, const int* active,
+                         int grid, hipStream_t st) {
+  if (bm == 64) return launch_grouped<float, 0, EPI_STORE, 0, 64>(args, tiles, ntiles, active, grid, st);
+  if (bm == 32) return launch_grouped<float, 0, EPI_STORE, 0, 32>(args, tiles, ntiles, active, grid, st);
+  return hipErrorInvalidValue;
+}
 
 }  // namespace sr

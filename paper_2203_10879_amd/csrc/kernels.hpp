@@ -42,6 +42,18 @@ struct GemmArgs {
 // Number of output tiles (= blocks, = partial sums written) of a GEMM launch.
 int gemm_tiles(int m, int n);
 
+// One output tile of a grouped (batched) product: matrix index, tile origin and
+// the partial-sum slot its SPLIT / YDEF epilogue writes.
+struct GTile {
+  int mat, m0, n0, slot;
+};
+// Grouped products over a table of tiles (bm = 64 or 32: the tile edge); matrices
+// with active[mat] == 0 are skipped (active may be NULL). grid = persistent blocks.
+hipError_t zgemm_grouped(int opa, int epi, int comp, int bm, const GemmArgs* args, const GTile* tiles,
+                         int ntiles, const int* active, int grid, hipStream_t st);
+hipError_t cgemm_grouped(int bm, const GemmArgs* args, const GTile* tiles, int ntiles, const int* active,
+                         int grid, hipStream_t st);
+
 // complex128 product on FP64 MFMA; opa: 0 = A, 1 = A^H; comp: compensated accumulation.
 hipError_t zgemm(int opa, int epi, int comp, const GemmArgs& g, hipStream_t st);
 // complex64 product on FP32 MFMA (C = A B).
@@ -89,5 +101,11 @@ hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* w
                     unsigned* status, hipStream_t st);
 hipError_t trisolve64(const zc* T, const zc* E, zc* L, int n, void* ws, unsigned* status,
                       hipStream_t st);
+// Batched FP32 solves over a device table of `count` matrix records, filled on the
+// host with trimatrix_fill (each record trimatrix_bytes() bytes).
+hipError_t trisolve_batched(const void* mats, int count, float trunc, hipStream_t st);
+size_t trimatrix_bytes();
+void trimatrix_fill(void* dst, const cc* T, const cc* E, cc* L, int n, const int* active,
+                    unsigned* flag);
 
 }  // namespace sr

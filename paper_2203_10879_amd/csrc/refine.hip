@@ -587,18 +587,6 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   return status;
 }
 
-int schur_refine_batched(int batch, const int* n, const void* const* A, void* const* Q,
-                         void* const* T, int iters, double tol, const sr_opts* opts,
-                         sr_info* info) {
-  if (batch < 0 || (batch > 0 && (!n || !A || !Q || !T))) return SR_EINVAL;
-  int worst = SR_OK;
-  for (int b = 0; b < batch; b++) {
-    const int r = schur_refine(A[b], Q[b], T[b], n[b], iters, tol, opts, info ? info + b : nullptr);
-    if (r < 0) return r;
-    if (r > worst) worst = r;
-  }
-  return worst;
-}
 
 }  // extern "C"
 

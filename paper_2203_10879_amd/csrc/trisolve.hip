@@ -30,6 +30,8 @@
 // No block waits on another and no device-scope fence is needed: all data a
 // launch reads were written by earlier launches. Small matrices (and the batched
 // path) use one block that walks all tiles.
+#include <string.h>
+
 #include "kernels.hpp"
 
 namespace sr {
@@ -313,6 +315,8 @@ struct TriMatrix {
   const cplx<Rl>* E;
   cplx<Rl>* L;
   int n;
+  const int* active;  // batched use: skip the matrix when *active == 0 (may be NULL)
+  unsigned* flag;     // batched use: per-matrix status bits (NULL: the shared word)
 };
 
 // One block per matrix walks every tile diagonal; used for small n and batches.
@@ -323,6 +327,8 @@ __global__ __launch_bounds__(TNT) void trisolve_single_kernel(const TriMatrix<Rl
   using C = cplx<Rl>;
   __shared__ C S1[kSolveS1], S2[kSolveS2], S3[TB * TLD];
   const TriMatrix<Rl> mt = mats ? mats[blockIdx.x] : one;
+  if (mt.active && *mt.active == 0) return;
+  if (mt.flag) status = mt.flag;
   const int n = mt.n, nb = (n + TB - 1) / TB;
   const Own o = owner();
   for (int D = nb - 1; D >= 0; D--) {
@@ -371,7 +377,7 @@ static hipError_t trisolve_t(const cplx<Rl>* T, const cplx<Rl>* E, cplx<Rl>* L, 
   hipError_t e = fill_zero(L, (size_t)n * n * sizeof(C), st);
   if (e != hipSuccess) return e;
   if (nb <= 2) {
-    TriMatrix<Rl> one{T, E, L, n};
+    TriMatrix<Rl> one{T, E, L, n, nullptr, nullptr};
     hipLaunchKernelGGL(trisolve_single_kernel<Rl>, dim3(1), dim3(TNT), 0, st,
                        (const TriMatrix<Rl>*)nullptr, one, status, trunc);
     return hipGetLastError();
@@ -399,6 +405,22 @@ hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* w
 hipError_t trisolve64(const zc* T, const zc* E, zc* L, int n, void* ws, unsigned* status,
                       hipStream_t st) {
   return trisolve_t<double>(T, E, L, n, 0.f, ws, status, st);
+}
+
+// Batched FP32 solves: one block per matrix (entries of the device table `mats`);
+// the strictly lower part of each L is written, the rest is left as it is.
+hipError_t trisolve_batched(const void* mats, int count, float trunc, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(trisolve_single_kernel<float>, dim3(count), dim3(TNT), 0, st,
+                     (const TriMatrix<float>*)mats, TriMatrix<float>{}, (unsigned*)nullptr, trunc);
+  return hipGetLastError();
+}
+
+size_t trimatrix_bytes() { return sizeof(TriMatrix<float>); }
+void trimatrix_fill(void* dst, const cc* T, const cc* E, cc* L, int n, const int* active,
+                    unsigned* flag) {
+  TriMatrix<float> m{T, E, L, n, active, flag};
+  memcpy(dst, &m, sizeof(m));
 }
 
 }  // namespace sr
