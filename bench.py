@@ -1,16 +1,28 @@
 """Benchmark: refined Schur decompositions per second on one MI355X.
 
-Workload: one complex128 matrix of size n = 1024 built as A = Q0 T0 Q0^H (Haar
-Q0, gap-separated complex normal eigenvalues >= 0.05 apart, strictly upper part
-CN(0,1)/sqrt(n)), started from the complex64 Schur basis of complex64(A)
-(LAPACK cgees). One step is one complete refinement (Algorithm 4 from the
-Newton-Schulz start) to ||stril(Q^H A Q)||_F / ||A||_F <= 1e-15 in the FP64 tier
-(FP64 MFMA products with compensated accumulation, FP32 solve). A, the start and
-the workspace are resident in HBM before timing; each step first restores the
-start into Q with a device-to-device copy (inside the timed region).
+Default workload (the headline line): one complex128 matrix of size n = 1024 built
+as A = Q0 T0 Q0^H (Haar Q0, gap-separated complex normal eigenvalues >= 0.05
+apart, strictly upper part CN(0,1)/sqrt(n)), started from the complex64 Schur
+basis of complex64(A) (LAPACK cgees). One step is one complete refinement
+(Algorithm 4 from the Newton-Schulz start) to ||stril(Q^H A Q)||_F / ||A||_F <=
+1e-15 in the FP64 tier (FP64 MFMA products with compensated accumulation, FP32
+solve). A, the start and the workspace are resident in HBM before timing; each
+step first restores the start into Q with a device-to-device copy (inside the
+timed region).
 
-Prints one JSON line. `roofline` covers the FP64 complex GEMM (all hp product
-launches), timed with HIP events on the library's stream during the timed steps.
+Other workloads (--workload), each one JSON line of its own:
+  precision       n = 4096, eigenvalue gaps >= 1e-3, cgees start: the FP64 tier
+                  with native FP64 products and with Ozaki INT8 splits, time to
+                  1e-15 and the binary128 error on sampled rows for each;
+  batched         2000 matrices, n uniform in [16, 256], each from its own seed
+                  with a cgees start, refined together (schur_refine_batched);
+                  matrices/s and the p50 / p99 pass counts;
+  dd_continuation A(t_k) = A0 + (k/64) A1, n = 2048, k = 0..63, double-double
+                  tier to 1e-28, each step warm-started from the previous one,
+                  the first from the zgees Schur form of A0.
+
+Prints one JSON line. `roofline` covers the dominant kernel of the workload's hp
+products, timed with HIP events on the library's stream during the timed steps.
 `cpu_baseline` times the binary128 oracle on a bounded sample (one quad product
 A Q[:, :c]) and scales it to one refinement.
 """
@@ -28,6 +40,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+INT8_PEAK_TOPS = 5000.0  # MI355X dense INT8 matrix peak
+METRIC = "refined Schur decomps/sec to ||stril||/||A||<=1e-15; GEMM % MFMA peak"
 N = 1024
 TOL = 1e-15
 
@@ -49,21 +63,14 @@ def cpu_baseline(a: np.ndarray, q: np.ndarray, hp_products: int, cols: int = 256
                       f"per refinement; solve and elementwise work not counted"}
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=N)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compensated", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the refinement of one matrix is not sharded across GPUs in this build)",
-              file=sys.stderr)
-        return 2
+def base_record(args, value, unit, ms_per_step, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
 
+
+def run_default(args) -> int:
     import torch
 
     import paper_2203_10879_amd as sr
@@ -72,8 +79,7 @@ def main() -> int:
     n = args.n
     g = synth.schur_test_matrix(n, seed=1, gap=0.05)
     qh = synth.lp_schur_start(g["A"])
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(torch.device("cuda:0"))
     A = sr.colmajor(g["A"])
     Q0 = sr.colmajor(qh)
     Q = sr.colmajor_empty(n, n)
@@ -102,41 +108,223 @@ def main() -> int:
     ms_gemm = sum(i["ms_hp_gemm"] for i in infos)
     launches = sum(i["hp_gemm_launches"] for i in infos)
     avg_gemm_ms = ms_gemm / max(1, launches)
-    flops = 8.0 * n ** 3
-    achieved = flops / (avg_gemm_ms * 1e-3) / 1e12
+    achieved = 8.0 * n ** 3 / (avg_gemm_ms * 1e-3) / 1e12
     last = infos[-1]
-    out = {
-        "metric": "refined Schur decomps/sec to ||stril||/||A||<=1e-15; GEMM % MFMA peak",
-        "value": args.steps / dt if ok else 0.0,
-        "unit": "decomps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"single matrix n={n}, eigenvalue gaps >= 0.05, FP32 cgees start, "
-                               "FP64 tier (FP64 MFMA products, FP32 solve), tol 1e-15",
-                   "n": n, "tol": TOL, "compensated": not args.no_compensated,
-                   "parallelism": "1 GPU"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "complex FP64 GEMM (gemm_kernel<double,...>), 8n^3 flop per launch",
-                     "avg_launch_ms": avg_gemm_ms, "launches_per_step": launches / args.steps},
-        "passes": last["iters"],
-        "hp_gemms": last["hp_gemms"],
-        "resid_hist": last["resid_hist"],
-        "ms_solve_per_step": sum(i["ms_solve"] for i in infos) / args.steps,
-        "ms_hp_gemm_per_step": ms_gemm / args.steps,
-        "all_converged": ok,
-    }
+    out = base_record(args, args.steps / dt if ok else 0.0, "decomps/s", 1e3 * dt / args.steps, "f64",
+                      {"workload": f"single matrix n={n}, eigenvalue gaps >= 0.05, FP32 cgees start, "
+                                   "FP64 tier (FP64 MFMA products, FP32 solve), tol 1e-15",
+                       "n": n, "tol": TOL, "compensated": not args.no_compensated,
+                       "parallelism": "1 GPU"})
+    out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                       "kernel": "complex FP64 GEMM (gemm_kernel<double,...>), 8n^3 flop per launch",
+                       "avg_launch_ms": avg_gemm_ms, "launches_per_step": launches / args.steps}
+    out.update({"passes": last["iters"], "hp_gemms": last["hp_gemms"], "resid_hist": last["resid_hist"],
+                "ms_solve_per_step": sum(i["ms_solve"] for i in infos) / args.steps,
+                "ms_hp_gemm_per_step": ms_gemm / args.steps, "all_converged": ok})
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g["A"], qh, hp_products=last["hp_gemms"])
     print(json.dumps(out), flush=True)
     return 0 if ok else 1
+
+
+def run_precision(args) -> int:
+    import torch
+
+    import oracle
+    import paper_2203_10879_amd as sr
+    import synth
+
+    n = 4096 if args.n == N else args.n
+    t0 = time.perf_counter()
+    g = synth.schur_test_matrix(n, seed=2, gap=1e-3)
+    qh = synth.lp_schur_start(g["A"])
+    print(f"# inputs n={n} ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.set_device(torch.device("cuda:0"))
+    A, Q0 = sr.colmajor(g["A"]), sr.colmajor(qh)
+    Q, T = sr.colmajor_empty(n, n), sr.colmajor_empty(n, n)
+    rows = np.random.default_rng(7).choice(n, args.rows, replace=False)
+    forms = {}
+    for mode in ("fp64", "ozaki_i8"):
+        ws = sr.workspace(n, gemm=mode)
+        for _ in range(args.warmup):
+            Q.copy_(Q0)
+            sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=mode, workspace=ws)
+        torch.cuda.synchronize()
+        infos, t1 = [], time.perf_counter()
+        for _ in range(args.steps):
+            Q.copy_(Q0)
+            infos.append(sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=mode, timing=True, workspace=ws))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        last = infos[-1]
+        ev = oracle.evaluate_rows(g["A"], sr.to_numpy(Q), rows)
+        launches = sum(i["hp_gemm_launches"] for i in infos)
+        forms[mode] = {"status": last["status"], "passes": last["iters"], "ms_to_tol": 1e3 * dt,
+                       "ms_hp_products": sum(i["ms_hp_gemm"] for i in infos) / args.steps,
+                       "avg_hp_product_ms": sum(i["ms_hp_gemm"] for i in infos) / max(1, launches),
+                       "ms_solve": sum(i["ms_solve"] for i in infos) / args.steps,
+                       "resid_hist": last["resid_hist"], "update_digits": last["update_slices_hist"],
+                       "quad_stril_rows": float(ev["stril"]), "quad_orth_rows": float(ev["orth"])}
+        print(f"# {mode}: {forms[mode]['ms_to_tol']:.1f} ms", file=sys.stderr, flush=True)
+        del ws
+    oz, fp = forms["ozaki_i8"], forms["fp64"]
+    ok = oz["status"] == "OK" and fp["status"] == "OK"
+    out = base_record(args, 1e3 / oz["ms_to_tol"] if ok else 0.0, "decomps/s", oz["ms_to_tol"], "f64+i8",
+                      {"workload": f"precision comparison n={n}, eigenvalue gaps >= 1e-3, FP32 cgees start; "
+                                   "value = Ozaki INT8 form (P = AQ, the start's products and Q Delta on "
+                                   "INT8 digits; That and Y native FP64)",
+                       "n": n, "tol": TOL, "quad_rows": args.rows})
+    out["forms"] = forms
+    out["ozaki_speedup_vs_fp64"] = fp["ms_to_tol"] / oz["ms_to_tol"]
+    out["roofline"] = None
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
+def _gen_batched(item):
+    n, seed = item
+    import synth
+
+    g = synth.schur_test_matrix(n, seed=seed)
+    return g["A"], synth.lp_schur_start(g["A"])
+
+
+def run_batched(args) -> int:
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    import synth
+
+    count = args.count
+    sizes = [int(x) for x in synth.batched_sizes(count, seed=3)]
+    t0 = time.perf_counter()
+    # inputs are made before the GPU is touched; workers run single-threaded BLAS
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    workers = min(16, os.cpu_count() or 1)
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        data = list(ex.map(_gen_batched, [(n, 10000 + i) for i, n in enumerate(sizes)], chunksize=16))
+    print(f"# {count} inputs ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    import torch
+
+    import oracle
+    import paper_2203_10879_amd as sr
+
+    torch.cuda.set_device(torch.device("cuda:0"))
+    As = [sr.colmajor(a) for a, _ in data]
+    Q0 = [sr.colmajor(q) for _, q in data]
+    Qs = [sr.colmajor_empty(n, n) for n in sizes]
+    Ts = [sr.colmajor_empty(n, n) for n in sizes]
+    ws = sr.workspace_batched(sizes)
+
+    def step():
+        for q, q0 in zip(Qs, Q0):
+            q.copy_(q0)
+        return sr.schur_refine_batched(As, Qs, Ts, iters=8, tol=TOL, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        rc, infos = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / args.steps
+    passes = np.array([i["iters"] for i in infos])
+    ok = rc == 0
+    # binary128 check of a few matrices
+    checks = []
+    for i in np.random.default_rng(5).choice(count, 4, replace=False):
+        ev = oracle.evaluate(data[i][0], sr.to_numpy(Qs[i]), sr.to_numpy(Ts[i]))
+        checks.append({"n": sizes[i], "stril": float(ev["stril"]), "orth": float(ev["orth"])})
+    flops = sum(8.0 * n ** 3 * inf["hp_gemms"] for n, inf in zip(sizes, infos))
+    out = base_record(args, count / dt if ok else 0.0, "decomps/s", 1e3 * dt, "f64",
+                      {"workload": f"batched: {count} matrices, n uniform in [16, 256] (seed 3), "
+                                   "eigenvalue gaps >= 0.05, FP32 cgees starts, FP64 tier, tol 1e-15, "
+                                   "one schur_refine_batched call per step",
+                       "count": count, "tol": TOL,
+                       "tile_edges": {str(b): sr.lib().sr_batched_tile_edge(b) for b in (32, 64, 128, 192, 256)}})
+    out.update({"passes_p50": float(np.percentile(passes, 50)), "passes_p99": float(np.percentile(passes, 99)),
+                "passes_max": int(passes.max()), "hp_flops_per_step": flops,
+                "hp_tflops_effective": flops / dt / 1e12, "quad_checks": checks, "roofline": None})
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
+def run_dd_continuation(args) -> int:
+    import torch
+
+    import oracle
+    import paper_2203_10879_amd as sr
+    import synth
+
+    n = 2048 if args.n == N else args.n
+    steps = args.cont_steps
+    t0 = time.perf_counter()
+    g = synth.schur_test_matrix(n, seed=4, gap=0.05)
+    a1 = synth.continuation_perturbation(n, seed=5)
+    q0 = synth.hp_schur_start(g["A"])
+    pairs = [synth.continuation_step_dd(g["A"], a1, k) for k in range(steps)]
+    print(f"# inputs n={n} ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.set_device(torch.device("cuda:0"))
+    dev = [(sr.colmajor(h), sr.colmajor(l)) for h, l in pairs]
+    Qh, Ql = sr.colmajor(q0), sr.colmajor(np.zeros_like(q0))
+    Th, Tl = sr.colmajor_empty(n, n), sr.colmajor_empty(n, n)
+    ws = sr.workspace_dd(n, update_slices=-1)
+    per = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(steps):
+        info = sr.schur_refine_dd(dev[k][0], dev[k][1], Qh, Ql, Th, Tl, iters=8, tol=1e-28, timing=True,
+                                  workspace=ws, update_slices=-1)
+        per.append({"k": k, "status": info["status"], "passes": info["iters"], "ms": info["ms_total"],
+                    "ms_hp": info["ms_hp_gemm"], "resid": info["resid"]})
+        if k % 8 == 0:
+            print(f"# step {k}: {info['status']} {info['iters']} passes {info['ms_total']:.1f} ms",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    ok = all(p["status"] == "OK" for p in per)
+    rows = np.random.default_rng(9).choice(n, args.rows, replace=False)
+    ah, al = pairs[-1]
+    ev = oracle.evaluate_rows(oracle.QMat.from_dd(ah, al),
+                              oracle.QMat.from_dd(sr.to_numpy(Qh), sr.to_numpy(Ql)), rows)
+    hp_ms = sum(p["ms_hp"] for p in per)
+    launches = sum(4 * p["passes"] for p in per)
+    out = base_record(args, steps / dt if ok else 0.0, "decomps/s", 1e3 * dt / steps, "dd(int8)",
+                      {"workload": f"double-double continuation A0 + (k/{steps}) A1, n={n}, A1 = 1e-3 CN(0,1) "
+                                   "(46-bit), tol 1e-28, warm starts, first from zgees",
+                       "n": n, "steps": steps, "tol": 1e-28})
+    out.update({"passes_per_step": [p["passes"] for p in per], "ms_per_step_each": [p["ms"] for p in per],
+                "hp_ms_total": hp_ms, "quad_stril_rows_last": float(ev["stril"]),
+                "quad_orth_rows_last": float(ev["orth"]), "roofline": None, "steps": steps, "warmup": 0})
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=N)
+    ap.add_argument("--workload", default="default",
+                    choices=["default", "precision", "batched", "dd_continuation"])
+    ap.add_argument("--count", type=int, default=2000, help="batched: number of matrices")
+    ap.add_argument("--cont-steps", type=int, default=64, help="dd_continuation: steps")
+    ap.add_argument("--rows", type=int, default=32, help="rows of the binary128 check")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compensated", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the refinement of one matrix is not sharded across GPUs in this build)",
+              file=sys.stderr)
+        return 2
+    return {"default": run_default, "precision": run_precision, "batched": run_batched,
+            "dd_continuation": run_dd_continuation}[args.workload](args)
 
 
 if __name__ == "__main__":
