@@ -38,7 +38,10 @@ constexpr int kSplitNT = 256;
 
 __host__ __device__ inline int oz_kp(int K) { return (K + OBK - 1) / OBK * OBK; }
 
-size_t oz_slice_bytes(int rows, int K, int S) { return (size_t)S * 2 * rows * oz_kp(K); }
+// Slice buffers hold three parts per slice: real digits, imaginary digits and the
+// negated imaginary digits (so that a product never negates on the fly).
+constexpr int kParts = 3;
+size_t oz_slice_bytes(int rows, int K, int S) { return (size_t)S * kParts * rows * oz_kp(K); }
 
 // ------------------------------------------------------------------- splitting
 
@@ -93,9 +96,10 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
   }
   __syncthreads();
   const int e = e_sh;
-  const long stride = 2L * ncols * Kp;  // slice s -> s+1
+  const long stride = (long)kParts * ncols * Kp;  // slice s -> s+1
   int8_t* o_re = out + (long)col * Kp;
   int8_t* o_im = out + ((long)ncols + col) * Kp;
+  int8_t* o_ni = out + (2L * ncols + col) * Kp;
   for (int k = threadIdx.x; k < Kp; k += kSplitNT) {
     if (k < K) {
       const zc v = x[k];
@@ -105,19 +109,24 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
         double ih = ldexp(v.im, -e), il = ldexp(w.im, -e);
         for (int s = 0; s < S; s++) {
           o_re[s * stride + k] = (int8_t)dd_digit(rh, rl);
-          o_im[s * stride + k] = (int8_t)dd_digit(ih, il);
+          const int di = dd_digit(ih, il);
+          o_im[s * stride + k] = (int8_t)di;
+          o_ni[s * stride + k] = (int8_t)(-di);
         }
       } else {
         double r = ldexp(v.re, -e), i = ldexp(v.im, -e);
         for (int s = 0; s < S; s++) {
           o_re[s * stride + k] = (int8_t)fp_digit(r);
-          o_im[s * stride + k] = (int8_t)fp_digit(i);
+          const int di = fp_digit(i);
+          o_im[s * stride + k] = (int8_t)di;
+          o_ni[s * stride + k] = (int8_t)(-di);
         }
       }
     } else {
       for (int s = 0; s < S; s++) {
         o_re[s * stride + k] = 0;
         o_im[s * stride + k] = 0;
+        o_ni[s * stride + k] = 0;
       }
     }
   }
@@ -200,20 +209,23 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
       rl[c] = il[c] = 0;
     }
   }
-  const long stride = 2L * M * Kp;
+  const long stride = (long)kParts * M * Kp;
   int* o_re = (int*)(out + (long)gi * Kp + k0 + kg);
   int* o_im = (int*)(out + ((long)M + gi) * Kp + k0 + kg);
+  int* o_ni = (int*)(out + (2L * M + gi) * Kp + k0 + kg);
   for (int s = 0; s < S; s++) {
-    unsigned pr = 0, pi = 0;
+    unsigned pr = 0, pi = 0, pn = 0;
 #pragma unroll
     for (int c = 0; c < 4; c++) {
       const int dr = Xlo ? dd_digit(rh[c], rl[c]) : fp_digit(rh[c]);
       const int di = Xlo ? dd_digit(ih[c], il[c]) : fp_digit(ih[c]);
       pr |= (unsigned)(dr & 0xff) << (8 * c);
       pi |= (unsigned)(di & 0xff) << (8 * c);
+      pn |= (unsigned)((-di) & 0xff) << (8 * c);
     }
     o_re[s * stride / 4] = (int)pr;
     o_im[s * stride / 4] = (int)pi;
+    o_ni[s * stride / 4] = (int)pn;
   }
 }
 
@@ -277,7 +289,7 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
   const int m0 = (first_m + within % gsize) * OBM, n0 = (within / gsize) * OBN;
 
   const int KT = a.Kp / OBK;
-  const long sA = 2L * g.m * a.Kp, sB = 2L * g.n * a.Kp;  // bytes per slice
+  const long sA = (long)kParts * g.m * a.Kp, sB = (long)kParts * g.n * a.Kp;  // bytes per slice
 
   double out_re[16], out_im[16];
 #pragma unroll
@@ -374,33 +386,44 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
 
 // ------------------------------------------------------- large-tile product
 //
-// For products with at least one 128 x 128 tile per CU. A 256-thread block (one
-// wave per SIMD) computes a 128 x 128 complex tile; each wave owns 64 x 64 as
-// 2 x 2 blocks of 32 x 32. Only two int32 accumulators per output are kept: with
-// the negated imaginary digits of op(A) staged beside the real and imaginary
-// ones, re = Ar Br + (-Ai) Bi and im = Ar Bi + Ai Br (conjugated op(A):
-// re = Ar Br + Ai Bi, im = Ar Bi + (-Ai) Br), all summed exactly in int32
-// (|sum| <= 2 * steps * 64 * 127^2, so a diagonal is folded at least every
-// kSeg steps). The FP64 partial sums live between folds in a per-tile scratch
-// laid out in the waves' register order (coalesced), not in registers, so the
-// register file holds the large wave tile.
-constexpr int PBM = 128, PBN = 128, PNT = 256, PLD = 80, kSeg = 1024;
+// For products with at least one 128 x 128 tile per CU, and for every
+// double-double product. A 256-thread block (one wave per SIMD) computes a 128 x 128
+// complex tile; each wave owns 64 x 64 as 2 x 2 blocks of 32 x 32. Only two int32
+// accumulators per output are kept: with the negated imaginary digits of op(A)
+// stored beside the real and imaginary ones, re = Ar Br + (-Ai) Bi and
+// im = Ar Bi + Ai Br (conjugated op(A): re = Ar Br + Ai Bi, im = Ar Bi + (-Ai) Br),
+// all summed exactly in int32 (|sum| <= 2 * steps * 64 * 127^2, so a diagonal is
+// folded at least every kSeg steps). The FP64 partial sums live between folds in
+// a per-tile scratch laid out in the waves' register order (coalesced), not in
+// registers, so the register file holds the large wave tile.
+//
+// Staging: the K-tiles go from global memory straight into LDS
+// (global_load_lds_dwordx4: lane l of an instruction writes 16 bytes at
+// base + 16 l), through a ring of three stages, issued two steps ahead. A stage
+// holds 3 parts of op(A) and 2 of B, each 128 rows of 64 bytes; within a row the
+// four 16-byte chunks are stored in the order chunk ^ f(row),
+// f(row) = ((row >> 1) ^ (row >> 3)) & 3, so that fragment reads of 32 consecutive
+// rows at one chunk spread over all banks.
+constexpr int PBM = 128, PBN = 128, PNT = 256, kSeg = 1024, kStages = 3;
+constexpr int kRowBytes = 64, kPartBytes = PBM * kRowBytes;            // 8 KiB
+constexpr int kStageBytes = 5 * kPartBytes;                             // 3 A parts + 2 B parts
+constexpr int kLoadsPerWave = 5 * (PBM / 16) / (PNT / 64);              // 10 wave instructions
 
-__device__ inline v4i neg_bytes(v4i x) {
-  // per-byte two's-complement negation (digits lie in [-127, 127])
-  v4i r;
-#pragma unroll
-  for (int c = 0; c < 4; c++) {
-    const unsigned n = ~(unsigned)x[c];
-    r[c] = (int)(((n & 0x7f7f7f7fu) + 0x01010101u) ^ (n & 0x80808080u));
-  }
-  return r;
-}
+typedef __attribute__((address_space(3))) void lds_ptr_t;
+typedef __attribute__((address_space(1))) const void gbl_ptr_t;
+
+__device__ inline int chunk_swz(int row) { return ((row >> 1) ^ (row >> 3)) & 3; }
+
+// s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8; a field at its maximum does not wait).
+constexpr int kWaitLgkm0 = 0xC07F;                   // lgkmcnt(0)
+constexpr int kWaitVm0 = 0x0F70;                     // vmcnt(0)
+constexpr int kWaitVmStep = 0x0F70 | kLoadsPerWave;  // vmcnt(10): one step in flight
+static_assert(kLoadsPerWave < 16, "vmcnt immediate");
 
 template <int EPI, bool DD>
 __global__ __launch_bounds__(PNT, 1) void oz_gemm2_kernel(OzArgs a) {
-  __shared__ __align__(16) int8_t As[2][3][PBM][PLD];
-  __shared__ __align__(16) int8_t Bs[2][2][PBN][PLD];
+  extern __shared__ __align__(16) int8_t lds[];  // kStages * kStageBytes
   __shared__ double red[PNT / 64];
   const GemmArgs& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -421,44 +444,101 @@ __global__ __launch_bounds__(PNT, 1) void oz_gemm2_kernel(OzArgs a) {
   const int m0 = (first_m + within % gsize) * PBM, n0 = (within / gsize) * PBN;
 
   const int KT = a.Kp / OBK;
-  const long sA = 2L * g.m * a.Kp, sB = 2L * g.n * a.Kp;
+  const long sA = (long)kParts * g.m * a.Kp, sB = (long)kParts * g.n * a.Kp;
   const int pa2 = a.conjA ? 1 : 2, pa3 = a.conjA ? 2 : 1;
   // per wave 4096 (x, y, v, lane) partial sums; the double-double product keeps
   // each as a three-term expansion (see the fold)
   constexpr int kWave = 16 * 4 * 64;
   double2* sp = a.scratch ? a.scratch + ((long)bid * 4 + wave) * (DD ? 3 * kWave : kWave) + lane : nullptr;
 
-  v4i sa[2][2], sb[2][2];  // staged chunks: [pair][part]
-  auto gload = [&](int s, int t, int kt) {
+  // This lane's part of the wave's load instructions: instruction j of wave w is
+  // q = w * 10 + j; q < 24 covers A part q / 8, rows 16 (q % 8) + lane / 4; the
+  // rest B part (q - 24) / 8. Rows past the matrix read its last row (their
+  // outputs are not stored). Offsets are relative to slice 1, K-tile 0.
+  const int uwave = __builtin_amdgcn_readfirstlane(wave);
+  int goff[kLoadsPerWave];
 #pragma unroll
-    for (int r = 0; r < 2; r++) {
-      const int q = r * PNT + tid, row = q >> 2, ch = q & 3;
-      const int gi = m0 + row, gj = n0 + row;
+  for (int j = 0; j < kLoadsPerWave; j++) {
+    const int q = uwave * kLoadsPerWave + j;
+    const bool isA = q < 24;
+    const int qq = isA ? q : q - 24;
+    const int part = qq >> 3, row = 16 * (qq & 7) + (lane >> 2);
+    const int chunk = (lane & 3) ^ chunk_swz(row);
+    const int lim = isA ? g.m : g.n;
+    const int grow = min((isA ? m0 : n0) + row, lim - 1);
+    goff[j] = (part * lim + grow) * a.Kp + chunk * 16;
+  }
+  auto issue = [&](int s, int t, int kt, int stage) {
+    const int8_t* baseA = a.A + (long)(s - 1) * sA + kt * OBK;
+    const int8_t* baseB = a.B + (long)(t - 1) * sB + kt * OBK;
 #pragma unroll
-      for (int part = 0; part < 2; part++) {
-        v4i v = {0, 0, 0, 0}, w = {0, 0, 0, 0};
-        if (gi < g.m)
-          v = *(const v4i*)(a.A + (long)(s - 1) * sA + ((long)part * g.m + gi) * a.Kp + kt * OBK + ch * 16);
-        if (gj < g.n)
-          w = *(const v4i*)(a.B + (long)(t - 1) * sB + ((long)part * g.n + gj) * a.Kp + kt * OBK + ch * 16);
-        sa[r][part] = v;
-        sb[r][part] = w;
-      }
+    for (int j = 0; j < kLoadsPerWave; j++) {
+      const int q = uwave * kLoadsPerWave + j;
+      const bool isA = q < 24;
+      const int qq = isA ? q : q - 24;
+      const int loff = (isA ? (qq >> 3) : 3 + (qq >> 3)) * kPartBytes + 16 * (qq & 7) * kRowBytes;
+      const int8_t* src = (isA ? baseA : baseB) + goff[j];
+      __builtin_amdgcn_global_load_lds((gbl_ptr_t*)src, (lds_ptr_t*)(lds + stage * kStageBytes + loff), 16, 0, 0);
     }
   };
-  auto sstore = [&](int buf) {
+  // Fragments of one K-half (32 deep) of a stage: B parts 3, 4 and A parts 0,
+  // pa2, pa3 for this wave's two column and two row blocks.
+  struct Frags {
+    v4i b0[2], b1[2], a0[2], a2[2], a3[2];
+  };
+  auto load_frags = [&](Frags& f, int stage, int kh) {
+    const int c = 2 * kh + (lane >> 5);
+    const int8_t* base = lds + stage * kStageBytes;
 #pragma unroll
-    for (int r = 0; r < 2; r++) {
-      const int q = r * PNT + tid, row = q >> 2, ch = q & 3;
-      *(v4i*)&As[buf][0][row][ch * 16] = sa[r][0];
-      *(v4i*)&As[buf][1][row][ch * 16] = sa[r][1];
-      *(v4i*)&As[buf][2][row][ch * 16] = neg_bytes(sa[r][1]);
-      *(v4i*)&Bs[buf][0][row][ch * 16] = sb[r][0];
-      *(v4i*)&Bs[buf][1][row][ch * 16] = sb[r][1];
+    for (int y = 0; y < 2; y++) {
+      const int r = wn + y * 32 + (lane & 31);
+      const int o = r * kRowBytes + ((c ^ chunk_swz(r)) << 4);
+      f.b0[y] = *(const v4i*)(base + 3 * kPartBytes + o);
+      f.b1[y] = *(const v4i*)(base + 4 * kPartBytes + o);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; x++) {
+      const int r = wm + x * 32 + (lane & 31);
+      const int o = r * kRowBytes + ((c ^ chunk_swz(r)) << 4);
+      f.a0[x] = *(const v4i*)(base + o);
+      f.a2[x] = *(const v4i*)(base + pa2 * kPartBytes + o);
+      f.a3[x] = *(const v4i*)(base + pa3 * kPartBytes + o);
     }
   };
 
   v16i acc_re[2][2], acc_im[2][2];
+  auto mfmas = [&](const Frags& f) {
+#pragma unroll
+    for (int x = 0; x < 2; x++)
+#pragma unroll
+      for (int y = 0; y < 2; y++)
+        acc_re[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a0[x], f.b0[y], acc_re[x][y], 0, 0, 0);
+#pragma unroll
+    for (int x = 0; x < 2; x++)
+#pragma unroll
+      for (int y = 0; y < 2; y++)
+        acc_im[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a0[x], f.b1[y], acc_im[x][y], 0, 0, 0);
+#pragma unroll
+    for (int x = 0; x < 2; x++)
+#pragma unroll
+      for (int y = 0; y < 2; y++)
+        acc_re[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a2[x], f.b1[y], acc_re[x][y], 0, 0, 0);
+#pragma unroll
+    for (int x = 0; x < 2; x++)
+#pragma unroll
+      for (int y = 0; y < 2; y++)
+        acc_im[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a3[x], f.b0[y], acc_im[x][y], 0, 0, 0);
+  };
+  // Workgroup barrier without a memory fence: the waits before it are explicit
+  // (a fenced barrier would also wait for the loads still in flight for later
+  // stages). The empty asm statements keep the compiler from moving LDS accesses
+  // across it.
+  auto barrier = [&]() {
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+
   double part = 0;
   bool first = true;
   const int d_last = min(a.dmax, a.SA + a.SB);
@@ -473,59 +553,38 @@ __global__ __launch_bounds__(PNT, 1) void oz_gemm2_kernel(OzArgs a) {
       for (int x = 0; x < 2; x++)
 #pragma unroll
         for (int y = 0; y < 2; y++) acc_re[x][y] = acc_im[x][y] = v16i{};
-      __syncthreads();  // LDS of the previous segment no longer read
-      {
-        const int s = s_lo + seg0 / KT;
-        gload(s, d - s, seg0 % KT);
-      }
-      sstore(0);
-      __syncthreads();
+      auto issue_step = [&](int st) {
+        const int q = seg0 + st, s = s_lo + q / KT;
+        issue(s, d - s, q % KT, st % kStages);
+      };
+      // Schedule of step st (stage st % 3):
+      //   read K-half 1 of st | MFMAs of K-half 0 of st |
+      //   wait for step st+1's loads, barrier | issue step st+2's loads |
+      //   read K-half 0 of st+1 | MFMAs of K-half 1 of st.
+      // A stage is rewritten two barriers after its last fragment read.
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      barrier();  // the previous segment no longer reads the ring
+      issue_step(0);
+      if (steps > 1) issue_step(1);
+      if (steps > 1) __builtin_amdgcn_s_waitcnt(kWaitVmStep);
+      else __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      barrier();
+      if (steps > 2) issue_step(2);
+      Frags f0, f1;
+      load_frags(f0, 0, 0);
       for (int st = 0; st < steps; st++) {
-        const int cur = st & 1;
+        const int cur = st % kStages;
+        load_frags(f1, cur, 1);
+        mfmas(f0);
         if (st + 1 < steps) {
-          const int q = seg0 + st + 1, s = s_lo + q / KT;
-          gload(s, d - s, q % KT);
+          // step st+1's loads complete: at most step st+2's are still in flight
+          if (st + 2 < steps) __builtin_amdgcn_s_waitcnt(kWaitVmStep);
+          else __builtin_amdgcn_s_waitcnt(kWaitVm0);
+          barrier();
+          if (st + 3 < steps) issue_step(st + 3);
+          load_frags(f0, (st + 1) % kStages, 0);
         }
-#pragma unroll
-        for (int kh = 0; kh < 2; kh++) {
-          const int kq = 32 * kh + 16 * (lane >> 5);
-          v4i fb0[2], fb1[2], fa0[2], fa2[2], fa3[2];
-#pragma unroll
-          for (int y = 0; y < 2; y++) {
-            const int col = wn + y * 32 + (lane & 31);
-            fb0[y] = *(const v4i*)&Bs[cur][0][col][kq];
-            fb1[y] = *(const v4i*)&Bs[cur][1][col][kq];
-          }
-#pragma unroll
-          for (int x = 0; x < 2; x++) {
-            const int row = wm + x * 32 + (lane & 31);
-            fa0[x] = *(const v4i*)&As[cur][0][row][kq];
-            fa2[x] = *(const v4i*)&As[cur][pa2][row][kq];
-            fa3[x] = *(const v4i*)&As[cur][pa3][row][kq];
-          }
-#pragma unroll
-          for (int x = 0; x < 2; x++)
-#pragma unroll
-            for (int y = 0; y < 2; y++)
-              acc_re[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa0[x], fb0[y], acc_re[x][y], 0, 0, 0);
-#pragma unroll
-          for (int x = 0; x < 2; x++)
-#pragma unroll
-            for (int y = 0; y < 2; y++)
-              acc_im[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa0[x], fb1[y], acc_im[x][y], 0, 0, 0);
-#pragma unroll
-          for (int x = 0; x < 2; x++)
-#pragma unroll
-            for (int y = 0; y < 2; y++)
-              acc_re[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa2[x], fb1[y], acc_re[x][y], 0, 0, 0);
-#pragma unroll
-          for (int x = 0; x < 2; x++)
-#pragma unroll
-            for (int y = 0; y < 2; y++)
-              acc_im[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa3[x], fb0[y], acc_im[x][y], 0, 0, 0);
-        }
-        if (st + 1 < steps) sstore(cur ^ 1);
-        __syncthreads();
+        mfmas(f1);
       }
       // fold: partial = previous partial + acc 2^{-7 d} (acc 2^{-7 d} is exact in FP64)
       const double sc = ldexp(1.0, -7 * d);
@@ -615,8 +674,14 @@ int oz_gemm_tiles(int m, int n, bool dd) {
 
 template <int EPI>
 static void launch_large(bool dd, int nt, const OzArgs& a, hipStream_t st) {
-  if (dd) oz_gemm2_kernel<EPI, true><<<dim3(nt), dim3(PNT), 0, st>>>(a);
-  else oz_gemm2_kernel<EPI, false><<<dim3(nt), dim3(PNT), 0, st>>>(a);
+  const size_t lds = (size_t)kStages * kStageBytes;
+  if (dd) {
+    hipFuncSetAttribute((const void*)oz_gemm2_kernel<EPI, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    oz_gemm2_kernel<EPI, true><<<dim3(nt), dim3(PNT), lds, st>>>(a);
+  } else {
+    hipFuncSetAttribute((const void*)oz_gemm2_kernel<EPI, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    oz_gemm2_kernel<EPI, false><<<dim3(nt), dim3(PNT), lds, st>>>(a);
+  }
 }
 
 hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t* B, const int* eb,
