@@ -63,6 +63,27 @@ def cpu_baseline(a: np.ndarray, q: np.ndarray, hp_products: int, cols: int = 256
                       f"per refinement; solve and elementwise work not counted"}
 
 
+def gemm_traffic():
+    """HBM bytes per FP64 GEMM launch from the committed rocprofv3 PMC summary, or None
+    when the GEMM sources have changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "refine_n1024_gemm_hbm_traffic.txt")
+    csrc = os.path.join(ROOT, "paper_2203_10879_amd", "csrc")
+    try:
+        text = open(path).read()
+        h = hashlib.sha256()
+        for f in ("gemm.hip", "epilogue.hpp", "kernels.hpp", "common.hpp"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+        vals = dict(line.split(":", 1) for line in text.splitlines()
+                    if line.startswith(("traffic_bytes_per_launch:", "gemm_source_sha256_16:")))
+        if vals["gemm_source_sha256_16"].split()[0] != h.hexdigest()[:16]:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def base_record(args, value, unit, ms_per_step, dtype, config):
     return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
@@ -115,8 +136,10 @@ def run_default(args) -> int:
                                    "FP64 tier (FP64 MFMA products, FP32 solve), tol 1e-15",
                        "n": n, "tol": TOL, "compensated": not args.no_compensated,
                        "parallelism": "1 GPU"})
+    traffic = gemm_traffic() if n == N else None
     out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                       "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                       "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x 1.997 + WRITE_SIZE)",
                        "kernel": "complex FP64 GEMM (gemm_kernel<double,...>), 8n^3 flop per launch",
                        "avg_launch_ms": avg_gemm_ms, "launches_per_step": launches / args.steps}
     out.update({"passes": last["iters"], "hp_gemms": last["hp_gemms"], "resid_hist": last["resid_hist"],

@@ -299,6 +299,17 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
   return SR_OK;
 }
 
+// Y = Q^H Q - I (scal[2] = ||Y||^2).
+int ydef(const zc* Q, const zc* QH, int n, int comp, const Work& w, hipStream_t st, Timer* tm) {
+  GemmArgs g = gargs(n, n, n, QH ? QH : Q, n, Q, n, w.Y, n);
+  g.partials = w.partials;
+  TIC(tm, 0);
+  CK(zgemm(QH ? 0 : 1, EPI_YDEF, comp, g, st));
+  TOC(tm, 0);
+  CK(reduce_partials(w.partials, gemm_tiles(n, n), w.scal + 2, st));
+  return SR_OK;
+}
+
 // Y = Q^H Q - I (scal[2] = ||Y||^2), W = L - L^H (scal[3] = ||W||^2).
 int defects(const zc* Q, const zc* QH, int n, int comp, const Work& w, hipStream_t st,
             Timer* tm = nullptr) {
@@ -536,10 +547,15 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
     eps1 = eps;
     if (p == iters - 1) break;
 
+    // Y does not depend on L, but running it beside the solve on a second
+    // stream lets its blocks fill the CUs the latency-bound solve needs (measured:
+    // slower at n >= 2048), so the two run one after the other.
     TIC(tm, 1);
     CK(trisolve(w.Tlp, w.Elp, w.Llp, n, o.trunc ? 1e-5f : 0.f, w.tri, w.status, st));
     TOC(tm, 1);
-    if ((rc = defects(cur, w.QH, n, comp, w, st, tm)) != SR_OK) return rc;
+    if ((rc = ydef(cur, w.QH, n, comp, w, st, tm)) != SR_OK) return rc;
+    CK(form_w(w.Llp, w.W, n, w.partials, st));
+    CK(reduce_partials(w.partials, form_w_parts(n), w.scal + 3, st));
     double nrm[4];
     if ((rc = read_back(st, w, 4, nrm, &dst)) != SR_OK) return rc;
     if (dst & DEV_BREAKDOWN) {
