@@ -39,9 +39,22 @@ constexpr int kSplitNT = 256;
 __host__ __device__ inline int oz_kp(int K) { return (K + OBK - 1) / OBK * OBK; }
 
 // Slice buffers hold three parts per slice: real digits, imaginary digits and the
-// negated imaginary digits (so that a product never negates on the fly).
+// negated imaginary digits (so that a product never negates on the fly). Within a
+// part ("plane"), the digits of 16 rows x 64 K-positions form one contiguous KiB
+// (row-block major, then K-block), so a 64-lane load of 16 bytes per lane moves
+// one whole block; inside a block a row is 64 bytes whose four 16-byte chunks are
+// stored in the order chunk ^ f(row) (f below), which spreads the fragment reads of
+// consecutive rows over the LDS banks after the block is copied as it is.
 constexpr int kParts = 3;
-size_t oz_slice_bytes(int rows, int K, int S) { return (size_t)S * kParts * rows * oz_kp(K); }
+__host__ __device__ inline int oz_rows_pad(int rows) { return (rows + 15) / 16 * 16; }
+__host__ __device__ inline int chunk_swz(int row) { return ((row >> 1) ^ (row >> 3)) & 3; }
+__host__ __device__ inline long oz_plane_bytes(int rows, int Kp) { return (long)oz_rows_pad(rows) * Kp; }
+// byte of (row, k) inside a plane with KB = Kp / 64 K-blocks
+__device__ inline long oz_off(int row, int k, int KB) {
+  return ((long)(row >> 4) * KB + (k >> 6)) * 1024 + (row & 15) * 64 + ((((k >> 4) & 3) ^ chunk_swz(row)) << 4) +
+         (k & 15);
+}
+size_t oz_slice_bytes(int rows, int K, int S) { return (size_t)S * kParts * oz_plane_bytes(rows, oz_kp(K)); }
 
 // ------------------------------------------------------------------- splitting
 
@@ -70,8 +83,9 @@ __device__ inline int fp_digit(double& r) {
   return (int)d;
 }
 
-// Slices of the columns of X (K x ncols, leading dim ld): out[(s*2+part)*ncols + c][k].
-// These serve as B, and as op(A) = X^H when the product applies the conjugation.
+// Slices of the columns of X (K x ncols, leading dim ld), one block per column of
+// the padded count (padding columns get zero digits). These serve as B, and as
+// op(A) = X^H when the product applies the conjugation.
 __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __restrict__ X,
                                                                  const zc* __restrict__ Xlo, long ld,
                                                                  int K, int ncols, int S, int Kp,
@@ -80,6 +94,17 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
   __shared__ double red[kSplitNT / 64];
   __shared__ int e_sh;
   const int col = blockIdx.x;
+  const long plane = oz_plane_bytes(ncols, Kp);
+  const long stride = (long)kParts * plane;  // slice s -> s+1
+  const int KB = Kp / 64;
+  if (col >= ncols) {
+    for (int k = threadIdx.x; k < Kp; k += kSplitNT) {
+      const long o = oz_off(col, k, KB);
+      for (int s = 0; s < S; s++)
+        for (int p = 0; p < kParts; p++) out[s * stride + p * plane + o] = 0;
+    }
+    return;
+  }
   const zc* x = X + (long)col * ld;
   const zc* xl = Xlo ? Xlo + (long)col * ld : nullptr;
   double m = 0;
@@ -96,11 +121,11 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
   }
   __syncthreads();
   const int e = e_sh;
-  const long stride = (long)kParts * ncols * Kp;  // slice s -> s+1
-  int8_t* o_re = out + (long)col * Kp;
-  int8_t* o_im = out + ((long)ncols + col) * Kp;
-  int8_t* o_ni = out + (2L * ncols + col) * Kp;
   for (int k = threadIdx.x; k < Kp; k += kSplitNT) {
+    const long o = oz_off(col, k, KB);
+    int8_t* o_re = out + o;
+    int8_t* o_im = out + plane + o;
+    int8_t* o_ni = out + 2 * plane + o;
     if (k < K) {
       const zc v = x[k];
       if (xl) {
@@ -108,25 +133,25 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
         double rh = ldexp(v.re, -e), rl = ldexp(w.re, -e);
         double ih = ldexp(v.im, -e), il = ldexp(w.im, -e);
         for (int s = 0; s < S; s++) {
-          o_re[s * stride + k] = (int8_t)dd_digit(rh, rl);
+          o_re[s * stride] = (int8_t)dd_digit(rh, rl);
           const int di = dd_digit(ih, il);
-          o_im[s * stride + k] = (int8_t)di;
-          o_ni[s * stride + k] = (int8_t)(-di);
+          o_im[s * stride] = (int8_t)di;
+          o_ni[s * stride] = (int8_t)(-di);
         }
       } else {
         double r = ldexp(v.re, -e), i = ldexp(v.im, -e);
         for (int s = 0; s < S; s++) {
-          o_re[s * stride + k] = (int8_t)fp_digit(r);
+          o_re[s * stride] = (int8_t)fp_digit(r);
           const int di = fp_digit(i);
-          o_im[s * stride + k] = (int8_t)di;
-          o_ni[s * stride + k] = (int8_t)(-di);
+          o_im[s * stride] = (int8_t)di;
+          o_ni[s * stride] = (int8_t)(-di);
         }
       }
     } else {
       for (int s = 0; s < S; s++) {
-        o_re[s * stride + k] = 0;
-        o_im[s * stride + k] = 0;
-        o_ni[s * stride + k] = 0;
+        o_re[s * stride] = 0;
+        o_im[s * stride] = 0;
+        o_ni[s * stride] = 0;
       }
     }
   }
@@ -166,8 +191,8 @@ __global__ void oz_exp_fix_kernel(int* __restrict__ exps, int M) {
   if (r < M && exps[r] == kNoExp) exps[r] = 0;
 }
 
-// Slices of the rows of X: out[(s*2+part)*M + i][k]; one block per 32 x 32 tile,
-// staged through LDS so that reads follow the columns and writes the rows.
+// Slices of the rows of X; one block per 32 x 32 tile, staged through LDS so that
+// reads follow the columns and writes the rows (padding rows get zero digits).
 __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __restrict__ X,
                                                                  const zc* __restrict__ Xlo, long ld,
                                                                  int M, int K, int S, int Kp,
@@ -193,7 +218,17 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
   __syncthreads();
   const int row = threadIdx.x >> 3, kg = (threadIdx.x & 7) * 4;
   const int gi = i0 + row;
-  if (gi >= M) return;
+  if (gi >= oz_rows_pad(M)) return;
+  const long plane = oz_plane_bytes(M, Kp);
+  const long stride = (long)kParts * plane;
+  const long o = oz_off(gi, k0 + kg, Kp / 64);  // 4 consecutive k stay in one chunk
+  int* o_re = (int*)(out + o);
+  int* o_im = (int*)(out + plane + o);
+  int* o_ni = (int*)(out + 2 * plane + o);
+  if (gi >= M) {
+    for (int s = 0; s < S; s++) o_re[s * stride / 4] = o_im[s * stride / 4] = o_ni[s * stride / 4] = 0;
+    return;
+  }
   const int e = exps[gi];
   double rh[4], rl[4], ih[4], il[4];
 #pragma unroll
@@ -209,10 +244,6 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
       rl[c] = il[c] = 0;
     }
   }
-  const long stride = (long)kParts * M * Kp;
-  int* o_re = (int*)(out + (long)gi * Kp + k0 + kg);
-  int* o_im = (int*)(out + ((long)M + gi) * Kp + k0 + kg);
-  int* o_ni = (int*)(out + (2L * M + gi) * Kp + k0 + kg);
   for (int s = 0; s < S; s++) {
     unsigned pr = 0, pi = 0, pn = 0;
 #pragma unroll
@@ -232,7 +263,7 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
 hipError_t oz_split_cols(const zc* X, const zc* Xlo, long ld, int K, int ncols, int S, int8_t* out,
                          int* exps, hipStream_t st) {
   if (ncols == 0) return hipSuccess;
-  hipLaunchKernelGGL(oz_split_cols_kernel, dim3(ncols), dim3(kSplitNT), 0, st, X, Xlo, ld, K, ncols, S,
+  hipLaunchKernelGGL(oz_split_cols_kernel, dim3(oz_rows_pad(ncols)), dim3(kSplitNT), 0, st, X, Xlo, ld, K, ncols, S,
                      oz_kp(K), out, exps);
   return hipGetLastError();
 }
@@ -289,7 +320,8 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
   const int m0 = (first_m + within % gsize) * OBM, n0 = (within / gsize) * OBN;
 
   const int KT = a.Kp / OBK;
-  const long sA = (long)kParts * g.m * a.Kp, sB = (long)kParts * g.n * a.Kp;  // bytes per slice
+  const long pA = oz_plane_bytes(g.m, a.Kp), pB = oz_plane_bytes(g.n, a.Kp);  // bytes per part
+  const long sA = kParts * pA, sB = kParts * pB;                              // bytes per slice
 
   double out_re[16], out_im[16];
 #pragma unroll
@@ -304,16 +336,14 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
       const int part = idx >> 9, row = (idx >> 2) & 127, ch = idx & 3;
       const int gi = m0 + row;
       v4i v = {0, 0, 0, 0};
-      if (gi < g.m)
-        v = *(const v4i*)(a.A + (long)(s - 1) * sA + ((long)part * g.m + gi) * a.Kp + kt * OBK + ch * 16);
+      if (gi < g.m) v = *(const v4i*)(a.A + (long)(s - 1) * sA + part * pA + oz_off(gi, kt * OBK + ch * 16, KT));
       ra[r] = v;
     }
     {
       const int part = tid >> 8, col = (tid >> 2) & 63, ch = tid & 3;
       const int gj = n0 + col;
       v4i v = {0, 0, 0, 0};
-      if (gj < g.n)
-        v = *(const v4i*)(a.B + (long)(t - 1) * sB + ((long)part * g.n + gj) * a.Kp + kt * OBK + ch * 16);
+      if (gj < g.n) v = *(const v4i*)(a.B + (long)(t - 1) * sB + part * pB + oz_off(gj, kt * OBK + ch * 16, KT));
       rb = v;
     }
   };
@@ -404,15 +434,13 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
 // four 16-byte chunks are stored in the order chunk ^ f(row),
 // f(row) = ((row >> 1) ^ (row >> 3)) & 3, so that fragment reads of 32 consecutive
 // rows at one chunk spread over all banks.
-constexpr int PBM = 128, PBN = 128, PNT = 256, kSeg = 1024, kStages = 3;
+constexpr int PBM = 128, PBN = 128, PNT = 256, kSeg = 1024, kStages = 2;
 constexpr int kRowBytes = 64, kPartBytes = PBM * kRowBytes;            // 8 KiB
 constexpr int kStageBytes = 5 * kPartBytes;                             // 3 A parts + 2 B parts
 constexpr int kLoadsPerWave = 5 * (PBM / 16) / (PNT / 64);              // 10 wave instructions
 
 typedef __attribute__((address_space(3))) void lds_ptr_t;
 typedef __attribute__((address_space(1))) const void gbl_ptr_t;
-
-__device__ inline int chunk_swz(int row) { return ((row >> 1) ^ (row >> 3)) & 3; }
 
 // s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4,
 // lgkmcnt 11:8; a field at its maximum does not wait).
@@ -422,9 +450,8 @@ constexpr int kWaitVmStep = 0x0F70 | kLoadsPerWave;  // vmcnt(10): one step in f
 static_assert(kLoadsPerWave < 16, "vmcnt immediate");
 
 template <int EPI, bool DD>
-__global__ __launch_bounds__(PNT, 1) void oz_gemm2_kernel(OzArgs a) {
+__global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(2))) void oz_gemm2_kernel(OzArgs a) {
   extern __shared__ __align__(16) int8_t lds[];  // kStages * kStageBytes
-  __shared__ double red[PNT / 64];
   const GemmArgs& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
@@ -444,7 +471,8 @@ __global__ __launch_bounds__(PNT, 1) void oz_gemm2_kernel(OzArgs a) {
   const int m0 = (first_m + within % gsize) * PBM, n0 = (within / gsize) * PBN;
 
   const int KT = a.Kp / OBK;
-  const long sA = (long)kParts * g.m * a.Kp, sB = (long)kParts * g.n * a.Kp;
+  const long pA = oz_plane_bytes(g.m, a.Kp), pB = oz_plane_bytes(g.n, a.Kp);
+  const long sA = kParts * pA, sB = kParts * pB;
   const int pa2 = a.conjA ? 1 : 2, pa3 = a.conjA ? 2 : 1;
   // per wave 4096 (x, y, v, lane) partial sums; the double-double product keeps
   // each as a three-term expansion (see the fold)
@@ -452,25 +480,26 @@ __global__ __launch_bounds__(PNT, 1) void oz_gemm2_kernel(OzArgs a) {
   double2* sp = a.scratch ? a.scratch + ((long)bid * 4 + wave) * (DD ? 3 * kWave : kWave) + lane : nullptr;
 
   // This lane's part of the wave's load instructions: instruction j of wave w is
-  // q = w * 10 + j; q < 24 covers A part q / 8, rows 16 (q % 8) + lane / 4; the
-  // rest B part (q - 24) / 8. Rows past the matrix read its last row (their
-  // outputs are not stored). Offsets are relative to slice 1, K-tile 0.
+  // q = w * 10 + j; q < 24 covers A part q / 8, row block q % 8 of the tile; the
+  // rest B part (q - 24) / 8. Each instruction copies one KiB block of the digit
+  // planes as it is (lane l: bytes 16 l .. 16 l + 15). Row blocks past the matrix
+  // read its last block (their outputs are not stored). Offsets are relative to
+  // slice 1, K-tile 0.
   const int uwave = __builtin_amdgcn_readfirstlane(wave);
+  const int RBA = oz_rows_pad(g.m) / 16, RBB = oz_rows_pad(g.n) / 16;
   int goff[kLoadsPerWave];
 #pragma unroll
   for (int j = 0; j < kLoadsPerWave; j++) {
     const int q = uwave * kLoadsPerWave + j;
     const bool isA = q < 24;
     const int qq = isA ? q : q - 24;
-    const int part = qq >> 3, row = 16 * (qq & 7) + (lane >> 2);
-    const int chunk = (lane & 3) ^ chunk_swz(row);
-    const int lim = isA ? g.m : g.n;
-    const int grow = min((isA ? m0 : n0) + row, lim - 1);
-    goff[j] = (part * lim + grow) * a.Kp + chunk * 16;
+    const int part = qq >> 3;
+    const int rb = min((isA ? m0 : n0) / 16 + (qq & 7), (isA ? RBA : RBB) - 1);
+    goff[j] = (int)(part * (isA ? pA : pB)) + rb * KT * 1024 + lane * 16;
   }
   auto issue = [&](int s, int t, int kt, int stage) {
-    const int8_t* baseA = a.A + (long)(s - 1) * sA + kt * OBK;
-    const int8_t* baseB = a.B + (long)(t - 1) * sB + kt * OBK;
+    const int8_t* baseA = a.A + (long)(s - 1) * sA + kt * 1024;
+    const int8_t* baseB = a.B + (long)(t - 1) * sB + kt * 1024;
 #pragma unroll
     for (int j = 0; j < kLoadsPerWave; j++) {
       const int q = uwave * kLoadsPerWave + j;
@@ -557,45 +586,34 @@ __global__ __launch_bounds__(PNT, 1) void oz_gemm2_kernel(OzArgs a) {
         const int q = seg0 + st, s = s_lo + q / KT;
         issue(s, d - s, q % KT, st % kStages);
       };
-      // Schedule of step st (stage st % 3):
-      //   read K-half 1 of st | MFMAs of K-half 0 of st |
-      //   wait for step st+1's loads, barrier | issue step st+2's loads |
-      //   read K-half 0 of st+1 | MFMAs of K-half 1 of st.
-      // A stage is rewritten two barriers after its last fragment read.
+      // Schedule of step st (stage st % 2): wait for its loads, barrier (its data
+      // are visible; the other stage is no longer read), issue step st+1's loads
+      // into the other stage, read the fragments of both K-halves, MFMAs. Two
+      // blocks share a CU (80 KiB of LDS each), so one block's waits overlap the
+      // other's MFMAs.
       __builtin_amdgcn_s_waitcnt(kWaitVm0);
       barrier();  // the previous segment no longer reads the ring
       issue_step(0);
-      if (steps > 1) issue_step(1);
-      if (steps > 1) __builtin_amdgcn_s_waitcnt(kWaitVmStep);
-      else __builtin_amdgcn_s_waitcnt(kWaitVm0);
-      barrier();
-      if (steps > 2) issue_step(2);
-      Frags f0, f1;
-      load_frags(f0, 0, 0);
       for (int st = 0; st < steps; st++) {
-        const int cur = st % kStages;
+        const int cur = st & 1;
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        barrier();
+        if (st + 1 < steps) issue_step(st + 1);
+        Frags f0, f1;
+        load_frags(f0, cur, 0);
         load_frags(f1, cur, 1);
         mfmas(f0);
-        if (st + 1 < steps) {
-          // step st+1's loads complete: at most step st+2's are still in flight
-          if (st + 2 < steps) __builtin_amdgcn_s_waitcnt(kWaitVmStep);
-          else __builtin_amdgcn_s_waitcnt(kWaitVm0);
-          barrier();
-          if (st + 3 < steps) issue_step(st + 3);
-          load_frags(f0, (st + 1) % kStages, 0);
-        }
         mfmas(f1);
       }
       // fold: partial = previous partial + acc 2^{-7 d} (acc 2^{-7 d} is exact in FP64)
       const double sc = ldexp(1.0, -7 * d);
-#pragma unroll
-      for (int x = 0; x < 2; x++)
-#pragma unroll
-        for (int y = 0; y < 2; y++)
+      // one 32 x 32 block at a time (the empty asm keeps the blocks' scratch
+      // accesses apart, which bounds the registers the fold needs)
+      auto fold_block = [&](const v16i& ar, const v16i& ai, int x, int y) {
 #pragma unroll
           for (int v = 0; v < 16; v++) {
             const int o = ((x * 2 + y) * 16 + v) * 64;
-            double re = (double)acc_re[x][y][v] * sc, im = (double)acc_im[x][y][v] * sc;
+            double re = (double)ar[v] * sc, im = (double)ai[v] * sc;
             // double-double: the partial sum is a0 + a1 + a2, extended with two exact
             // TwoSum steps per fold; the partial sums can exceed the final value by
             // the ratio of the row/column scales to it, which a two-term sum would
@@ -650,10 +668,19 @@ __global__ __launch_bounds__(PNT, 1) void oz_gemm2_kernel(OzArgs a) {
               }
             }
           }
+      };
+      fold_block(acc_re[0][0], acc_im[0][0], 0, 0);
+      asm volatile("" ::: "memory");
+      fold_block(acc_re[0][1], acc_im[0][1], 0, 1);
+      asm volatile("" ::: "memory");
+      fold_block(acc_re[1][0], acc_im[1][0], 1, 0);
+      asm volatile("" ::: "memory");
+      fold_block(acc_re[1][1], acc_im[1][1], 1, 1);
       first = false;
     }
   }
-  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<PNT>(g, part, red, bid);
+  // the ring is free after the last segment: its first bytes hold the block reduction
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<PNT>(g, part, (double*)lds, bid);
 }
 
 // The large-tile kernel is used when it still gives every CU a tile, and for

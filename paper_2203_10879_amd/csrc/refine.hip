@@ -218,14 +218,16 @@ int oz_update(const zc* Q, const zc* D, zc* Qout, zc* QHout, int n, int Su, cons
   return SR_OK;
 }
 
-// Digits per operand of Q Delta: the dropped part of each operand is below
-// 2^(-7 Su) of its row or column scale, so Su is taken with 2^(-7 Su) ||Delta||_F
-// under 0.05 u (plus one digit for the pairs dropped beyond Su + 1).
+// Digits per operand of Q Delta. With pairs kept up to s + t = Su + 1, the
+// product is exact to about 2^(-7 Su) relative to sum_k |q_ik| |delta_kj|
+// <= ||q_i|| ||delta_j||; Q's rows have norm ~1 and its entries ~1/sqrt(n), a
+// column of Delta ~||Delta||_F / sqrt(n), so the error relative to Q's entries is
+// ~2^(-7 Su) ||Delta||_F, and Su is the least count with that under 0.05 u.
 int update_slices(const sr_opts& o, double norm_delta) {
   if (o.update_slices > 0) return o.update_slices;
   if (!(norm_delta > 0)) return kOzMinUpd;
   const double bits = log2(norm_delta / (0.05 * kU64));
-  int s = (int)ceil(bits / 7.0) + 1;
+  int s = (int)ceil(bits / 7.0);
   if (s < kOzMinUpd) s = kOzMinUpd;
   if (s > kOzMaxUpd) s = kOzMaxUpd;
   return s;
@@ -729,7 +731,7 @@ int dd_update_slices(const sr_opts& o, int S, double norm_delta) {
   if (o.update_slices > 0) return o.update_slices;
   if (o.update_slices == 0) return S;
   if (!(norm_delta > 0)) return 2;
-  int s = (int)ceil(log2(norm_delta / (0.05 * kUDD)) / 7.0) + 1;
+  int s = (int)ceil(log2(norm_delta / (0.05 * kUDD)) / 7.0);
   if (s < 2) s = 2;
   if (s > kDDMaxUpd) s = kDDMaxUpd;
   return s;
