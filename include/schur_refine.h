@@ -63,11 +63,11 @@ typedef enum {
 
 typedef struct {
   int gemm;               /* sr_gemm_mode for the hp products                         */
-  int slices;             /* SR_GEMM_OZAKI_I8: 7-bit digits per operand of P = A Q and
+  int slices;             /* SR_GEMM_OZAKI_I8: 8-bit digits per operand of P = A Q and
                              of the start's Gram matrix, slice pairs up to s + t =
-                             slices + 1 (0 = default 8, at most 16)                   */
+                             slices + 1 (0 = default 7, at most 16)                   */
   int update_slices;      /* SR_GEMM_OZAKI_I8: digits per operand of Q * Delta
-                             (0 = chosen per update from ||Delta||_F, 2..8)           */
+                             (0 = chosen per update from ||Delta||_F, 2..7)           */
   int compensated;        /* 1: chunked K accumulation with error-free (TwoSum)
                              combination in the FP64 products P, That and Y            */
   int gate_lp_terms;      /* 1: skip YW, W^2, W^3 whose Frobenius bound is below
@@ -150,13 +150,13 @@ int sr_batched_tile_edge(int n);
  * Newton-Schulz start and Q Delta) is an Ozaki split product of the double-double
  * operands on INT8 MFMA with double-double accumulation; the solve and the lp
  * products YW, W^2, W^3 run in FP64, gated against 0.1 * 2^-104.
- *  opts->slices: digits per operand of the hp products (0 = 15, at most 32). The
- *    digits of a row or column are relative to its largest entry, so a matrix
+ *  opts->slices: 8-bit digits per operand of the hp products (0 = 14, at most 32).
+ *    The digits of a row or column are relative to its largest entry, so a matrix
  *    whose rows or columns span many orders of magnitude needs more digits to keep
- *    its small entries to double-double accuracy (15 digits cover 105 bits);
+ *    its small entries to double-double accuracy (14 digits cover about 111 bits);
  *  opts->update_slices: digits of Q Delta: 0 = the same as opts->slices (the digits
  *    of Q are relative to its row maxima, and the Schur vectors of a badly scaled
- *    matrix have entries far below them); -1 = chosen from ||Delta|| (2..16, for
+ *    matrix have entries far below them); -1 = chosen from ||Delta|| (2..14, for
  *    well-scaled matrices); otherwise the count given (at most 32);
  *  opts->gemm and opts->compensated are ignored. The stagnation floor is
  *  100 * 2^-104 * sqrt(n). Outputs and statuses as for schur_refine. */
@@ -224,11 +224,14 @@ int sr_ns_init(const void* Qh, void* Q, int n, int compensated, void* ws, void* 
 
 /* Ozaki split product (the hp products of Section 4 built from an Ozaki-scheme
  * splitting) on INT8 MFMA: C = op(A) B (+ Cin), complex128, arguments as sr_zgemm.
- * op(A) is split into slices_a 7-bit slices per row, B into slices_b per column
- * (each with a power-of-two scale per row / column); slice pairs (s, t) with
+ * op(A) is split into slices_a slices of balanced 8-bit digits per row, B into
+ * slices_b per column (each with a power-of-two scale per row / column, about
+ * 8 * slices - 1 bits below the row / column maximum); slice pairs (s, t) with
  * s + t <= dmax are multiplied exactly in int32 and combined in FP64. dmax =
- * slices_a + slices_b keeps every pair. Requires pairs-per-diagonal * k * 127^2 <
- * 2^31 (SR_EINVAL otherwise). ws: device workspace of >= sr_ozaki_ws_bytes(...). */
+ * slices_a + slices_b keeps every pair. Outputs with fewer than 256 tiles of
+ * 128 x 128 require min(slices_a, slices_b) * k * 2^14 < 2^31 (SR_EINVAL
+ * otherwise); larger ones are exact for every k.
+ * ws: device workspace of >= sr_ozaki_ws_bytes(...). */
 size_t sr_ozaki_ws_bytes(int m, int n, int k, int slices_a, int slices_b);
 int sr_ozaki_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
                    const void* Cin, int ldcin, void* C, int ldc, int slices_a, int slices_b,
@@ -237,9 +240,9 @@ int sr_ozaki_zgemm(int opa, int m, int n, int k, const void* A, int lda, const v
 /* Double-double operands and result: C_hi + C_lo = op(A_hi + A_lo) (B_hi + B_lo)
  * (+ Cin_hi + Cin_lo), each pair stored as two complex128 matrices with a shared
  * leading dimension. The digits are taken from the exact double-double values, the
- * pair sums are exact in int32 and are accumulated in double-double, so with 16
- * digits per operand and dmax = 17 the result carries about 2^-105 relative to the
- * row and column scales. A_lo, B_lo, Cin_lo may be NULL (zero). ws as above. */
+ * pair sums are exact in int32 and are accumulated in double-double, so with 14
+ * digits per operand and dmax = 15 the result carries about 2^-106 relative to the
+ * row and column maxima. A_lo, B_lo, Cin_lo may be NULL (zero). ws as above. */
 int sr_ozaki_zgemm_dd(int opa, int m, int n, int k, const void* A_hi, const void* A_lo, int lda,
                       const void* B_hi, const void* B_lo, int ldb, const void* Cin_hi,
                       const void* Cin_lo, int ldcin, void* C_hi, void* C_lo, int ldc,

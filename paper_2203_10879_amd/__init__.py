@@ -264,7 +264,7 @@ def sr_zgemm(A, B, C, opa: int = 0, Cin=None, compensated: bool = False, stream=
                           int(bool(compensated)), _stream(stream))
 
 
-def sr_ozaki_zgemm(A, B, C, opa: int = 0, slices_a: int = 8, slices_b: int = 8, dmax=None, Cin=None,
+def sr_ozaki_zgemm(A, B, C, opa: int = 0, slices_a: int = 7, slices_b: int = 7, dmax=None, Cin=None,
                    ws=None, stream=None) -> int:
     """Ozaki split product on INT8 MFMA (see include/schur_refine.h)."""
     import torch
@@ -282,8 +282,8 @@ def sr_ozaki_zgemm(A, B, C, opa: int = 0, slices_a: int = 8, slices_b: int = 8, 
                                 ws.numel() * ws.element_size(), _stream(stream))
 
 
-def sr_ozaki_zgemm_dd(A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, opa: int = 0, slices_a: int = 16,
-                      slices_b: int = 16, dmax=None, Cin_hi=None, Cin_lo=None, ws=None,
+def sr_ozaki_zgemm_dd(A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, opa: int = 0, slices_a: int = 14,
+                      slices_b: int = 14, dmax=None, Cin_hi=None, Cin_lo=None, ws=None,
                       stream=None) -> int:
     """Double-double Ozaki split product (see include/schur_refine.h)."""
     import torch

@@ -38,14 +38,14 @@ __device__ inline void cfms(cplx<R>& a, cplx<R> b, cplx<R> c) {
 }
 
 // Error-free sum s + e = a + b (Knuth).
-__device__ inline void two_sum(double a, double b, double& s, double& e) {
+__host__ __device__ inline void two_sum(double a, double b, double& s, double& e) {
   s = a + b;
   double bb = s - a;
   e = (a - (s - bb)) + (b - bb);
 }
 
 // Double-double arithmetic (Dekker, Knuth): a value is hi + lo with |lo| <= ulp(hi)/2.
-__device__ inline void fast_two_sum(double a, double b, double& s, double& e) {
+__host__ __device__ inline void fast_two_sum(double a, double b, double& s, double& e) {
   s = a + b;
   e = b - (s - a);
 }

@@ -90,6 +90,8 @@ hipError_t oz_split_rows(const zc* X, const zc* Xlo, long ld, int M, int K, int 
 int oz_gemm_tiles(int m, int n, bool dd = false);
 // Bytes of scratch the product of an m x n output needs (0 for small FP64 outputs).
 size_t oz_gemm_scratch_bytes(int m, int n, bool dd = false);
+// Whether the int32 sums of a product stay exact for these sizes.
+bool oz_gemm_exact(int m, int n, int k, int SA, int SB, bool dd = false);
 hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t* B, const int* eb,
                    int SB, int conjA, int dmax, GemmArgs g, void* scratch, hipStream_t st,
                    bool dd = false);

@@ -4,22 +4,27 @@
 // accumulation.
 //
 // Splitting. For an operand role, every row of op(A) (every column of B) gets a
-// power-of-two scale 2^e with max |re|, |im| < 2^e over the row (column). A value
-// x is written as 2^e sum_{s=1..S} d_s 2^{-7 s} with integer digits
-// d_s in [-127, 127], taken by truncation toward zero: r = x 2^-e; d = trunc(128 r);
-// r = 128 r - d. Each step is exact in FP64 (double-double inputs are split the
-// same way with an exact double-double remainder), so the retained digits
-// reproduce x up to 2^(e - 7 S).
+// power-of-two scale 2^e, the least with 256 m / 2^e < 126 for the largest
+// |re|, |im| m over the row (column). A value x is written as
+// 2^e sum_{s=1..S} d_s 2^{-8 s} with balanced radix-256 digits d_s in
+// [-128, 127] (eight bits each, the full int8 range): r = x 2^-e; raw digit
+// d = rint(256 r) in [-128, 128], r = 256 r - d in [-1/2, 1/2]; a raw 128 becomes
+// -128 with a carry of one into the digit above, and carries ripple through raw
+// 127s (resolved from two bit masks, see digit_carries). The top digit is at most
+// 126 before its carry, so no carry leaves the expansion. Each step is exact in
+// FP64 (double-double inputs are split the same way with an exact double-double
+// remainder), so the retained digits reproduce x up to 2^(e - 8 S - 1), about
+// 2^(-8 S + 1) of the row maximum.
 //
-// Product. C_ij = 2^(e_i + f_j) sum_{s,t} 2^{-7(s+t)} (A_s B_t)_ij. The slice
+// Product. C_ij = 2^(e_i + f_j) sum_{s,t} 2^{-8(s+t)} (A_s B_t)_ij. The slice
 // pairs are grouped by d = s + t; within one d every pair has the same scale, so
-// their products are summed exactly in int32 (|sum| <= pairs * 2 K * 127^2 <
-// 2^31 for the sizes the host admits) with v_mfma_i32_32x32x32_i8 (the INT8 form
-// that runs at the full matrix rate; the 16 x 16 x 64 form runs at half), and the int32
-// sums are folded into FP64 accumulators with scale 2^{-7 d} once d is done.
-// Pairs with s + t > dmax are dropped (their weight is below 2^{-7 dmax}). A
-// complex product keeps four real accumulators (re*re, im*im, re*im, im*re) so
-// that op(A) = conj(A slices) only changes signs at the fold.
+// their products are summed exactly in int32 (each digit product is at most 2^14
+// in magnitude; the host admits sizes that keep the sums below 2^31) with v_mfma_i32_32x32x32_i8 (the INT8 form that runs at the full
+// matrix rate; the 16 x 16 x 64 form runs at half), and the int32 sums are folded
+// into FP64 accumulators with scale 2^{-8 d} once d is done. Pairs with
+// s + t > dmax are dropped (their weight is below 2^{-8 dmax}). A complex product
+// keeps four real accumulators (re*re, im*im, re*im, im*re) so that
+// op(A) = conj(A slices) only changes signs at the fold.
 //
 // Tiling: a 512-thread block computes a 128 x 64 complex tile; its eight waves
 // (4 along M x 2 along N) each own one 32 x 32 block. Per step the block
@@ -58,29 +63,88 @@ size_t oz_slice_bytes(int rows, int K, int S) { return (size_t)S * kParts * oz_p
 
 // ------------------------------------------------------------------- splitting
 
-__device__ inline int scale_exponent(double m) {
+__host__ __device__ inline int scale_exponent(double m) {
   if (!(m > 0)) return 0;
   int e;
   frexp(m, &e);  // m = f 2^e, f in [0.5, 1): m < 2^e
   return e;
 }
 
-// One digit of x in (-128, 128) given as a double-double (yh, yl): truncation
-// toward zero of the exact value, and the exact remainder.
-__device__ inline int dd_digit(double& rh, double& rl) {
-  const double yh = rh * 128.0, yl = rl * 128.0;
-  double d = trunc(yh);
-  if (d == yh && yl != 0.0 && ((yl < 0.0) != (yh < 0.0)) && yh != 0.0) d -= (yh > 0.0 ? 1.0 : -1.0);
-  const double t = yh - d;  // exact: |yh - d| <= 1
-  two_sum(t, yl, rh, rl);
+// Scale exponent of a row (column) with largest magnitude m: the least e with
+// 256 m / 2^e < 126 (m 256 / 126 is rounded at most twice, which keeps
+// 256 |x| / 2^e below 126.5 for every |x| <= m(1 + 2^-52), so the top raw digit
+// is at most 126).
+__host__ __device__ inline int digit_exponent(double m) { return scale_exponent(m * (256.0 / 126.0)); }
+
+// Raw balanced digit of r in [-1/2, 1/2] (the first call: |r| < 126.5 / 256):
+// d = rint(256 r) in [-128, 128], r = 256 r - d in [-1/2, 1/2], both exact.
+__host__ __device__ inline int raw_digit(double& r) {
+  const double y = r * 256.0;
+  const double d = rint(y);
+  r = y - d;
   return (int)d;
 }
 
-__device__ inline int fp_digit(double& r) {
-  const double y = r * 128.0;
-  const double d = trunc(y);
-  r = y - d;  // exact fractional part
+// The same for a double-double remainder (rh, rl): d rounds the exact value, the
+// remainder stays exact and within [-1/2, 1/2].
+__host__ __device__ inline int raw_digit_dd(double& rh, double& rl) {
+  const double yh = rh * 256.0, yl = rl * 256.0;
+  double d = rint(yh);
+  double h, l;
+  two_sum(yh - d, yl, h, l);  // yh - d is exact, |yh - d| <= 1/2
+  if (h > 0.5 || (h == 0.5 && l > 0.0)) {
+    d += 1.0;
+    h -= 1.0;  // exact: h is within an ulp of 1/2
+  } else if (h < -0.5 || (h == -0.5 && l < 0.0)) {
+    d -= 1.0;
+    h += 1.0;
+  }
+  rh = h;
+  rl = l;
   return (int)d;
+}
+
+// Carries of a raw digit string. Digit s (1..S) sits at bit S - s; raw 128
+// generates a carry into the digit above, raw 127 passes an incoming one on. The
+// carry into every position is that of the binary sum G + (G | P), i.e.
+// (G + (G | P)) ^ G ^ (G | P).
+__host__ __device__ inline uint64_t digit_carries(uint64_t gen, uint64_t prop) {
+  const uint64_t gp = gen | prop;
+  return (gen + gp) ^ gen ^ gp;
+}
+
+// Final digit s (1..S) from its raw value and the carry mask.
+__host__ __device__ inline int8_t final_digit(int raw, uint64_t carries, int s, int S) {
+  int v = raw + (int)((carries >> (S - s)) & 1u);
+  if (v > 127) v -= 256;
+  return (int8_t)v;
+}
+
+// Carry masks of x and of -x (whose raw digits are the negated raw digits of x,
+// rint being symmetric) from a first pass over the raw digits of x. The
+// imaginary parts are stored negated too; -x has its own carries (a raw -128 of x
+// is a raw 128 of -x).
+struct Carries {
+  uint64_t pos, neg;
+};
+
+__host__ __device__ inline void note_digit(int d, uint64_t bit, uint64_t (&m)[4]) {
+  if (d == 128) m[0] |= bit;
+  if (d == 127) m[1] |= bit;
+  if (d == -128) m[2] |= bit;
+  if (d == -127) m[3] |= bit;
+}
+
+__host__ __device__ inline Carries value_carries(double r, int S) {
+  uint64_t m[4] = {0, 0, 0, 0};
+  for (int s = 1; s <= S; s++) note_digit(raw_digit(r), 1ull << (S - s), m);
+  return {digit_carries(m[0], m[1]), digit_carries(m[2], m[3])};
+}
+
+__host__ __device__ inline Carries value_carries_dd(double rh, double rl, int S) {
+  uint64_t m[4] = {0, 0, 0, 0};
+  for (int s = 1; s <= S; s++) note_digit(raw_digit_dd(rh, rl), 1ull << (S - s), m);
+  return {digit_carries(m[0], m[1]), digit_carries(m[2], m[3])};
 }
 
 // Slices of the columns of X (K x ncols, leading dim ld), one block per column of
@@ -116,7 +180,7 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
   if (threadIdx.x == 0) {
     double t = 0;
     for (int w = 0; w < kSplitNT / 64; w++) t = fmax(t, red[w]);
-    e_sh = scale_exponent(t);
+    e_sh = digit_exponent(t);
     exps[col] = e_sh;
   }
   __syncthreads();
@@ -132,19 +196,21 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
         const zc w = xl[k];
         double rh = ldexp(v.re, -e), rl = ldexp(w.re, -e);
         double ih = ldexp(v.im, -e), il = ldexp(w.im, -e);
+        const Carries cr = value_carries_dd(rh, rl, S), ci = value_carries_dd(ih, il, S);
         for (int s = 0; s < S; s++) {
-          o_re[s * stride] = (int8_t)dd_digit(rh, rl);
-          const int di = dd_digit(ih, il);
-          o_im[s * stride] = (int8_t)di;
-          o_ni[s * stride] = (int8_t)(-di);
+          o_re[s * stride] = final_digit(raw_digit_dd(rh, rl), cr.pos, s + 1, S);
+          const int di = raw_digit_dd(ih, il);
+          o_im[s * stride] = final_digit(di, ci.pos, s + 1, S);
+          o_ni[s * stride] = final_digit(-di, ci.neg, s + 1, S);
         }
       } else {
         double r = ldexp(v.re, -e), i = ldexp(v.im, -e);
+        const Carries cr = value_carries(r, S), ci = value_carries(i, S);
         for (int s = 0; s < S; s++) {
-          o_re[s * stride] = (int8_t)fp_digit(r);
-          const int di = fp_digit(i);
-          o_im[s * stride] = (int8_t)di;
-          o_ni[s * stride] = (int8_t)(-di);
+          o_re[s * stride] = final_digit(raw_digit(r), cr.pos, s + 1, S);
+          const int di = raw_digit(i);
+          o_im[s * stride] = final_digit(di, ci.pos, s + 1, S);
+          o_ni[s * stride] = final_digit(-di, ci.neg, s + 1, S);
         }
       }
     } else {
@@ -182,7 +248,7 @@ __global__ __launch_bounds__(kSplitNT) void oz_rowmax_kernel(const zc* __restric
   __syncthreads();
   if (c == 0 && r < M) {
     const double t = fmax(fmax(red[0][threadIdx.x], red[1][threadIdx.x]), fmax(red[2][threadIdx.x], red[3][threadIdx.x]));
-    if (t > 0) atomicMax(&exps[r], scale_exponent(t));
+    if (t > 0) atomicMax(&exps[r], digit_exponent(t));
   }
 }
 
@@ -244,15 +310,21 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
       rl[c] = il[c] = 0;
     }
   }
+  Carries cr[4], ci[4];
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    cr[c] = Xlo ? value_carries_dd(rh[c], rl[c], S) : value_carries(rh[c], S);
+    ci[c] = Xlo ? value_carries_dd(ih[c], il[c], S) : value_carries(ih[c], S);
+  }
   for (int s = 0; s < S; s++) {
     unsigned pr = 0, pi = 0, pn = 0;
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-      const int dr = Xlo ? dd_digit(rh[c], rl[c]) : fp_digit(rh[c]);
-      const int di = Xlo ? dd_digit(ih[c], il[c]) : fp_digit(ih[c]);
-      pr |= (unsigned)(dr & 0xff) << (8 * c);
-      pi |= (unsigned)(di & 0xff) << (8 * c);
-      pn |= (unsigned)((-di) & 0xff) << (8 * c);
+      const int dr = Xlo ? raw_digit_dd(rh[c], rl[c]) : raw_digit(rh[c]);
+      const int di = Xlo ? raw_digit_dd(ih[c], il[c]) : raw_digit(ih[c]);
+      pr |= (unsigned)(uint8_t)final_digit(dr, cr[c].pos, s + 1, S) << (8 * c);
+      pi |= (unsigned)(uint8_t)final_digit(di, ci[c].pos, s + 1, S) << (8 * c);
+      pn |= (unsigned)(uint8_t)final_digit(-di, ci[c].neg, s + 1, S) << (8 * c);
     }
     o_re[s * stride / 4] = (int)pr;
     o_im[s * stride / 4] = (int)pi;
@@ -389,8 +461,8 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
       if (st + 1 < steps) sstore(cur ^ 1);
       __syncthreads();
     }
-    // fold diagonal d: scale 2^{-7 d}
-    const double sc = ldexp(1.0, -7 * d);
+    // fold diagonal d: scale 2^{-8 d}
+    const double sc = ldexp(1.0, -8 * d);
     const double sg = a.conjA ? 1.0 : -1.0;  // re = rr + sg ii, im = ri - sg ir
 #pragma unroll
     for (int v = 0; v < 16; v++) {
@@ -417,24 +489,25 @@ __global__ __launch_bounds__(ONT) void oz_gemm_kernel(OzArgs a) {
 // ------------------------------------------------------- large-tile product
 //
 // For products with at least one 128 x 128 tile per CU, and for every
-// double-double product. A 256-thread block (one wave per SIMD) computes a 128 x 128
-// complex tile; each wave owns 64 x 64 as 2 x 2 blocks of 32 x 32. Only two int32
-// accumulators per output are kept: with the negated imaginary digits of op(A)
-// stored beside the real and imaginary ones, re = Ar Br + (-Ai) Bi and
-// im = Ar Bi + Ai Br (conjugated op(A): re = Ar Br + Ai Bi, im = Ar Bi + (-Ai) Br),
-// all summed exactly in int32 (|sum| <= 2 * steps * 64 * 127^2, so a diagonal is
-// folded at least every kSeg steps). The FP64 partial sums live between folds in
-// a per-tile scratch laid out in the waves' register order (coalesced), not in
-// registers, so the register file holds the large wave tile.
+// double-double product. A 256-thread block computes a 128 x 128 complex tile;
+// each of its four waves owns 64 x 64 as 2 x 2 blocks of 32 x 32, and two blocks
+// share a CU (two waves per SIMD). Only two int32 accumulators per output are
+// kept: with the negated imaginary digits of op(A) stored beside the real and
+// imaginary ones, re = Ar Br + (-Ai) Bi and im = Ar Bi + Ai Br (conjugated op(A):
+// re = Ar Br + Ai Bi, im = Ar Bi + (-Ai) Br), all summed exactly in int32
+// (|sum| <= 2 * 64 * steps * 2^14 <= 2^30 with a diagonal folded at least every
+// kSeg = 512 steps). The FP64 partial sums live between folds in a per-tile
+// scratch laid out in the waves' register order (coalesced), not in registers,
+// so the register file holds the large wave tile.
 //
 // Staging: the K-tiles go from global memory straight into LDS
 // (global_load_lds_dwordx4: lane l of an instruction writes 16 bytes at
-// base + 16 l), through a ring of three stages, issued two steps ahead. A stage
-// holds 3 parts of op(A) and 2 of B, each 128 rows of 64 bytes; within a row the
-// four 16-byte chunks are stored in the order chunk ^ f(row),
-// f(row) = ((row >> 1) ^ (row >> 3)) & 3, so that fragment reads of 32 consecutive
-// rows at one chunk spread over all banks.
-constexpr int PBM = 128, PBN = 128, PNT = 256, kSeg = 1024, kStages = 2;
+// base + 16 l), through two stages, the next step's loads issued while the
+// current one is multiplied. A stage holds 3 parts of op(A) and 2 of B, each 128
+// rows of 64 bytes; within a row the four 16-byte chunks are stored in the order
+// chunk ^ f(row), f(row) = ((row >> 1) ^ (row >> 3)) & 3, so that fragment reads
+// of 32 consecutive rows at one chunk spread over all banks.
+constexpr int PBM = 128, PBN = 128, PNT = 256, kSeg = 512, kStages = 2;
 constexpr int kRowBytes = 64, kPartBytes = PBM * kRowBytes;            // 8 KiB
 constexpr int kStageBytes = 5 * kPartBytes;                             // 3 A parts + 2 B parts
 constexpr int kLoadsPerWave = 5 * (PBM / 16) / (PNT / 64);              // 10 wave instructions
@@ -605,8 +678,8 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(2))) void o
         mfmas(f0);
         mfmas(f1);
       }
-      // fold: partial = previous partial + acc 2^{-7 d} (acc 2^{-7 d} is exact in FP64)
-      const double sc = ldexp(1.0, -7 * d);
+      // fold: partial = previous partial + acc 2^{-8 d} (acc 2^{-8 d} is exact in FP64)
+      const double sc = ldexp(1.0, -8 * d);
       // one 32 x 32 block at a time (the empty asm keeps the blocks' scratch
       // accesses apart, which bounds the registers the fold needs)
       auto fold_block = [&](const v16i& ar, const v16i& ai, int x, int y) {
@@ -694,21 +767,36 @@ size_t oz_gemm_scratch_bytes(int m, int n, bool dd) {
   return (size_t)ceil_div(m, PBM) * ceil_div(n, PBN) * PBM * PBN * sizeof(double2) * (dd ? 3 : 1);
 }
 
+// The small-tile kernel sums one product per accumulator over a whole diagonal
+// (at most min(SA, SB) pairs of Kp terms, each at most 2^14 in magnitude); the
+// large-tile kernel folds in segments and is exact for every size.
+bool oz_gemm_exact(int m, int n, int k, int SA, int SB, bool dd) {
+  if (use_large_tiles(m, n, dd)) return true;
+  const long pairs = SA < SB ? SA : SB;
+  return pairs * (long)oz_kp(k) * 16384L < 2147483648L;
+}
+
 int oz_gemm_tiles(int m, int n, bool dd) {
   if (use_large_tiles(m, n, dd)) return ceil_div(m, PBM) * ceil_div(n, PBN);
   return ceil_div(m, OBM) * ceil_div(n, OBN);
 }
 
 template <int EPI>
-static void launch_large(bool dd, int nt, const OzArgs& a, hipStream_t st) {
+static hipError_t launch_large(bool dd, int nt, const OzArgs& a, hipStream_t st) {
   const size_t lds = (size_t)kStages * kStageBytes;
+  hipError_t e;
   if (dd) {
-    hipFuncSetAttribute((const void*)oz_gemm2_kernel<EPI, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    e = hipFuncSetAttribute((const void*)oz_gemm2_kernel<EPI, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
     oz_gemm2_kernel<EPI, true><<<dim3(nt), dim3(PNT), lds, st>>>(a);
   } else {
-    hipFuncSetAttribute((const void*)oz_gemm2_kernel<EPI, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    e = hipFuncSetAttribute((const void*)oz_gemm2_kernel<EPI, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
     oz_gemm2_kernel<EPI, false><<<dim3(nt), dim3(PNT), lds, st>>>(a);
   }
+  return hipGetLastError();
 }
 
 hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t* B, const int* eb,
@@ -722,13 +810,12 @@ hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t
     const int nt = g.tiles_m * g.tiles_n;
     OzArgs a{A, ea, B, eb, SA, SB, dmax, conjA, oz_kp(g.k), g, (double2*)scratch};
     switch (epi) {
-      case EPI_STORE: launch_large<EPI_STORE>(dd, nt, a, st); break;
-      case EPI_ADD: launch_large<EPI_ADD>(dd, nt, a, st); break;
-      case EPI_SPLIT: launch_large<EPI_SPLIT>(dd, nt, a, st); break;
-      case EPI_YDEF: launch_large<EPI_YDEF>(dd, nt, a, st); break;
+      case EPI_STORE: return launch_large<EPI_STORE>(dd, nt, a, st);
+      case EPI_ADD: return launch_large<EPI_ADD>(dd, nt, a, st);
+      case EPI_SPLIT: return launch_large<EPI_SPLIT>(dd, nt, a, st);
+      case EPI_YDEF: return launch_large<EPI_YDEF>(dd, nt, a, st);
       default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
   }
   g.tiles_m = ceil_div(g.m, OBM);
   g.tiles_n = ceil_div(g.n, OBN);

@@ -36,9 +36,10 @@ int partial_slots(int n) {
 }
 
 // Ozaki mode: slice counts. P = A Q and the Gram matrix of the start take
-// kOzSlices digits per operand (56 bits) with pairs up to s + t = kOzSlices + 1;
-// the products Q Delta take between kOzMinUpd and kOzMaxUpd, chosen from ||Delta||.
-constexpr int kOzSlices = 8, kOzMinUpd = 2, kOzMaxUpd = 8;
+// kOzSlices 8-bit digits per operand (about 55 bits below the row maxima) with
+// pairs up to s + t = kOzSlices + 1; the products Q Delta take between kOzMinUpd
+// and kOzMaxUpd, chosen from ||Delta||.
+constexpr int kOzSlices = 7, kOzMinUpd = 2, kOzMaxUpd = 7;
 
 struct Work {
   zc *Qa, *QH, *P, *Y;
@@ -219,15 +220,15 @@ int oz_update(const zc* Q, const zc* D, zc* Qout, zc* QHout, int n, int Su, cons
 }
 
 // Digits per operand of Q Delta. With pairs kept up to s + t = Su + 1, the
-// product is exact to about 2^(-7 Su) relative to sum_k |q_ik| |delta_kj|
+// product is exact to about 2^(-8 Su) relative to sum_k |q_ik| |delta_kj|
 // <= ||q_i|| ||delta_j||; Q's rows have norm ~1 and its entries ~1/sqrt(n), a
 // column of Delta ~||Delta||_F / sqrt(n), so the error relative to Q's entries is
-// ~2^(-7 Su) ||Delta||_F, and Su is the least count with that under 0.05 u.
+// ~2^(-8 Su) ||Delta||_F, and Su is the least count with that under 0.05 u.
 int update_slices(const sr_opts& o, double norm_delta) {
   if (o.update_slices > 0) return o.update_slices;
   if (!(norm_delta > 0)) return kOzMinUpd;
   const double bits = log2(norm_delta / (0.05 * kU64));
-  int s = (int)ceil(bits / 7.0);
+  int s = (int)ceil(bits / 8.0);
   if (s < kOzMinUpd) s = kOzMinUpd;
   if (s > kOzMaxUpd) s = kOzMaxUpd;
   return s;
@@ -461,7 +462,7 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   }
   if (o.gemm == SR_GEMM_OZAKI_I8 &&
       (o.slices < 0 || o.slices > 16 || o.update_slices < 0 || o.update_slices > kOzMaxUpd ||
-       (long)oz_main_slices(&o) * ((n + 63) / 64 * 64) * 127L * 127L >= 2147483647L)) {
+       !oz_gemm_exact(n, n, n, oz_main_slices(&o), oz_main_slices(&o)))) {
     if (info) info->status = SR_EINVAL;
     return SR_EINVAL;
   }
@@ -615,7 +616,7 @@ namespace {
 // (the solve and the lp products).
 
 constexpr double kUDD = 4.930380657631324e-32;  // 2^-104
-constexpr int kDDSlices = 15, kDDMaxUpd = 16;
+constexpr int kDDSlices = 14, kDDMaxUpd = 14;
 
 struct DDWork {
   zc *Qh, *Ql, *Ph, *Pl, *Yh, *Yl, *Dh, *Dl;
@@ -731,7 +732,7 @@ int dd_update_slices(const sr_opts& o, int S, double norm_delta) {
   if (o.update_slices > 0) return o.update_slices;
   if (o.update_slices == 0) return S;
   if (!(norm_delta > 0)) return 2;
-  int s = (int)ceil(log2(norm_delta / (0.05 * kUDD)) / 7.0);
+  int s = (int)ceil(log2(norm_delta / (0.05 * kUDD)) / 8.0);
   if (s < 2) s = 2;
   if (s > kDDMaxUpd) s = kDDMaxUpd;
   return s;
@@ -1009,15 +1010,6 @@ size_t sr_ozaki_ws_bytes(int m, int n, int k, int slices_a, int slices_b) {
          align256((size_t)(m + n) * sizeof(int)) + align256(oz_gemm_scratch_bytes(m, n, true));
 }
 
-// Largest slice-pair count on one diagonal times k must keep int32 sums exact.
-// (the large-tile kernel sums two products per accumulator and folds long
-// diagonals in segments, so it only needs 2 * 64 K-steps per segment bounded).
-static bool oz_exact_ok(int k, int sa, int sb) {
-  const long pairs = sa < sb ? sa : sb;
-  const long kp = (k + 63) / 64 * 64;
-  return pairs * kp * 127L * 127L < 2147483647L;
-}
-
 int sr_ozaki_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
                    const void* Cin, int ldcin, void* C, int ldc, int slices_a, int slices_b, int dmax,
                    void* ws, size_t ws_bytes, void* stream) {
@@ -1027,7 +1019,7 @@ int sr_ozaki_zgemm(int opa, int m, int n, int k, const void* A, int lda, const v
   if (k > 0 && (!A || !B)) return SR_EINVAL;
   if (lda < (opa ? (k > 1 ? k : 1) : (m > 1 ? m : 1)) || ldb < (k > 1 ? k : 1) || ldc < m) return SR_EINVAL;
   if (Cin && ldcin < m) return SR_EINVAL;
-  if (!oz_exact_ok(k, slices_a, slices_b)) return SR_EINVAL;
+  if (!oz_gemm_exact(m, n, k, slices_a, slices_b)) return SR_EINVAL;
   if (!ws || ws_bytes < sr_ozaki_ws_bytes(m, n, k, slices_a, slices_b)) return SR_ENOMEM;
   hipStream_t st = (hipStream_t)stream;
   int8_t* qa = (int8_t*)ws;

@@ -27,8 +27,9 @@ def _gauss_int(rng, shape, lim=256):
 @pytest.mark.parametrize("opa", [0, 1])
 @pytest.mark.parametrize("shape", [(130, 97, 75), (64, 64, 64), (1, 1, 1), (200, 33, 129)])
 def test_ozaki_exact_on_integers(sr, opa, shape):
-    # 9-bit integers fit in two 7-bit digits; with every slice pair kept the
-    # product is exact and so is its FP64 combination
+    # 9-bit integers fit in two 8-bit digits (the row scale leaves the top digit
+    # below 127); with every slice pair kept the product is exact and so is its
+    # FP64 combination
     m, n, k = shape
     rng = np.random.default_rng(m + 7 * n + 13 * k)
     a = _gauss_int(rng, (k, m) if opa else (m, k))
@@ -40,13 +41,13 @@ def test_ozaki_exact_on_integers(sr, opa, shape):
 
 
 @pytest.mark.parametrize("opa", [0, 1])
-def test_ozaki_fp64_faithful_with_8_slices(sr, opa):
+def test_ozaki_fp64_faithful_with_7_slices(sr, opa):
     rng = np.random.default_rng(21 + opa)
     m, n, k = 150, 131, 260
     a = rand_c(rng, (k, m) if opa else (m, k))
     b = rand_c(rng, (k, n))
     c = empty(m, n)
-    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=8, slices_b=8, dmax=9) == 0
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=7, slices_b=7, dmax=8) == 0
     chi, clo = oracle.gemm(a, b, opa=opa).to_dd()
     err = np.abs((host(c) - chi) - clo)
     aa = np.abs(a.conj().T if opa else a)
@@ -65,8 +66,42 @@ def test_ozaki_error_decreases_with_slices(sr):
         assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, slices_a=s, slices_b=s, dmax=s + 1) == 0
         errs.append(np.linalg.norm((host(c) - chi) - clo) / scale)
     for e_prev, e_next in zip(errs[:-1], errs[1:]):
-        assert e_next < e_prev / 30  # about 7 bits per slice
-    assert errs[0] < 2.0 ** -(7 * 3 - 6)
+        assert e_next < e_prev / 60  # about 8 bits per slice
+    assert errs[0] < 2.0 ** -(8 * 3 - 6)
+
+
+def _carry_ints(rng, shape):
+    """Integers k 2^14 + r up to 2^20 + 8160 in magnitude. With that maximum in every
+    row and column the scale is 2^22, the first raw digit is about k and the second
+    r / 64 rounded to nearest even: r = 8160 gives 127.5 -> 128 (a carry into the
+    first digit), r = -8192 and -8160 give -128 (a carry of the negated digits),
+    r = 8128 gives 127."""
+    k = rng.integers(-64, 64, shape) * 2**14
+    r = rng.choice([8160, 8128, 8144, 8159, -8192, -8160, 8136, 0, 63], shape)
+    return k + r
+
+
+@pytest.mark.parametrize("opa", [0, 1])
+@pytest.mark.parametrize("shape", [(96, 80, 70), (2085, 2048, 66)])
+def test_ozaki_exact_with_digit_carries(sr, opa, shape):
+    m, n, k = shape
+    rng = np.random.default_rng(11 + opa + m)
+    ar, ai = _carry_ints(rng, (k, m) if opa else (m, k)), _carry_ints(rng, (k, m) if opa else (m, k))
+    br, bi = _carry_ints(rng, (k, n)), _carry_ints(rng, (k, n))
+    # every row of op(A) and column of B holds the maximum 2^20 + 8160 once
+    big = 2**20 + 8160
+    if opa:
+        ar[0, :] = big
+    else:
+        ar[:, 0] = big
+    br[0, :] = big
+    a = np.asfortranarray(ar + 1j * ai)
+    b = np.asfortranarray(br + 1j * bi)
+    c = empty(m, n)
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=3, slices_b=3, dmax=6) == 0
+    ref = (a.conj().T if opa else a) @ b  # |entries| < 2^47: exact in FP64
+    rows = np.arange(m) if m < 200 else np.random.default_rng(2).choice(m, 40, replace=False)
+    assert np.array_equal(host(c)[rows], ref[rows])
 
 
 def test_ozaki_add_epilogue_and_validation(sr):
@@ -97,15 +132,15 @@ def test_ozaki_large_tiles_exact_on_integers(sr, opa):
 
 
 def test_ozaki_large_tiles_segmented_diagonal(sr):
-    # k = 8256 gives 129 K-steps; the diagonal s + t = 9 of 8 x 8 slices then
-    # has 8 * 129 > 1024 steps and is folded in two segments
+    # k = 8256 gives 129 K-steps; the diagonal s + t = 8 of 7 x 7 slices then
+    # has 7 * 129 > 512 steps and is folded in two segments
     m = n = 2048
     k = 8256
     rng = np.random.default_rng(17)
     a = _gauss_int(rng, (m, k))
     b = _gauss_int(rng, (k, n))
     c = empty(m, n)
-    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, slices_a=8, slices_b=8, dmax=9) == 0
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, slices_a=7, slices_b=7, dmax=8) == 0
     rows = np.random.default_rng(3).choice(m, 48, replace=False)
     assert np.array_equal(host(c)[rows], a[rows] @ b)
 
@@ -118,7 +153,7 @@ def test_ozaki_large_tiles_fp64_faithful(sr, opa):
     a = rand_c(rng, (k, m) if opa else (m, k))
     b = rand_c(rng, (k, n))
     c = empty(m, n)
-    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=8, slices_b=8, dmax=9) == 0
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=7, slices_b=7, dmax=8) == 0
     rows = np.random.default_rng(4).choice(m, 32, replace=False)
     asub = np.asfortranarray(a[:, rows] if opa else a[rows])
     chi, clo = oracle.gemm(asub, b, opa=opa).to_dd()
