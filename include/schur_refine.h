@@ -99,6 +99,10 @@ typedef struct {
   float ms_solve;         /* with opts.timing: summed time of the triangular solves    */
   int update_slices_hist[16]; /* SR_GEMM_OZAKI_I8: digits used by the Newton-Schulz start
                              (entry 0) and by updates 1..15                           */
+  int hp_gemm_herm_launches; /* with opts.timing: how many of the timed launches were
+                             the Hermitian products Y = Q^H Q - I, which form only the
+                             tiles on and above the diagonal (half the work)          */
+  float ms_hp_gemm_herm;  /* with opts.timing: the part of ms_hp_gemm they took        */
 } sr_info;
 
 /* Default options: FP64 MFMA, compensated accumulation on, gating on, no trunc. */

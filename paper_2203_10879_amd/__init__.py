@@ -42,7 +42,8 @@ class SrInfo(ctypes.Structure):
                 ("resid_hist", ctypes.c_double * 16), ("norm_w_hist", ctypes.c_double * 16),
                 ("ms_total", ctypes.c_float), ("ms_hp_gemm", ctypes.c_float),
                 ("hp_gemm_launches", ctypes.c_int), ("ms_solve", ctypes.c_float),
-                ("update_slices_hist", ctypes.c_int * 16)]
+                ("update_slices_hist", ctypes.c_int * 16), ("hp_gemm_herm_launches", ctypes.c_int),
+                ("ms_hp_gemm_herm", ctypes.c_float)]
 
     def as_dict(self) -> dict:
         k = min(self.iters, 16)
@@ -53,7 +54,9 @@ class SrInfo(ctypes.Structure):
                 "resid_hist": list(self.resid_hist[:k]), "norm_w_hist": list(self.norm_w_hist[:u]),
                 "ms_total": self.ms_total, "ms_hp_gemm": self.ms_hp_gemm,
                 "hp_gemm_launches": self.hp_gemm_launches, "ms_solve": self.ms_solve,
-                "update_slices_hist": list(self.update_slices_hist[:min(u + 1, 16)])}
+                "update_slices_hist": list(self.update_slices_hist[:min(u + 1, 16)]),
+                "hp_gemm_herm_launches": self.hp_gemm_herm_launches,
+                "ms_hp_gemm_herm": self.ms_hp_gemm_herm}
 
 
 # name -> (restype, argtypes); mirrors include/schur_refine.h

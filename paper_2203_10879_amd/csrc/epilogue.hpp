@@ -37,9 +37,17 @@ __device__ inline void epi_element(const GemmArgs& g, int i, int j, cplx<R> val,
       part += (double)val.re * val.re + (double)val.im * val.im;
     }
   } else {  // EPI_YDEF
+    if (g.herm && i > j) return;  // the conjugate of (j, i) is stored there
     if (i == j) val.re -= 1;
     Cp[o] = val;
-    part += (double)val.re * val.re + (double)val.im * val.im;
+    const double p = (double)val.re * val.re + (double)val.im * val.im;
+    part += p;
+    if (g.herm && i < j) {
+      // lanes 16 apart hold consecutive j, so the mirrored store writes runs of
+      // consecutive elements
+      Cp[j + (long)i * g.ldc] = mk<R>(val.re, -val.im);
+      part += p;
+    }
   }
 }
 
@@ -76,11 +84,19 @@ __device__ inline void epi_element_dd(const GemmArgs& g, int i, int j, zc hi, zc
       part += hi.re * hi.re + hi.im * hi.im;
     }
   } else {  // EPI_YDEF
+    if (g.herm && i > j) return;  // the conjugate of (j, i) is stored there
     double rh = hi.re, rl = lo.re;
     if (i == j) dd_add(rh, rl, -1.0);
     Ch[o] = mk<double>(rh, hi.im);
     Cl[o] = mk<double>(rl, lo.im);
-    part += rh * rh + hi.im * hi.im;
+    const double p = rh * rh + hi.im * hi.im;
+    part += p;
+    if (g.herm && i < j) {
+      const long t = j + (long)i * g.ldc;
+      Ch[t] = mk<double>(rh, -hi.im);
+      Cl[t] = mk<double>(rl, -lo.im);
+      part += p;
+    }
   }
 }
 

@@ -236,20 +236,29 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
   // give each XCD a contiguous run of logical tiles, then walk tiles in groups of
   // kGroup tile-rows so that concurrently running blocks share A rows and B columns
   // in their XCD's L2.
-  const int ntiles = g.tiles_m * g.tiles_n;
+  const int ntiles = gridDim.x;
   const int bid = blockIdx.x;
   int logical = bid;
   {
     const int per = ntiles / kXCDs;
     if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
   }
-  constexpr int kGroup = 4;
-  const int group = logical / (kGroup * g.tiles_n);
-  const int first_m = group * kGroup;
-  const int gsize = min(g.tiles_m - first_m, kGroup);
-  const int within = logical - group * kGroup * g.tiles_n;
-  const int tm = first_m + within % gsize;
-  const int tn = within / gsize;
+  int tm, tn;
+  if (EPI == EPI_YDEF && g.herm) {
+    // upper triangle of tiles, column by column: logical = tn (tn + 1) / 2 + tm
+    tn = (int)((sqrtf(8.f * logical + 1.f) - 1.f) * 0.5f);
+    while (tn * (tn + 1) / 2 > logical) tn--;
+    while ((tn + 1) * (tn + 2) / 2 <= logical) tn++;
+    tm = logical - tn * (tn + 1) / 2;
+  } else {
+    constexpr int kGroup = 4;
+    const int group = logical / (kGroup * g.tiles_n);
+    const int first_m = group * kGroup;
+    const int gsize = min(g.tiles_m - first_m, kGroup);
+    const int within = logical - group * kGroup * g.tiles_n;
+    tm = first_m + within % gsize;
+    tn = within / gsize;
+  }
   gemm_tile<R, OPA, EPI, COMP, GBM>(g, tm * GBM, tn * GBN, bid, As, Bs, red);
 }
 
@@ -273,12 +282,17 @@ __global__ __launch_bounds__(Shape<BM>::NT) void gemm_grouped_kernel(const GemmA
 }
 
 int gemm_tiles(int m, int n) { return ceil_div(m, GBM) * ceil_div(n, GBN); }
+int gemm_tiles_herm(int n) {
+  const int t = ceil_div(n, GBM);
+  return t * (t + 1) / 2;
+}
 
 template <typename R, int OPA, int EPI, int COMP>
 static hipError_t launch(GemmArgs g, hipStream_t st) {
   g.tiles_m = ceil_div(g.m, GBM);
   g.tiles_n = ceil_div(g.n, GBN);
-  const int nt = g.tiles_m * g.tiles_n;
+  if (g.herm && (EPI != EPI_YDEF || g.m != g.n)) return hipErrorInvalidValue;
+  const int nt = g.herm ? gemm_tiles_herm(g.n) : g.tiles_m * g.tiles_n;
   if (nt == 0) return hipSuccess;
   hipLaunchKernelGGL((gemm_kernel<R, OPA, EPI, COMP>), dim3(nt), dim3(GNT), 0, st, g);
   return hipGetLastError();

@@ -37,10 +37,18 @@ struct GemmArgs {
   const void* Cinlo;
   zc* Tlp64;
   zc* Elp64;
+  // EPI_YDEF: the product is Hermitian (the same matrix on both sides). Only the
+  // elements with i <= j are stored from the product, each with its conjugate at
+  // (j, i), so the result is exactly Hermitian; the squared norm counts both. The
+  // square FP64 and large-tile INT8 kernels then launch only the tiles on and above
+  // the diagonal.
+  int herm;
 };
 
-// Number of output tiles (= blocks, = partial sums written) of a GEMM launch.
+// Number of output tiles (= blocks, = partial sums written) of a GEMM launch, and
+// of a Hermitian (herm) n x n product.
 int gemm_tiles(int m, int n);
+int gemm_tiles_herm(int n);
 
 // One output tile of a grouped (batched) product: matrix index, tile origin and
 // the partial-sum slot its SPLIT / YDEF epilogue writes.
@@ -86,8 +94,9 @@ hipError_t oz_split_cols(const zc* X, const zc* Xlo, long ld, int K, int ncols, 
 hipError_t oz_split_rows(const zc* X, const zc* Xlo, long ld, int M, int K, int S, int8_t* out,
                          int* exps, hipStream_t st);
 // Output tiles (= partial sums written) of a product; dd selects the kernel with
-// double-double accumulation, which serves every size.
-int oz_gemm_tiles(int m, int n, bool dd = false);
+// double-double accumulation, which serves every size; herm: a Hermitian product
+// (GemmArgs::herm).
+int oz_gemm_tiles(int m, int n, bool dd = false, bool herm = false);
 // Bytes of scratch the product of an m x n output needs (0 for small FP64 outputs).
 size_t oz_gemm_scratch_bytes(int m, int n, bool dd = false);
 // Whether the int32 sums of a product stay exact for these sizes.

@@ -529,19 +529,30 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(2))) void o
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
 
-  const int ntiles = g.tiles_m * g.tiles_n;
+  const int ntiles = gridDim.x;
   const int bid = blockIdx.x;
   int logical = bid;
   {
     const int per = ntiles / kXCDs;
     if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
   }
-  constexpr int kGroup = 4;
-  const int group = logical / (kGroup * g.tiles_n);
-  const int first_m = group * kGroup;
-  const int gsize = min(g.tiles_m - first_m, kGroup);
-  const int within = logical - group * kGroup * g.tiles_n;
-  const int m0 = (first_m + within % gsize) * PBM, n0 = (within / gsize) * PBN;
+  int tm, tn;
+  if (EPI == EPI_YDEF && g.herm) {
+    // upper triangle of tiles, column by column: logical = tn (tn + 1) / 2 + tm
+    tn = (int)((sqrtf(8.f * logical + 1.f) - 1.f) * 0.5f);
+    while (tn * (tn + 1) / 2 > logical) tn--;
+    while ((tn + 1) * (tn + 2) / 2 <= logical) tn++;
+    tm = logical - tn * (tn + 1) / 2;
+  } else {
+    constexpr int kGroup = 4;
+    const int group = logical / (kGroup * g.tiles_n);
+    const int first_m = group * kGroup;
+    const int gsize = min(g.tiles_m - first_m, kGroup);
+    const int within = logical - group * kGroup * g.tiles_n;
+    tm = first_m + within % gsize;
+    tn = within / gsize;
+  }
+  const int m0 = tm * PBM, n0 = tn * PBN;
 
   const int KT = a.Kp / OBK;
   const long pA = oz_plane_bytes(g.m, a.Kp), pB = oz_plane_bytes(g.n, a.Kp);
@@ -776,8 +787,11 @@ bool oz_gemm_exact(int m, int n, int k, int SA, int SB, bool dd) {
   return pairs * (long)oz_kp(k) * 16384L < 2147483648L;
 }
 
-int oz_gemm_tiles(int m, int n, bool dd) {
-  if (use_large_tiles(m, n, dd)) return ceil_div(m, PBM) * ceil_div(n, PBN);
+int oz_gemm_tiles(int m, int n, bool dd, bool herm) {
+  if (use_large_tiles(m, n, dd)) {
+    const int t = ceil_div(n, PBN);
+    return herm ? t * (t + 1) / 2 : ceil_div(m, PBM) * t;
+  }
   return ceil_div(m, OBM) * ceil_div(n, OBN);
 }
 
@@ -803,11 +817,12 @@ hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t
                    int SB, int conjA, int dmax, GemmArgs g, void* scratch, hipStream_t st,
                    bool dd) {
   if (g.m == 0 || g.n == 0) return hipSuccess;
+  if (g.herm && (epi != EPI_YDEF || g.m != g.n)) return hipErrorInvalidValue;
   if (use_large_tiles(g.m, g.n, dd)) {
     if (!scratch) return hipErrorInvalidValue;
     g.tiles_m = ceil_div(g.m, PBM);
     g.tiles_n = ceil_div(g.n, PBN);
-    const int nt = g.tiles_m * g.tiles_n;
+    const int nt = oz_gemm_tiles(g.m, g.n, dd, g.herm != 0);
     OzArgs a{A, ea, B, eb, SA, SB, dmax, conjA, oz_kp(g.k), g, (double2*)scratch};
     switch (epi) {
       case EPI_STORE: return launch_large<EPI_STORE>(dd, nt, a, st);

@@ -174,6 +174,8 @@ struct Timer {
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> ev[2];
   int count[2] = {0, 0};
+  int herm = 0;                  // timed hp products that were Hermitian (Y)
+  std::vector<char> herm_pair;   // per event pair of channel 0
   void mark(int c) {
     hipEvent_t e;
     if (hipEventCreate(&e) == hipSuccess) {
@@ -181,9 +183,12 @@ struct Timer {
       ev[c].push_back(e);
     }
   }
-  float total(int c) const {  // after the stream has been synchronised
+  // after the stream has been synchronised; only_herm: 0 all pairs, 1 the
+  // Hermitian ones
+  float total(int c, int only_herm = 0) const {
     float s = 0;
     for (size_t i = 0; i + 1 < ev[c].size(); i += 2) {
+      if (only_herm && !(c == 0 && i / 2 < herm_pair.size() && herm_pair[i / 2])) continue;
       float ms = 0;
       hipEventElapsedTime(&ms, ev[c][i], ev[c][i + 1]);
       s += ms;
@@ -197,10 +202,19 @@ struct Timer {
 };
 #define TIC(tm, c) \
   if (tm) (tm)->mark(c)
-#define TOC(tm, c)        \
-  if (tm) {               \
-    (tm)->mark(c);        \
-    (tm)->count[c]++;     \
+#define TOC(tm, c)                                                   \
+  if (tm) {                                                          \
+    (tm)->mark(c);                                                   \
+    (tm)->count[c]++;                                                \
+    if ((c) == 0) (tm)->herm_pair.resize((tm)->ev[0].size() / 2, 0); \
+  }
+#define TOC_HERM(tm)                                             \
+  if (tm) {                                                      \
+    (tm)->mark(0);                                               \
+    (tm)->count[0]++;                                            \
+    (tm)->herm++;                                                \
+    (tm)->herm_pair.resize((tm)->ev[0].size() / 2, 0);           \
+    if (!(tm)->herm_pair.empty()) (tm)->herm_pair.back() = 1;    \
   }
 
 // Newton-Schulz start into Qout: Y0 = Qh^H Qh - I, Qout = Qh + Qh (-Y0/2);
@@ -243,9 +257,10 @@ int ns_init(const zc* Qh, zc* Qout, zc* QHout, int n, int comp, const Work& w, h
     CK(oz_split_cols(Qh, nullptr, n, n, n, S, w.sQc, w.eQc, st));
     GemmArgs g = gargs(n, n, n, nullptr, 0, nullptr, 0, w.Y, n);
     g.partials = w.partials;
+    g.herm = 1;
     CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, S, w.sQc, w.eQc, S, 1, S + 1, g, w.oz_scratch, st));
-    TOC(tm, 0);
-    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n), w.scal + 2, st));
+    TOC_HERM(tm);
+    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, false, true), w.scal + 2, st));
     double nrm[3];
     unsigned dst = 0;
     int rc = read_back(st, w, 3, nrm, &dst);
@@ -260,9 +275,10 @@ int ns_init(const zc* Qh, zc* Qout, zc* QHout, int n, int comp, const Work& w, h
   }
   GemmArgs g = gargs(n, n, n, Qh, n, Qh, n, w.Y, n);
   g.partials = w.partials;
+  g.herm = 1;
   TIC(tm, 0);
   CK(zgemm(1, EPI_YDEF, comp, g, st));
-  TOC(tm, 0);
+  TOC_HERM(tm);
   CK(form_delta(nullptr, w.Y, nullptr, nullptr, nullptr, w.P, n, st));
   GemmArgs u = gargs(n, n, n, Qh, n, w.P, n, Qout, n);
   u.Cin = Qh;
@@ -306,10 +322,11 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
 int ydef(const zc* Q, const zc* QH, int n, int comp, const Work& w, hipStream_t st, Timer* tm) {
   GemmArgs g = gargs(n, n, n, QH ? QH : Q, n, Q, n, w.Y, n);
   g.partials = w.partials;
+  g.herm = 1;
   TIC(tm, 0);
   CK(zgemm(QH ? 0 : 1, EPI_YDEF, comp, g, st));
-  TOC(tm, 0);
-  CK(reduce_partials(w.partials, gemm_tiles(n, n), w.scal + 2, st));
+  TOC_HERM(tm);
+  CK(reduce_partials(w.partials, gemm_tiles_herm(n), w.scal + 2, st));
   return SR_OK;
 }
 
@@ -318,10 +335,11 @@ int defects(const zc* Q, const zc* QH, int n, int comp, const Work& w, hipStream
             Timer* tm = nullptr) {
   GemmArgs g = gargs(n, n, n, QH ? QH : Q, n, Q, n, w.Y, n);
   g.partials = w.partials;
+  g.herm = 1;
   TIC(tm, 0);
   CK(zgemm(QH ? 0 : 1, EPI_YDEF, comp, g, st));
-  TOC(tm, 0);
-  CK(reduce_partials(w.partials, gemm_tiles(n, n), w.scal + 2, st));
+  TOC_HERM(tm);
+  CK(reduce_partials(w.partials, gemm_tiles_herm(n), w.scal + 2, st));
   CK(form_w(w.Llp, w.W, n, w.partials, st));
   CK(reduce_partials(w.partials, form_w_parts(n), w.scal + 3, st));
   return SR_OK;
@@ -600,6 +618,8 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
     if (tm) {
       info->ms_hp_gemm = timer.total(0);
       info->hp_gemm_launches = timer.count[0];
+      info->hp_gemm_herm_launches = timer.herm;
+      info->ms_hp_gemm_herm = timer.total(0, 1);
       info->ms_solve = timer.total(1);
     }
   }
@@ -761,8 +781,9 @@ int dd_update(const zc* Qh, const zc* Ql, zc* Oh, zc* Ol, int n, int Su, const D
 int dd_ydef(int n, const DDWork& w, hipStream_t st) {
   GemmArgs g = dd_args(n, w.Yh, w.Yl);
   g.partials = w.partials;
+  g.herm = 1;
   CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, w.S, w.sQc, w.eQc, w.S, 1, w.S + 1, g, w.scratch, st, true));
-  CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, true), w.scal + 2, st));
+  CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, true, true), w.scal + 2, st));
   return SR_OK;
 }
 
@@ -847,7 +868,7 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
   TIC(tm, 0);
   CK(oz_split_cols(othh, othl, n, n, n, S, w.sQc, w.eQc, st));
   if ((rc = dd_ydef(n, w, st)) != SR_OK) return rc;
-  TOC(tm, 0);
+  TOC_HERM(tm);
   double nrm[4] = {0, 0, 0, 0};
   unsigned dst = 0;
   if ((rc = read_back_dd(st, w, 3, nrm, &dst)) != SR_OK) return rc;
@@ -910,7 +931,7 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
     TOC(tm, 1);
     TIC(tm, 0);
     if ((rc = dd_ydef(n, w, st)) != SR_OK) return rc;
-    TOC(tm, 0);
+    TOC_HERM(tm);
     CK(form_w64(w.L, w.W, n, w.partials, st));
     CK(reduce_partials(w.partials, form_w_parts(n), w.scal + 3, st));
     if ((rc = read_back_dd(st, w, 4, nrm, &dst)) != SR_OK) return rc;
@@ -979,6 +1000,8 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
     if (tm) {
       info->ms_hp_gemm = timer.total(0);
       info->hp_gemm_launches = timer.count[0];
+      info->hp_gemm_herm_launches = timer.herm;
+      info->ms_hp_gemm_herm = timer.total(0, 1);
       info->ms_solve = timer.total(1);
     }
   }

@@ -73,6 +73,17 @@ __device__ inline void load_tile(C* S, const C* __restrict__ G, int n, int I, in
   S[q * TLD + p] = keep(ok, v);
 }
 
+// This thread's element of tile (I, J) of G in the load_tile ownership (zero
+// outside the matrix, also for a negative tile index).
+template <typename C>
+__device__ inline C tile_val(const C* __restrict__ G, int n, int I, int J) {
+  const int p = threadIdx.x & (TB - 1), q = threadIdx.x / TB;
+  const int gi = I * TB + p, gj = J * TB + q;
+  const bool ok = I >= 0 && J >= 0 && gi < n && gj < n;
+  const C v = G[ok ? gi + (long)gj * n : 0];
+  return keep(ok, v);
+}
+
 template <int SIGN, typename C>
 __device__ inline void tile_mac(C& acc, const C* F, const C* G, Own o) {
 #pragma unroll 8
@@ -166,8 +177,9 @@ constexpr int kSolveS2 = TB * kTbLd;     // elements of the second LDS buffer
 // with operands that read as zero where the entry does not exist, and addresses
 // that move by a constant per step. Waves whose entries are all final skip the
 // update.
+// tii, tjj: this thread's elements (tile_val ownership) of T_II and T_JJ.
 template <typename Rl>
-__device__ void tile_solve(cplx<Rl> acc, const cplx<Rl>* T, cplx<Rl>* L, int n, int I, int J,
+__device__ void tile_solve(cplx<Rl> acc, cplx<Rl> tii, cplx<Rl> tjj, cplx<Rl>* L, int n, int I, int J,
                            float trunc, unsigned* status, cplx<Rl>* TaP, cplx<Rl>* TbP,
                            cplx<Rl>* R, Own o) {
   using C = cplx<Rl>;
@@ -179,17 +191,10 @@ __device__ void tile_solve(cplx<Rl> acc, const cplx<Rl>* T, cplx<Rl>* L, int n, 
   {
     // TaP columns 0..31 from T_II, 32..62 zero
     const int p = threadIdx.x & (TB - 1), c = threadIdx.x / TB;
-    const int gi = I * TB + p, gj = I * TB + c;
-    const bool ok = gi < n && gj < n;
-    const C v = T[ok ? gi + (long)gj * n : 0];
-    TaP[c * TLD + p] = keep(ok, v);
+    TaP[c * TLD + p] = tii;
     if (c < TB - 1) TaP[(TB + c) * TLD + p] = z;
     // TbP rows -31..31 of column c (offset 31), rows < 0 zero
-    const int K = diag ? I : J;
-    const int gk = K * TB + p, gc = K * TB + c;
-    const bool okb = gk < n && gc < n;
-    const C w = T[okb ? gk + (long)gc * n : 0];
-    TbP[c * kTbLd + (TB - 1) + p] = keep(okb, w);
+    TbP[c * kTbLd + (TB - 1) + p] = tjj;
     if (p < TB - 1) TbP[c * kTbLd + p] = z;
     if (threadIdx.x < 2 * TB) {
       dv[0][threadIdx.x] = z;
@@ -282,17 +287,51 @@ __global__ __launch_bounds__(TNT) void trisolve_level_kernel(TriLevelArgs<Rl> a)
   const int tiles = a.nb - a.D;
   C acc = mk<Rl>(0, 0);
   if ((int)blockIdx.x < tiles) {
-    // solve block for tile (D + t, t)
+    // solve block for tile (D + t, t). Every global operand is requested before
+    // the first one is used (the partial sums in batches), so the block waits for
+    // a few rounds of memory latency rather than one per operand; the sums are
+    // still formed in the same order.
     const int t = blockIdx.x, I = a.D + t, J = t;
-    add_e(acc, a.E, a.n, I, J, o);
-    for (int s = 0; s < a.S_cur; s++) {
-      const C v = a.part_cur[((long)t * a.S_cur + s) * kTileElems + o.p + o.q * TB];
-      acc.re += v.re;
-      acc.im += v.im;
+    const C ta = tile_val(a.T, a.n, I, I + 1), la = tile_val(a.L, a.n, I + 1, J);
+    const C lb = tile_val(a.L, a.n, I, J - 1), tb = tile_val(a.T, a.n, J - 1, J);
+    const C tii = tile_val(a.T, a.n, I, I), tjj = tile_val(a.T, a.n, J, J);
+    // R = E_IJ (strictly lower part) + the far partial sums in order. The first
+    // batch is loaded unconditionally (indices kept inside the partial buffer,
+    // unused values not added) so that its loads overlap the ones above.
+    const int gi = I * TB + o.p, gj = J * TB + o.q;
+    const bool eok = gi < a.n && gj < a.n && gi > gj;
+    const C ev = a.E[eok ? gi + (long)gj * a.n : 0];
+    const C* part = a.part_cur + (long)t * a.S_cur * kTileElems + o.p + o.q * TB;
+    constexpr int kBatch = 16;
+    auto batch = [&](int s0) {
+      C v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; u++) v[u] = part[(long)max(0, min(s0 + u, a.S_cur - 1)) * kTileElems];
+      if (s0 == 0) acc = keep(eok, ev);
+#pragma unroll
+      for (int u = 0; u < kBatch; u++) {
+        if (s0 + u < a.S_cur) {
+          acc.re += v[u].re;
+          acc.im += v[u].im;
+        }
+      }
+    };
+    batch(0);
+    for (int s0 = kBatch; s0 < a.S_cur; s0 += kBatch) batch(s0);
+    if (I + 1 < a.nb) {
+      S1[o.q * TLD + o.p] = ta;
+      S2[o.q * TLD + o.p] = la;
+      __syncthreads();
+      tile_mac<+1>(acc, S1, S2, o);
     }
-    if (I + 1 < a.nb) block_product(acc, a.T, a.L, a.n, I, J, I + 1, true, S1, S2, o);
-    if (J >= 1) block_product(acc, a.T, a.L, a.n, I, J, J - 1, false, S1, S2, o);
-    tile_solve(acc, a.T, a.L, a.n, I, J, a.trunc, a.status, S1, S2, S3, o);
+    if (J >= 1) {
+      __syncthreads();
+      S1[o.q * TLD + o.p] = lb;
+      S2[o.q * TLD + o.p] = tb;
+      __syncthreads();
+      tile_mac<-1>(acc, S1, S2, o);
+    }
+    tile_solve(acc, tii, tjj, a.L, a.n, I, J, a.trunc, a.status, S1, S2, S3, o);
     return;
   }
   // partial block for diagonal D - 1: tile t2 = (D - 1 + t2, t2), split s
@@ -337,7 +376,8 @@ __global__ __launch_bounds__(TNT) void trisolve_single_kernel(const TriMatrix<Rl
       C acc = mk<Rl>(0, 0);
       add_e(acc, mt.E, n, I, J, o);
       all_products(acc, mt.T, mt.L, n, nb, I, J, S1, S2, o);
-      tile_solve(acc, mt.T, mt.L, n, I, J, trunc, status, S1, S2, S3, o);
+      tile_solve(acc, tile_val(mt.T, n, I, I), tile_val(mt.T, n, J, J), mt.L, n, I, J, trunc, status, S1,
+                 S2, S3, o);
     }
   }
 }

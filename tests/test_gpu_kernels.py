@@ -207,3 +207,25 @@ def test_update_matches_oracle_merged_step(sr):
     err = np.linalg.norm((host(qo) - hi) - lo)
     # FP64 rounding of Q + Q Delta, plus FP32 rounding of the (1e-8 sized) lp products
     assert err <= 16 * U64 * n + 1e-7 * np.linalg.norm(w @ w) * np.sqrt(n)
+
+
+@pytest.mark.parametrize("n", [64, 200])
+def test_update_hermitian_defect(sr, n):
+    """Y = Q^H Q - I is formed from the tiles on and above the diagonal and mirrored;
+    with a Q far from unitary (Y of order 0.1) its norm and the update built from
+    it are checked against FP64 and the binary128 merged step (n = 200 leaves a
+    ragged diagonal tile)."""
+    rng = np.random.default_rng(70 + n)
+    q = np.asfortranarray(np.eye(n) + 0.3 * rand_c(rng, (n, n)) / np.sqrt(n))
+    lmat = (1e-4 * np.tril(rand_c(rng, (n, n)), -1)).astype(np.complex64)
+    w = lmat.astype(np.complex128) - lmat.astype(np.complex128).conj().T
+    qo = empty(n, n)
+    rc, (nw, ny) = sr.sr_update(dev(q), dev(lmat), qo, sr.workspace(n), gate=False)
+    assert rc == 0
+    y = q.conj().T @ q - np.eye(n)
+    assert abs(ny - np.linalg.norm(y)) <= 1e-12 * np.linalg.norm(y)
+    hi, lo = oracle.ns_merged(q, w, lp="float", full=False).to_dd()
+    # FP64 products plus FP32 lp products YW, W^2, W^3 (Y ~ 0.1, W ~ 1e-4)
+    err = np.linalg.norm((host(qo) - hi) - lo)
+    assert err <= 1e-9 * np.linalg.norm(hi)
+
