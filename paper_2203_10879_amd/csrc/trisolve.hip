@@ -176,9 +176,10 @@ constexpr int kSolveS2 = TB * kTbLd;     // elements of the second LDS buffer
 //   - X(p, p-s) Tb(p-s, q)   (entry left of it in its row)
 // with operands that read as zero where the entry does not exist, and addresses
 // that move by a constant per step. Waves whose entries are all final skip the
-// update.
+// update. Without truncation (TRUNC false) the finiteness of the entries is
+// checked once after the loop, off the dependent chain of the steps.
 // tii, tjj: this thread's elements (tile_val ownership) of T_II and T_JJ.
-template <typename Rl>
+template <typename Rl, bool TRUNC>
 __device__ void tile_solve(cplx<Rl> acc, cplx<Rl> tii, cplx<Rl> tjj, cplx<Rl>* L, int n, int I, int J,
                            float trunc, unsigned* status, cplx<Rl>* TaP, cplx<Rl>* TbP,
                            cplx<Rl>* R, Own o) {
@@ -243,8 +244,10 @@ __device__ void tile_solve(cplx<Rl> acc, cplx<Rl> tii, cplx<Rl> tjj, cplx<Rl>* L
         x = cmul(a, rd);
         x.re = -x.re;
         x.im = -x.im;
-        bad |= !isfinite(x.re) || !isfinite(x.im);
-        if (trunc2 > Rl(0) && x.re * x.re + x.im * x.im > trunc2) x = z;
+        if constexpr (TRUNC) {
+          bad |= !isfinite(x.re) || !isfinite(x.im);
+          if (x.re * x.re + x.im * x.im > trunc2) x = z;
+        }
       }
       xf = x;
       cur[TB + q] = x;
@@ -261,8 +264,20 @@ __device__ void tile_solve(cplx<Rl> acc, cplx<Rl> tii, cplx<Rl> tjj, cplx<Rl>* L
     xb_i += 1;
     tb_i += 1;
   }
+  if constexpr (!TRUNC) bad |= !isfinite(xf.re) || !isfinite(xf.im);  // xf = 0 unless live
   if (live) L[gaddr] = xf;
   if (bad) atomicOr(status, (unsigned)DEV_BREAKDOWN);
+}
+
+// The truncating form only when the (FP32 or FP64) squared threshold is positive.
+template <typename Rl>
+__device__ inline void tile_solve_any(cplx<Rl> acc, cplx<Rl> tii, cplx<Rl> tjj, cplx<Rl>* L, int n, int I,
+                                      int J, float trunc, unsigned* status, cplx<Rl>* TaP, cplx<Rl>* TbP,
+                                      cplx<Rl>* R, Own o) {
+  if ((Rl)trunc * (Rl)trunc > Rl(0))
+    tile_solve<Rl, true>(acc, tii, tjj, L, n, I, J, trunc, status, TaP, TbP, R, o);
+  else
+    tile_solve<Rl, false>(acc, tii, tjj, L, n, I, J, trunc, status, TaP, TbP, R, o);
 }
 
 template <typename Rl>
@@ -331,7 +346,7 @@ __global__ __launch_bounds__(TNT) void trisolve_level_kernel(TriLevelArgs<Rl> a)
       __syncthreads();
       tile_mac<-1>(acc, S1, S2, o);
     }
-    tile_solve(acc, tii, tjj, a.L, a.n, I, J, a.trunc, a.status, S1, S2, S3, o);
+    tile_solve_any(acc, tii, tjj, a.L, a.n, I, J, a.trunc, a.status, S1, S2, S3, o);
     return;
   }
   // partial block for diagonal D - 1: tile t2 = (D - 1 + t2, t2), split s
@@ -376,8 +391,8 @@ __global__ __launch_bounds__(TNT) void trisolve_single_kernel(const TriMatrix<Rl
       C acc = mk<Rl>(0, 0);
       add_e(acc, mt.E, n, I, J, o);
       all_products(acc, mt.T, mt.L, n, nb, I, J, S1, S2, o);
-      tile_solve(acc, tile_val(mt.T, n, I, I), tile_val(mt.T, n, J, J), mt.L, n, I, J, trunc, status, S1,
-                 S2, S3, o);
+      tile_solve_any(acc, tile_val(mt.T, n, I, I), tile_val(mt.T, n, J, J), mt.L, n, I, J, trunc, status,
+                     S1, S2, S3, o);
     }
   }
 }
@@ -390,11 +405,17 @@ static int max_far(int nb, int D) {
   return m - 1;  // the first and last tile lack one near product
 }
 
+// Partial blocks per tile of diagonal D: about kProdsPerBlock far products each
+// (a partial block then still ends before the solve blocks of the same launch,
+// and few blocks share a CU with a solve block), but no more than kTargetBlocks
+// in all, so that at large n every block carries more of the far products.
+constexpr int kProdsPerBlock = 4;
 static int splits(int nb, int D) {
   const int mf = max_far(nb, D);
   if (mf <= 0) return 0;
-  int S = ceil_div(kTargetBlocks, nb - D);
-  if (S > mf) S = mf;
+  int S = ceil_div(mf, kProdsPerBlock);
+  const int cap = ceil_div(kTargetBlocks, nb - D);
+  if (S > cap) S = cap;
   return S < 1 ? 1 : S;
 }
 
