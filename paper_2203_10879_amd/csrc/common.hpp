@@ -37,6 +37,17 @@ __device__ inline void cfms(cplx<R>& a, cplx<R> b, cplx<R> c) {
   a.im = fma(-b.re, c.im, fma(-b.im, c.re, a.im));
 }
 
+// Workgroup barrier that orders LDS accesses only: it waits for this wave's LDS
+// operations (lgkmcnt(0)) but not for global loads still in flight, which a
+// __syncthreads (a workgroup release) would also wait for. The empty asm
+// statements keep the compiler from moving memory accesses across it.
+__device__ inline void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt fields at their maximum
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Error-free sum s + e = a + b (Knuth).
 __host__ __device__ inline void two_sum(double a, double b, double& s, double& e) {
   s = a + b;

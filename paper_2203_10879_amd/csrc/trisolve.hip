@@ -84,6 +84,24 @@ __device__ inline C tile_val(const C* __restrict__ G, int n, int I, int J) {
   return keep(ok, v);
 }
 
+// The same as a raw load and a flag, so that the zero padding (keep) can be
+// applied where the value is used and the load stays in flight until then.
+template <typename C>
+struct Pending {
+  C v;
+  bool ok;
+  __device__ C get() const { return keep(ok, v); }
+};
+template <typename C>
+__device__ inline Pending<C> tile_load(const C* __restrict__ G, int n, int I, int J) {
+  const int p = threadIdx.x & (TB - 1), q = threadIdx.x / TB;
+  const int gi = I * TB + p, gj = J * TB + q;
+  Pending<C> r;
+  r.ok = I >= 0 && J >= 0 && gi < n && gj < n;
+  r.v = G[r.ok ? gi + (long)gj * n : 0];
+  return r;
+}
+
 template <int SIGN, typename C>
 __device__ inline void tile_mac(C& acc, const C* F, const C* G, Own o) {
 #pragma unroll 8
@@ -94,29 +112,40 @@ __device__ inline void tile_mac(C& acc, const C* F, const C* G, Own o) {
   }
 }
 
-// acc += one block product of tile (I, J): + T_IK L_KJ (typeA) or - L_IK T_KJ.
+// acc += the block products u0 .. u1-1 of tile (I, J) from the list
+//   u < nA:  + T_{I,K} L_{K,J}, K = kA + u;   u >= nA:  - L_{I,K} T_{K,J}, K = u - nA,
+// in that order. The operands of the next product are loaded into registers while
+// the current one is multiplied, so a block waits for one memory round trip in
+// all rather than one per product.
 template <typename C>
-__device__ inline void block_product(C& acc, const C* T, const C* L, int n, int I, int J, int K,
-                                     bool typeA, C* S1, C* S2, Own o) {
-  __syncthreads();
-  if (typeA) {
-    load_tile(S1, T, n, I, K);
-    load_tile(S2, L, n, K, J);
-  } else {
-    load_tile(S1, L, n, I, K);
-    load_tile(S2, T, n, K, J);
+__device__ void product_range(C& acc, const C* T, const C* L, int n, int I, int J, int kA, int nA, int u0,
+                              int u1, C* S1, C* S2, Own o) {
+  auto operands = [&](int u, Pending<C>& f, Pending<C>& g) {
+    const bool a = u < nA;
+    const int K = a ? kA + u : u - nA;
+    f = tile_load(a ? T : L, n, I, K);
+    g = tile_load(a ? L : T, n, K, J);
+  };
+  Pending<C> f, g;
+  if (u0 < u1) operands(u0, f, g);
+  for (int u = u0; u < u1; u++) {
+    lds_barrier();  // the previous product no longer reads S1, S2
+    S1[o.q * TLD + o.p] = f.get();
+    S2[o.q * TLD + o.p] = g.get();
+    if (u + 1 < u1) operands(u + 1, f, g);
+    lds_barrier();  // the loads just issued stay in flight
+    if (u < nA) tile_mac<+1>(acc, S1, S2, o);
+    else tile_mac<-1>(acc, S1, S2, o);
   }
-  __syncthreads();
-  if (typeA) tile_mac<+1>(acc, S1, S2, o);
-  else tile_mac<-1>(acc, S1, S2, o);
 }
 
-// All block products of tile (I, J) (K = I+1..nb-1 of type A, K = 0..J-1 of type B).
+// All block products of tile (I, J) (K = I+1..nb-1 of the first kind, K = 0..J-1 of
+// the second).
 template <typename C>
 __device__ void all_products(C& acc, const C* T, const C* L, int n, int nb, int I, int J, C* S1,
                              C* S2, Own o) {
-  for (int K = I + 1; K < nb; K++) block_product(acc, T, L, n, I, J, K, true, S1, S2, o);
-  for (int K = 0; K < J; K++) block_product(acc, T, L, n, I, J, K, false, S1, S2, o);
+  const int nA = nb - 1 - I;
+  product_range(acc, T, L, n, I, J, I + 1, nA, 0, nA + J, S1, S2, o);
 }
 
 template <typename C>
@@ -356,10 +385,8 @@ __global__ __launch_bounds__(TNT) void trisolve_level_kernel(TriLevelArgs<Rl> a)
   const int fa = max(0, a.nb - 2 - I), fb = max(0, J - 1);
   const int m = fa + fb;
   const int u0 = (int)((long)m * s / a.S_next), u1 = (int)((long)m * (s + 1) / a.S_next);
-  for (int u = u0; u < u1; u++) {
-    if (u < fa) block_product(acc, a.T, a.L, a.n, I, J, I + 2 + u, true, S1, S2, o);
-    else block_product(acc, a.T, a.L, a.n, I, J, u - fa, false, S1, S2, o);
-  }
+  // far products: K = I+2..nb-1 (first kind), K = 0..J-2 (second kind)
+  product_range(acc, a.T, a.L, a.n, I, J, I + 2, fa, u0, u1, S1, S2, o);
   a.part_next[((long)t2 * a.S_next + s) * kTileElems + o.p + o.q * TB] = acc;
 }
 
