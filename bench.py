@@ -15,7 +15,8 @@ Other workloads (--workload), each one JSON line of its own:
                   with native FP64 products and with Ozaki INT8 splits, time to
                   1e-15 and the binary128 error on sampled rows for each;
   batched         2000 matrices, n uniform in [16, 256], each from its own seed
-                  with a cgees start, refined together (schur_refine_batched);
+                  with a cgees start, refined together (schur_refine_batched;
+                  a step restores all starts with one device copy);
                   matrices/s and the p50 / p99 pass counts;
   dd_continuation A(t_k) = A0 + (k/64) A1, n = 2048, k = 0..63, double-double
                   tier to 1e-28, each step warm-started from the previous one,
@@ -247,14 +248,24 @@ def run_batched(args) -> int:
 
     torch.cuda.set_device(torch.device("cuda:0"))
     As = [sr.colmajor(a) for a, _ in data]
-    Q0 = [sr.colmajor(q) for _, q in data]
-    Qs = [sr.colmajor_empty(n, n) for n in sizes]
+    # the starts and the refined Q of all matrices are column-major views into one
+    # buffer each, so that a step restores every start with a single copy
+    offs = np.concatenate([[0], np.cumsum([n * n for n in sizes])]).astype(np.int64)
+    q0_flat = torch.empty(int(offs[-1]), dtype=torch.complex128, device="cuda")
+    q_flat = torch.empty_like(q0_flat)
+
+    def view(flat, i):
+        n = sizes[i]
+        return flat[int(offs[i]):int(offs[i + 1])].view(n, n).T
+
+    for i, (_, q) in enumerate(data):
+        view(q0_flat, i).copy_(sr.colmajor(q))
+    Qs = [view(q_flat, i) for i in range(count)]
     Ts = [sr.colmajor_empty(n, n) for n in sizes]
     ws = sr.workspace_batched(sizes)
 
     def step():
-        for q, q0 in zip(Qs, Q0):
-            q.copy_(q0)
+        q_flat.copy_(q0_flat)
         return sr.schur_refine_batched(As, Qs, Ts, iters=8, tol=TOL, workspace=ws)
 
     for _ in range(args.warmup):
