@@ -70,14 +70,25 @@ __device__ inline int swz(int k, int m) {
 // One output tile (m0, n0) of g; `slot` is the partial-sum slot of SPLIT / YDEF.
 // Operand layout of v_mfma_*_16x16x4 (one block): lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16]; accumulator element v of lane l is D[MF<R>::row(l, v)][l % 16].
-template <typename R, int OPA, int EPI, int COMP, int BM>
+//
+// KS > 1 splits K inside the block: the block has KS groups of NT threads, group
+// g takes the K-tiles g, g + KS, g + 2 KS, ... with its own double-buffered
+// operand tiles (As, Bs hold 2 KS buffers), and at the end the groups' sums are
+// added in group order through LDS before group 0 stores the tile. A tile then
+// keeps KS times the waves busy, which is what fills the CUs when there are
+// fewer than two tiles per CU.
+template <typename R, int OPA, int EPI, int COMP, int BM, int KS = 1>
 __device__ inline void gemm_tile(const GemmArgs& g, int m0, int n0, int slot,
                                  cplx<R> (*As)[GBK][BM], cplx<R> (*Bs)[GBK][BM], double* red) {
   using V = typename MF<R>::v4;
   using C = cplx<R>;
   using S = Shape<BM>;
   constexpr int WM = S::WM, WN = S::WN, NT = S::NT, kLoads = S::LOADS;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int grp = KS > 1 ? (int)threadIdx.x / NT : 0;
+  const int tid = (int)threadIdx.x - grp * NT, lane = tid & 63, wave = tid >> 6;
+  R* const xch = (R*)&As[0][0][0];  // the group exchange after the K loop
+  As += 2 * grp;
+  Bs += 2 * grp;
   const int wm = (wave & 1) * (16 * WM), wn = (wave >> 1) * (16 * WN);
 
   const C* __restrict__ Ap = (const C*)g.A;
@@ -158,13 +169,16 @@ __device__ inline void gemm_tile(const GemmArgs& g, int m0, int n0, int slot,
     }
   };
 
+  // This group's K-tiles are kt = i KS + grp, i < iters; a K-tile past the end loads
+  // zeros, which add nothing.
   const int KT = (g.k + GBK - 1) / GBK;
-  gload(0);
+  const int iters = (KT + KS - 1) / KS;
+  gload(grp * GBK);
   sstore(0);
   __syncthreads();
-  for (int kt = 0; kt < KT; kt++) {
-    const int cur = kt & 1;
-    if (kt + 1 < KT) gload((kt + 1) * GBK);
+  for (int it = 0; it < iters; it++) {
+    const int cur = it & 1;
+    if (it + 1 < iters) gload(((it + 1) * KS + grp) * GBK);
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 4) {
       const int krow = kk + (lane >> 4);
@@ -199,39 +213,73 @@ __device__ inline void gemm_tile(const GemmArgs& g, int m0, int n0, int slot,
           acc_im[mi][ni] = MF<R>::op(a_im[mi], b_re[ni], acc_im[mi][ni]);
         }
     }
-    if (COMP && ((kt + 1) % kChunk == 0 || kt + 1 == KT)) fold();
-    if (kt + 1 < KT) sstore(cur ^ 1);
+    if (COMP && ((it + 1) % kChunk == 0 || it + 1 == iters)) fold();
+    if (it + 1 < iters) sstore(cur ^ 1);
     __syncthreads();
   }
 
-  // Epilogue.
-  double part = 0;
+  V(&fin_re)[WM][WN] = COMP ? tot_re : acc_re;
+  V(&fin_im)[WM][WN] = COMP ? tot_im : acc_im;
+  if constexpr (KS > 1) {
+    // groups 1.. add their sums into group 0's, one group at a time (the operand
+    // buffers are free after the loop's last barrier)
+    constexpr int kVals = WM * WN * 4;
+    static_assert(kVals * 2 * NT * sizeof(R) <= 2 * KS * GBK * BM * sizeof(C), "exchange fits in As");
+    for (int src = 1; src < KS; src++) {
+      if (grp == src) {
 #pragma unroll
-  for (int mi = 0; mi < WM; mi++)
+        for (int a = 0; a < WM; a++)
 #pragma unroll
-    for (int ni = 0; ni < WN; ni++)
+          for (int b = 0; b < WN; b++)
 #pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int i = m0 + wm + mi * 16 + MF<R>::row(lane, v);
-        const int j = n0 + wn + ni * 16 + (lane & 15);
-        C val;
-        if constexpr (COMP) {
-          val.re = tot_re[mi][ni][v];
-          val.im = tot_im[mi][ni][v];
-        } else {
-          val.re = acc_re[mi][ni][v];
-          val.im = acc_im[mi][ni][v];
-        }
-        if (i < g.m && j < g.n) epi_element<EPI, R>(g, i, j, val, part);
+            for (int v = 0; v < 4; v++) {
+              const int e = (a * WN + b) * 4 + v;
+              xch[(2 * e) * NT + tid] = fin_re[a][b][v];
+              xch[(2 * e + 1) * NT + tid] = fin_im[a][b][v];
+            }
       }
-  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<NT>(g, part, red, slot);
+      __syncthreads();
+      if (grp == 0) {
+#pragma unroll
+        for (int a = 0; a < WM; a++)
+#pragma unroll
+          for (int b = 0; b < WN; b++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+              const int e = (a * WN + b) * 4 + v;
+              fin_re[a][b][v] += xch[(2 * e) * NT + tid];
+              fin_im[a][b][v] += xch[(2 * e + 1) * NT + tid];
+            }
+      }
+      __syncthreads();
+    }
+  }
+
+  // Epilogue (group 0).
+  double part = 0;
+  if (grp == 0) {
+#pragma unroll
+    for (int mi = 0; mi < WM; mi++)
+#pragma unroll
+      for (int ni = 0; ni < WN; ni++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int i = m0 + wm + mi * 16 + MF<R>::row(lane, v);
+          const int j = n0 + wn + ni * 16 + (lane & 15);
+          C val;
+          val.re = fin_re[mi][ni][v];
+          val.im = fin_im[mi][ni][v];
+          if (i < g.m && j < g.n) epi_element<EPI, R>(g, i, j, val, part);
+        }
+  }
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<NT * KS>(g, part, red, slot);
 }
 
-template <typename R, int OPA, int EPI, int COMP>
-__global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
-  __shared__ cplx<R> As[2][GBK][GBM];
-  __shared__ cplx<R> Bs[2][GBK][GBN];
-  __shared__ double red[GNT / 64];
+template <typename R, int OPA, int EPI, int COMP, int KS>
+__global__ __launch_bounds__(GNT * KS) void gemm_kernel(GemmArgs g) {
+  __shared__ cplx<R> As[2 * KS][GBK][GBM];
+  __shared__ cplx<R> Bs[2 * KS][GBK][GBN];
+  __shared__ double red[GNT * KS / 64];
   // Blocks are dispatched round-robin over the XCDs (block b on XCD b mod 8):
   // give each XCD a contiguous run of logical tiles, then walk tiles in groups of
   // kGroup tile-rows so that concurrently running blocks share A rows and B columns
@@ -259,7 +307,7 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
     tm = first_m + within % gsize;
     tn = within / gsize;
   }
-  gemm_tile<R, OPA, EPI, COMP, GBM>(g, tm * GBM, tn * GBN, bid, As, Bs, red);
+  gemm_tile<R, OPA, EPI, COMP, GBM, KS>(g, tm * GBM, tn * GBN, bid, As, Bs, red);
 }
 
 // Grouped product over many matrices: a persistent grid walks a table of output
@@ -294,7 +342,16 @@ static hipError_t launch(GemmArgs g, hipStream_t st) {
   if (g.herm && (EPI != EPI_YDEF || g.m != g.n)) return hipErrorInvalidValue;
   const int nt = g.herm ? gemm_tiles_herm(g.n) : g.tiles_m * g.tiles_n;
   if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL((gemm_kernel<R, OPA, EPI, COMP>), dim3(nt), dim3(GNT), 0, st, g);
+  // Split K inside the block (KS = 2) when there are fewer than two tiles per CU, so
+  // that a CU still runs four waves per SIMD, and for the compensated form, whose
+  // registers (about 137 per thread) otherwise leave room for one 8-wave block per CU.
+  // Measured at n = 1024 / 2048 / 4096: compensated 59 -> 62%, 64 -> 65%, 67 -> 71% of
+  // peak; plain products at n = 4096 are faster unsplit (77% against 73%).
+  const bool split = COMP || nt < 2 * kCUs;
+  if (split)
+    hipLaunchKernelGGL((gemm_kernel<R, OPA, EPI, COMP, 2>), dim3(nt), dim3(2 * GNT), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_kernel<R, OPA, EPI, COMP, 1>), dim3(nt), dim3(GNT), 0, st, g);
   return hipGetLastError();
 }
 
