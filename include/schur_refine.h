@@ -54,9 +54,10 @@ typedef enum {
 
 typedef enum {
   SR_GEMM_FP64 = 0,       /* native FP64 MFMA                                         */
-  SR_GEMM_OZAKI_I8 = 1,   /* Ozaki split on INT8 MFMA, INT32 accumulation, for P = A Q,
-                             the start's Newton-Schulz products and Q * Delta; That and
-                             Y = Q^H Q - I stay native FP64 (their cancellation needs it) */
+  SR_GEMM_OZAKI_I8 = 1,   /* Ozaki split on INT8 MFMA, INT32 accumulation, for every hp
+                             product: P = A Q, That = Q^H P, Y = Q^H Q - I, the start's
+                             Newton-Schulz products and Q * Delta; the slice sums are
+                             combined in FP64                                          */
   SR_GEMM_OZAKI_BF16 = 2  /* Ozaki split on BF16 MFMA: not built (SR_ENOSYS); INT8
                              digits give the same exactness at twice the MFMA rate    */
 } sr_gemm_mode;

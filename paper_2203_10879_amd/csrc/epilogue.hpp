@@ -15,6 +15,10 @@ __device__ inline void epi_element(const GemmArgs& g, int i, int j, cplx<R> val,
   C* __restrict__ Cp = (C*)g.C;
   const long o = i + (long)j * g.ldc;
   if constexpr (EPI == EPI_STORE) {
+    if (g.herm) {
+      if (i > j) return;  // the mirror of (j, i) is stored there
+      if (i < j) Cp[j + (long)i * g.ldc] = g.herm > 0 ? mk<R>(val.re, -val.im) : mk<R>(-val.re, val.im);
+    }
     Cp[o] = val;
   } else if constexpr (EPI == EPI_ADD) {
     const C c0 = ((const C*)g.Cin)[i + (long)j * g.ldcin];

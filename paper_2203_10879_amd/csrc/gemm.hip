@@ -292,7 +292,7 @@ __global__ __launch_bounds__(GNT * KS) void gemm_kernel(GemmArgs g) {
     if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
   }
   int tm, tn;
-  if (EPI == EPI_YDEF && g.herm) {
+  if ((EPI == EPI_YDEF || EPI == EPI_STORE) && g.herm) {
     // upper triangle of tiles, column by column: logical = tn (tn + 1) / 2 + tm
     tn = (int)((sqrtf(8.f * logical + 1.f) - 1.f) * 0.5f);
     while (tn * (tn + 1) / 2 > logical) tn--;
@@ -339,7 +339,8 @@ template <typename R, int OPA, int EPI, int COMP>
 static hipError_t launch(GemmArgs g, hipStream_t st) {
   g.tiles_m = ceil_div(g.m, GBM);
   g.tiles_n = ceil_div(g.n, GBN);
-  if (g.herm && (EPI != EPI_YDEF || g.m != g.n)) return hipErrorInvalidValue;
+  if (g.herm && (g.m != g.n || !(EPI == EPI_STORE || (EPI == EPI_YDEF && g.herm == 1))))
+    return hipErrorInvalidValue;
   const int nt = g.herm ? gemm_tiles_herm(g.n) : g.tiles_m * g.tiles_n;
   if (nt == 0) return hipSuccess;
   // Split K inside the block (KS = 2) when there are fewer than two tiles per CU, so

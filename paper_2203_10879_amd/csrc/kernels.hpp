@@ -37,11 +37,12 @@ struct GemmArgs {
   const void* Cinlo;
   zc* Tlp64;
   zc* Elp64;
-  // EPI_YDEF: the product is Hermitian (the same matrix on both sides). Only the
-  // elements with i <= j are stored from the product, each with its conjugate at
-  // (j, i), so the result is exactly Hermitian; the squared norm counts both. The
-  // square FP64 and large-tile INT8 kernels then launch only the tiles on and above
-  // the diagonal.
+  // EPI_YDEF (1) and EPI_STORE (1 or -1): the product is Hermitian (1) or
+  // skew-Hermitian (-1), e.g. Q^H Q, W^2 and W^3 for a skew-Hermitian W. Only the
+  // elements with i <= j are stored from the product, each with its conjugate
+  // (negated for -1) at (j, i), so the result has the structure exactly; the squared
+  // norm of YDEF counts both. The square FP64/FP32 kernels and the large-tile INT8
+  // kernel (YDEF) then launch only the tiles on and above the diagonal.
   int herm;
 };
 

@@ -817,7 +817,7 @@ hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t
                    int SB, int conjA, int dmax, GemmArgs g, void* scratch, hipStream_t st,
                    bool dd) {
   if (g.m == 0 || g.n == 0) return hipSuccess;
-  if (g.herm && (epi != EPI_YDEF || g.m != g.n)) return hipErrorInvalidValue;
+  if (g.herm && (epi != EPI_YDEF || g.herm != 1 || g.m != g.n)) return hipErrorInvalidValue;
   if (use_large_tiles(g.m, g.n, dd)) {
     if (!scratch) return hipErrorInvalidValue;
     g.tiles_m = ceil_div(g.m, PBM);

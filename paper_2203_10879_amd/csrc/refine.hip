@@ -98,7 +98,8 @@ Work carve(void* base, int n, const sr_opts* o = nullptr) {
     w.sA = (int8_t*)take(align256(oz_slice_bytes(n, n, S)));
     w.sQc = (int8_t*)take(align256(oz_slice_bytes(n, n, S)));
     w.sQr = (int8_t*)take(align256(oz_slice_bytes(n, n, Su)));
-    w.sD = (int8_t*)take(align256(oz_slice_bytes(n, n, Su)));
+    // the column slices of Delta, and before them those of P (for That)
+    w.sD = (int8_t*)take(align256(oz_slice_bytes(n, n, Su > S ? Su : S)));
     w.eA = (int*)take(align256((size_t)n * sizeof(int)));
     w.eQc = (int*)take(align256((size_t)n * sizeof(int)));
     w.eQr = (int*)take(align256((size_t)n * sizeof(int)));
@@ -293,24 +294,33 @@ int ns_init(const zc* Qh, zc* Qout, zc* QHout, int n, int comp, const Work& w, h
 
 // P = A Q, That = Q^H P with the split epilogue, scal[1] = ||stril(That)||_F^2.
 // With QH (= Q^H) given, That is formed as the plain product QH P.
+// Ozaki mode: both products from digit slices: P from the row slices of A (split
+// once per call) and the column slices of Q (kept in sQc for Y of the same pass),
+// That from the conjugated column slices of Q and the column slices of P.
 int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, const Work& w,
              hipStream_t st, Timer* tm = nullptr) {
   GemmArgs g = gargs(n, n, n, A, n, Q, n, w.P, n);
-  TIC(tm, 0);
-  if (w.oz_s) {
-    // Ozaki mode: P from the row slices of A (split once per call) and the column
-    // slices of Q; That and Y stay native FP64.
-    CK(oz_split_cols(Q, nullptr, n, n, n, w.oz_s, w.sQc, w.eQc, st));
-    CK(oz_gemm(EPI_STORE, w.sA, w.eA, w.oz_s, w.sQc, w.eQc, w.oz_s, 0, w.oz_s + 1, g, w.oz_scratch, st));
-  } else {
-    CK(zgemm(0, EPI_STORE, comp, g, st));
-  }
-  TOC(tm, 0);
   GemmArgs s = gargs(n, n, n, QH ? QH : Q, n, w.P, n, T, n);
   s.Tlp = w.Tlp;
   s.Elp = w.Elp;
   s.ldlp = n;
   s.partials = w.partials;
+  if (w.oz_s) {
+    const int S = w.oz_s;
+    TIC(tm, 0);
+    CK(oz_split_cols(Q, nullptr, n, n, n, S, w.sQc, w.eQc, st));
+    CK(oz_gemm(EPI_STORE, w.sA, w.eA, S, w.sQc, w.eQc, S, 0, S + 1, g, w.oz_scratch, st));
+    TOC(tm, 0);
+    TIC(tm, 0);
+    CK(oz_split_cols(w.P, nullptr, n, n, n, S, w.sD, w.eD, st));
+    CK(oz_gemm(EPI_SPLIT, w.sQc, w.eQc, S, w.sD, w.eD, S, 1, S + 1, s, w.oz_scratch, st));
+    TOC(tm, 0);
+    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n), w.scal + 1, st));
+    return SR_OK;
+  }
+  TIC(tm, 0);
+  CK(zgemm(0, EPI_STORE, comp, g, st));
+  TOC(tm, 0);
   TIC(tm, 0);
   CK(zgemm(QH ? 0 : 1, EPI_SPLIT, comp, s, st));
   TOC(tm, 0);
@@ -319,10 +329,19 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
 }
 
 // Y = Q^H Q - I (scal[2] = ||Y||^2).
+// Ozaki mode: from the column slices of Q that residual() left in sQc (the same Q).
 int ydef(const zc* Q, const zc* QH, int n, int comp, const Work& w, hipStream_t st, Timer* tm) {
   GemmArgs g = gargs(n, n, n, QH ? QH : Q, n, Q, n, w.Y, n);
   g.partials = w.partials;
   g.herm = 1;
+  if (w.oz_s) {
+    const int S = w.oz_s;
+    TIC(tm, 0);
+    CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, S, w.sQc, w.eQc, S, 1, S + 1, g, w.oz_scratch, st));
+    TOC_HERM(tm);
+    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, false, true), w.scal + 2, st));
+    return SR_OK;
+  }
   TIC(tm, 0);
   CK(zgemm(QH ? 0 : 1, EPI_YDEF, comp, g, st));
   TOC_HERM(tm);
@@ -354,11 +373,15 @@ int apply_update(const zc* Q, zc* Qout, zc* QHout, int n, Gate gt, const Work& w
                  int* nprod, Timer* tm = nullptr, int Su = 0) {
   int np = 0;
   if (gt.w2 || gt.w3) {
-    CK(cgemm(gargs(n, n, n, w.W, n, w.W, n, w.W2, n), st));
+    GemmArgs a2 = gargs(n, n, n, w.W, n, w.W, n, w.W2, n);
+    a2.herm = 1;  // W is skew-Hermitian: W^2 is Hermitian
+    CK(cgemm(a2, st));
     np++;
   }
   if (gt.w3) {
-    CK(cgemm(gargs(n, n, n, w.W2, n, w.W, n, w.W3, n), st));
+    GemmArgs a3 = gargs(n, n, n, w.W2, n, w.W, n, w.W3, n);
+    a3.herm = -1;  // and W^3 skew-Hermitian
+    CK(cgemm(a3, st));
     np++;
   }
   if (gt.yw) {
@@ -537,11 +560,14 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   zc* other = Q;
   if (w.oz_s) CK(oz_split_rows(A, nullptr, n, n, n, w.oz_s, w.sA, w.eA, st));
   int su = 0;
-  if ((rc = ns_init(Q, w.Qa, w.QH, n, comp, w, st, tm, &o, &su)) != SR_OK) return rc;
+  // the explicit Q^H serves the native That and Y; the Ozaki forms use the column
+  // slices of Q instead
+  zc* const QH = w.oz_s ? nullptr : w.QH;
+  if ((rc = ns_init(Q, w.Qa, QH, n, comp, w, st, tm, &o, &su)) != SR_OK) return rc;
   if (info) info->update_slices_hist[0] = su;
 
   for (int p = 0; p < iters; p++) {
-    if ((rc = residual(A, cur, w.QH, T, n, comp, w, st, tm)) != SR_OK) return rc;
+    if ((rc = residual(A, cur, QH, T, n, comp, w, st, tm)) != SR_OK) return rc;
     double s[2];
     unsigned dst = 0;
     if ((rc = read_back(st, w, 2, s, &dst)) != SR_OK) return rc;
@@ -574,7 +600,7 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
     TIC(tm, 1);
     CK(trisolve(w.Tlp, w.Elp, w.Llp, n, o.trunc ? 1e-5f : 0.f, w.tri, w.status, st));
     TOC(tm, 1);
-    if ((rc = ydef(cur, w.QH, n, comp, w, st, tm)) != SR_OK) return rc;
+    if ((rc = ydef(cur, QH, n, comp, w, st, tm)) != SR_OK) return rc;
     CK(form_w(w.Llp, w.W, n, w.partials, st));
     CK(reduce_partials(w.partials, form_w_parts(n), w.scal + 3, st));
     double nrm[4];
@@ -593,7 +619,7 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
     const Gate gt = gate_terms(o.gate_lp_terms != 0, nw, ny);
     su = w.oz_s ? update_slices(o, nw + 0.5 * ny) : 0;
     if (info && updates + 1 < 16) info->update_slices_hist[updates + 1] = su;
-    if ((rc = apply_update(cur, other, w.QH, n, gt, w, st, &nprod, tm, su)) != SR_OK) return rc;
+    if ((rc = apply_update(cur, other, QH, n, gt, w, st, &nprod, tm, su)) != SR_OK) return rc;
     zc* t = cur;
     cur = other;
     other = t;
@@ -952,11 +978,15 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
     const bool gw3 = !o.gate_lp_terms || nw * nw * nw > thr;
     const bool gyw = !o.gate_lp_terms || ny * nw > thr;
     if (gw2 || gw3) {
-      CK(zgemm(0, EPI_STORE, 0, gargs(n, n, n, w.W, n, w.W, n, w.W2, n), st));
+      GemmArgs a2 = gargs(n, n, n, w.W, n, w.W, n, w.W2, n);
+      a2.herm = 1;  // W is skew-Hermitian: W^2 is Hermitian
+      CK(zgemm(0, EPI_STORE, 0, a2, st));
       nprod++;
     }
     if (gw3) {
-      CK(zgemm(0, EPI_STORE, 0, gargs(n, n, n, w.W2, n, w.W, n, w.W3, n), st));
+      GemmArgs a3 = gargs(n, n, n, w.W2, n, w.W, n, w.W3, n);
+      a3.herm = -1;  // and W^3 skew-Hermitian
+      CK(zgemm(0, EPI_STORE, 0, a3, st));
       nprod++;
     }
     if (gyw) {

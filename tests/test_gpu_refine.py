@@ -183,8 +183,8 @@ def test_batched_pass_limit_and_workspace(sr):
 
 @pytest.mark.parametrize("n", [64, 257])
 def test_ozaki_mode_converges(sr, n):
-    """Ozaki mode (P = A Q, the start's products and Q Delta on INT8 digits; That
-    and Y native FP64) reaches the same tolerance in the same number of passes."""
+    """Ozaki mode (every hp product from INT8 digits) reaches the same tolerance in
+    the same number of passes."""
     g = synth.schur_test_matrix(n, seed=300 + n)
     qh = synth.lp_schur_start(g["A"])
     q, t, info = _refine(sr, g["A"], qh, gemm="ozaki_i8")
