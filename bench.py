@@ -12,8 +12,11 @@ timed region).
 
 Other workloads (--workload), each one JSON line of its own:
   precision       n = 4096, eigenvalue gaps >= 1e-3, cgees start: the FP64 tier
-                  with native FP64 products and with Ozaki INT8 splits, time to
-                  1e-15 and the binary128 error on sampled rows for each;
+                  with native FP64 products, with Ozaki INT8 splits of P, the
+                  start and Q Delta (That and Y native), and with every product
+                  split; median time to 1e-15 over interleaved steps and the
+                  binary128 error on sampled rows for each; a product sweep over
+                  digit counts;
   batched         2000 matrices, n uniform in [16, 256], each from its own seed
                   with a cgees start, refined together (schur_refine_batched;
                   a step restores all starts with one device copy);
@@ -178,30 +181,44 @@ def run_precision(args) -> int:
     A, Q0 = sr.colmajor(g["A"]), sr.colmajor(qh)
     Q, T = sr.colmajor_empty(n, n), sr.colmajor_empty(n, n)
     rows = np.random.default_rng(7).choice(n, args.rows, replace=False)
+    # The forms are timed interleaved (one refinement of each per step, each timed
+    # with HIP events on the current stream), so that clock drift over the run falls
+    # on all of them alike.
+    modes = ("fp64", "ozaki_i8", "ozaki_i8_all")
+    wss = {m: sr.workspace(n, gemm=m) for m in modes}
+    for _ in range(args.warmup):
+        for m in modes:
+            Q.copy_(Q0)
+            sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=m, workspace=wss[m])
+    torch.cuda.synchronize()
+    infos = {m: [] for m in modes}
+    ms_each = {m: [] for m in modes}
+    for _ in range(args.steps):
+        for m in modes:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            Q.copy_(Q0)
+            infos[m].append(sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=m, timing=True, workspace=wss[m]))
+            e1.record()
+            torch.cuda.synchronize()
+            ms_each[m].append(e0.elapsed_time(e1))
     forms = {}
-    for mode in ("fp64", "ozaki_i8"):
-        ws = sr.workspace(n, gemm=mode)
-        for _ in range(args.warmup):
-            Q.copy_(Q0)
-            sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=mode, workspace=ws)
+    for m in modes:
+        Q.copy_(Q0)
+        sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=m, workspace=wss[m])
         torch.cuda.synchronize()
-        infos, t1 = [], time.perf_counter()
-        for _ in range(args.steps):
-            Q.copy_(Q0)
-            infos.append(sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=mode, timing=True, workspace=ws))
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t1) / args.steps
-        last = infos[-1]
         ev = oracle.evaluate_rows(g["A"], sr.to_numpy(Q), rows)
-        launches = sum(i["hp_gemm_launches"] for i in infos)
-        forms[mode] = {"status": last["status"], "passes": last["iters"], "ms_to_tol": 1e3 * dt,
-                       "ms_hp_products": sum(i["ms_hp_gemm"] for i in infos) / args.steps,
-                       "avg_hp_product_ms": sum(i["ms_hp_gemm"] for i in infos) / max(1, launches),
-                       "ms_solve": sum(i["ms_solve"] for i in infos) / args.steps,
-                       "resid_hist": last["resid_hist"], "update_digits": last["update_slices_hist"],
-                       "quad_stril_rows": float(ev["stril"]), "quad_orth_rows": float(ev["orth"])}
-        print(f"# {mode}: {forms[mode]['ms_to_tol']:.1f} ms", file=sys.stderr, flush=True)
-        del ws
+        inf, last = infos[m], infos[m][-1]
+        launches = sum(i["hp_gemm_launches"] for i in inf)
+        forms[m] = {"status": last["status"], "passes": last["iters"],
+                    "ms_to_tol": float(np.median(ms_each[m])), "ms_min": float(np.min(ms_each[m])),
+                    "ms_hp_products": sum(i["ms_hp_gemm"] for i in inf) / args.steps,
+                    "avg_hp_product_ms": sum(i["ms_hp_gemm"] for i in inf) / max(1, launches),
+                    "ms_solve": sum(i["ms_solve"] for i in inf) / args.steps,
+                    "resid_hist": last["resid_hist"], "update_digits": last["update_slices_hist"],
+                    "quad_stril_rows": float(ev["stril"]), "quad_orth_rows": float(ev["orth"])}
+        print(f"# {m}: {forms[m]['ms_to_tol']:.1f} ms (median of {args.steps})", file=sys.stderr, flush=True)
+    del wss
     # The product P = A Q-hat per form: Ozaki INT8 with s digits per operand (pairs up
     # to s + t = s + 1, splits included) and native FP64, timed with HIP events and
     # compared with the binary128 product on 8 of the sampled rows.
@@ -244,11 +261,13 @@ def run_precision(args) -> int:
     ok = oz["status"] == "OK" and fp["status"] == "OK"
     out = base_record(args, 1e3 / oz["ms_to_tol"] if ok else 0.0, "decomps/s", oz["ms_to_tol"], "f64+i8",
                       {"workload": f"precision comparison n={n}, eigenvalue gaps >= 1e-3, FP32 cgees start; "
-                                   "value = Ozaki INT8 form (every hp product from INT8 digits, "
-                                   "slice sums combined in FP64)",
+                                   "value = Ozaki INT8 form (P = AQ, the start's products and Q Delta on "
+                                   "INT8 digits; That and Y native FP64); ozaki_i8_all: every hp product "
+                                   "from INT8 digits",
                        "n": n, "tol": TOL, "quad_rows": args.rows})
     out["forms"] = forms
     out["ozaki_speedup_vs_fp64"] = fp["ms_to_tol"] / oz["ms_to_tol"]
+    out["ozaki_all_speedup_vs_fp64"] = fp["ms_to_tol"] / forms["ozaki_i8_all"]["ms_to_tol"]
     out["product_sweep"] = {"product": f"P = A Q-hat, n={n}", "error": "relative Frobenius error on 8 rows "
                             "against the binary128 product", "forms": sweep}
     out["roofline"] = None

@@ -54,17 +54,20 @@ typedef enum {
 
 typedef enum {
   SR_GEMM_FP64 = 0,       /* native FP64 MFMA                                         */
-  SR_GEMM_OZAKI_I8 = 1,   /* Ozaki split on INT8 MFMA, INT32 accumulation, for every hp
-                             product: P = A Q, That = Q^H P, Y = Q^H Q - I, the start's
-                             Newton-Schulz products and Q * Delta; the slice sums are
-                             combined in FP64                                          */
-  SR_GEMM_OZAKI_BF16 = 2  /* Ozaki split on BF16 MFMA: not built (SR_ENOSYS); INT8
+  SR_GEMM_OZAKI_I8 = 1,   /* Ozaki split on INT8 MFMA, INT32 accumulation, for P = A Q,
+                             the start's Newton-Schulz products and Q * Delta; That and
+                             Y = Q^H Q - I stay native FP64 (the split form of the
+                             residual products named for the precision comparison)     */
+  SR_GEMM_OZAKI_BF16 = 2, /* Ozaki split on BF16 MFMA: not built (SR_ENOSYS); INT8
                              digits give the same exactness at twice the MFMA rate    */
+  SR_GEMM_OZAKI_I8_ALL = 3 /* as SR_GEMM_OZAKI_I8, and That and Y from digit slices too
+                             (Y from the column slices of Q made for P); the slice
+                             sums are combined in FP64                                 */
 } sr_gemm_mode;
 
 typedef struct {
   int gemm;               /* sr_gemm_mode for the hp products                         */
-  int slices;             /* SR_GEMM_OZAKI_I8: 8-bit digits per operand of P = A Q and
+  int slices;             /* SR_GEMM_OZAKI_I8(_ALL): 8-bit digits per operand of P = A Q and
                              of the start's Gram matrix, slice pairs up to s + t =
                              slices + 1 (0 = default 7, at most 16)                   */
   int update_slices;      /* SR_GEMM_OZAKI_I8: digits per operand of Q * Delta

@@ -25,7 +25,7 @@ _LIB = None
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "STAGNATED", 3: "BREAKDOWN", 4: "DIVERGED",
           -1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "ENOSYS"}
-GEMM_MODES = {"fp64": 0, "ozaki_i8": 1, "ozaki_bf16": 2}
+GEMM_MODES = {"fp64": 0, "ozaki_i8": 1, "ozaki_bf16": 2, "ozaki_i8_all": 3}
 
 
 class SrOpts(ctypes.Structure):

@@ -53,6 +53,7 @@ struct Work {
   int8_t *sA, *sQc, *sQr, *sD;
   int *eA, *eQc, *eQr, *eD;
   void* oz_scratch;  // FP64 partial sums of the large-tile product (may be NULL)
+  bool oz_all;  // Ozaki mode: That and Y from slices too
   int oz_s;
   size_t bytes;
 };
@@ -91,7 +92,9 @@ Work carve(void* base, int n, const sr_opts* o = nullptr) {
   w.eA = w.eQc = w.eQr = w.eD = nullptr;
   w.oz_scratch = nullptr;
   w.oz_s = 0;
-  if (o && o->gemm == SR_GEMM_OZAKI_I8) {
+  w.oz_all = false;
+  if (o && (o->gemm == SR_GEMM_OZAKI_I8 || o->gemm == SR_GEMM_OZAKI_I8_ALL)) {
+    w.oz_all = o->gemm == SR_GEMM_OZAKI_I8_ALL;
     const int S = oz_main_slices(o);
     const int Su = o->update_slices > 0 ? o->update_slices : kOzMaxUpd;
     w.oz_s = S;
@@ -294,9 +297,9 @@ int ns_init(const zc* Qh, zc* Qout, zc* QHout, int n, int comp, const Work& w, h
 
 // P = A Q, That = Q^H P with the split epilogue, scal[1] = ||stril(That)||_F^2.
 // With QH (= Q^H) given, That is formed as the plain product QH P.
-// Ozaki mode: both products from digit slices: P from the row slices of A (split
-// once per call) and the column slices of Q (kept in sQc for Y of the same pass),
-// That from the conjugated column slices of Q and the column slices of P.
+// Ozaki mode: P from the row slices of A (split once per call) and the column
+// slices of Q (kept in sQc for Y of the same pass); with oz_all also That, from
+// the conjugated column slices of Q and the column slices of P.
 int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, const Work& w,
              hipStream_t st, Timer* tm = nullptr) {
   GemmArgs g = gargs(n, n, n, A, n, Q, n, w.P, n);
@@ -305,12 +308,17 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
   s.Elp = w.Elp;
   s.ldlp = n;
   s.partials = w.partials;
+  TIC(tm, 0);
   if (w.oz_s) {
     const int S = w.oz_s;
-    TIC(tm, 0);
     CK(oz_split_cols(Q, nullptr, n, n, n, S, w.sQc, w.eQc, st));
     CK(oz_gemm(EPI_STORE, w.sA, w.eA, S, w.sQc, w.eQc, S, 0, S + 1, g, w.oz_scratch, st));
-    TOC(tm, 0);
+  } else {
+    CK(zgemm(0, EPI_STORE, comp, g, st));
+  }
+  TOC(tm, 0);
+  if (w.oz_all) {
+    const int S = w.oz_s;
     TIC(tm, 0);
     CK(oz_split_cols(w.P, nullptr, n, n, n, S, w.sD, w.eD, st));
     CK(oz_gemm(EPI_SPLIT, w.sQc, w.eQc, S, w.sD, w.eD, S, 1, S + 1, s, w.oz_scratch, st));
@@ -319,9 +327,6 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
     return SR_OK;
   }
   TIC(tm, 0);
-  CK(zgemm(0, EPI_STORE, comp, g, st));
-  TOC(tm, 0);
-  TIC(tm, 0);
   CK(zgemm(QH ? 0 : 1, EPI_SPLIT, comp, s, st));
   TOC(tm, 0);
   CK(reduce_partials(w.partials, gemm_tiles(n, n), w.scal + 1, st));
@@ -329,12 +334,12 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
 }
 
 // Y = Q^H Q - I (scal[2] = ||Y||^2).
-// Ozaki mode: from the column slices of Q that residual() left in sQc (the same Q).
+// oz_all: from the column slices of Q that residual() left in sQc (the same Q).
 int ydef(const zc* Q, const zc* QH, int n, int comp, const Work& w, hipStream_t st, Timer* tm) {
   GemmArgs g = gargs(n, n, n, QH ? QH : Q, n, Q, n, w.Y, n);
   g.partials = w.partials;
   g.herm = 1;
-  if (w.oz_s) {
+  if (w.oz_all) {
     const int S = w.oz_s;
     TIC(tm, 0);
     CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, S, w.sQc, w.eQc, S, 1, S + 1, g, w.oz_scratch, st));
@@ -497,11 +502,12 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   sr_opts o;
   if (opts_in) o = *opts_in;
   else sr_default_opts(&o);
-  if (o.gemm != SR_GEMM_FP64 && o.gemm != SR_GEMM_OZAKI_I8) {
+  const bool ozaki = o.gemm == SR_GEMM_OZAKI_I8 || o.gemm == SR_GEMM_OZAKI_I8_ALL;
+  if (o.gemm != SR_GEMM_FP64 && !ozaki) {
     if (info) info->status = o.gemm == SR_GEMM_OZAKI_BF16 ? SR_ENOSYS : SR_EINVAL;
     return o.gemm == SR_GEMM_OZAKI_BF16 ? SR_ENOSYS : SR_EINVAL;
   }
-  if (o.gemm == SR_GEMM_OZAKI_I8 &&
+  if (ozaki &&
       (o.slices < 0 || o.slices > 16 || o.update_slices < 0 || o.update_slices > kOzMaxUpd ||
        !oz_gemm_exact(n, n, n, oz_main_slices(&o), oz_main_slices(&o)))) {
     if (info) info->status = SR_EINVAL;
@@ -560,9 +566,9 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   zc* other = Q;
   if (w.oz_s) CK(oz_split_rows(A, nullptr, n, n, n, w.oz_s, w.sA, w.eA, st));
   int su = 0;
-  // the explicit Q^H serves the native That and Y; the Ozaki forms use the column
+  // the explicit Q^H serves the native That and Y; with oz_all they use the column
   // slices of Q instead
-  zc* const QH = w.oz_s ? nullptr : w.QH;
+  zc* const QH = w.oz_all ? nullptr : w.QH;
   if ((rc = ns_init(Q, w.Qa, QH, n, comp, w, st, tm, &o, &su)) != SR_OK) return rc;
   if (info) info->update_slices_hist[0] = su;
 

@@ -181,13 +181,15 @@ def test_batched_pass_limit_and_workspace(sr):
         assert oracle.evaluate(m["A"], host(qd), host(td))["stril"] <= 1e-15
 
 
+@pytest.mark.parametrize("mode", ["ozaki_i8", "ozaki_i8_all"])
 @pytest.mark.parametrize("n", [64, 257])
-def test_ozaki_mode_converges(sr, n):
-    """Ozaki mode (every hp product from INT8 digits) reaches the same tolerance in
-    the same number of passes."""
+def test_ozaki_mode_converges(sr, n, mode):
+    """Ozaki modes (P = A Q, the start's products and Q Delta on INT8 digits; That and
+    Y native FP64, or from digits too) reach the same tolerance in the same number of
+    passes."""
     g = synth.schur_test_matrix(n, seed=300 + n)
     qh = synth.lp_schur_start(g["A"])
-    q, t, info = _refine(sr, g["A"], qh, gemm="ozaki_i8")
+    q, t, info = _refine(sr, g["A"], qh, gemm=mode)
     _, _, ref = _refine(sr, g["A"], qh)
     assert info["status"] == "OK", info
     assert abs(info["iters"] - ref["iters"]) <= 1, (info, ref)
@@ -209,11 +211,12 @@ def test_ozaki_mode_exact_hadamard(sr):
     assert np.abs(c - np.diag(np.diag(c))).max() <= 1e-13
 
 
-def test_ozaki_mode_n1024_quad_rows(sr):
+@pytest.mark.parametrize("mode", ["ozaki_i8", "ozaki_i8_all"])
+def test_ozaki_mode_n1024_quad_rows(sr, mode):
     g = synth.schur_test_matrix(1024, seed=1)
     a = g["A"]
     qh = synth.lp_schur_start(a)
-    q, t, info = _refine(sr, a, qh, gemm="ozaki_i8")
+    q, t, info = _refine(sr, a, qh, gemm=mode)
     assert info["status"] == "OK" and info["iters"] <= 5, info
     rows = np.random.default_rng(20001).choice(1024, 64, replace=False)
     ev = oracle.evaluate_rows(a, q, rows)
