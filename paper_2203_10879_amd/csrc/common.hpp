@@ -80,6 +80,31 @@ enum : unsigned {
   DEV_BREAKDOWN = 1u,  // t_ii == t_jj or a non-finite value in the solve
 };
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct MF;
+// Accumulator layout: element v of lane l holds D[row(l, v)][l % 16]. The FP64
+// instruction interleaves its rows (row = l/16 + 4v); the FP32 one stacks them
+// (row = 4 (l/16) + v). Both were confirmed with a one-instruction probe.
+template <>
+struct MF<double> {
+  using v4 = d4;
+  __device__ static inline v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct MF<float> {
+  using v4 = f4;
+  __device__ static inline v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
 constexpr int kCUs = 256;  // MI355X compute units
 constexpr int kXCDs = 8;   // accelerator complex dies (one L2 each)
 

@@ -94,10 +94,10 @@ hipError_t oz_split_cols(const zc* X, const zc* Xlo, long ld, int K, int ncols, 
                          int* exps, hipStream_t st);
 hipError_t oz_split_rows(const zc* X, const zc* Xlo, long ld, int M, int K, int S, int8_t* out,
                          int* exps, hipStream_t st);
-// Output tiles (= partial sums written) of a product; dd selects the kernel with
-// double-double accumulation, which serves every size; herm: a Hermitian product
-// (GemmArgs::herm).
-int oz_gemm_tiles(int m, int n, bool dd = false, bool herm = false);
+// Output tiles (= partial sums written) of a product; the sizes, the digit counts
+// and dd (double-double accumulation) select the kernel; herm: a Hermitian
+// product (GemmArgs::herm).
+int oz_gemm_tiles(int m, int n, int k, bool dd, bool herm, int SA, int SB, int dmax);
 // Bytes of scratch the product of an m x n output needs (0 for small FP64 outputs).
 size_t oz_gemm_scratch_bytes(int m, int n, bool dd = false);
 // Whether the int32 sums of a product stay exact for these sizes.

@@ -767,15 +767,248 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(2))) void o
   if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<PNT>(g, part, (double*)lds, bid);
 }
 
+// ------------------------------------------------------ all-pairs product
+//
+// The FP64 tier's products (at most kApS digits per operand, pairs up to
+// s + t = kApS + 1) on outputs with at least one 64 x 64 tile per CU. The kernel
+// above reads both slices of a pair once per pair, so every slice is fetched
+// once per pair it takes part in (28 pairs from 7 + 7 slices), and those reads
+// miss L2. Here a K-step (32 deep) stages the digits of every slice of both
+// operands in LDS at once, and each wave forms all pairs of the step from
+// registers, with one int32 accumulator pair (re, im) per diagonal s + t: the
+// operand bytes per tile drop by the ratio of pairs to slices.
+//
+// A 256-thread block computes a 64 x 64 complex tile, each wave one 32 x 32
+// block (re and im: 2 x 16 int32 per diagonal and lane, up to 7 diagonals), one
+// block per CU (LDS: two stages of 70 KiB). The int32 sums of a diagonal stay
+// exact for kApSeg K-steps (at most 7 pairs x 2 products x 32 terms x 2^14 per
+// step, 7 * 2^28 < 2^31 over a segment); every segment is folded into FP64
+// partial sums in registers, the diagonals from the smallest weight up.
+//
+// LDS layout of a stage: one 2 KiB region per part (A: 3 parts per slice, B: 2),
+// 64 rows x 32 bytes (the step's half of each 64-byte K-block row). Within a row
+// the two 16-byte chunks sit at position c ^ lsw(row), lsw(row) = bit 2 ^ bit 3
+// of the row, so that fragment reads of 8 or 16 consecutive rows at one chunk hit
+// distinct banks. The loads gather those halves from the global planes
+// (global_load_lds_dwordx4: lane l writes 16 bytes at base + 16 l, i.e. row
+// l / 2, position l % 2 of a 32-row half region).
+constexpr int kApS = 7;
+constexpr int ABM = 64, ANT = 256, kApSeg = 256;
+constexpr int kApRegion = ABM * 32;                       // 2 KiB
+constexpr int kApStageBytes = kApS * 5 * kApRegion;       // 70 KiB
+constexpr int kApLds = 2 * kApStageBytes;
+static_assert(kApS * 2 * 32 * 16384L * kApSeg < 2147483648L, "segment bound");
+__host__ __device__ inline int ap_lsw(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
+
+template <int EPI, int S>
+__global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(1, 1))) void oz_gemm_allpairs_kernel(
+    OzArgs a) {
+  extern __shared__ __align__(16) int8_t lds[];  // kApLds
+  __shared__ double red[ANT / 64];
+  const GemmArgs& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+
+  const int ntiles = gridDim.x, bid = blockIdx.x;
+  int logical = bid;
+  {
+    const int per = ntiles / kXCDs;
+    if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
+  }
+  int tm, tn;
+  if (EPI == EPI_YDEF && g.herm) {
+    tn = (int)((sqrtf(8.f * logical + 1.f) - 1.f) * 0.5f);
+    while (tn * (tn + 1) / 2 > logical) tn--;
+    while ((tn + 1) * (tn + 2) / 2 <= logical) tn++;
+    tm = logical - tn * (tn + 1) / 2;
+  } else {
+    // groups of kGroup tile rows, column by column within a group: the 32 blocks
+    // an XCD runs at once share 4 row panels and 8 column panels
+    constexpr int kGroup = 4;
+    const int group = logical / (kGroup * g.tiles_n);
+    const int first_m = group * kGroup;
+    const int gsize = min(g.tiles_m - first_m, kGroup);
+    const int within = logical - group * kGroup * g.tiles_n;
+    tm = first_m + within % gsize;
+    tn = within / gsize;
+  }
+  const int m0 = tm * ABM, n0 = tn * ABM;
+
+  // S digits per operand, pairs s + t <= S + 1 (diagonals d = 2 .. S + 1)
+  const int KB = a.Kp / OBK, KS = a.Kp / 32;
+  const long pA = oz_plane_bytes(g.m, a.Kp), pB = oz_plane_bytes(g.n, a.Kp);
+  const long sA = kParts * pA, sB = kParts * pB;
+  const int pa2 = a.conjA ? 1 : 2, pa3 = a.conjA ? 2 : 1;
+
+  // this lane's source offset within a plane for each half region (rows 0-31,
+  // 32-63 of the tile) at K-block 0, K-half 0; rows past the padded matrix read
+  // its last row block (their outputs are not stored)
+  const int uwave = __builtin_amdgcn_readfirstlane(wave);
+  const int RBA = oz_rows_pad(g.m) / 16, RBB = oz_rows_pad(g.n) / 16;
+  int offA[2], offB[2];
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    const int r = 32 * h + (lane >> 1);
+    const int c = (lane & 1) ^ ap_lsw(r);
+    const int rba = min((m0 + r) >> 4, RBA - 1), rbb = min((n0 + r) >> 4, RBB - 1);
+    const int rowa = rba * 16 + (r & 15), rowb = rbb * 16 + (r & 15);
+    offA[h] = rba * KB * 1024 + (r & 15) * 64 + ((c ^ chunk_swz(rowa)) << 4);
+    offB[h] = rbb * KB * 1024 + (r & 15) * 64 + ((c ^ chunk_swz(rowb)) << 4);
+  }
+  // The step's 1 KiB load instructions: 6 S for A (slice q / 6, part (q % 6) / 2,
+  // half q % 2), 4 S for B (slice q / 4, part (q / 2) % 2, half q % 2). Wave w
+  // issues A instructions w, w + 4, ... (past 6 S it repeats instruction q - 4,
+  // which rewrites the same bytes) and B instructions w, w + 4, .... Source
+  // offsets (plane and lane part, K-block 0, K-half 0) and LDS offsets are fixed
+  // for the whole tile.
+  constexpr int kQA = (6 * S + 3) / 4, kQ = kQA + S;
+  int goff[kQ], loff[kQ];
+#pragma unroll
+  for (int k = 0; k < kQ; k++) {
+    if (k < kQA) {
+      int q = uwave + 4 * k;
+      if (q >= 6 * S) q -= 4;
+      const int sl = q / 6, rem = q - 6 * sl, part = rem >> 1, h = rem & 1;
+      goff[k] = (int)(sl * sA + part * pA) + offA[h];
+      loff[k] = (3 * sl + part) * kApRegion + h * 1024;
+    } else {
+      const int q = uwave + 4 * (k - kQA), t = q >> 2, part = (q >> 1) & 1, h = q & 1;
+      goff[k] = (int)(t * sB + part * pB) + offB[h];
+      loff[k] = (3 * kApS + 2 * t + part) * kApRegion + h * 1024;
+    }
+  }
+  // load instructions k0 .. k1-1 of step ks into a stage
+  auto issue = [&](int ks, int stage, int k0, int k1) {
+    const int kbo = (ks >> 1) * 1024, kx = (ks & 1) << 5;
+    int8_t* lb = lds + stage * kApStageBytes;
+#pragma unroll
+    for (int k = 0; k < kQ; k++) {
+      if (k >= k0 && k < k1) {
+        // the plane offsets are multiples of 1 KiB, so the K-half flips bit 5 of
+        // the lane part only
+        const int8_t* src = (k < kQA ? a.A : a.B) + kbo + (goff[k] ^ kx);
+        __builtin_amdgcn_global_load_lds((gbl_ptr_t*)src, (lds_ptr_t*)(lb + loff[k]), 16, 0, 0);
+      }
+    }
+  };
+  // fragment offsets of this lane within a region: row (lane & 31) of the wave's
+  // block, K-chunk lane >> 5
+  const int ra = wm + (lane & 31), rb = wn + (lane & 31);
+  const int fa = ra * 32 + ((((lane >> 5) ^ ap_lsw(ra))) << 4);
+  const int fb = rb * 32 + ((((lane >> 5) ^ ap_lsw(rb))) << 4);
+
+  v16i acc_re[S], acc_im[S];
+  auto barrier = [&]() {
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  auto load_a = [&](const int8_t* lb, int s, v4i& x0, v4i& x2, v4i& x3) {
+    x0 = *(const v4i*)(lb + (3 * s) * kApRegion + fa);
+    x2 = *(const v4i*)(lb + (3 * s + pa2) * kApRegion + fa);
+    x3 = *(const v4i*)(lb + (3 * s + pa3) * kApRegion + fa);
+  };
+  // FP64 partial sums between segments (K beyond kApSeg steps) live in the
+  // per-tile scratch, in the waves' register order (coalesced)
+  double2* sp = a.scratch ? a.scratch + ((long)bid * 4 + wave) * 1024 + lane : nullptr;
+  double part = 0;
+
+  issue(0, 0, 0, kQ);
+  for (int seg0 = 0; seg0 < KS; seg0 += kApSeg) {
+    const int seg1 = min(KS, seg0 + kApSeg);
+#pragma unroll
+    for (int di = 0; di < S; di++) acc_re[di] = acc_im[di] = v16i{};
+    for (int ks = seg0; ks < seg1; ks++) {
+      // wait for this step's loads (issued one step earlier), barrier (every
+      // wave's loads have landed; the other stage is no longer read), issue the
+      // next step's loads into the other stage, then all pairs of this step
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      barrier();
+      const int8_t* lb = lds + (ks & 1) * kApStageBytes;
+      v4i br[S], bi[S];
+#pragma unroll
+      for (int t = 0; t < S; t++) {
+        br[t] = *(const v4i*)(lb + (3 * kApS + 2 * t) * kApRegion + fb);
+        bi[t] = *(const v4i*)(lb + (3 * kApS + 2 * t + 1) * kApRegion + fb);
+      }
+      v4i a0, a2, a3;
+      load_a(lb, 0, a0, a2, a3);
+      const bool more = ks + 1 < KS;
+#pragma unroll
+      for (int s = 0; s < S; s++) {
+        // the next slice's fragments are requested before this slice's MFMAs,
+        // and with them a share of the next step's loads, so that the load
+        // instructions issue between MFMAs
+        v4i n0, n2, n3;
+        if (s + 1 < S) load_a(lb, s + 1, n0, n2, n3);
+        if (more) issue(ks + 1, (ks + 1) & 1, s * kQ / S, (s + 1) * kQ / S);
+#pragma unroll
+        for (int t = 0; s + t < S; t++) {
+          // slices s + 1, t + 1: diagonal d = s + t + 2
+          acc_re[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, br[t], acc_re[s + t], 0, 0, 0);
+          acc_im[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, bi[t], acc_im[s + t], 0, 0, 0);
+          acc_re[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, bi[t], acc_re[s + t], 0, 0, 0);
+          acc_im[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, br[t], acc_im[s + t], 0, 0, 0);
+        }
+        a0 = n0;
+        a2 = n2;
+        a3 = n3;
+      }
+    }
+    // fold: every term acc 2^{-8 d} is exact in FP64; smallest weights first,
+    // then the partial sum of the earlier segments
+    const bool first = seg0 == 0, last = seg1 == KS;
+#pragma unroll
+    for (int v = 0; v < 16; v++) {
+      double re = 0, im = 0;
+#pragma unroll
+      for (int di = S - 1; di >= 0; di--) {
+        const double sc = __builtin_ldexp(1.0, -8 * (di + 2));
+        re += (double)acc_re[di][v] * sc;
+        im += (double)acc_im[di][v] * sc;
+      }
+      if (!first) {
+        const double2 pv = sp[v * 64];
+        re = pv.x + re;
+        im = pv.y + im;
+      }
+      if (!last) {
+        sp[v * 64] = make_double2(re, im);
+      } else {
+        const int i = m0 + wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int j = n0 + wn + (lane & 31);
+        if (i < g.m && j < g.n) {
+          const int e = a.ea[i] + a.eb[j];
+          epi_element<EPI, double>(g, i, j, mk<double>(ldexp(re, e), ldexp(im, e)), part);
+        }
+      }
+    }
+  }
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<ANT>(g, part, red, bid);
+}
+
 // The large-tile kernel is used when it still gives every CU a tile, and for
 // every double-double product.
 static bool use_large_tiles(int m, int n, bool dd) {
   return dd || ceil_div(m, PBM) * ceil_div(n, PBN) >= kCUs;
 }
 
+// The all-pairs kernel takes the FP64 tier's products (S digits per operand,
+// pairs s + t <= S + 1, S <= kApS) with a 64 x 64 tile per CU.
+static bool use_allpairs(int m, int n, bool dd, int SA, int SB, int dmax, int k) {
+  // the kernel addresses the slices of an operand with 32-bit offsets
+  const long span = (long)SA * kParts * oz_plane_bytes(m > n ? m : n, oz_kp(k));
+  return !dd && SA == SB && SA >= 1 && SA <= kApS && dmax == SA + 1 && span < 2147483647L &&
+         ceil_div(m, ABM) * ceil_div(n, ABM) >= kCUs;
+}
+
+// Scratch for either large-tile kernel (the all-pairs one needs at most the same:
+// a 64 x 64 double2 tile per 64-tile, and only for K past one segment).
 size_t oz_gemm_scratch_bytes(int m, int n, bool dd) {
-  if (!use_large_tiles(m, n, dd)) return 0;
-  return (size_t)ceil_div(m, PBM) * ceil_div(n, PBN) * PBM * PBN * sizeof(double2) * (dd ? 3 : 1);
+  const size_t ap = (size_t)ceil_div(m, ABM) * ceil_div(n, ABM) * ABM * ABM * sizeof(double2);
+  if (!use_large_tiles(m, n, dd)) return dd || ceil_div(m, ABM) * ceil_div(n, ABM) < kCUs ? 0 : ap;
+  const size_t lt = (size_t)ceil_div(m, PBM) * ceil_div(n, PBN) * PBM * PBN * sizeof(double2) * (dd ? 3 : 1);
+  return lt > ap ? lt : ap;
 }
 
 // The small-tile kernel sums one product per accumulator over a whole diagonal
@@ -787,7 +1020,11 @@ bool oz_gemm_exact(int m, int n, int k, int SA, int SB, bool dd) {
   return pairs * (long)oz_kp(k) * 16384L < 2147483648L;
 }
 
-int oz_gemm_tiles(int m, int n, bool dd, bool herm) {
+int oz_gemm_tiles(int m, int n, int k, bool dd, bool herm, int SA, int SB, int dmax) {
+  if (use_allpairs(m, n, dd, SA, SB, dmax, k)) {
+    const int t = ceil_div(n, ABM);
+    return herm ? t * (t + 1) / 2 : ceil_div(m, ABM) * t;
+  }
   if (use_large_tiles(m, n, dd)) {
     const int t = ceil_div(n, PBN);
     return herm ? t * (t + 1) / 2 : ceil_div(m, PBM) * t;
@@ -813,16 +1050,54 @@ static hipError_t launch_large(bool dd, int nt, const OzArgs& a, hipStream_t st)
   return hipGetLastError();
 }
 
+template <int EPI, int S>
+static hipError_t launch_allpairs_s(int nt, const OzArgs& a, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void*)oz_gemm_allpairs_kernel<EPI, S>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kApLds);
+  if (e != hipSuccess) return e;
+  oz_gemm_allpairs_kernel<EPI, S><<<dim3(nt), dim3(ANT), kApLds, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int EPI>
+static hipError_t launch_allpairs(int nt, const OzArgs& a, hipStream_t st) {
+  switch (a.SA) {
+    case 1: return launch_allpairs_s<EPI, 1>(nt, a, st);
+    case 2: return launch_allpairs_s<EPI, 2>(nt, a, st);
+    case 3: return launch_allpairs_s<EPI, 3>(nt, a, st);
+    case 4: return launch_allpairs_s<EPI, 4>(nt, a, st);
+    case 5: return launch_allpairs_s<EPI, 5>(nt, a, st);
+    case 6: return launch_allpairs_s<EPI, 6>(nt, a, st);
+    case 7: return launch_allpairs_s<EPI, 7>(nt, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t* B, const int* eb,
                    int SB, int conjA, int dmax, GemmArgs g, void* scratch, hipStream_t st,
                    bool dd) {
   if (g.m == 0 || g.n == 0) return hipSuccess;
   if (g.herm && (epi != EPI_YDEF || g.herm != 1 || g.m != g.n)) return hipErrorInvalidValue;
+  if (use_allpairs(g.m, g.n, dd, SA, SB, dmax, g.k)) {
+    g.tiles_m = ceil_div(g.m, ABM);
+    g.tiles_n = ceil_div(g.n, ABM);
+    const int nt = oz_gemm_tiles(g.m, g.n, g.k, dd, g.herm != 0, SA, SB, dmax);
+    // the FP64 partial sums need the scratch only past one segment
+    if (!scratch && oz_kp(g.k) / 32 > kApSeg) return hipErrorInvalidValue;
+    OzArgs a{A, ea, B, eb, SA, SB, dmax, conjA, oz_kp(g.k), g, (double2*)scratch};
+    switch (epi) {
+      case EPI_STORE: return launch_allpairs<EPI_STORE>(nt, a, st);
+      case EPI_ADD: return launch_allpairs<EPI_ADD>(nt, a, st);
+      case EPI_SPLIT: return launch_allpairs<EPI_SPLIT>(nt, a, st);
+      case EPI_YDEF: return launch_allpairs<EPI_YDEF>(nt, a, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (use_large_tiles(g.m, g.n, dd)) {
     if (!scratch) return hipErrorInvalidValue;
     g.tiles_m = ceil_div(g.m, PBM);
     g.tiles_n = ceil_div(g.n, PBN);
-    const int nt = oz_gemm_tiles(g.m, g.n, dd, g.herm != 0);
+    const int nt = oz_gemm_tiles(g.m, g.n, g.k, dd, g.herm != 0, SA, SB, dmax);
     OzArgs a{A, ea, B, eb, SA, SB, dmax, conjA, oz_kp(g.k), g, (double2*)scratch};
     switch (epi) {
       case EPI_STORE: return launch_large<EPI_STORE>(dd, nt, a, st);

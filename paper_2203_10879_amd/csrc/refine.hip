@@ -264,7 +264,7 @@ int ns_init(const zc* Qh, zc* Qout, zc* QHout, int n, int comp, const Work& w, h
     g.herm = 1;
     CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, S, w.sQc, w.eQc, S, 1, S + 1, g, w.oz_scratch, st));
     TOC_HERM(tm);
-    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, false, true), w.scal + 2, st));
+    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, false, true, S, S, S + 1), w.scal + 2, st));
     double nrm[3];
     unsigned dst = 0;
     int rc = read_back(st, w, 3, nrm, &dst);
@@ -323,7 +323,7 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
     CK(oz_split_cols(w.P, nullptr, n, n, n, S, w.sD, w.eD, st));
     CK(oz_gemm(EPI_SPLIT, w.sQc, w.eQc, S, w.sD, w.eD, S, 1, S + 1, s, w.oz_scratch, st));
     TOC(tm, 0);
-    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n), w.scal + 1, st));
+    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, false, false, S, S, S + 1), w.scal + 1, st));
     return SR_OK;
   }
   TIC(tm, 0);
@@ -344,7 +344,7 @@ int ydef(const zc* Q, const zc* QH, int n, int comp, const Work& w, hipStream_t 
     TIC(tm, 0);
     CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, S, w.sQc, w.eQc, S, 1, S + 1, g, w.oz_scratch, st));
     TOC_HERM(tm);
-    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, false, true), w.scal + 2, st));
+    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, false, true, S, S, S + 1), w.scal + 2, st));
     return SR_OK;
   }
   TIC(tm, 0);
@@ -756,7 +756,7 @@ DDWork carve_dd(void* base, int n, const sr_opts* o) {
   w.eQr = (int*)take(n * sizeof(int));
   w.eD = (int*)take(n * sizeof(int));
   w.scratch = take(oz_gemm_scratch_bytes(n, n, true));
-  int np = oz_gemm_tiles(n, n, true);
+  int np = oz_gemm_tiles(n, n, n, true, false, w.S, w.S, w.S + 1);
   if (form_w_parts(n) > np) np = form_w_parts(n);
   if (np < 1024) np = 1024;
   w.partials = (double*)take((size_t)np * sizeof(double));
@@ -815,7 +815,7 @@ int dd_ydef(int n, const DDWork& w, hipStream_t st) {
   g.partials = w.partials;
   g.herm = 1;
   CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, w.S, w.sQc, w.eQc, w.S, 1, w.S + 1, g, w.scratch, st, true));
-  CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, true, true), w.scal + 2, st));
+  CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, true, true, w.S, w.S, w.S + 1), w.scal + 2, st));
   return SR_OK;
 }
 
@@ -932,7 +932,7 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
       CK(oz_gemm(EPI_SPLIT, w.sQc, w.eQc, S, w.sP, w.eP, S, 1, S + 1, g, w.scratch, st, true));
     }
     TOC(tm, 0);
-    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, true), w.scal + 1, st));
+    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, true, false, w.S, w.S, w.S + 1), w.scal + 1, st));
     double s2[2];
     if ((rc = read_back_dd(st, w, 2, s2, &dst)) != SR_OK) return rc;
     eps = sqrt(s2[1]) / sqrt(s2[0]);

@@ -114,9 +114,9 @@ def test_ozaki_add_epilogue_and_validation(sr):
     assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, slices_a=0, slices_b=2) == -1
 
 
-# Outputs with at least one 128 x 128 tile per CU (256 tiles) take the
-# large-tile kernel (two int32 accumulators per output, FP64 partial sums in
-# scratch between folds).
+# Outputs with at least one 128 x 128 tile per CU (256 tiles) and digit sets
+# other than the FP64 tier's take the large-tile kernel (two int32 accumulators
+# per output, FP64 partial sums in scratch between folds).
 
 @pytest.mark.parametrize("opa", [0, 1])
 def test_ozaki_large_tiles_exact_on_integers(sr, opa):
@@ -132,8 +132,8 @@ def test_ozaki_large_tiles_exact_on_integers(sr, opa):
 
 
 def test_ozaki_large_tiles_segmented_diagonal(sr):
-    # k = 8256 gives 129 K-steps; the diagonal s + t = 8 of 7 x 7 slices then
-    # has 7 * 129 > 512 steps and is folded in two segments
+    # k = 8256: 258 K-steps of 32 in the all-pairs kernel, folded in two
+    # segments of at most 256
     m = n = 2048
     k = 8256
     rng = np.random.default_rng(17)
@@ -145,18 +145,75 @@ def test_ozaki_large_tiles_segmented_diagonal(sr):
     assert np.array_equal(host(c)[rows], a[rows] @ b)
 
 
+# slices 7 (pairs up to s + t = 8) take the all-pairs kernel, 8 the large-tile one
+@pytest.mark.parametrize("slices", [7, 8])
 @pytest.mark.parametrize("opa", [0, 1])
-def test_ozaki_large_tiles_fp64_faithful(sr, opa):
+def test_ozaki_large_tiles_fp64_faithful(sr, opa, slices):
     m = n = 2048
     k = 192
     rng = np.random.default_rng(40 + opa)
     a = rand_c(rng, (k, m) if opa else (m, k))
     b = rand_c(rng, (k, n))
     c = empty(m, n)
-    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=7, slices_b=7, dmax=8) == 0
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=slices, slices_b=slices, dmax=slices + 1) == 0
     rows = np.random.default_rng(4).choice(m, 32, replace=False)
     asub = np.asfortranarray(a[:, rows] if opa else a[rows])
     chi, clo = oracle.gemm(asub, b, opa=opa).to_dd()
     err = np.abs((host(c)[rows] - chi) - clo)
     aa = np.abs(asub.conj().T if opa else asub)
     assert np.all(err <= gemm_bound(aa, np.abs(b), k, U64))
+
+
+# The FP64 tier's digit sets (S digits per operand, pairs up to s + t = S + 1) on
+# outputs with a 64 x 64 tile per CU take the all-pairs kernel: every slice of a
+# K-step staged at once, one int32 accumulator pair per diagonal.
+
+def _one_digit_ints(rng, shape):
+    # |x| <= 63: the scale leaves x 2^(8-e) an integer below 126, a single digit
+    return rng.integers(-63, 64, shape)
+
+
+@pytest.mark.parametrize("add", [False, True])
+@pytest.mark.parametrize("opa", [0, 1])
+@pytest.mark.parametrize("S", [1, 3, 7])
+def test_ozaki_allpairs_exact_on_integers(sr, S, opa, add):
+    # op(A) of 9-bit integers needs two digits (one for S = 1: 6-bit), B one, so
+    # the pairs (s, 1), s <= 2, that the triangle keeps give the exact product
+    m, n, k = 2085, 2048, 130  # ragged rows, a ragged K-tile
+    rng = np.random.default_rng(500 + 10 * S + 2 * opa + add)
+    shp = (k, m) if opa else (m, k)
+    if S == 1:
+        a = np.asfortranarray(_one_digit_ints(rng, shp) + 1j * _one_digit_ints(rng, shp))
+    else:
+        a = _gauss_int(rng, shp)
+    b = np.asfortranarray(_one_digit_ints(rng, (k, n)) + 1j * _one_digit_ints(rng, (k, n)))
+    c0 = _gauss_int(rng, (m, n)) if add else None
+    c = empty(m, n)
+    rc = sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=S, slices_b=S, dmax=S + 1,
+                           Cin=dev(c0) if add else None)
+    assert rc == 0
+    ref = (a.conj().T if opa else a) @ b
+    if add:
+        ref = ref + c0
+    assert np.array_equal(host(c), ref)
+
+
+@pytest.mark.parametrize("opa", [0, 1])
+def test_ozaki_allpairs_exact_with_digit_carries(sr, opa):
+    # op(A) with three digits and carries (see _carry_ints), B with one digit:
+    # S = 3 keeps the pairs (s, 1) the product needs
+    m, n, k = 1100, 1030, 66
+    rng = np.random.default_rng(77 + opa)
+    shp = (k, m) if opa else (m, k)
+    ar, ai = _carry_ints(rng, shp), _carry_ints(rng, shp)
+    big = 2**20 + 8160
+    if opa:
+        ar[0, :] = big
+    else:
+        ar[:, 0] = big
+    a = np.asfortranarray(ar + 1j * ai)
+    b = np.asfortranarray(_one_digit_ints(rng, (k, n)) + 1j * _one_digit_ints(rng, (k, n)))
+    c = empty(m, n)
+    assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=3, slices_b=3, dmax=4) == 0
+    ref = (a.conj().T if opa else a) @ b
+    assert np.array_equal(host(c), ref)

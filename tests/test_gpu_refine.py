@@ -236,7 +236,7 @@ def test_gemm_mode_validation(sr):
 
 
 def test_ozaki_mode_n2048_large_tiles(sr):
-    """n = 2048: every Ozaki product takes the large-tile kernel."""
+    """n = 2048: every Ozaki product takes the all-pairs kernel (64 x 64 tiles)."""
     g = synth.schur_test_matrix(2048, seed=6, gap=0.01)
     a = g["A"]
     qh = synth.lp_schur_start(a)
