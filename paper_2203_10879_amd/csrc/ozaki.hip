@@ -778,12 +778,17 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(2))) void o
 // registers, with one int32 accumulator pair (re, im) per diagonal s + t: the
 // operand bytes per tile drop by the ratio of pairs to slices.
 //
-// A 256-thread block computes a 64 x 64 complex tile, each wave one 32 x 32
-// block (re and im: 2 x 16 int32 per diagonal and lane, up to 7 diagonals), one
-// block per CU (LDS: two stages of 70 KiB). The int32 sums of a diagonal stay
-// exact for kApSeg K-steps (at most 7 pairs x 2 products x 32 terms x 2^14 per
-// step, 7 * 2^28 < 2^31 over a segment); every segment is folded into FP64
-// partial sums in registers, the diagonals from the smallest weight up.
+// A 512-thread block computes a 64 x 64 complex tile. Wave w owns quadrant
+// w % 4 (32 x 32) and one part of the result: the real part for w < 4, the
+// imaginary part for w >= 4, so that a wave keeps one int32 accumulator per
+// diagonal and lane (16 x up to 7) and two waves share every SIMD: while one
+// waits (a barrier, an LDS read, an MFMA result), the other issues. One block per
+// CU (LDS: two stages of 70 KiB). The int32 sums of a diagonal stay exact for
+// kApSeg K-steps (at most 7 pairs x 2 products x 32 terms x 2^14 per step,
+// 7 * 2^28 < 2^31 over a segment); each segment is folded into FP64, the
+// diagonals from the smallest weight up. After the last segment the imaginary
+// parts pass through LDS to the waves of the real parts, which apply the
+// epilogue.
 //
 // LDS layout of a stage: one 2 KiB region per part (A: 3 parts per slice, B: 2),
 // 64 rows x 32 bytes (the step's half of each 64-byte K-block row). Within a row
@@ -793,21 +798,24 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(2))) void o
 // (global_load_lds_dwordx4: lane l writes 16 bytes at base + 16 l, i.e. row
 // l / 2, position l % 2 of a 32-row half region).
 constexpr int kApS = 7;
-constexpr int ABM = 64, ANT = 256, kApSeg = 256;
+constexpr int ABM = 64, ANT = 512, kApSeg = 256;
 constexpr int kApRegion = ABM * 32;                       // 2 KiB
 constexpr int kApStageBytes = kApS * 5 * kApRegion;       // 70 KiB
 constexpr int kApLds = 2 * kApStageBytes;
 static_assert(kApS * 2 * 32 * 16384L * kApSeg < 2147483648L, "segment bound");
+static_assert(4 * 16 * 64 * sizeof(double) <= (size_t)kApLds, "imaginary parts fit in the stages");
 __host__ __device__ inline int ap_lsw(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
 
 template <int EPI, int S>
-__global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(1, 1))) void oz_gemm_allpairs_kernel(
+__global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) void oz_gemm_allpairs_kernel(
     OzArgs a) {
   extern __shared__ __align__(16) int8_t lds[];  // kApLds
   __shared__ double red[ANT / 64];
   const GemmArgs& g = a.g;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int quad = wave & 3;
+  const bool re_part = wave < 4;
+  const int wm = (quad & 1) * 32, wn = (quad >> 1) * 32;
 
   const int ntiles = gridDim.x, bid = blockIdx.x;
   int logical = bid;
@@ -838,7 +846,10 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const int KB = a.Kp / OBK, KS = a.Kp / 32;
   const long pA = oz_plane_bytes(g.m, a.Kp), pB = oz_plane_bytes(g.n, a.Kp);
   const long sA = kParts * pA, sB = kParts * pB;
-  const int pa2 = a.conjA ? 1 : 2, pa3 = a.conjA ? 2 : 1;
+  // real part: Ar Br + (A part pa2) Bi; imaginary part: Ar Bi + (A part pa3) Br
+  // (pa2 = -Ai, pa3 = Ai; conjugated op(A): pa2 = Ai, pa3 = -Ai)
+  const int pax = re_part ? (a.conjA ? 1 : 2) : (a.conjA ? 2 : 1);
+  const int pbf = re_part ? 0 : 1, pbs = re_part ? 1 : 0;
 
   // this lane's source offset within a plane for each half region (rows 0-31,
   // 32-63 of the tile) at K-block 0, K-half 0; rows past the padded matrix read
@@ -857,22 +868,22 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
   // The step's 1 KiB load instructions: 6 S for A (slice q / 6, part (q % 6) / 2,
   // half q % 2), 4 S for B (slice q / 4, part (q / 2) % 2, half q % 2). Wave w
-  // issues A instructions w, w + 4, ... (past 6 S it repeats instruction q - 4,
-  // which rewrites the same bytes) and B instructions w, w + 4, .... Source
+  // issues A instructions w, w + 8, ... and B instructions w, w + 8, ...; past
+  // the last one a wave repeats it (the same bytes to the same place). Source
   // offsets (plane and lane part, K-block 0, K-half 0) and LDS offsets are fixed
   // for the whole tile.
-  constexpr int kQA = (6 * S + 3) / 4, kQ = kQA + S;
+  constexpr int NW = ANT / 64;
+  constexpr int kQA = (6 * S + NW - 1) / NW, kQ = kQA + (4 * S + NW - 1) / NW;
   int goff[kQ], loff[kQ];
 #pragma unroll
   for (int k = 0; k < kQ; k++) {
     if (k < kQA) {
-      int q = uwave + 4 * k;
-      if (q >= 6 * S) q -= 4;
+      const int q = min(uwave + NW * k, 6 * S - 1);
       const int sl = q / 6, rem = q - 6 * sl, part = rem >> 1, h = rem & 1;
       goff[k] = (int)(sl * sA + part * pA) + offA[h];
       loff[k] = (3 * sl + part) * kApRegion + h * 1024;
     } else {
-      const int q = uwave + 4 * (k - kQA), t = q >> 2, part = (q >> 1) & 1, h = q & 1;
+      const int q = min(uwave + NW * (k - kQA), 4 * S - 1), t = q >> 2, part = (q >> 1) & 1, h = q & 1;
       goff[k] = (int)(t * sB + part * pB) + offB[h];
       loff[k] = (3 * kApS + 2 * t + part) * kApRegion + h * 1024;
     }
@@ -897,62 +908,57 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const int fa = ra * 32 + ((((lane >> 5) ^ ap_lsw(ra))) << 4);
   const int fb = rb * 32 + ((((lane >> 5) ^ ap_lsw(rb))) << 4);
 
-  v16i acc_re[S], acc_im[S];
+  v16i acc[S];
   auto barrier = [&]() {
     __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
   };
-  auto load_a = [&](const int8_t* lb, int s, v4i& x0, v4i& x2, v4i& x3) {
+  auto load_a = [&](const int8_t* lb, int s, v4i& x0, v4i& xx) {
     x0 = *(const v4i*)(lb + (3 * s) * kApRegion + fa);
-    x2 = *(const v4i*)(lb + (3 * s + pa2) * kApRegion + fa);
-    x3 = *(const v4i*)(lb + (3 * s + pa3) * kApRegion + fa);
+    xx = *(const v4i*)(lb + (3 * s + pax) * kApRegion + fa);
   };
   // FP64 partial sums between segments (K beyond kApSeg steps) live in the
-  // per-tile scratch, in the waves' register order (coalesced)
-  double2* sp = a.scratch ? a.scratch + ((long)bid * 4 + wave) * 1024 + lane : nullptr;
-  double part = 0;
+  // per-tile scratch (64 x 64 double2 per tile: one double per wave, v and lane)
+  double* sp = a.scratch ? (double*)a.scratch + ((long)bid * NW + wave) * 1024 + lane : nullptr;
+  double val[16];
 
   issue(0, 0, 0, kQ);
   for (int seg0 = 0; seg0 < KS; seg0 += kApSeg) {
     const int seg1 = min(KS, seg0 + kApSeg);
 #pragma unroll
-    for (int di = 0; di < S; di++) acc_re[di] = acc_im[di] = v16i{};
+    for (int di = 0; di < S; di++) acc[di] = v16i{};
     for (int ks = seg0; ks < seg1; ks++) {
       // wait for this step's loads (issued one step earlier), barrier (every
-      // wave's loads have landed; the other stage is no longer read), issue the
-      // next step's loads into the other stage, then all pairs of this step
+      // wave's loads have landed; the other stage is no longer read), then all
+      // pairs of this step, with the next step's loads issued between them
       __builtin_amdgcn_s_waitcnt(kWaitVm0);
       barrier();
       const int8_t* lb = lds + (ks & 1) * kApStageBytes;
-      v4i br[S], bi[S];
+      v4i bf[S], bs[S];
 #pragma unroll
       for (int t = 0; t < S; t++) {
-        br[t] = *(const v4i*)(lb + (3 * kApS + 2 * t) * kApRegion + fb);
-        bi[t] = *(const v4i*)(lb + (3 * kApS + 2 * t + 1) * kApRegion + fb);
+        bf[t] = *(const v4i*)(lb + (3 * kApS + 2 * t + pbf) * kApRegion + fb);
+        bs[t] = *(const v4i*)(lb + (3 * kApS + 2 * t + pbs) * kApRegion + fb);
       }
-      v4i a0, a2, a3;
-      load_a(lb, 0, a0, a2, a3);
+      v4i a0, ax;
+      load_a(lb, 0, a0, ax);
       const bool more = ks + 1 < KS;
 #pragma unroll
       for (int s = 0; s < S; s++) {
         // the next slice's fragments are requested before this slice's MFMAs,
-        // and with them a share of the next step's loads, so that the load
-        // instructions issue between MFMAs
-        v4i n0, n2, n3;
-        if (s + 1 < S) load_a(lb, s + 1, n0, n2, n3);
+        // and with them a share of the next step's loads
+        v4i n0, nx;
+        if (s + 1 < S) load_a(lb, s + 1, n0, nx);
         if (more) issue(ks + 1, (ks + 1) & 1, s * kQ / S, (s + 1) * kQ / S);
 #pragma unroll
         for (int t = 0; s + t < S; t++) {
           // slices s + 1, t + 1: diagonal d = s + t + 2
-          acc_re[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, br[t], acc_re[s + t], 0, 0, 0);
-          acc_im[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, bi[t], acc_im[s + t], 0, 0, 0);
-          acc_re[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, bi[t], acc_re[s + t], 0, 0, 0);
-          acc_im[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a3, br[t], acc_im[s + t], 0, 0, 0);
+          acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, bf[t], acc[s + t], 0, 0, 0);
+          acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ax, bs[t], acc[s + t], 0, 0, 0);
         }
         a0 = n0;
-        a2 = n2;
-        a3 = n3;
+        ax = nx;
       }
     }
     // fold: every term acc 2^{-8 d} is exact in FP64; smallest weights first,
@@ -960,27 +966,32 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const bool first = seg0 == 0, last = seg1 == KS;
 #pragma unroll
     for (int v = 0; v < 16; v++) {
-      double re = 0, im = 0;
+      double x = 0;
 #pragma unroll
-      for (int di = S - 1; di >= 0; di--) {
-        const double sc = __builtin_ldexp(1.0, -8 * (di + 2));
-        re += (double)acc_re[di][v] * sc;
-        im += (double)acc_im[di][v] * sc;
-      }
-      if (!first) {
-        const double2 pv = sp[v * 64];
-        re = pv.x + re;
-        im = pv.y + im;
-      }
-      if (!last) {
-        sp[v * 64] = make_double2(re, im);
-      } else {
-        const int i = m0 + wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int j = n0 + wn + (lane & 31);
-        if (i < g.m && j < g.n) {
-          const int e = a.ea[i] + a.eb[j];
-          epi_element<EPI, double>(g, i, j, mk<double>(ldexp(re, e), ldexp(im, e)), part);
-        }
+      for (int di = S - 1; di >= 0; di--) x += (double)acc[di][v] * __builtin_ldexp(1.0, -8 * (di + 2));
+      if (!first) x = sp[v * 64] + x;
+      if (!last) sp[v * 64] = x;
+      val[v] = x;
+    }
+  }
+  // imaginary parts to the waves of the real parts (the stages are free once
+  // every wave is past its last fragment read)
+  double* xch = (double*)lds + (quad * 16) * 64 + lane;
+  __syncthreads();
+  if (!re_part) {
+#pragma unroll
+    for (int v = 0; v < 16; v++) xch[v * 64] = val[v];
+  }
+  __syncthreads();
+  double part = 0;
+  if (re_part) {
+#pragma unroll
+    for (int v = 0; v < 16; v++) {
+      const int i = m0 + wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const int j = n0 + wn + (lane & 31);
+      if (i < g.m && j < g.n) {
+        const int e = a.ea[i] + a.eb[j];
+        epi_element<EPI, double>(g, i, j, mk<double>(ldexp(val[v], e), ldexp(xch[v * 64], e)), part);
       }
     }
   }
