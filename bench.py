@@ -95,6 +95,27 @@ def base_record(args, value, unit, ms_per_step, dtype, config):
             "config": config}
 
 
+def sweep_traffic():
+    """Bytes per solve beyond L2 of the triangular-equation sweep from the committed
+    rocprofv3 PMC summary, or None when the solve sources have changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "trisolve_n1024_hbm_traffic.txt")
+    csrc = os.path.join(ROOT, "paper_2203_10879_amd", "csrc")
+    try:
+        text = open(path).read()
+        h = hashlib.sha256()
+        for f in ("trisolve.hip", "trisolve_tiles.inc", "kernels.hpp", "common.hpp"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+        vals = dict(line.split(":", 1) for line in text.splitlines()
+                    if line.startswith(("sweep_hbm_bytes_per_solve:", "trisolve_source_sha256_16:")))
+        if vals["trisolve_source_sha256_16"].split()[0] != h.hexdigest()[:16]:
+            return None
+        return float(vals["sweep_hbm_bytes_per_solve"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_default(args) -> int:
     import torch
 
@@ -156,6 +177,22 @@ def run_default(args) -> int:
                        "hermitian_products": {"launches_per_step": herm / args.steps,
                                               "avg_launch_ms": ms_herm / max(1, herm),
                                               "flop_per_launch": 4.0 * n * n * (n + 1)}}
+    # The triangular-equation sweep: one solve per update, timed with HIP events around
+    # its launches; bytes beyond L2 per solve from the committed counter summary.
+    solves = sum(i["updates"] for i in infos)
+    ms_solve = sum(i["ms_solve"] for i in infos) / max(1, solves)
+    alg_bytes = 12.0 * n * n
+    sweep_bytes = sweep_traffic() if n == N else None
+    out["sweep"] = {"kernel": "triangular-equation sweep (trisolve_level_kernel<float>, one launch per tile "
+                              "diagonal)",
+                    "bound": f"latency: {(n + 15) // 16 if n <= 2048 else (n + 31) // 32} dependent launches "
+                             "(tile diagonals)",
+                    "ms_per_solve": ms_solve, "solves_per_step": solves / args.steps,
+                    "algorithmic_bytes_per_solve": alg_bytes,
+                    "algorithmic_GBps": alg_bytes / (ms_solve * 1e-3) / 1e9,
+                    "beyond_l2_bytes_per_solve": sweep_bytes,
+                    "beyond_l2_GBps": sweep_bytes / (ms_solve * 1e-3) / 1e9 if sweep_bytes else None,
+                    "hbm_peak_GBps": 8000.0}
     out.update({"passes": last["iters"], "hp_gemms": last["hp_gemms"], "resid_hist": last["resid_hist"],
                 "ms_solve_per_step": sum(i["ms_solve"] for i in infos) / args.steps,
                 "ms_hp_gemm_per_step": ms_gemm / args.steps, "all_converged": ok})
