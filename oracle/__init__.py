@@ -61,6 +61,7 @@ def lib():
         L.orc_eval_rows.argtypes = [i32, vp, vp, i32, vp, vp]
         L.orc_schur_qr.argtypes = [i32, i32, vp, vp, vp]
         L.orc_schur_qr.restype = i32
+        L.orc_reorder.argtypes = [i32, vp, vp, f64, vp, vp]
         _LIB = L
     return _LIB
 
@@ -154,6 +155,16 @@ def refine(a, qh, lp: str = "float", maxit: int = 6, tol: float = 1e-15,
                           qo.ptr, to.ptr, hist.ctypes.data, ctypes.byref(it))
     return {"Q": qo, "T": to, "hist": hist[: it.value].copy(), "iters": it.value,
             "status": STATUS.get(rc, rc)}
+
+
+def reorder(a, qh, theta: float):
+    """Reordered start (see oracle.h): returns (Q, perm) with Q a QMat."""
+    a, qh = _q(a), _q(qh)
+    n = a.n
+    qo = QMat(n, n)
+    perm = np.zeros(n, dtype=np.int32)
+    lib().orc_reorder(n, a.ptr, qh.ptr, float(theta), qo.ptr, perm.ctypes.data)
+    return qo, perm
 
 
 def evaluate(a, q, t=None) -> dict:

@@ -456,3 +456,62 @@ int orc_schur_qr(int lp, int n, const orc_qc* A, orc_qc* Z, orc_qc* S)
   free(z);
   return rc;
 }
+
+/* ------------------------------------------------------- reordering of the start */
+void orc_reorder(int n, const orc_qc* A, const orc_qc* Qh, double theta, orc_qc* Qout, int* perm)
+{
+  long nn = (long)n * n;
+  orc_qc* P = NEWQ(nn);
+  orc_qc* T = NEWQ(nn);
+  orc_gemm(0, n, n, n, A, Qh, P); /* P = A Qh */
+  orc_gemm(1, n, n, n, Qh, P, T); /* T = Qh^H A Qh, then its upper triangle */
+  for (int j = 0; j < n; j++)
+    for (int i = j + 1; i < n; i++) T[i + (long)j * n] = qc_mk(0, 0);
+  memcpy(Qout, Qh, sizeof(orc_qc) * nn);
+  double* key = (double*)xmalloc(sizeof(double) * n);
+  const double c = cos(theta), s = sin(theta);
+  for (int i = 0; i < n; i++) {
+    key[i] = (double)T[i + (long)i * n].re * c + (double)T[i + (long)i * n].im * s;
+    perm[i] = i;
+  }
+  for (int p = 0; p < n; p++) {
+    for (int i = p & 1; i + 1 < n; i += 2) {
+      if (!(key[i] > key[i + 1])) continue;
+      const orc_qc a = T[i + (long)i * n], b = T[i + (long)(i + 1) * n], d = T[(i + 1) + (long)(i + 1) * n];
+      const quad xr = d.re - a.re, xi = d.im - a.im;
+      const quad r = sqrtq(b.re * b.re + b.im * b.im + xr * xr + xi * xi);
+      const orc_qc g1 = qc_mk(b.re / r, b.im / r), g2 = qc_mk(xr / r, xi / r);
+      /* T <- G^H T G on rows / columns i, i+1 with G = [[g1, -conj(g2)], [g2, conj(g1)]];
+         Q <- Q G */
+      for (int j = 0; j < n; j++) {
+        const orc_qc u = T[i + (long)j * n], v = T[(i + 1) + (long)j * n];
+        /* row i: conj(g1) u + conj(g2) v; row i+1: -g2 u + g1 v */
+        T[i + (long)j * n] = qc_mk(g1.re * u.re + g1.im * u.im + g2.re * v.re + g2.im * v.im,
+                                   g1.re * u.im - g1.im * u.re + g2.re * v.im - g2.im * v.re);
+        T[(i + 1) + (long)j * n] = qc_mk(-(g2.re * u.re - g2.im * u.im) + g1.re * v.re - g1.im * v.im,
+                                         -(g2.re * u.im + g2.im * u.re) + g1.re * v.im + g1.im * v.re);
+      }
+      for (int m = 0; m < 2; m++) {
+        orc_qc* X = m ? Qout : T;
+        for (int r2 = 0; r2 < n; r2++) {
+          const orc_qc u = X[r2 + (long)i * n], v = X[r2 + (long)(i + 1) * n];
+          /* column i: g1 u + g2 v; column i+1: -conj(g2) u + conj(g1) v */
+          X[r2 + (long)i * n] = qc_mk(g1.re * u.re - g1.im * u.im + g2.re * v.re - g2.im * v.im,
+                                      g1.re * u.im + g1.im * u.re + g2.re * v.im + g2.im * v.re);
+          X[r2 + (long)(i + 1) * n] = qc_mk(-(g2.re * u.re + g2.im * u.im) + g1.re * v.re + g1.im * v.im,
+                                            -(g2.re * u.im - g2.im * u.re) + g1.re * v.im - g1.im * v.re);
+        }
+      }
+      T[(i + 1) + (long)i * n] = qc_mk(0, 0);
+      const double tk = key[i];
+      key[i] = key[i + 1];
+      key[i + 1] = tk;
+      const int tp = perm[i];
+      perm[i] = perm[i + 1];
+      perm[i + 1] = tp;
+    }
+  }
+  free(key);
+  free(T);
+  free(P);
+}

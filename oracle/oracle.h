@@ -106,6 +106,21 @@ void orc_eval_rows(int n, const orc_qc* A, const orc_qc* Q, int nr, const int* r
  * matrices with known spectrum. */
 int orc_schur_qr(int lp, int n, const orc_qc* A, orc_qc* Z, orc_qc* S);
 
+/* Reordering of the start (Section 4, the paragraph on Algorithm 4's first step):
+ * the Schur form T = triu(Qh^H A Qh) is reordered by unitary swaps of adjacent
+ * diagonal entries so that the eigenvalues appear in increasing order of their
+ * projection Re(lambda e^{-i theta}) onto the line with direction e^{i theta}
+ * (clustered eigenvalues become neighbours). Swaps follow odd-even transposition
+ * order: phase p = 0 .. n-1 swaps every pair (i, i+1), i = p mod 2, whose keys are
+ * out of order (keys are computed once, in double, and travel with their
+ * entries). A swap of [[a, b], [0, d]] uses the unitary G whose first column is
+ * the eigenvector (b, d - a) / r of d. Returns Qout = Qh G_1 G_2 ... and perm[k] =
+ * the original diagonal position of the entry now at k. Pinned by the property
+ * checks that fix the result independently of the steps: Qout unitary,
+ * Qout^H A Qout upper triangular to the start's residual, its diagonal in key
+ * order; and the 2 x 2 closed form. */
+void orc_reorder(int n, const orc_qc* A, const orc_qc* Qh, double theta, orc_qc* Qout, int* perm);
+
 #ifdef __cplusplus
 }
 #endif
