@@ -214,6 +214,22 @@ int sr_residual(const void* A, const void* Q, int n, void* T, void* T_lp, void* 
 int sr_trisolve(const void* T_lp, const void* E_lp, void* L_lp, int n, float trunc,
                 void* ws, void* stream);
 
+/* Reordering of the start (Section 4, the paragraph on the first step of
+ * Algorithm 4: clustered eigenvalues are moved next to each other, in the order of
+ * their projections onto a random line). A: complex128 n x n (read); Q: complex128
+ * n x n start, in/out. With T = triu(Q^H A Q) (FP64), unitary swaps of adjacent
+ * diagonal entries put the eigenvalues in increasing order of
+ * Re(lambda e^{-i theta}); Q is replaced by Q G_1 G_2 ... (the swaps in
+ * odd-even transposition order, n phases). theta: the line's direction, chosen by
+ * the caller (e.g. at random). perm (device int[n], may be NULL): the original
+ * diagonal position of each entry of the new order. ws: device workspace of at
+ * least sr_reorder_ws_bytes(n) bytes, caller-owned. Returns SR_EINVAL for null
+ * pointers, n < 1, a non-finite theta or a short workspace; otherwise SR_OK without
+ * synchronising. */
+size_t sr_reorder_ws_bytes(int n);
+int sr_reorder_start(const void* A, void* Q, int n, double theta, int* perm, void* ws, size_t ws_bytes,
+                     void* stream);
+
 /* The same equation in FP64 (the solve of the double-double tier): T, E, L are
  * complex128 with the roles above; no truncation. Same outcomes. */
 int sr_trisolve64(const void* T, const void* E, void* L, int n, void* ws, void* stream);

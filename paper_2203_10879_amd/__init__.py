@@ -75,6 +75,8 @@ _SIGS = {
     "sr_residual": (_i, [_vp, _vp, _i, _vp, _vp, _vp, ctypes.POINTER(_d), _i, _vp, _vp]),
     "sr_trisolve": (_i, [_vp, _vp, _vp, _i, _f, _vp, _vp]),
     "sr_trisolve64": (_i, [_vp, _vp, _vp, _i, _vp, _vp]),
+    "sr_reorder_ws_bytes": (_sz, [_i]),
+    "sr_reorder_start": (_i, [_vp, _vp, _i, ctypes.c_double, _vp, _vp, _sz, _vp]),
     "sr_update": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.POINTER(_d), _vp, _vp]),
     "sr_ns_init": (_i, [_vp, _vp, _i, _i, _vp, _vp]),
     "sr_ozaki_ws_bytes": (_sz, [_i, _i, _i, _i, _i]),
@@ -334,6 +336,23 @@ def sr_trisolve64(T, E, L, ws, stream=None) -> int:
     n = T.shape[0]
     return lib().sr_trisolve64(_mat(T, "c128", n, n), _mat(E, "c128", n, n), _mat(L, "c128", n, n), n,
                                ctypes.c_void_p(ws.data_ptr()), _stream(stream))
+
+
+def reorder_start(A, Q, theta: float, perm=None, ws=None, stream=None) -> int:
+    """Reorder the start Q in place (see sr_reorder_start); perm: optional int32 device
+    tensor of length n for the original position of each new diagonal entry."""
+    import torch
+
+    n = A.shape[0]
+    nb = lib().sr_reorder_ws_bytes(n)
+    if ws is None:
+        ws = torch.empty(nb, dtype=torch.uint8, device=A.device)
+    if perm is not None and (perm.dtype != torch.int32 or perm.numel() != n or not perm.is_cuda):
+        raise ValueError("perm must be an int32 CUDA tensor of length n")
+    return lib().sr_reorder_start(_mat(A, "c128", n, n), _mat(Q, "c128", n, n), n, float(theta),
+                                  ctypes.c_void_p(perm.data_ptr()) if perm is not None else None,
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                  _stream(stream))
 
 
 def sr_update(Q, L_lp, Q_out, ws, gate=True, compensated=True, stream=None):

@@ -113,6 +113,12 @@ hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* w
                     unsigned* status, hipStream_t st);
 hipError_t trisolve64(const zc* T, const zc* E, zc* L, int n, void* ws, unsigned* status,
                       hipStream_t st);
+// Reordering of the start: T (complex128 n x n, Q^H A Q on entry) is made upper
+// triangular and reordered by adjacent swaps in the order of Re(lambda e^{-i theta});
+// Q is updated in place; perm_out (device, may be NULL) receives the original
+// position of each new diagonal entry. scratch: reorder_scratch_bytes(n) bytes.
+size_t reorder_scratch_bytes(int n);
+hipError_t reorder_swaps(zc* T, zc* Q, int n, double theta, void* scratch, int* perm_out, hipStream_t st);
 // Batched FP32 solves over a device table of `count` matrix records, filled on the
 // host with trimatrix_fill (each record trimatrix_bytes() bytes).
 hipError_t trisolve_batched(const void* mats, int count, float trunc, hipStream_t st);

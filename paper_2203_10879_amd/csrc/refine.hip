@@ -1181,6 +1181,26 @@ int sr_trisolve(const void* T_lp, const void* E_lp, void* L_lp, int n, float tru
   return (d & DEV_BREAKDOWN) ? SR_BREAKDOWN : SR_OK;
 }
 
+size_t sr_reorder_ws_bytes(int n) {
+  if (n < 1) return 0;
+  return 2 * align256((size_t)n * n * sizeof(zc)) + align256(reorder_scratch_bytes(n));
+}
+
+int sr_reorder_start(const void* A, void* Q, int n, double theta, int* perm, void* ws, size_t ws_bytes,
+                     void* stream) {
+  if (!A || !Q || !ws || n < 1 || !isfinite(theta) || ws_bytes < sr_reorder_ws_bytes(n)) return SR_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t z = align256((size_t)n * n * sizeof(zc));
+  zc* P = (zc*)ws;
+  zc* T = (zc*)((char*)ws + z);
+  void* scratch = (char*)ws + 2 * z;
+  // T = Q^H (A Q) in FP64
+  CK(zgemm(0, EPI_STORE, 0, gargs(n, n, n, A, n, Q, n, P, n), st));
+  CK(zgemm(1, EPI_STORE, 0, gargs(n, n, n, Q, n, P, n, T, n), st));
+  CK(reorder_swaps(T, (zc*)Q, n, theta, scratch, perm, st));
+  return SR_OK;
+}
+
 int sr_trisolve64(const void* T, const void* E, void* L, int n, void* ws, void* stream) {
   if (!T || !E || !L || !ws || n < 1) return SR_EINVAL;
   hipStream_t st = (hipStream_t)stream;
