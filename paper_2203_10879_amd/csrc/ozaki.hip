@@ -31,6 +31,8 @@
 // stages one K-tile (64) of one slice of op(A) (both parts) and one slice of B in
 // LDS, double-buffered; LDS rows are padded to 80 bytes, which makes the 16-byte
 // fragment reads of 16 consecutive rows conflict-free.
+#include <type_traits>
+
 #include "epilogue.hpp"
 
 namespace sr {
@@ -998,10 +1000,266 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<ANT>(g, part, red, bid);
 }
 
+// --------------------------------------------- windowed product (double-double)
+//
+// The double-double tier's products: S digits per operand (14 by default) and pairs
+// up to s + t = S + 1 (105 pairs), too many diagonals for one set of accumulators.
+// The slices are taken in windows of kWin = 4 per operand: window (wa, wb) holds
+// A slices 4 wa + 1 .. 4 wa + 4 and B slices 4 wb + 1 .. 4 wb + 4, whose pairs lie on
+// the diagonals d0 .. d0 + 6, d0 = 4 (wa + wb) + 2; those up to dmax are formed
+// (local s + t <= DL = min(6, dmax - d0)). With dmax = S + 1 a window at the end of
+// the slice range reaches only the slices that exist (DL + 1 <= slices left). Each
+// window is one K-sweep in the manner of the all-pairs kernel (64 x 64 tile, 8 waves,
+// one part per wave, two LDS stages of 40 KiB, the staged slices limited to
+// min(4, DL + 1) per operand). After each segment the window's diagonal sums are
+// added, smallest weight first, to a three-term FP64 expansion per output with two
+// exact TwoSum steps each (the partial sums can exceed the final value by the ratio
+// of the row and column scales to it, which two terms would turn into error); the
+// expansion lives in the per-tile scratch between windows and becomes double-double
+// after the last one.
+constexpr int kWin = 4;
+constexpr int kWinStageBytes = kWin * 5 * kApRegion;  // 40 KiB
+constexpr int kWinLds = 2 * kWinStageBytes;
+static_assert(4 * 16 * 64 * 2 * sizeof(double) <= (size_t)kWinLds, "hi and lo of the imaginary parts fit");
+
+template <int EPI>
+__global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) void oz_gemm_windows_kernel(
+    OzArgs a) {
+  extern __shared__ __align__(16) int8_t lds[];  // kWinLds
+  __shared__ double red[ANT / 64];
+  const GemmArgs& g = a.g;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int quad = wave & 3;
+  const bool re_part = wave < 4;
+  const int wm = (quad & 1) * 32, wn = (quad >> 1) * 32;
+
+  const int ntiles = gridDim.x, bid = blockIdx.x;
+  int logical = bid;
+  {
+    const int per = ntiles / kXCDs;
+    if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
+  }
+  int tm, tn;
+  if (EPI == EPI_YDEF && g.herm) {
+    tn = (int)((sqrtf(8.f * logical + 1.f) - 1.f) * 0.5f);
+    while (tn * (tn + 1) / 2 > logical) tn--;
+    while ((tn + 1) * (tn + 2) / 2 <= logical) tn++;
+    tm = logical - tn * (tn + 1) / 2;
+  } else {
+    constexpr int kGroup = 4;
+    const int group = logical / (kGroup * g.tiles_n);
+    const int first_m = group * kGroup;
+    const int gsize = min(g.tiles_m - first_m, kGroup);
+    const int within = logical - group * kGroup * g.tiles_n;
+    tm = first_m + within % gsize;
+    tn = within / gsize;
+  }
+  const int m0 = tm * ABM, n0 = tn * ABM;
+
+  const int KB = a.Kp / OBK, KS = a.Kp / 32;
+  const long pA = oz_plane_bytes(g.m, a.Kp), pB = oz_plane_bytes(g.n, a.Kp);
+  const long sA = kParts * pA, sB = kParts * pB;
+  const int pax = re_part ? (a.conjA ? 1 : 2) : (a.conjA ? 2 : 1);
+  const int pbf = re_part ? 0 : 1, pbs = re_part ? 1 : 0;
+
+  const int uwave = __builtin_amdgcn_readfirstlane(wave);
+  const int RBA = oz_rows_pad(g.m) / 16, RBB = oz_rows_pad(g.n) / 16;
+  int offA[2], offB[2];
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    const int r = 32 * h + (lane >> 1);
+    const int c = (lane & 1) ^ ap_lsw(r);
+    const int rba = min((m0 + r) >> 4, RBA - 1), rbb = min((n0 + r) >> 4, RBB - 1);
+    const int rowa = rba * 16 + (r & 15), rowb = rbb * 16 + (r & 15);
+    offA[h] = rba * KB * 1024 + (r & 15) * 64 + ((c ^ chunk_swz(rowa)) << 4);
+    offB[h] = rbb * KB * 1024 + (r & 15) * 64 + ((c ^ chunk_swz(rowb)) << 4);
+  }
+  const int ra = wm + (lane & 31), rb = wn + (lane & 31);
+  const int fa = ra * 32 + ((((lane >> 5) ^ ap_lsw(ra))) << 4);
+  const int fb = rb * 32 + ((((lane >> 5) ^ ap_lsw(rb))) << 4);
+  auto barrier = [&]() {
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+
+  // the three-term expansions of this wave's 16 outputs per lane, between windows
+  constexpr int NW = ANT / 64;
+  double* sp = (double*)a.scratch + ((long)bid * NW + wave) * 3072 + lane;
+  int nwin = 0;  // windows with at least one pair
+  for (int wa = 0; wa * kWin < a.SA; wa++)
+    for (int wb = 0; wb * kWin < a.SB; wb++)
+      if (kWin * (wa + wb) + 2 <= a.dmax) nwin++;
+  int widx = 0;
+  v16i acc[7];
+
+  // one window: its K-sweep in segments, each folded into the expansions
+  auto window = [&](auto dlc, int wa, int wb) {
+    constexpr int DL = decltype(dlc)::value;
+    constexpr int NS = DL < kWin - 1 ? DL + 1 : kWin;  // slices staged per operand
+    constexpr int nIA = 6 * NS, nI = nIA + 4 * NS, kQ = (nI + NW - 1) / NW;
+    const int d0 = kWin * (wa + wb) + 2;
+    const int8_t* Aw = a.A + (long)(kWin * wa) * sA;
+    const int8_t* Bw = a.B + (long)(kWin * wb) * sB;
+    int goff[kQ], loff[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; k++) {
+      const int q = min(uwave + NW * k, nI - 1);  // past the last: repeat it
+      if (q < nIA) {
+        const int sl = q / 6, rem = q - 6 * sl, part = rem >> 1, h = rem & 1;
+        goff[k] = (int)(sl * sA + part * pA) + offA[h];
+        loff[k] = (3 * sl + part) * kApRegion + h * 1024;
+      } else {
+        const int qb = q - nIA, t = qb >> 2, part = (qb >> 1) & 1, h = qb & 1;
+        goff[k] = (int)(t * sB + part * pB) + offB[h];
+        loff[k] = (3 * kWin + 2 * t + part) * kApRegion + h * 1024;
+      }
+    }
+    auto issue = [&](int ks, int stage, int k0, int k1) {
+      const int kbo = (ks >> 1) * 1024, kx = (ks & 1) << 5;
+      int8_t* lb = lds + stage * kWinStageBytes;
+#pragma unroll
+      for (int k = 0; k < kQ; k++) {
+        if (k >= k0 && k < k1) {
+          const int q = min(uwave + NW * k, nI - 1);
+          const int8_t* src = (q < nIA ? Aw : Bw) + kbo + (goff[k] ^ kx);
+          __builtin_amdgcn_global_load_lds((gbl_ptr_t*)src, (lds_ptr_t*)(lb + loff[k]), 16, 0, 0);
+        }
+      }
+    };
+    barrier();  // the previous window no longer reads the stages
+    issue(0, 0, 0, kQ);
+    for (int seg0 = 0; seg0 < KS; seg0 += kApSeg) {
+      const int seg1 = min(KS, seg0 + kApSeg);
+#pragma unroll
+      for (int di = 0; di <= DL; di++) acc[di] = v16i{};
+      for (int ks = seg0; ks < seg1; ks++) {
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        barrier();
+        const int8_t* lb = lds + (ks & 1) * kWinStageBytes;
+        v4i bf[NS], bs[NS];
+#pragma unroll
+        for (int t = 0; t < NS; t++) {
+          bf[t] = *(const v4i*)(lb + (3 * kWin + 2 * t + pbf) * kApRegion + fb);
+          bs[t] = *(const v4i*)(lb + (3 * kWin + 2 * t + pbs) * kApRegion + fb);
+        }
+        v4i a0 = *(const v4i*)(lb + fa), ax = *(const v4i*)(lb + pax * kApRegion + fa);
+        const bool more = ks + 1 < KS;
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+          v4i n0, nx;
+          if (s + 1 < NS) {
+            n0 = *(const v4i*)(lb + (3 * (s + 1)) * kApRegion + fa);
+            nx = *(const v4i*)(lb + (3 * (s + 1) + pax) * kApRegion + fa);
+          }
+          if (more) issue(ks + 1, (ks + 1) & 1, s * kQ / NS, (s + 1) * kQ / NS);
+#pragma unroll
+          for (int t = 0; t < NS && s + t <= DL; t++) {
+            acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, bf[t], acc[s + t], 0, 0, 0);
+            acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ax, bs[t], acc[s + t], 0, 0, 0);
+          }
+          a0 = n0;
+          ax = nx;
+        }
+      }
+      // fold: x = acc 2^{-8 d} (exact) into (h, m, l) with two TwoSum steps each
+      const bool first = widx == 0 && seg0 == 0;
+      const bool final = widx == nwin - 1 && seg1 == KS;
+#pragma unroll
+      for (int v = 0; v < 16; v++) {
+        double h = 0, m = 0, l = 0;
+        if (!first) {
+          h = sp[v * 64];
+          m = sp[1024 + v * 64];
+          l = sp[2048 + v * 64];
+        }
+#pragma unroll
+        for (int di = DL; di >= 0; di--) {
+          const double x = (double)acc[di][v] * __builtin_ldexp(1.0, -8 * (d0 + di));
+          double s0, e0, s1, e1;
+          two_sum(h, x, s0, e0);
+          two_sum(m, e0, s1, e1);
+          h = s0;
+          m = s1;
+          l += e1;
+        }
+        if (!final) {
+          sp[v * 64] = h;
+          sp[1024 + v * 64] = m;
+          sp[2048 + v * 64] = l;
+        } else {
+          // to double-double, kept in the first two slots for the epilogue
+          double hh, e, dh, dl;
+          two_sum(h, m, hh, e);
+          e += l;
+          fast_two_sum(hh, e, dh, dl);
+          sp[v * 64] = dh;
+          sp[1024 + v * 64] = dl;
+        }
+      }
+    }
+    widx++;
+  };
+  for (int wa = 0; wa * kWin < a.SA; wa++) {
+    for (int wb = 0; wb * kWin < a.SB; wb++) {
+      const int d0 = kWin * (wa + wb) + 2;
+      if (d0 > a.dmax) continue;
+      switch (min(6, a.dmax - d0)) {
+        case 6: window(std::integral_constant<int, 6>{}, wa, wb); break;
+        case 5: window(std::integral_constant<int, 5>{}, wa, wb); break;
+        case 4: window(std::integral_constant<int, 4>{}, wa, wb); break;
+        case 3: window(std::integral_constant<int, 3>{}, wa, wb); break;
+        case 2: window(std::integral_constant<int, 2>{}, wa, wb); break;
+        case 1: window(std::integral_constant<int, 1>{}, wa, wb); break;
+        default: window(std::integral_constant<int, 0>{}, wa, wb); break;
+      }
+    }
+  }
+  // imaginary parts (hi, lo) to the waves of the real parts
+  double hi[16], lo[16];
+#pragma unroll
+  for (int v = 0; v < 16; v++) {
+    hi[v] = sp[v * 64];
+    lo[v] = sp[1024 + v * 64];
+  }
+  double* xch = (double*)lds + (quad * 16) * 64 + lane;
+  __syncthreads();
+  if (!re_part) {
+#pragma unroll
+    for (int v = 0; v < 16; v++) {
+      xch[v * 64] = hi[v];
+      xch[4096 + v * 64] = lo[v];
+    }
+  }
+  __syncthreads();
+  double part = 0;
+  if (re_part) {
+#pragma unroll
+    for (int v = 0; v < 16; v++) {
+      const int i = m0 + wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      const int j = n0 + wn + (lane & 31);
+      if (i < g.m && j < g.n) {
+        const int e = a.ea[i] + a.eb[j];
+        epi_element_dd<EPI>(g, i, j, mk<double>(ldexp(hi[v], e), ldexp(xch[v * 64], e)),
+                            mk<double>(ldexp(lo[v], e), ldexp(xch[4096 + v * 64], e)), part);
+      }
+    }
+  }
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<ANT>(g, part, red, bid);
+}
+
 // The large-tile kernel is used when it still gives every CU a tile, and for
 // every double-double product.
 static bool use_large_tiles(int m, int n, bool dd) {
   return dd || ceil_div(m, PBM) * ceil_div(n, PBN) >= kCUs;
+}
+
+// The windowed kernel takes the double-double tier's products (S digits per
+// operand, pairs s + t <= S + 1) with a 64 x 64 tile per CU.
+static bool use_windows(int m, int n, bool dd, int SA, int SB, int dmax, int k) {
+  const long span = (long)(SA + kWin) * kParts * oz_plane_bytes(m > n ? m : n, oz_kp(k));
+  return dd && SA == SB && SA >= 1 && dmax == SA + 1 && span < 2147483647L &&
+         ceil_div(m, ABM) * ceil_div(n, ABM) >= kCUs;
 }
 
 // The all-pairs kernel takes the FP64 tier's products (S digits per operand,
@@ -1016,8 +1274,11 @@ static bool use_allpairs(int m, int n, bool dd, int SA, int SB, int dmax, int k)
 // Scratch for either large-tile kernel (the all-pairs one needs at most the same:
 // a 64 x 64 double2 tile per 64-tile, and only for K past one segment).
 size_t oz_gemm_scratch_bytes(int m, int n, bool dd) {
-  const size_t ap = (size_t)ceil_div(m, ABM) * ceil_div(n, ABM) * ABM * ABM * sizeof(double2);
-  if (!use_large_tiles(m, n, dd)) return dd || ceil_div(m, ABM) * ceil_div(n, ABM) < kCUs ? 0 : ap;
+  // a 64 x 64 tile: one double2 per output (all-pairs), or three doubles per output
+  // and part (windowed)
+  const size_t t64 = (size_t)ceil_div(m, ABM) * ceil_div(n, ABM);
+  const size_t ap = t64 * ABM * ABM * (dd ? 6 * sizeof(double) : sizeof(double2));
+  if (!use_large_tiles(m, n, dd)) return t64 < (size_t)kCUs ? 0 : ap;
   const size_t lt = (size_t)ceil_div(m, PBM) * ceil_div(n, PBN) * PBM * PBN * sizeof(double2) * (dd ? 3 : 1);
   return lt > ap ? lt : ap;
 }
@@ -1032,7 +1293,7 @@ bool oz_gemm_exact(int m, int n, int k, int SA, int SB, bool dd) {
 }
 
 int oz_gemm_tiles(int m, int n, int k, bool dd, bool herm, int SA, int SB, int dmax) {
-  if (use_allpairs(m, n, dd, SA, SB, dmax, k)) {
+  if (use_allpairs(m, n, dd, SA, SB, dmax, k) || use_windows(m, n, dd, SA, SB, dmax, k)) {
     const int t = ceil_div(n, ABM);
     return herm ? t * (t + 1) / 2 : ceil_div(m, ABM) * t;
   }
@@ -1071,6 +1332,15 @@ static hipError_t launch_allpairs_s(int nt, const OzArgs& a, hipStream_t st) {
 }
 
 template <int EPI>
+static hipError_t launch_windows(int nt, const OzArgs& a, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void*)oz_gemm_windows_kernel<EPI>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kWinLds);
+  if (e != hipSuccess) return e;
+  oz_gemm_windows_kernel<EPI><<<dim3(nt), dim3(ANT), kWinLds, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int EPI>
 static hipError_t launch_allpairs(int nt, const OzArgs& a, hipStream_t st) {
   switch (a.SA) {
     case 1: return launch_allpairs_s<EPI, 1>(nt, a, st);
@@ -1101,6 +1371,20 @@ hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t
       case EPI_ADD: return launch_allpairs<EPI_ADD>(nt, a, st);
       case EPI_SPLIT: return launch_allpairs<EPI_SPLIT>(nt, a, st);
       case EPI_YDEF: return launch_allpairs<EPI_YDEF>(nt, a, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (use_windows(g.m, g.n, dd, SA, SB, dmax, g.k)) {
+    if (!scratch) return hipErrorInvalidValue;
+    g.tiles_m = ceil_div(g.m, ABM);
+    g.tiles_n = ceil_div(g.n, ABM);
+    const int nt = oz_gemm_tiles(g.m, g.n, g.k, dd, g.herm != 0, SA, SB, dmax);
+    OzArgs a{A, ea, B, eb, SA, SB, dmax, conjA, oz_kp(g.k), g, (double2*)scratch};
+    switch (epi) {
+      case EPI_STORE: return launch_windows<EPI_STORE>(nt, a, st);
+      case EPI_ADD: return launch_windows<EPI_ADD>(nt, a, st);
+      case EPI_SPLIT: return launch_windows<EPI_SPLIT>(nt, a, st);
+      case EPI_YDEF: return launch_windows<EPI_YDEF>(nt, a, st);
       default: return hipErrorInvalidValue;
     }
   }

@@ -216,3 +216,63 @@ def test_dd_validation(sr):
     z = dev(np.zeros_like(a))
     assert sr.schur_refine_dd(dev(a), z, q, dev(np.zeros_like(a)), t, empty(8, 8), slices=33)["rc"] == -1
     assert sr.schur_refine_dd(dev(a), z, q, dev(np.zeros_like(a)), t, empty(8, 8), iters=0)["rc"] == -1
+
+
+# Outputs with a 64 x 64 tile per CU and the tier's digit sets (S digits per
+# operand, pairs up to s + t = S + 1) take the windowed kernel: 4 x 4 windows of
+# slices, a three-term FP64 expansion per output between windows.
+
+def _ints(rng, shape, lim):
+    return np.asfortranarray(rng.integers(-lim, lim + 1, shape) + 1j * rng.integers(-lim, lim + 1, shape))
+
+
+@pytest.mark.parametrize("add", [False, True])
+@pytest.mark.parametrize("opa", [0, 1])
+@pytest.mark.parametrize("S", [2, 6, 14])
+def test_dd_windows_exact_on_integers(sr, S, opa, add):
+    # op(A) of 9-bit integers (two digits), B of 6-bit ones (one digit): the pairs
+    # (s, 1), s <= 2, give the exact product, which FP64 holds (lo = 0)
+    m, n, k = 2085, 2048, 130  # ragged rows, a ragged K-tile
+    rng = np.random.default_rng(900 + 10 * S + 2 * opa + add)
+    a = _ints(rng, (k, m) if opa else (m, k), 256)
+    b = _ints(rng, (k, n), 63)
+    c0 = _ints(rng, (m, n), 2**30) if add else None
+    ch, cl = empty(m, n), empty(m, n)
+    assert sr.sr_ozaki_zgemm_dd(dev(a), None, dev(b), None, ch, cl, opa=opa, slices_a=S, slices_b=S, dmax=S + 1,
+                                Cin_hi=dev(c0) if add else None) == 0
+    exact = (a.conj().T if opa else a) @ b
+    if add:
+        exact = exact + c0
+    assert np.array_equal(host(ch), exact) and not host(cl).any()
+
+
+@pytest.mark.parametrize("opa", [0, 1])
+def test_dd_windows_matches_quad(sr, opa):
+    m = n = 2048
+    k = 192
+    rng = np.random.default_rng(77 + opa)
+    ah, al = _dd_rand(rng, (k, m) if opa else (m, k))
+    bh, bl = _dd_rand(rng, (k, n))
+    ch, cl = empty(m, n), empty(m, n)
+    assert sr.sr_ozaki_zgemm_dd(dev(ah), dev(al), dev(bh), dev(bl), ch, cl, opa=opa,
+                                slices_a=14, slices_b=14, dmax=15) == 0
+    rows = np.random.default_rng(5).choice(m, 24, replace=False)
+    sub_h = np.asfortranarray(ah[:, rows] if opa else ah[rows])
+    sub_l = np.asfortranarray(al[:, rows] if opa else al[rows])
+    ref = oracle.gemm(oracle.QMat.from_dd(sub_h, sub_l), oracle.QMat.from_dd(bh, bl), opa=opa)
+    err = _dd_err(host(ch)[rows], host(cl)[rows], ref)
+    aa = np.abs(sub_h.conj().T if opa else sub_h)
+    bound = 4 * (k + 4) * UDD * np.sqrt(2.0) * (aa @ np.abs(bh))
+    assert np.all(err <= bound), (err / np.maximum(bound, 1e-300)).max()
+
+
+def test_dd_refine_n1024_windows(sr):
+    """n = 1024: every double-double product takes the windowed kernel."""
+    g = synth.schur_test_matrix(1024, seed=12)
+    a = g["A"]
+    qh = synth.hp_schur_start(a)
+    q_hi, q_lo, _, _, info = _refine_dd(sr, a, np.zeros_like(a), qh, np.zeros_like(qh))
+    assert info["status"] == "OK" and info["iters"] <= 4, info
+    rows = np.random.default_rng(31).choice(1024, 24, replace=False)
+    ev = oracle.evaluate_rows(oracle.QMat.from_dd(a), oracle.QMat.from_dd(q_hi, q_lo), rows)
+    assert ev["stril"] <= 1e-28 and ev["orth"] <= 1e-26, ev
