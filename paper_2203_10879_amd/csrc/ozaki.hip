@@ -1010,16 +1010,15 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // (local s + t <= DL = min(6, dmax - d0)). With dmax = S + 1 a window at the end of
 // the slice range reaches only the slices that exist (DL + 1 <= slices left). Each
 // window is one K-sweep in the manner of the all-pairs kernel (64 x 64 tile, 8 waves,
-// one part per wave, two LDS stages of 40 KiB, the staged slices limited to
-// min(4, DL + 1) per operand). After each segment the window's diagonal sums are
+// one part per wave, the staged slices limited to min(4, DL + 1) per operand: two
+// LDS stages of up to 40 KiB, four for windows of one or two slices). After each segment the window's diagonal sums are
 // added, smallest weight first, to a three-term FP64 expansion per output with two
 // exact TwoSum steps each (the partial sums can exceed the final value by the ratio
 // of the row and column scales to it, which two terms would turn into error); the
 // expansion lives in the per-tile scratch between windows and becomes double-double
 // after the last one.
 constexpr int kWin = 4;
-constexpr int kWinStageBytes = kWin * 5 * kApRegion;  // 40 KiB
-constexpr int kWinLds = 2 * kWinStageBytes;
+constexpr int kWinLds = 2 * kWin * 5 * kApRegion;  // two stages of 40 KiB
 static_assert(4 * 16 * 64 * 2 * sizeof(double) <= (size_t)kWinLds, "hi and lo of the imaginary parts fit");
 
 template <int EPI>
@@ -1098,6 +1097,12 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     constexpr int DL = decltype(dlc)::value;
     constexpr int NS = DL < kWin - 1 ? DL + 1 : kWin;  // slices staged per operand
     constexpr int nIA = 6 * NS, nI = nIA + 4 * NS, kQ = (nI + NW - 1) / NW;
+    // a stage holds 3 NS A regions then 2 NS B regions; windows of one or two
+    // slices have room for four stages (loads three steps ahead), the others two
+    constexpr int kStB = 5 * NS * kApRegion;
+    constexpr int NST = kWinLds / kStB >= 4 ? 4 : 2;
+    constexpr int kVmAhead = 0x0F70 | ((NST - 2) * kQ);  // vmcnt: later steps' loads may be in flight
+    static_assert((NST - 2) * kQ < 16 && NST * kStB <= kWinLds, "pipeline of a window");
     const int d0 = kWin * (wa + wb) + 2;
     const int8_t* Aw = a.A + (long)(kWin * wa) * sA;
     const int8_t* Bw = a.B + (long)(kWin * wb) * sB;
@@ -1112,12 +1117,12 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       } else {
         const int qb = q - nIA, t = qb >> 2, part = (qb >> 1) & 1, h = qb & 1;
         goff[k] = (int)(t * sB + part * pB) + offB[h];
-        loff[k] = (3 * kWin + 2 * t + part) * kApRegion + h * 1024;
+        loff[k] = (3 * NS + 2 * t + part) * kApRegion + h * 1024;
       }
     }
     auto issue = [&](int ks, int stage, int k0, int k1) {
       const int kbo = (ks >> 1) * 1024, kx = (ks & 1) << 5;
-      int8_t* lb = lds + stage * kWinStageBytes;
+      int8_t* lb = lds + stage * kStB;
 #pragma unroll
       for (int k = 0; k < kQ; k++) {
         if (k >= k0 && k < k1) {
@@ -1128,23 +1133,29 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
     };
     barrier();  // the previous window no longer reads the stages
-    issue(0, 0, 0, kQ);
+#pragma unroll
+    for (int j = 0; j < NST - 1; j++)
+      if (j < KS) issue(j, j, 0, kQ);
     for (int seg0 = 0; seg0 < KS; seg0 += kApSeg) {
       const int seg1 = min(KS, seg0 + kApSeg);
 #pragma unroll
       for (int di = 0; di <= DL; di++) acc[di] = v16i{};
       for (int ks = seg0; ks < seg1; ks++) {
-        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        // this step's loads have landed once at most the NST - 2 later steps' are
+        // in flight (all of them near the end, where fewer were issued)
+        if (ks + NST - 2 < KS) __builtin_amdgcn_s_waitcnt(kVmAhead);
+        else __builtin_amdgcn_s_waitcnt(kWaitVm0);
         barrier();
-        const int8_t* lb = lds + (ks & 1) * kWinStageBytes;
+        const int8_t* lb = lds + (ks % NST) * kStB;
         v4i bf[NS], bs[NS];
 #pragma unroll
         for (int t = 0; t < NS; t++) {
-          bf[t] = *(const v4i*)(lb + (3 * kWin + 2 * t + pbf) * kApRegion + fb);
-          bs[t] = *(const v4i*)(lb + (3 * kWin + 2 * t + pbs) * kApRegion + fb);
+          bf[t] = *(const v4i*)(lb + (3 * NS + 2 * t + pbf) * kApRegion + fb);
+          bs[t] = *(const v4i*)(lb + (3 * NS + 2 * t + pbs) * kApRegion + fb);
         }
         v4i a0 = *(const v4i*)(lb + fa), ax = *(const v4i*)(lb + pax * kApRegion + fa);
-        const bool more = ks + 1 < KS;
+        const int nxt = ks + NST - 1;  // the step whose loads go out now
+        const bool more = nxt < KS;
 #pragma unroll
         for (int s = 0; s < NS; s++) {
           v4i n0, nx;
@@ -1152,7 +1163,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             n0 = *(const v4i*)(lb + (3 * (s + 1)) * kApRegion + fa);
             nx = *(const v4i*)(lb + (3 * (s + 1) + pax) * kApRegion + fa);
           }
-          if (more) issue(ks + 1, (ks + 1) & 1, s * kQ / NS, (s + 1) * kQ / NS);
+          if (more) issue(nxt, nxt % NST, s * kQ / NS, (s + 1) * kQ / NS);
 #pragma unroll
           for (int t = 0; t < NS && s + t <= DL; t++) {
             acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, bf[t], acc[s + t], 0, 0, 0);
