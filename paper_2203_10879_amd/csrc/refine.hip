@@ -150,6 +150,20 @@ int read_back(hipStream_t st, const Work& w, int count, double* out, unsigned* s
   return SR_OK;
 }
 
+// Side stream for the Hermitian product Y beside the solve: one per device, created
+// on first use (non-blocking, default priority) and kept for the process.
+constexpr int kSideYMaxN = 2048;
+hipStream_t side_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
+
 GemmArgs gargs(int m, int n, int k, const void* A, long lda, const void* B, long ldb, void* C,
                long ldc) {
   GemmArgs g;
@@ -564,6 +578,12 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   double eps = 0, eps1 = -1, eps2 = -1, orth = 0;
   zc* cur = w.Qa;
   zc* other = Q;
+  hipStream_t sst = n <= kSideYMaxN ? side_stream() : nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  if (sst) {
+    CK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  }
   if (w.oz_s) CK(oz_split_rows(A, nullptr, n, n, n, w.oz_s, w.sA, w.eA, st));
   int su = 0;
   // the explicit Q^H serves the native That and Y; with oz_all they use the column
@@ -600,13 +620,27 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
     eps1 = eps;
     if (p == iters - 1) break;
 
-    // Y does not depend on L, but running it beside the solve on a second
-    // stream lets its blocks fill the CUs the latency-bound solve needs (measured:
-    // slower at n >= 2048), so the two run one after the other.
+    // Y does not depend on L. Up to kSideYMaxN it runs beside the solve on a side
+    // stream: the solve's early tile levels leave most CUs idle (measured: +7.5% per
+    // refinement at n = 1024, +2.7% at 2048). At n = 4096 Y's blocks take the CUs the
+    // solve's later levels need (the solve doubled, the pass gained 1.5%), so there
+    // the two run one after the other.
+    const bool side = sst && n <= kSideYMaxN;
+    if (side) {
+      CK(hipEventRecord(ev_fork, st));
+      CK(hipStreamWaitEvent(sst, ev_fork, 0));
+      hipStream_t keep = tm ? tm->st : nullptr;
+      if (tm) tm->st = sst;
+      rc = ydef(cur, QH, n, comp, w, sst, tm);
+      if (tm) tm->st = keep;
+      if (rc != SR_OK) return rc;
+      CK(hipEventRecord(ev_join, sst));
+    }
     TIC(tm, 1);
     CK(trisolve(w.Tlp, w.Elp, w.Llp, n, o.trunc ? 1e-5f : 0.f, w.tri, w.status, st));
     TOC(tm, 1);
-    if ((rc = ydef(cur, QH, n, comp, w, st, tm)) != SR_OK) return rc;
+    if (side) CK(hipStreamWaitEvent(st, ev_join, 0));
+    else if ((rc = ydef(cur, QH, n, comp, w, st, tm)) != SR_OK) return rc;
     CK(form_w(w.Llp, w.W, n, w.partials, st));
     CK(reduce_partials(w.partials, form_w_parts(n), w.scal + 3, st));
     double nrm[4];
@@ -638,6 +672,8 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   hipEventElapsedTime(&ms, e0, e1);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  if (ev_fork) hipEventDestroy(ev_fork);
+  if (ev_join) hipEventDestroy(ev_join);
   if (info) {
     info->status = status;
     info->iters = passes;
