@@ -152,7 +152,7 @@ int read_back(hipStream_t st, const Work& w, int count, double* out, unsigned* s
 
 // Side stream for the Hermitian product Y beside the solve: one per device, created
 // on first use (non-blocking, default priority) and kept for the process.
-constexpr int kSideYMaxN = 2048;
+constexpr int kSideYMaxN = 2048, kSideYMaxNdd = 2048;
 hipStream_t side_stream() {
   static std::mutex mu;
   static hipStream_t streams[64] = {};
@@ -927,6 +927,12 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
   CK(fro2_partials(Ah, (long)n * n, w.partials, 1024, st));
   CK(reduce_partials(w.partials, 1024, w.scal, st));
   CK(oz_split_rows(Ah, Al, n, n, n, S, w.sA, w.eA, st));
+  hipStream_t sst = n <= kSideYMaxNdd ? side_stream() : nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  if (sst) {
+    CK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  }
 
   // Newton-Schulz start from Q-hat = (Q_hi, Q_lo)
   zc* curh = w.Qh;
@@ -994,12 +1000,30 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
     eps1 = eps;
     if (p == iters - 1) break;
 
+    // Y beside the solve on the side stream up to kSideYMaxNdd (see the FP64 tier)
+    const bool side = sst && n <= kSideYMaxNdd;
+    if (side) {
+      CK(hipEventRecord(ev_fork, st));
+      CK(hipStreamWaitEvent(sst, ev_fork, 0));
+      hipStream_t keep = tm ? tm->st : nullptr;
+      if (tm) tm->st = sst;
+      TIC(tm, 0);
+      rc = dd_ydef(n, w, sst);
+      if (rc == SR_OK) TOC_HERM(tm);
+      if (tm) tm->st = keep;
+      if (rc != SR_OK) return rc;
+      CK(hipEventRecord(ev_join, sst));
+    }
     TIC(tm, 1);
     CK(trisolve64(w.Tlp, w.Elp, w.L, n, w.tri, w.status, st));
     TOC(tm, 1);
-    TIC(tm, 0);
-    if ((rc = dd_ydef(n, w, st)) != SR_OK) return rc;
-    TOC_HERM(tm);
+    if (side) {
+      CK(hipStreamWaitEvent(st, ev_join, 0));
+    } else {
+      TIC(tm, 0);
+      if ((rc = dd_ydef(n, w, st)) != SR_OK) return rc;
+      TOC_HERM(tm);
+    }
     CK(form_w64(w.L, w.W, n, w.partials, st));
     CK(reduce_partials(w.partials, form_w_parts(n), w.scal + 3, st));
     if ((rc = read_back_dd(st, w, 4, nrm, &dst)) != SR_OK) return rc;
@@ -1060,6 +1084,8 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
   hipEventElapsedTime(&ms, e0, e1);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  if (ev_fork) hipEventDestroy(ev_fork);
+  if (ev_join) hipEventDestroy(ev_join);
   if (info) {
     info->status = status;
     info->iters = passes;
