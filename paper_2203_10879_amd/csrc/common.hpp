@@ -105,6 +105,33 @@ struct MF<float> {
   __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+// Tile (tm, tn), tm <= tn, of the upper triangle of a T x T tile grid for logical
+// index L, in groups of kHermGroup tile rows: group g holds the rows from
+// kHermGroup g on and walks its columns (from its own diagonal) one by one, so the
+// blocks that run at once share row panels as well as column panels.
+constexpr int kHermGroup = 4;
+__host__ __device__ inline void herm_tile(int L, int T, int& tm, int& tn) {
+  for (int r0 = 0;; r0 += kHermGroup) {
+    const int h = T - r0 < kHermGroup ? T - r0 : kHermGroup;
+    const int tri = h * (h + 1) / 2, cnt = tri + h * (T - r0 - h);
+    if (L < cnt) {
+      if (L < tri) {
+        int k = (int)((sqrtf(8.f * L + 1.f) - 1.f) * 0.5f);
+        while (k * (k + 1) / 2 > L) k--;
+        while ((k + 1) * (k + 2) / 2 <= L) k++;
+        tm = r0 + L - k * (k + 1) / 2;
+        tn = r0 + k;
+      } else {
+        const int q = L - tri;
+        tm = r0 + q % h;
+        tn = r0 + h + q / h;
+      }
+      return;
+    }
+    L -= cnt;
+  }
+}
+
 constexpr int kCUs = 256;  // MI355X compute units
 constexpr int kXCDs = 8;   // accelerator complex dies (one L2 each)
 

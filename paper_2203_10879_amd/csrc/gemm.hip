@@ -268,11 +268,7 @@ __global__ __launch_bounds__(GNT * KS) void gemm_kernel(GemmArgs g) {
   }
   int tm, tn;
   if ((EPI == EPI_YDEF || EPI == EPI_STORE) && g.herm) {
-    // upper triangle of tiles, column by column: logical = tn (tn + 1) / 2 + tm
-    tn = (int)((sqrtf(8.f * logical + 1.f) - 1.f) * 0.5f);
-    while (tn * (tn + 1) / 2 > logical) tn--;
-    while ((tn + 1) * (tn + 2) / 2 <= logical) tn++;
-    tm = logical - tn * (tn + 1) / 2;
+    herm_tile(logical, g.tiles_n, tm, tn);  // the upper triangle of tiles
   } else {
     constexpr int kGroup = 4;
     const int group = logical / (kGroup * g.tiles_n);

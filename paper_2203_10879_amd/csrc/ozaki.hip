@@ -540,11 +540,7 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(2))) void o
   }
   int tm, tn;
   if (EPI == EPI_YDEF && g.herm) {
-    // upper triangle of tiles, column by column: logical = tn (tn + 1) / 2 + tm
-    tn = (int)((sqrtf(8.f * logical + 1.f) - 1.f) * 0.5f);
-    while (tn * (tn + 1) / 2 > logical) tn--;
-    while ((tn + 1) * (tn + 2) / 2 <= logical) tn++;
-    tm = logical - tn * (tn + 1) / 2;
+    herm_tile(logical, g.tiles_n, tm, tn);  // the upper triangle of tiles
   } else {
     constexpr int kGroup = 4;
     const int group = logical / (kGroup * g.tiles_n);
@@ -827,10 +823,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
   int tm, tn;
   if (EPI == EPI_YDEF && g.herm) {
-    tn = (int)((sqrtf(8.f * logical + 1.f) - 1.f) * 0.5f);
-    while (tn * (tn + 1) / 2 > logical) tn--;
-    while ((tn + 1) * (tn + 2) / 2 <= logical) tn++;
-    tm = logical - tn * (tn + 1) / 2;
+    herm_tile(logical, g.tiles_n, tm, tn);  // the upper triangle of tiles
   } else {
     // groups of kGroup tile rows, column by column within a group: the 32 blocks
     // an XCD runs at once share 4 row panels and 8 column panels
@@ -1040,10 +1033,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
   int tm, tn;
   if (EPI == EPI_YDEF && g.herm) {
-    tn = (int)((sqrtf(8.f * logical + 1.f) - 1.f) * 0.5f);
-    while (tn * (tn + 1) / 2 > logical) tn--;
-    while ((tn + 1) * (tn + 2) / 2 <= logical) tn++;
-    tm = logical - tn * (tn + 1) / 2;
+    herm_tile(logical, g.tiles_n, tm, tn);  // the upper triangle of tiles
   } else {
     constexpr int kGroup = 4;
     const int group = logical / (kGroup * g.tiles_n);
