@@ -155,6 +155,32 @@ def test_trisolve_matches_exact_solution(sr, n):
     assert res <= 8 * n * U32 * (np.linalg.norm(t64) * np.linalg.norm(lg) + np.linalg.norm(e64))
 
 
+def test_trisolve_32_wide_tiles(sr):
+    """Above n = 2048 the level solve runs on 32-wide tiles (66 tile rows here, the
+    last one ragged), in FP32 and in FP64. The quad solve is out of reach at this
+    size, so the oracle's Algorithm 2 in FP64 is the reference: the FP32 solve must
+    stay within 10x of the oracle's FP32 error, the FP64 solve within 10x of that
+    error scaled by u64/u32, and both must meet the backward-error bound of the
+    defining equation (eq. (7))."""
+    n = 2100
+    t, e = _sweep_case(n, 100 + n)
+    t64, e64 = t.astype(np.complex128), e.astype(np.complex128)
+    ld = oracle.trisolve(t64, e64, lp="double")[0].to_c128()
+    lf = oracle.trisolve(t64, e64, lp="float")[0].to_c128()
+    err_alg2 = np.linalg.norm(lf - ld)
+    nt, nl = np.linalg.norm(t64), np.linalg.norm(ld)
+    l32 = empty(n, n, True)
+    assert sr.sr_trisolve(dev(t), dev(e), l32, sr.workspace(n)) == 0
+    l64 = empty(n, n)
+    assert sr.sr_trisolve64(dev(t64), dev(e64), l64, sr.workspace(n)) == 0
+    for lg, u, bound in [(host(l32).astype(np.complex128), U32, 10 * err_alg2 + 10 * U32 * nl),
+                         (host(l64), U64, 10 * err_alg2 * U64 / U32 + 10 * U64 * nl)]:
+        assert not np.triu(lg).any()
+        assert np.linalg.norm(lg - ld) <= bound
+        res = np.linalg.norm(np.tril(t64 @ lg - lg @ t64, -1) + e64)
+        assert res <= 8 * n * u * (nt * np.linalg.norm(lg) + np.linalg.norm(e64))
+
+
 def test_trisolve_one_by_one_and_breakdown(sr):
     ws = sr.workspace(4)
     l = empty(1, 1, True)
