@@ -52,6 +52,10 @@ __device__ inline int swz(int k, int m) {
 // added in group order through LDS before group 0 stores the tile. A tile then
 // keeps KS times the waves busy, which is what fills the CUs when there are
 // fewer than two tiles per CU.
+// K step after which the next K-tile is stored (of 0, 4, 8, 12). Measured against
+// storing after the last step: 1-4% faster at n = 1024..4096 in FP64 and FP32.
+constexpr int kStoreAt = 4;
+
 template <typename R, int OPA, int EPI, int COMP, int BM, int KS = 1>
 __device__ inline void gemm_tile(const GemmArgs& g, int m0, int n0, int slot,
                                  cplx<R> (*As)[GBK][BM], cplx<R> (*Bs)[GBK][BM], double* red) {
@@ -187,9 +191,12 @@ __device__ inline void gemm_tile(const GemmArgs& g, int m0, int n0, int slot,
           acc_re[mi][ni] = MF<R>::op(na_im[mi], b_im[ni], acc_re[mi][ni]);
           acc_im[mi][ni] = MF<R>::op(a_im[mi], b_re[ni], acc_im[mi][ni]);
         }
+      // The next K-tile goes to the other buffer (free since the last barrier)
+      // while this one's products are still in the matrix pipe, so that the LDS
+      // stores of the waves overlap other waves' MFMAs instead of the barrier.
+      if (kk == kStoreAt && it + 1 < iters) sstore(cur ^ 1);
     }
     if (COMP && ((it + 1) % kChunk == 0 || it + 1 == iters)) fold();
-    if (it + 1 < iters) sstore(cur ^ 1);
     __syncthreads();
   }
 
