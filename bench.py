@@ -460,7 +460,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the refinement of one matrix is not sharded across GPUs in this build)",
+              "(the refinement of one matrix is not sharded across GPUs)",
               file=sys.stderr)
         return 2
     return {"default": run_default, "precision": run_precision, "batched": run_batched,

@@ -49,7 +49,7 @@ typedef enum {
   SR_EINVAL = -1,        /* invalid argument                                         */
   SR_EHIP = -2,          /* a HIP runtime call failed                                */
   SR_ENOMEM = -3,        /* workspace too small or allocation failed                 */
-  SR_ENOSYS = -4         /* option not supported by this build                       */
+  SR_ENOSYS = -4         /* option not supported by the library                      */
 } sr_status;
 
 typedef enum {
