@@ -256,6 +256,31 @@ hipError_t to_c64(const zc* x, cc* y, long count, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename C>
+__global__ __launch_bounds__(ENT) void w2_minus_y_kernel(const C* __restrict__ W2, const zc* __restrict__ Y,
+                                                         C* __restrict__ X, long count) {
+  using R = decltype(C::re);
+  for (long i = blockIdx.x * (long)ENT + threadIdx.x; i < count; i += (long)gridDim.x * ENT) {
+    const C w = W2[i];
+    const zc y = Y[i];
+    X[i] = mk<R>((R)((double)w.re - y.re), (R)((double)w.im - y.im));
+  }
+}
+
+template <typename C>
+static hipError_t launch_w2_minus_y(const C* W2, const zc* Y, C* X, long count, hipStream_t st) {
+  const int blocks = (int)std::min<long>(4096, (count + ENT - 1) / ENT);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(w2_minus_y_kernel<C>, dim3(blocks), dim3(ENT), 0, st, W2, Y, X, count);
+  return hipGetLastError();
+}
+hipError_t w2_minus_y(const cc* W2, const zc* Y, cc* X, long count, hipStream_t st) {
+  return launch_w2_minus_y(W2, Y, X, count, st);
+}
+hipError_t w2_minus_y(const zc* W2, const zc* Y, zc* X, long count, hipStream_t st) {
+  return launch_w2_minus_y(W2, Y, X, count, st);
+}
+
 __global__ __launch_bounds__(ENT) void zero_kernel(uint32_t* __restrict__ p, long words) {
   for (long i = blockIdx.x * (long)ENT + threadIdx.x; i < words; i += (long)gridDim.x * ENT) p[i] = 0u;
 }

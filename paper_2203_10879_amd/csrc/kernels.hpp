@@ -80,6 +80,10 @@ hipError_t form_w(const cc* L, cc* W, int n, double* partials, hipStream_t st);
 hipError_t form_delta(const cc* L, const zc* Y, const cc* W2, const cc* W3, const cc* YW, zc* D,
                       int n, hipStream_t st);
 hipError_t to_c64(const zc* x, cc* y, long count, hipStream_t st);
+// X = W2 - Y, the left factor of (W^2 - Y) W = W^3 - YW: FP32 (Y narrowed from FP64,
+// one rounding) or FP64.
+hipError_t w2_minus_y(const cc* W2, const zc* Y, cc* X, long count, hipStream_t st);
+hipError_t w2_minus_y(const zc* W2, const zc* Y, zc* X, long count, hipStream_t st);
 // Double-double tier: W = L - L^H in FP64 (partials of ||W||^2), and
 // D = W - Y/2 + (W2 + W3 - YW)/2 with Y = Yhi + Ylo and D = Dhi + Dlo in
 // double-double (L and the lp products may be NULL: absent).

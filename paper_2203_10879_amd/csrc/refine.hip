@@ -397,19 +397,24 @@ int apply_update(const zc* Q, zc* Qout, zc* QHout, int n, Gate gt, const Work& w
     CK(cgemm(a2, st));
     np++;
   }
-  if (gt.w3) {
+  // With both W^3 and YW, one product gives their difference: (W^2 - Y) W (into W3).
+  const bool both = gt.w3 && gt.yw;
+  if (both) {
+    CK(w2_minus_y(w.W2, w.Y, w.Ylp, (long)n * n, st));
+    CK(cgemm(gargs(n, n, n, w.Ylp, n, w.W, n, w.W3, n), st));
+    np++;
+  } else if (gt.w3) {
     GemmArgs a3 = gargs(n, n, n, w.W2, n, w.W, n, w.W3, n);
     a3.herm = -1;  // and W^3 skew-Hermitian
     CK(cgemm(a3, st));
     np++;
-  }
-  if (gt.yw) {
+  } else if (gt.yw) {
     CK(to_c64(w.Y, w.Ylp, (long)n * n, st));
     CK(cgemm(gargs(n, n, n, w.Ylp, n, w.W, n, w.YW, n), st));
     np++;
   }
   CK(form_delta(w.Llp, w.Y, gt.w2 ? w.W2 : nullptr, gt.w3 ? w.W3 : nullptr,
-                gt.yw ? w.YW : nullptr, w.P, n, st));
+                gt.yw && !both ? w.YW : nullptr, w.P, n, st));
   TIC(tm, 0);
   if (w.oz_s) {
     const int rc = oz_update(Q, w.P, Qout, QHout, n, Su, w, st);
@@ -1049,18 +1054,23 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
       CK(zgemm(0, EPI_STORE, 0, a2, st));
       nprod++;
     }
-    if (gw3) {
+    // With both W^3 and YW, one product gives their difference: (W^2 - Y) W (into W3).
+    const bool both = gw3 && gyw;
+    if (both) {
+      CK(w2_minus_y(w.W2, w.Yh, w.YW, (long)n * n, st));
+      CK(zgemm(0, EPI_STORE, 0, gargs(n, n, n, w.YW, n, w.W, n, w.W3, n), st));
+      nprod++;
+    } else if (gw3) {
       GemmArgs a3 = gargs(n, n, n, w.W2, n, w.W, n, w.W3, n);
       a3.herm = -1;  // and W^3 skew-Hermitian
       CK(zgemm(0, EPI_STORE, 0, a3, st));
       nprod++;
-    }
-    if (gyw) {
+    } else if (gyw) {
       CK(zgemm(0, EPI_STORE, 0, gargs(n, n, n, w.Yh, n, w.W, n, w.YW, n), st));
       nprod++;
     }
     CK(form_delta_dd(w.L, w.Yh, w.Yl, gw2 ? w.W2 : nullptr, gw3 ? w.W3 : nullptr,
-                     gyw ? w.YW : nullptr, w.Dh, w.Dl, n, st));
+                     gyw && !both ? w.YW : nullptr, w.Dh, w.Dl, n, st));
     su = dd_update_slices(o, S, nw + 0.5 * ny);
     if (info && updates + 1 < 16) info->update_slices_hist[updates + 1] = su;
     TIC(tm, 0);
