@@ -88,6 +88,25 @@ def test_config1_n1024_quad_rows(sr):
     assert np.max(np.min(np.abs(np.diag(t)[:, None] - g["lam"][None, :]), axis=1)) <= 1e-10
 
 
+def test_config2_n4096_quad_rows(sr):
+    """n = 4096 with eigenvalue gaps >= 1e-3 (the precision-comparison workload), native
+    FP64 products and the all-split Ozaki form: 32-wide solve tiles, one 8-wave group
+    per block for the plain products. The start is the exact Schur basis perturbed by
+    1e-6 (an FP32-sized error) instead of the benchmark's LAPACK start, which would take
+    minutes to compute here; quad error on 4 rows."""
+    n = 4096
+    g = synth.schur_test_matrix(n, seed=2, gap=1e-3)
+    a = g["A"]
+    qh = synth.perturbed_start(g["Q0"], seed=4, delta=1e-6)
+    rows = np.random.default_rng(20002).choice(n, 4, replace=False)
+    for mode in ["fp64", "ozaki_i8_all"]:
+        q, t, info = _refine(sr, a, qh, iters=8, gemm=mode)
+        assert info["status"] == "OK" and info["iters"] <= 6, (mode, info)
+        ev = oracle.evaluate_rows(a, q, rows)
+        assert ev["stril"] <= 1e-15, (mode, ev)
+        assert ev["orth"] <= 4 * U64 * np.sqrt(n) * 10, (mode, ev)
+
+
 def test_status_codes(sr):
     g = synth.schur_test_matrix(40, seed=3)
     qh = synth.lp_schur_start(g["A"])
