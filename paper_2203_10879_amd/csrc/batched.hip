@@ -8,7 +8,9 @@
 //                     size bucket by the autotuner below);
 //   per-matrix blocks the residual test, W = L - L^H with its norm, the gates of the
 //                     lp terms and Delta: one block per matrix;
-//   solve             the FP32 triangular solve, one block per matrix.
+//   solve             the FP32 triangular solve by tile diagonal across the batch (one
+//                     launch per step, one block per tile), or one block per matrix
+//                     when no matrix has more than two 16-wide tile rows.
 // Loop control stays on the device: each matrix has a state record (its residual
 // history and outcome) and an `active` flag that the grouped launches and blocks
 // test, so matrices that have finished cost one early exit per launch. The
@@ -292,7 +294,7 @@ int tiles_of(int n, int bm) { return ceil_div(n, bm) * ceil_div(n, bm); }
 // Workspace layout of a batch.
 struct BLayout {
   std::vector<size_t> off;  // per matrix: offset of its arrays
-  size_t mats, states, active, act_w2, act_w3, act_yw, counter, partials, args, tiles, tri;
+  size_t mats, states, active, act_w2, act_w3, act_yw, counter, partials, args, tiles, tri, steps;
   size_t total;
   int nslots, ntiles64, ntiles32;
 };
@@ -336,6 +338,7 @@ BLayout layout(int batch, const int* n, const std::vector<int>& bm) {
   L.args = take(sizeof(GemmArgs) * batch * kArgTables);
   L.tiles = take(sizeof(GTile) * (L.ntiles64 + L.ntiles32 + 1));
   L.tri = take(trimatrix_bytes() * batch);
+  L.steps = take(sizeof(TriStepTile) * (trisolve_steps_tiles(n, batch) + 1));
   L.total = p;
   return L;
 }
@@ -538,6 +541,13 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
     std::vector<GemmArgs> args((size_t)kArgTables * batch);
     std::vector<GTile> t64, t32;
     std::vector<char> tri(trimatrix_bytes() * batch);
+    // The solve goes by tile diagonal across the batch once a matrix has three or more
+    // 16-wide tile rows; below that one block per matrix walks its few tiles.
+    std::vector<TriStepTile> step_tiles(trisolve_steps_tiles(n, batch) + 1);
+    std::vector<int> step_off(trisolve_steps_max(n, batch) + 1);
+    int nsteps = 0;
+    trisolve_steps_plan(n, batch, step_tiles.data(), step_off.data(), &nsteps);
+    const bool by_steps = nsteps >= 3;
     int* active = (int*)(w + L.active);
     int* act_w2 = (int*)(w + L.act_w2);
     int* act_w3 = (int*)(w + L.act_w3);
@@ -618,7 +628,9 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
         hipMemcpyAsync(w + L.args, args.data(), sizeof(GemmArgs) * args.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
         (t64.size() && hipMemcpyAsync(tiles_dev, t64.data(), sizeof(GTile) * t64.size(), hipMemcpyHostToDevice, st) != hipSuccess) ||
         (t32.size() && hipMemcpyAsync(tiles_dev + t64.size(), t32.data(), sizeof(GTile) * t32.size(), hipMemcpyHostToDevice, st) != hipSuccess) ||
-        hipMemcpyAsync(w + L.tri, tri.data(), tri.size(), hipMemcpyHostToDevice, st) != hipSuccess) {
+        hipMemcpyAsync(w + L.tri, tri.data(), tri.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        (by_steps && hipMemcpyAsync(w + L.steps, step_tiles.data(), sizeof(TriStepTile) * step_off[nsteps],
+                                    hipMemcpyHostToDevice, st) != hipSuccess)) {
       fail(SR_EHIP);
       break;
     }
@@ -645,7 +657,10 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
       if (!cap_ok) break;
       hipLaunchKernelGGL(b_decide_kernel, dim3(batch), dim3(BNT), 0, st, mats_dev, states, active, partials,
                          iters, tol, counter);
-      cap_ok = trisolve_batched(w + L.tri, batch, o.trunc ? 1e-5f : 0.f, st) == hipSuccess &&
+      const float tr = o.trunc ? 1e-5f : 0.f;
+      cap_ok = (by_steps ? trisolve_batched_steps(w + L.tri, (const TriStepTile*)(w + L.steps), step_off.data(),
+                                                  nsteps, tr, st)
+                         : trisolve_batched(w + L.tri, batch, tr, st)) == hipSuccess &&
                G.z(T_Y + 4 * e, 0, EPI_YDEF, comp, active) == hipSuccess;
       if (!cap_ok) break;
       hipLaunchKernelGGL(b_post_kernel, dim3(batch), dim3(BNT), 0, st, mats_dev, states, active, partials,

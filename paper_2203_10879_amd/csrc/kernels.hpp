@@ -129,5 +129,18 @@ hipError_t trisolve_batched(const void* mats, int count, float trunc, hipStream_
 size_t trimatrix_bytes();
 void trimatrix_fill(void* dst, const cc* T, const cc* E, cc* L, int n, const int* active,
                     unsigned* flag);
+// The same solves by tile diagonal: step s takes tile diagonal nb - 1 - s of every
+// matrix with nb > s tile rows (16-wide tiles), one block per tile, so that a large
+// matrix's tiles run in parallel. trisolve_steps_plan lists the (matrix, tile) pairs
+// of all steps (n[b] < 2: none) and the start of each step's run, ending with the
+// total; trisolve_batched_steps launches the steps from a device copy of the list.
+struct TriStepTile {
+  int mat, I, J;
+};
+void trisolve_steps_plan(const int* n, int count, TriStepTile* tiles, int* step_off, int* steps);
+size_t trisolve_steps_tiles(const int* n, int count);  // list length
+int trisolve_steps_max(const int* n, int count);       // number of steps
+hipError_t trisolve_batched_steps(const void* mats, const TriStepTile* tiles, const int* step_off, int steps,
+                                  float trunc, hipStream_t st);
 
 }  // namespace sr

@@ -28,9 +28,13 @@
 //     tile so that the launch fills the chip, written to a buffer selected by the
 //     parity of D.
 // No block waits on another and no device-scope fence is needed: all data a
-// launch reads were written by earlier launches. Small matrices (and the batched
-// path) use one block that walks all tiles.
+// launch reads were written by earlier launches. Small matrices use one block that
+// walks all tiles; batches go by tile diagonal across their matrices (one launch
+// per step, one block per tile), or one block per matrix when every matrix has at
+// most two tile rows.
 #include <string.h>
+
+#include <algorithm>
 
 #include "kernels.hpp"
 namespace sr {
@@ -89,6 +93,49 @@ hipError_t trisolve64(const zc* T, const zc* E, zc* L, int n, void* ws, unsigned
 // 2000-matrix batch: 50.8 against 53.6 ms per batch).
 hipError_t trisolve_batched(const void* mats, int count, float trunc, hipStream_t st) {
   return tri16::batched(mats, count, trunc, st);
+}
+
+static int step_rows(int n) { return n >= 2 ? (n + tri16::TB - 1) / tri16::TB : 0; }
+
+size_t trisolve_steps_tiles(const int* n, int count) {
+  size_t t = 0;
+  for (int b = 0; b < count; b++) t += (size_t)step_rows(n[b]) * (step_rows(n[b]) + 1) / 2;
+  return t;
+}
+
+int trisolve_steps_max(const int* n, int count) {
+  int m = 0;
+  for (int b = 0; b < count; b++) m = std::max(m, step_rows(n[b]));
+  return m;
+}
+
+void trisolve_steps_plan(const int* n, int count, TriStepTile* tiles, int* step_off, int* steps) {
+  const int S = trisolve_steps_max(n, count);
+  int k = 0;
+  for (int s = 0; s < S; s++) {
+    step_off[s] = k;
+    for (int b = 0; b < count; b++) {
+      const int nb = step_rows(n[b]);
+      if (nb <= s) continue;
+      const int D = nb - 1 - s;
+      for (int t = 0; t <= s; t++) tiles[k++] = TriStepTile{b, D + t, t};
+    }
+  }
+  step_off[S] = k;
+  *steps = S;
+}
+
+hipError_t trisolve_batched_steps(const void* mats, const TriStepTile* tiles, const int* step_off, int steps,
+                                  float trunc, hipStream_t st) {
+  for (int s = 0; s < steps; s++) {
+    const int cnt = step_off[s + 1] - step_off[s];
+    if (cnt == 0) continue;
+    hipLaunchKernelGGL(tri16::trisolve_step_kernel<float>, dim3(cnt), dim3(tri16::TNT), 0, st,
+                       (const TriMatrix<float>*)mats, tiles + step_off[s], trunc);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 size_t trimatrix_bytes() { return sizeof(TriMatrix<float>); }
