@@ -92,7 +92,7 @@ typedef struct {
   int iters;              /* passes = evaluations of That (the paper's iterations)    */
   int updates;            /* Q updates done (= iters - 1 when converged)              */
   int hp_gemms;           /* hp products counted as in the paper: 2 + 4(iters-1) + 2  */
-  int lp_products;        /* lp products (YW, W^2, W^3) actually formed               */
+  int lp_products;        /* lp products launched (W^2, W^3, YW; (W^2 - Y) W for both) */
   double resid;           /* last ||stril(That)||_F / ||A||_F, computed in hp         */
   double orth;            /* ||Q^H Q - I||_F of the last Y formed (0 if none)         */
   double resid_hist[16];  /* residual of passes 1..min(iters,16)                      */
@@ -134,8 +134,8 @@ int schur_refine(const void* A, void* Q, void* T, int n, int iters, double tol,
  *  matrix laid out as in schur_refine. info (host, sr_info[batch]) may be NULL
  *  (the ms_* fields are not filled).
  *  Each pass runs as one fixed sequence of grouped launches over the whole batch
- *  (persistent tile-table products, one block per matrix for the solve and the
- *  elementwise steps) with device-side loop control; two passes are captured in a
+ *  (persistent tile-table products, the solve by tile diagonal across the batch,
+ *  one block per matrix for the elementwise steps) with device-side loop control; two passes are captured in a
  *  HIP graph and replayed. The tile edge (64 or 32) of each size bucket is chosen
  *  by timing both on the first batch that contains the bucket (kept for the
  *  process). opts->gemm must be SR_GEMM_FP64. The work is ordered after the
@@ -157,7 +157,8 @@ int sr_batched_tile_edge(int n);
  * n x n, each pair a double-double matrix). Every hp product (P = A Q, That, Y, the
  * Newton-Schulz start and Q Delta) is an Ozaki split product of the double-double
  * operands on INT8 MFMA with double-double accumulation; the solve and the lp
- * products YW, W^2, W^3 run in FP64, gated against 0.1 * 2^-104.
+ * products YW, W^2, W^3 run in FP64, gated against 0.1 * 2^-104 (W^3 - YW as one
+ * product (W^2 - Y) W when both pass).
  *  opts->slices: 8-bit digits per operand of the hp products (0 = 14, at most 32).
  *    The digits of a row or column are relative to its largest entry, so a matrix
  *    whose rows or columns span many orders of magnitude needs more digits to keep
@@ -235,7 +236,8 @@ int sr_reorder_start(const void* A, void* Q, int n, double theta, int* perm, voi
 int sr_trisolve64(const void* T, const void* E, void* L, int n, void* ws, void* stream);
 
 /* Merged Newton-Schulz update (Algorithm 4, the W, Y, Sigma and Q steps) given L:
- * W = L - L^H, Y = Q^H Q - I (hp), lp products (gated when gate != 0),
+ * W = L - L^H, Y = Q^H Q - I (hp), lp products (gated when gate != 0; W^3 - YW as
+ * one product (W^2 - Y) W when both pass),
  * Delta = 1/2 Sigma - I = W - Y/2 + (-YW + W^2 + W^3)/2, Q_out = Q + Q Delta.
  * L_lp complex64; Q, Q_out complex128 (must not overlap). norms (host, may be NULL,
  * double[2]) receives ||W||_F and ||Y||_F (synchronises). */
