@@ -149,6 +149,45 @@ __host__ __device__ inline Carries value_carries_dd(double rh, double rl, int S)
   return {digit_carries(m[0], m[1]), digit_carries(m[2], m[3])};
 }
 
+// The raw digits of one value from a single pass, kept for the stores: digit s
+// (1..S) modulo 256 in byte (s - 1) mod 8 of word (s - 1) / 8, with the carry masks
+// of x and -x. (raw + carry) modulo 256 read as a signed byte is final_digit's
+// value (raw in [-128, 128], the sum in [-128, 129]), and -raw modulo 256 is the
+// negated byte, so the stores need no second pass over the digits. The loops run
+// to the fixed maximum so that every word is addressed by a constant.
+constexpr int kMaxDigits = 32;
+struct Digits {
+  uint64_t w[kMaxDigits / 8];
+  Carries c;
+};
+
+template <bool DD>
+__host__ __device__ inline Digits split_value(double rh, double rl, int S) {
+  Digits d;
+  uint64_t m[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < kMaxDigits / 8; q++) {
+    uint64_t word = 0;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int s = 8 * q + j + 1;
+      if (s <= S) {
+        const int r = DD ? raw_digit_dd(rh, rl) : raw_digit(rh);
+        note_digit(r, 1ull << (S - s), m);
+        word |= (uint64_t)(uint8_t)r << (8 * j);
+      }
+    }
+    d.w[q] = word;
+  }
+  d.c = {digit_carries(m[0], m[1]), digit_carries(m[2], m[3])};
+  return d;
+}
+
+// Final digit s (1..S) from its byte (raw modulo 256, or its negation) and a carry mask.
+__host__ __device__ inline int8_t byte_digit(unsigned byte, uint64_t carries, int s, int S) {
+  return (int8_t)(uint8_t)(byte + (unsigned)((carries >> (S - s)) & 1u));
+}
+
 // Slices of the columns of X (K x ncols, leading dim ld), one block per column of
 // the padded count (padding columns get zero digits). These serve as B, and as
 // op(A) = X^H when the product applies the conjugation.
@@ -194,27 +233,23 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
     int8_t* o_ni = out + 2 * plane + o;
     if (k < K) {
       const zc v = x[k];
-      if (xl) {
-        const zc w = xl[k];
-        double rh = ldexp(v.re, -e), rl = ldexp(w.re, -e);
-        double ih = ldexp(v.im, -e), il = ldexp(w.im, -e);
-        const Carries cr = value_carries_dd(rh, rl, S), ci = value_carries_dd(ih, il, S);
-        for (int s = 0; s < S; s++) {
-          o_re[s * stride] = final_digit(raw_digit_dd(rh, rl), cr.pos, s + 1, S);
-          const int di = raw_digit_dd(ih, il);
-          o_im[s * stride] = final_digit(di, ci.pos, s + 1, S);
-          o_ni[s * stride] = final_digit(-di, ci.neg, s + 1, S);
+      const zc w = xl ? xl[k] : mk<double>(0, 0);
+      const double rh = ldexp(v.re, -e), rl = ldexp(w.re, -e);
+      const double ih = ldexp(v.im, -e), il = ldexp(w.im, -e);
+      const Digits dr = xl ? split_value<true>(rh, rl, S) : split_value<false>(rh, 0.0, S);
+      const Digits di = xl ? split_value<true>(ih, il, S) : split_value<false>(ih, 0.0, S);
+#pragma unroll
+      for (int q = 0; q < kMaxDigits / 8; q++)
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const int s = 8 * q + j + 1;
+          if (s <= S) {
+            const unsigned br = (unsigned)(dr.w[q] >> (8 * j)) & 255u, bi = (unsigned)(di.w[q] >> (8 * j)) & 255u;
+            o_re[(s - 1) * stride] = byte_digit(br, dr.c.pos, s, S);
+            o_im[(s - 1) * stride] = byte_digit(bi, di.c.pos, s, S);
+            o_ni[(s - 1) * stride] = byte_digit((256u - bi) & 255u, di.c.neg, s, S);
+          }
         }
-      } else {
-        double r = ldexp(v.re, -e), i = ldexp(v.im, -e);
-        const Carries cr = value_carries(r, S), ci = value_carries(i, S);
-        for (int s = 0; s < S; s++) {
-          o_re[s * stride] = final_digit(raw_digit(r), cr.pos, s + 1, S);
-          const int di = raw_digit(i);
-          o_im[s * stride] = final_digit(di, ci.pos, s + 1, S);
-          o_ni[s * stride] = final_digit(-di, ci.neg, s + 1, S);
-        }
-      }
     } else {
       for (int s = 0; s < S; s++) {
         o_re[s * stride] = 0;
@@ -336,6 +371,7 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
 
 hipError_t oz_split_cols(const zc* X, const zc* Xlo, long ld, int K, int ncols, int S, int8_t* out,
                          int* exps, hipStream_t st) {
+  if (S < 1 || S > kMaxDigits) return hipErrorInvalidValue;
   if (ncols == 0) return hipSuccess;
   hipLaunchKernelGGL(oz_split_cols_kernel, dim3(oz_rows_pad(ncols)), dim3(kSplitNT), 0, st, X, Xlo, ld, K, ncols, S,
                      oz_kp(K), out, exps);
