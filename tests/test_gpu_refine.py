@@ -134,11 +134,12 @@ def test_resume_from_saved_iterate(sr):
     assert oracle.evaluate(g["A"], q2, t2)["stril"] <= 1e-15
 
 
-def test_batched_matches_single(sr):
+@pytest.mark.parametrize("sizes", [[20, 50, 90, 1, 2, 130], [2, 17, 32, 5, 31]])
+def test_batched_matches_single(sr, sizes):
     """The batched driver (grouped launches, device-side loop control, graph
     replays) reaches the same passes and, up to rounding, the same Q and T as
-    single calls."""
-    sizes = [20, 50, 90, 1, 2, 130]
+    single calls. The first batch solves by tile diagonal across the matrices, the
+    second (no matrix with more than two 16-wide tile rows) one block per matrix."""
     mats = [synth.schur_test_matrix(n, seed=200 + n) for n in sizes]
     starts = [synth.lp_schur_start(m["A"]) for m in mats]
     As = [dev(m["A"]) for m in mats]
