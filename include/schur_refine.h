@@ -152,7 +152,7 @@ size_t sr_workspace_bytes_batched(int batch, const int* n, const sr_opts* opts);
 /* Tile edge the batched autotuner chose for matrices of size n (-1: not tuned). */
 int sr_batched_tile_edge(int n);
 
-/* Double-double tier (Section 4 refines to higher than working precision the same
+/* Double-double tier (Section 3 refines to higher than working precision the same
  * way): A = A_hi + A_lo, Q = Q_hi + Q_lo, T = T_hi + T_lo (all device, complex128
  * n x n, each pair a double-double matrix). Every hp product (P = A Q, That, Y, the
  * Newton-Schulz start and Q Delta) is an Ozaki split product of the double-double
@@ -215,7 +215,7 @@ int sr_residual(const void* A, const void* Q, int n, void* T, void* T_lp, void* 
 int sr_trisolve(const void* T_lp, const void* E_lp, void* L_lp, int n, float trunc,
                 void* ws, void* stream);
 
-/* Reordering of the start (Section 4, the paragraph on the first step of
+/* Reordering of the start (Section 2.4, the paragraph on the reordering of
  * Algorithm 4: clustered eigenvalues are moved next to each other, in the order of
  * their projections onto a random line). A: complex128 n x n (read); Q: complex128
  * n x n start, in/out. With T = triu(Q^H A Q) (FP64), unitary swaps of adjacent
@@ -248,7 +248,7 @@ int sr_update(const void* Q, const void* L_lp, void* Q_out, int n, int gate,
  * (Algorithm 4, before the loop). Qh, Q complex128, must not overlap. */
 int sr_ns_init(const void* Qh, void* Q, int n, int compensated, void* ws, void* stream);
 
-/* Ozaki split product (the hp products of Section 4 built from an Ozaki-scheme
+/* Ozaki split product (the hp products of Section 3 built from an Ozaki-scheme
  * splitting) on INT8 MFMA: C = op(A) B (+ Cin), complex128, arguments as sr_zgemm.
  * op(A) is split into slices_a slices of balanced 8-bit digits per row, B into
  * slices_b per column (each with a power-of-two scale per row / column, about

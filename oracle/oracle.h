@@ -57,8 +57,9 @@ void orc_gemm(int opa, int m, int n, int k, const orc_qc* A, const orc_qc* B, or
  * order 0: Algorithm 2's column order; order 1: subdiagonal wavefront order
  * (entries with larger i - j first), which also satisfies the order condition (10).
  * trunc > 0: any computed entry with modulus above trunc is set to zero (the
- * Example 4 device). Returns ORC_OK or ORC_BREAKDOWN.
- * Pinned by the Kronecker-form linear system, closed forms, and Theorem 1. */
+ * Example 4 device: later entries see the zero). Returns ORC_OK or ORC_BREAKDOWN.
+ * Pinned by the Kronecker-form linear system, closed forms, and Theorem 1; the
+ * truncation by exact rational substitution that zeroes as computed. */
 int orc_trisolve(int lp, int order, int n, const orc_qc* T, const orc_qc* E, orc_qc* L,
                  double trunc);
 
@@ -70,7 +71,9 @@ void orc_ns(int n, const orc_qc* Qh, orc_qc* Q);
  * Y = Q^H Q - I in hp; the products Y W, W^2, W^3 (and W^2 Y, W^2 Y W when
  * full != 0) in lp; Sigma = 2I + 2W - Y - YW + W^2 + W^3 (+ W^2 Y + W^2 Y W)
  * summed in hp; Qn = 1/2 Q Sigma in hp.
- * Pinned against the unmerged Newton-Schulz step of Q (I + W). */
+ * Pinned against the unmerged Newton-Schulz step of Q (I + W) (lp = quad), and for
+ * lp = float and double by the size of the lp rounding of the products (bounded
+ * from both sides, scaling with the lp unit roundoff). */
 void orc_ns_merged(int lp, int n, const orc_qc* Q, const orc_qc* W, int full, orc_qc* Qn);
 
 /* Algorithm 4 from the start Qh: one Newton-Schulz step, then passes of
@@ -81,11 +84,12 @@ void orc_ns_merged(int lp, int n, const orc_qc* Q, const orc_qc* W, int full, or
  * *iters the number of passes. Qout receives the final Q, Tout = triu(That) of
  * the last pass. Returns an ORC_* outcome.
  * Pinned by exact Schur forms (Walsh-Hadamard test matrices), brute force at
- * small n and the quadratic decrease of eps (Theorem 2). */
+ * small n, the quadratic decrease of eps (Theorem 2), and a start rotated far
+ * from the Schur basis for the DIVERGED rule. */
 int orc_refine(int lp, int n, const orc_qc* A, const orc_qc* Qh, int maxit, double tol,
                int flags, orc_qc* Qout, orc_qc* Tout, double* hist, int* iters);
 
-/* Evaluation in hp of a computed pair (Q, T) for A (Section 4's checks):
+/* Evaluation in hp of a computed pair (Q, T) for A (the checks of Section 3):
  * out[0] = ||stril(Q^H A Q)||_F / ||A||_F, out[1] = ||Q^H Q - I||_F,
  * out[2] = ||T - triu(Q^H A Q)||_F (0 when T is NULL), out[3] = ||A||_F. */
 void orc_eval(int n, const orc_qc* A, const orc_qc* Q, const orc_qc* T, double out[4]);
@@ -106,7 +110,7 @@ void orc_eval_rows(int n, const orc_qc* A, const orc_qc* Q, int nr, const int* r
  * matrices with known spectrum. */
 int orc_schur_qr(int lp, int n, const orc_qc* A, orc_qc* Z, orc_qc* S);
 
-/* Reordering of the start (Section 4, the paragraph on Algorithm 4's first step):
+/* Reordering of the start (Section 2.4, the paragraph on the solve of Algorithm 4's loop):
  * the Schur form T = triu(Qh^H A Qh) is reordered by unitary swaps of adjacent
  * diagonal entries so that the eigenvalues appear in increasing order of their
  * projection Re(lambda e^{-i theta}) onto the line with direction e^{i theta}

@@ -1,5 +1,5 @@
 // Ozaki-style split product on CDNA4 INT8 matrix cores: the high-precision
-// products of the refinement (the paper's Section 4 obtains them from an
+// products of the refinement (the paper's Section 3 obtains them from an
 // Ozaki-scheme toolbox) computed from 8-bit slices with exact 32-bit integer
 // accumulation.
 //

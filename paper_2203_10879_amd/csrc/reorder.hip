@@ -1,4 +1,4 @@
-// Reordering of the start (Section 4, the paragraph on the first step of
+// Reordering of the start (Section 2.4, the paragraph on the reordering of
 // Algorithm 4): the Schur form T = triu(Qh^H A Qh) of the lp start is reordered by
 // unitary swaps of adjacent diagonal entries so that the eigenvalues follow the
 // order of their projections Re(lambda e^{-i theta}) onto a line with direction

@@ -4,7 +4,7 @@ Every generator is deterministic in its seed. Matrices come back as complex128
 numpy arrays in column-major (Fortran) order, which is the storage order of the
 library's C interface.
 
-Workloads follow the shape of the paper's dense random experiments (Section 4,
+Workloads follow the shape of the paper's dense random experiments (Section 3,
 Example 2): A = Q0 T0 Q0^H with a Haar-random unitary Q0 and an upper
 triangular T0 whose diagonal holds gap-separated complex normal eigenvalues.
 The starting basis is the Schur basis of the matrix rounded to a lower
@@ -163,7 +163,7 @@ def round_mantissa(x: np.ndarray, bits: int) -> np.ndarray:
 
 
 def wilkinson_companion_dd(n: int = 20):
-    """Companion matrix of prod_{i=1..n} (x - i) (Section 4, Example 1), first row
+    """Companion matrix of prod_{i=1..n} (x - i) (Section 3, Example 1), first row
     -c[1:], ones on the subdiagonal. The integer coefficients reach 20! > 2**53,
     so the matrix is returned exactly as a double-double pair (hi, lo)."""
     coeffs = [1]
@@ -188,7 +188,7 @@ def wilkinson_companion_dd(n: int = 20):
 
 def example3_matrix(n: int = 150, seed: int = 0, cond_x: float = 1e5,
                     radius: float = 1e-5, clusters: int = 2, size: int = 10) -> dict:
-    """A = X D X^{-1} (Section 4, Example 3): X random with condition number
+    """A = X D X^{-1} (Section 3, Example 3): X random with condition number
     cond_x (singular values log-spaced), D real diagonal uniform in [-10, 10]
     except for `clusters` groups of `size` eigenvalues within `radius` of a
     random centre."""

@@ -1,6 +1,6 @@
-"""Reordering of the start on the GPU (Section 4, the paragraph on the first step
+"""Reordering of the start on the GPU (Section 2.4, the paragraph on the reordering
 of Algorithm 4) against the binary128 oracle, and the clustered-spectrum example
-(Section 4, Example 3) as an acceptance test of the double-double tier."""
+(Section 3, Example 3) as an acceptance test of the double-double tier."""
 import numpy as np
 import pytest
 

@@ -1,4 +1,4 @@
-"""The oracle against the paper's worked examples (Section 4)."""
+"""The oracle against the paper's worked examples (Section 3)."""
 import os
 from fractions import Fraction
 

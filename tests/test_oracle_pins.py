@@ -180,6 +180,88 @@ def test_trisolve_truncation_device():
     assert not l.to_c128().any()
 
 
+def _fraction_trisolve(t, e, trunc):
+    """Algorithm 2 in exact rational arithmetic, written out from eq. (9) (column
+    index of L read as j), with the large-entry device of Example 4: an entry whose
+    modulus exceeds trunc is set to zero as soon as it is computed, before any later
+    entry uses it."""
+    n = t.shape[0]
+    fr = lambda z: (Fraction(z.real), Fraction(z.imag))
+    T = [[fr(t[i, j]) for j in range(n)] for i in range(n)]
+    E = [[fr(e[i, j]) for j in range(n)] for i in range(n)]
+    zero = (Fraction(0), Fraction(0))
+    L = [[zero] * n for _ in range(n)]
+    mul = lambda a, b: (a[0] * b[0] - a[1] * b[1], a[0] * b[1] + a[1] * b[0])
+    for j in range(n - 1):
+        for i in range(n - 1, j, -1):
+            s = E[i][j]
+            for k in range(i + 1, n):
+                p = mul(T[i][k], L[k][j])
+                s = (s[0] + p[0], s[1] + p[1])
+            for k in range(j):
+                p = mul(L[i][k], T[k][j])
+                s = (s[0] - p[0], s[1] - p[1])
+            d = (T[i][i][0] - T[j][j][0], T[i][i][1] - T[j][j][1])
+            den = d[0] * d[0] + d[1] * d[1]
+            l = (-(s[0] * d[0] + s[1] * d[1]) / den, -(s[1] * d[0] - s[0] * d[1]) / den)
+            if l[0] * l[0] + l[1] * l[1] > Fraction(trunc) ** 2:
+                l = zero
+            L[i][j] = l
+    # double-double rounding of the exact result: (hi, lo) with hi + lo = L to ~2^-106
+    def dd(x):
+        h = float(x)
+        return h, float(x - Fraction(h))
+    hi = np.zeros((n, n), dtype=np.complex128)
+    lo = np.zeros((n, n), dtype=np.complex128)
+    for i in range(n):
+        for j in range(n):
+            (rh, rl), (ih, il) = dd(L[i][j][0]), dd(L[i][j][1])
+            hi[i, j], lo[i, j] = complex(rh, ih), complex(rl, il)
+    return hi, lo
+
+
+def truncation_case(n, seed):
+    """T with O(1) off-diagonal entries and separated diagonal; E of size 1e-8 except
+    for entries early in every admissible order (bottom-left corner and one inside)
+    whose L entries are far above 1e-5. Every other entry of L then depends on
+    whether those are zeroed as computed or only afterwards."""
+    rng = np.random.default_rng(seed)
+    t = np.triu(_rand_c(rng, (n, n))) / np.sqrt(2)
+    t[np.diag_indices(n)] = np.arange(1, n + 1) * (1.0 + 0.5j)
+    e = np.tril(1e-8 * _rand_c(rng, (n, n)), -1)
+    e[n - 1, 0] = 0.5
+    e[n - 2, 1] = 0.3 - 0.2j
+    e[(2 * n) // 3, n // 3] = 0.2j
+    return np.asfortranarray(t), np.asfortranarray(e)
+
+
+def test_trisolve_truncation_as_computed():
+    """Example 4's device zeroes an entry of L while L is being computed, so entries
+    computed later see the zero. Pinned against exact rational substitution that
+    zeroes immediately; zeroing the large entries after the solve gives a different
+    L (here the large entries drag every entry that depends on them above 1e-5)."""
+    n, trunc = 10, 1e-5
+    t, e = truncation_case(n, 2)
+    ref, ref_lo = _fraction_trisolve(t, e, trunc)
+    assert np.count_nonzero(np.tril(ref, -1)) >= n * (n - 1) // 2 - 4  # small entries survive
+    lo = np.abs(ref[np.tril_indices(n, -1)])
+    assert np.all((lo == 0) | (lo < 0.1 * trunc))  # no entry near the threshold
+    l, st = oracle.trisolve(t, e, lp="quad", trunc=trunc)
+    assert st == "OK"
+    hi_, lo_ = l.to_dd()
+    assert np.abs((hi_ - ref) + (lo_ - ref_lo)).max() <= 1e-30 * np.abs(ref).max()
+    # the float solve takes the same zeroing decisions
+    lf, _ = oracle.trisolve(t, e, lp="float", trunc=trunc)
+    lf = lf.to_c128()
+    assert np.array_equal(lf == 0, ref == 0)
+    assert np.abs(lf - ref).max() <= 1e-5 * np.abs(ref).max()
+    # zeroing after the fact is a different device
+    full, _ = oracle.trisolve(t, e, lp="quad")
+    full = full.to_c128()
+    after = np.where(np.abs(full) > trunc, 0, full)
+    assert np.abs(after - ref).max() >= 0.1 * np.abs(ref).max()
+
+
 # ----------------------------------------------------------- orthogonalising ----
 
 def _near_unitary(rng, n, size):
@@ -233,6 +315,44 @@ def test_merged_update_truncation_error():
     expect = -0.5 * q @ (w @ w @ y + w @ w @ y @ w)
     assert np.linalg.norm(diff - expect) <= 1e-9 * np.linalg.norm(expect)
     assert np.linalg.norm(expect) > 1e-9
+
+
+@pytest.mark.parametrize("lp,u", [("float", 2.0 ** -24), ("double", 2.0 ** -53)])
+def test_merged_update_products_in_lp(lp, u):
+    """Algorithm 4 forms YW, W^2 and W^3 in lp (and sums in hp): the result differs
+    from the all-hp update by the lp rounding of those products, no less (a product
+    formed in hp would give no difference) and no more (first-order bound of an lp
+    product: operands rounded once, dot products of length n)."""
+    rng = np.random.default_rng(9)
+    n = 24
+    q, _ = np.linalg.qr(_rand_c(rng, (n, n)))
+    q = np.asfortranarray(q + 1e-3 * _rand_c(rng, (n, n)) / np.sqrt(n))
+    w = _skew(rng, n, 3e-2)
+    rh, rl = oracle.ns_merged(q, w, lp="quad").to_dd()
+    h, l = oracle.ns_merged(q, w, lp=lp).to_dd()
+    d = np.linalg.norm((h - rh) + (l - rl))
+    y = q.conj().T @ q - np.eye(n)
+    w2 = w @ w
+    size = np.linalg.norm(y @ w) + np.linalg.norm(w2) + np.linalg.norm(w2 @ w)
+    absb = (np.linalg.norm(np.abs(y) @ np.abs(w)) + np.linalg.norm(np.abs(w) @ np.abs(w))
+            + np.linalg.norm(np.abs(w2) @ np.abs(w)))
+    upper = 0.5 * np.linalg.norm(q, 2) * np.sqrt(2) * (n + 4) * u * absb
+    assert 0.05 * u * size <= d <= upper, (d / (u * size), d / upper)
+
+
+def test_merged_update_lp_precision_scales_with_u():
+    rng = np.random.default_rng(10)
+    n = 16
+    q, _ = np.linalg.qr(_rand_c(rng, (n, n)))
+    q = np.asfortranarray(q + 1e-3 * _rand_c(rng, (n, n)) / np.sqrt(n))
+    w = _skew(rng, n, 3e-2)
+    rh, rl = oracle.ns_merged(q, w, lp="quad").to_dd()
+    d = {}
+    for lp in ("float", "double"):
+        h, l = oracle.ns_merged(q, w, lp=lp).to_dd()
+        d[lp] = np.linalg.norm((h - rh) + (l - rl))
+    ratio = d["float"] / d["double"] / 2.0 ** 29  # u32 / u64
+    assert 0.1 <= ratio <= 10, ratio
 
 
 # -------------------------------------------------------------- Algorithm 4 ----
@@ -332,6 +452,34 @@ def test_refine_iteration_cap_and_counts():
     qh = synth.lp_schur_start(g["A"])
     r = oracle.refine(g["A"], qh, lp="float", maxit=1, tol=1e-30)
     assert r["status"] == "NOT_CONVERGED" and r["iters"] == 1
+
+
+def _rotated_start(q0, seed, delta):
+    """q0 exp(H) with H skew-Hermitian of size delta: a unitary start rotated away
+    from the Schur basis."""
+    rng = np.random.default_rng(seed)
+    n = q0.shape[0]
+    x = delta * _rand_c(rng, (n, n))
+    h = (x - x.conj().T) / 2
+    w, v = np.linalg.eigh(1j * h)
+    return np.asfortranarray(q0 @ (v @ np.diag(np.exp(-1j * w)) @ v.conj().T))
+
+
+def test_refine_diverged_rule():
+    """Reading of the stopping rule: DIVERGED when the residual rose on two
+    consecutive passes. A start rotated far (0.15) from the Schur basis makes the
+    residual wander: single rises followed by a fall do not stop the iteration, the
+    first pair of consecutive rises does."""
+    g = synth.schur_test_matrix(8, seed=5)
+    qh = _rotated_start(g["Q0"], 5, 0.15)
+    r = oracle.refine(g["A"], qh, lp="float", maxit=14, tol=1e-30)
+    h = r["hist"]
+    assert r["status"] == "DIVERGED"
+    triples = [p for p in range(2, len(h)) if h[p] > h[p - 1] > h[p - 2]]
+    assert triples == [len(h) - 1] and r["iters"] == len(h)
+    isolated = [p for p in range(1, len(h) - 2) if h[p] > h[p - 1] and h[p + 1] < h[p]]
+    assert isolated, h  # a single rise that did not stop it
+    assert r["iters"] < 14
 
 
 def test_refine_nan_input_breaks_down():

@@ -1,4 +1,4 @@
-"""Pins of the oracle's reordering of the start (Section 4, the paragraph on the
+"""Pins of the oracle's reordering of the start (Section 2.4, the paragraph on the
 first step of Algorithm 4: the lp Schur form is reordered so that clustered
 eigenvalues sit next to each other, in the order of their projections onto a
 random line). The reordered Schur form with a given diagonal order is unique up
