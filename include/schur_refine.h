@@ -215,6 +215,23 @@ int sr_residual(const void* A, const void* Q, int n, void* T, void* T_lp, void* 
 int sr_trisolve(const void* T_lp, const void* E_lp, void* L_lp, int n, float trunc,
                 void* ws, void* stream);
 
+/* The FP32 solve of sr_trisolve without allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc). Same kernels and the same result as sr_trisolve (bit
+ * for bit), but its scratch (the partial sums passed between the solve's launches)
+ * is a fixed device array inside the library, one per GPU, kept until the process
+ * ends, and the call never synchronises.
+ *  T_lp, E_lp, L_lp, n, trunc: as for sr_trisolve (device, complex64 n x n).
+ *  status (device, one unsigned, caller-owned): cleared by the call, then set to a
+ *    nonzero value if two diagonal entries of T coincide or a non-finite value
+ *    appears (sr_trisolve's SR_BREAKDOWN); read it after the stream has run.
+ *  n must be <= 4096 (the array holds 20 MiB): larger n returns SR_ENOMEM without
+ *  launching anything; null pointers or n < 1 return SR_EINVAL.
+ * Every call on one GPU uses the same array, so calls that may overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller. */
+int sr_trisolve_static(const void* T_lp, const void* E_lp, void* L_lp, int n, float trunc,
+                       unsigned* status, void* stream);
+
 /* Reordering of the start (Section 2.4, the paragraph on the reordering of
  * Algorithm 4: clustered eigenvalues are moved next to each other, in the order of
  * their projections onto a random line). A: complex128 n x n (read); Q: complex128

@@ -75,6 +75,7 @@ _SIGS = {
     "sr_residual": (_i, [_vp, _vp, _i, _vp, _vp, _vp, ctypes.POINTER(_d), _i, _vp, _vp]),
     "sr_trisolve": (_i, [_vp, _vp, _vp, _i, _f, _vp, _vp]),
     "sr_trisolve64": (_i, [_vp, _vp, _vp, _i, _vp, _vp]),
+    "sr_trisolve_static": (_i, [_vp, _vp, _vp, _i, _f, _vp, _vp]),
     "sr_reorder_ws_bytes": (_sz, [_i]),
     "sr_reorder_start": (_i, [_vp, _vp, _i, ctypes.c_double, _vp, _vp, _sz, _vp]),
     "sr_update": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.POINTER(_d), _vp, _vp]),
@@ -330,6 +331,20 @@ def sr_trisolve(T_lp, E_lp, L_lp, ws, trunc: float = 0.0, stream=None) -> int:
     return lib().sr_trisolve(_mat(T_lp, "c64", n, n), _mat(E_lp, "c64", n, n),
                              _mat(L_lp, "c64", n, n), n, float(trunc),
                              ctypes.c_void_p(ws.data_ptr()), _stream(stream))
+
+
+def sr_trisolve_static(T_lp, E_lp, L_lp, status, trunc: float = 0.0, stream=None) -> int:
+    """The no-allocation solve: status is a device int32 tensor of one element
+    (cleared, then nonzero on breakdown)."""
+    import torch
+
+    n = T_lp.shape[0]
+    if not (isinstance(status, torch.Tensor) and status.is_cuda and status.dtype == torch.int32
+            and status.numel() >= 1):
+        raise TypeError("status must be an int32 CUDA tensor")
+    return lib().sr_trisolve_static(_mat(T_lp, "c64", n, n), _mat(E_lp, "c64", n, n),
+                                    _mat(L_lp, "c64", n, n), n, float(trunc),
+                                    ctypes.c_void_p(status.data_ptr()), _stream(stream))
 
 
 def sr_trisolve64(T, E, L, ws, stream=None) -> int:
