@@ -85,6 +85,16 @@ typedef struct {
                              bytes, or NULL to let the library allocate and cache one  */
   size_t workspace_bytes;
   void* stream;           /* hipStream_t                                               */
+  int strict_stop;        /* 1: a pass with residual <= tol ends the refinement only
+                             after at least one update whose correction was
+                             negligible to second order, ||W||_F^2 <= u_hp (u_hp =
+                             2^-53, or 2^-104 in the double-double tier); until then
+                             passes continue (no stagnation or divergence test while
+                             the residual is below tol). For matrices whose entries
+                             span many orders of magnitude (graded, companion), where
+                             the normwise residual reaches tol, even at the start,
+                             while small parts of Q still move.
+                             0 (default): the residual alone decides                 */
 } sr_opts;
 
 typedef struct {
@@ -107,6 +117,13 @@ typedef struct {
                              the Hermitian products Y = Q^H Q - I, which form only the
                              tiles on and above the diagonal (half the work)          */
   float ms_hp_gemm_herm;  /* with opts.timing: the part of ms_hp_gemm they took        */
+  float ms_oz_full;       /* with opts.timing in an Ozaki mode: time of the full n x n x n
+                             split products with opts->slices digits per operand (P =
+                             A Q in every pass; That too with SR_GEMM_OZAKI_I8_ALL),
+                             the INT8 product kernel alone (its digit splits are in
+                             ms_hp_gemm only)                                          */
+  int oz_full_launches;   /* number of launches timed in ms_oz_full                     */
+  int oz_full_pairs;      /* slice pairs per such launch (s + t <= slices + 1)          */
 } sr_info;
 
 /* Default options: FP64 MFMA, compensated accumulation on, gating on, no trunc. */
@@ -135,11 +152,14 @@ int schur_refine(const void* A, void* Q, void* T, int n, int iters, double tol,
  *  (the ms_* fields are not filled).
  *  Each pass runs as one fixed sequence of grouped launches over the whole batch
  *  (persistent tile-table products, the solve by tile diagonal across the batch,
- *  one block per matrix for the elementwise steps) with device-side loop control; two passes are captured in a
- *  HIP graph and replayed. The tile edge (64 or 32) of each size bucket is chosen
- *  by timing both on the first batch that contains the bucket (kept for the
- *  process). opts->gemm must be SR_GEMM_FP64. The work is ordered after the
- *  caller's stream, and the call returns after it completed.
+ *  one block per matrix for the elementwise steps) with device-side loop control;
+ *  two passes are captured in a HIP graph and replayed (the graph is kept for the
+ *  next call, see sr_batched_graph_builds). The tile edge (64 or 32) of each size
+ *  bucket is chosen by timing both on the first batch that contains the bucket
+ *  (kept for the process). opts->gemm must be SR_GEMM_FP64. The work is ordered
+ *  after the caller's stream, and the call returns after it completed. With a
+ *  caller workspace the call allocates no device memory (one pinned host word per
+ *  host thread is made on the thread's first call).
  *  Returns the worst (largest) outcome over the batch, or a negative error. */
 int schur_refine_batched(int batch, const int* n, const void* const* A, void* const* Q,
                          void* const* T, int iters, double tol, const sr_opts* opts,
@@ -151,6 +171,13 @@ size_t sr_workspace_bytes_batched(int batch, const int* n, const sr_opts* opts);
 
 /* Tile edge the batched autotuner chose for matrices of size n (-1: not tuned). */
 int sr_batched_tile_edge(int n);
+
+/* Number of two-pass graphs schur_refine_batched has captured and instantiated in
+ * this process. A call with a caller-owned workspace keeps its graph (per host
+ * thread) and the next call on that thread replays it without a new capture when
+ * the workspace address, the sizes, the tile edges, iters, tol and the options are
+ * unchanged (the matrices' addresses may differ). */
+int sr_batched_graph_builds(void);
 
 /* Double-double tier (Section 3 refines to higher than working precision the same
  * way): A = A_hi + A_lo, Q = Q_hi + Q_lo, T = T_hi + T_lo (all device, complex128

@@ -32,7 +32,8 @@ class SrOpts(ctypes.Structure):
     _fields_ = [("gemm", ctypes.c_int), ("slices", ctypes.c_int), ("update_slices", ctypes.c_int),
                 ("compensated", ctypes.c_int), ("gate_lp_terms", ctypes.c_int),
                 ("trunc", ctypes.c_int), ("timing", ctypes.c_int), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p)]
+                ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
+                ("strict_stop", ctypes.c_int)]
 
 
 class SrInfo(ctypes.Structure):
@@ -43,7 +44,8 @@ class SrInfo(ctypes.Structure):
                 ("ms_total", ctypes.c_float), ("ms_hp_gemm", ctypes.c_float),
                 ("hp_gemm_launches", ctypes.c_int), ("ms_solve", ctypes.c_float),
                 ("update_slices_hist", ctypes.c_int * 16), ("hp_gemm_herm_launches", ctypes.c_int),
-                ("ms_hp_gemm_herm", ctypes.c_float)]
+                ("ms_hp_gemm_herm", ctypes.c_float), ("ms_oz_full", ctypes.c_float),
+                ("oz_full_launches", ctypes.c_int), ("oz_full_pairs", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         k = min(self.iters, 16)
@@ -56,7 +58,8 @@ class SrInfo(ctypes.Structure):
                 "hp_gemm_launches": self.hp_gemm_launches, "ms_solve": self.ms_solve,
                 "update_slices_hist": list(self.update_slices_hist[:min(u + 1, 16)]),
                 "hp_gemm_herm_launches": self.hp_gemm_herm_launches,
-                "ms_hp_gemm_herm": self.ms_hp_gemm_herm}
+                "ms_hp_gemm_herm": self.ms_hp_gemm_herm, "ms_oz_full": self.ms_oz_full,
+                "oz_full_launches": self.oz_full_launches, "oz_full_pairs": self.oz_full_pairs}
 
 
 # name -> (restype, argtypes); mirrors include/schur_refine.h
@@ -87,6 +90,7 @@ _SIGS = {
     "sr_workspace_bytes_dd": (_sz, [_i, ctypes.POINTER(SrOpts)]),
     "sr_workspace_bytes_batched": (_sz, [_i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SrOpts)]),
     "sr_batched_tile_edge": (_i, [_i]),
+    "sr_batched_graph_builds": (_i, []),
     "sr_diag_mfma": (_i, [_i, _vp, _vp, _vp]),
 }
 EXPORTS = tuple(_SIGS)
@@ -166,7 +170,7 @@ def _stream(stream):
 
 
 def make_opts(gemm="fp64", slices=0, update_slices=0, compensated=True, gate=True, trunc=False,
-              timing=False, workspace=None, stream=None) -> SrOpts:
+              timing=False, workspace=None, stream=None, strict_stop=False) -> SrOpts:
     o = SrOpts()
     lib().sr_default_opts(ctypes.byref(o))
     o.gemm = GEMM_MODES[gemm] if isinstance(gemm, str) else int(gemm)
@@ -176,6 +180,7 @@ def make_opts(gemm="fp64", slices=0, update_slices=0, compensated=True, gate=Tru
     o.gate_lp_terms = int(bool(gate))
     o.trunc = int(bool(trunc))
     o.timing = int(bool(timing))
+    o.strict_stop = int(bool(strict_stop))
     if workspace is not None:
         o.workspace = ctypes.c_void_p(workspace.data_ptr())
         o.workspace_bytes = workspace.numel() * workspace.element_size()

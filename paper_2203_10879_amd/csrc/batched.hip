@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -457,6 +458,51 @@ hipStream_t capture_stream() {
   return s;
 }
 
+// Pinned host slot for the device's count of matrices still refining, made once
+// per thread (the call reads it after every replay of the two-pass graph).
+int* host_counter() {
+  static thread_local int* h = nullptr;
+  if (!h && hipHostMalloc((void**)&h, sizeof(int), hipHostMallocDefault) != hipSuccess) h = nullptr;
+  return h;
+}
+
+// The instantiated two-pass graph of the last call on this thread, reused while
+// everything it bakes in is unchanged: the workspace address (every kernel
+// argument points into it; the per-matrix tables there are uploaded again on each
+// call, so the matrices' own addresses may change), the sizes and tile edges (the
+// grids and table offsets), the pass limit, tol and the options. Only calls with
+// a caller-owned workspace keep their graph.
+struct GraphKey {
+  int dev = -1;
+  const void* base = nullptr;
+  std::vector<int> n, bm;
+  int iters = 0, comp = 0, gate = 0;
+  double tol = 0;
+  float trunc = 0;
+  bool operator==(const GraphKey& o) const {
+    return dev == o.dev && base == o.base && n == o.n && bm == o.bm && iters == o.iters && comp == o.comp &&
+           gate == o.gate && tol == o.tol && trunc == o.trunc;
+  }
+};
+struct GraphCache {
+  GraphKey key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void clear() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key = GraphKey();
+  }
+  ~GraphCache() { clear(); }
+};
+GraphCache& graph_cache() {
+  static thread_local GraphCache c;
+  return c;
+}
+std::atomic<int> g_graph_builds{0};
+
 }  // namespace
 }  // namespace sr
 
@@ -647,38 +693,66 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
     if (G.z(T_NSU, 0, EPI_ADD, 0, active) != hipSuccess) { fail(SR_EHIP); break; }
     if (hipGetLastError() != hipSuccess) { fail(SR_EHIP); break; }
 
-    // capture two passes
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) { fail(SR_EHIP); break; }
-    bool cap_ok = true;
-    for (int e = 0; e < 2 && cap_ok; e++) {
-      hipLaunchKernelGGL(b_pass_start_kernel, dim3(small), dim3(256), 0, st, states, batch, counter);
-      cap_ok = G.z(T_P + 4 * e, 0, EPI_STORE, comp, active) == hipSuccess &&
-               G.z(T_T + 4 * e, 0, EPI_SPLIT, comp, active) == hipSuccess;
-      if (!cap_ok) break;
-      hipLaunchKernelGGL(b_decide_kernel, dim3(batch), dim3(BNT), 0, st, mats_dev, states, active, partials,
-                         iters, tol, counter);
-      const float tr = o.trunc ? 1e-5f : 0.f;
-      cap_ok = (by_steps ? trisolve_batched_steps(w + L.tri, (const TriStepTile*)(w + L.steps), step_off.data(),
-                                                  nsteps, tr, st)
-                         : trisolve_batched(w + L.tri, batch, tr, st)) == hipSuccess &&
-               G.z(T_Y + 4 * e, 0, EPI_YDEF, comp, active) == hipSuccess;
-      if (!cap_ok) break;
-      hipLaunchKernelGGL(b_post_kernel, dim3(batch), dim3(BNT), 0, st, mats_dev, states, active, partials,
-                         o.gate_lp_terms ? 1 : 0, act_w2, act_w3, act_yw);
-      cap_ok = G.c(T_W2, act_w2) == hipSuccess && G.c(T_W3, act_w3) == hipSuccess &&
-               G.c(T_YW, act_yw) == hipSuccess;
-      if (!cap_ok) break;
-      hipLaunchKernelGGL(b_delta_kernel, dim3(batch), dim3(BNT), 0, st, mats_dev, states, active);
-      cap_ok = G.z(T_U + 4 * e, 0, EPI_ADD, 0, active) == hipSuccess;
-      hipLaunchKernelGGL(b_flip_kernel, dim3(small), dim3(256), 0, st, states, active, batch);
+    // the two-pass graph: reused from the last call on this thread when nothing it
+    // depends on changed, otherwise captured anew
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) { fail(SR_EHIP); break; }
+    GraphKey key;
+    key.dev = dev;
+    key.base = base;
+    key.n.assign(n, n + batch);
+    key.bm = bm;
+    key.iters = iters;
+    key.comp = comp;
+    key.gate = o.gate_lp_terms ? 1 : 0;
+    key.tol = tol;
+    key.trunc = o.trunc ? 1e-5f : 0.f;
+    GraphCache& gc = graph_cache();
+    const bool reuse = !owned && gc.exec && gc.key == key;
+    if (reuse) {
+      exec = gc.exec;
+    } else {
+      if (!owned) gc.clear();
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) { fail(SR_EHIP); break; }
+      bool cap_ok = true;
+      for (int e = 0; e < 2 && cap_ok; e++) {
+        hipLaunchKernelGGL(b_pass_start_kernel, dim3(small), dim3(256), 0, st, states, batch, counter);
+        cap_ok = G.z(T_P + 4 * e, 0, EPI_STORE, comp, active) == hipSuccess &&
+                 G.z(T_T + 4 * e, 0, EPI_SPLIT, comp, active) == hipSuccess;
+        if (!cap_ok) break;
+        hipLaunchKernelGGL(b_decide_kernel, dim3(batch), dim3(BNT), 0, st, mats_dev, states, active, partials,
+                           iters, tol, counter);
+        const float tr = o.trunc ? 1e-5f : 0.f;
+        cap_ok = (by_steps ? trisolve_batched_steps(w + L.tri, (const TriStepTile*)(w + L.steps), step_off.data(),
+                                                    nsteps, tr, st)
+                           : trisolve_batched(w + L.tri, batch, tr, st)) == hipSuccess &&
+                 G.z(T_Y + 4 * e, 0, EPI_YDEF, comp, active) == hipSuccess;
+        if (!cap_ok) break;
+        hipLaunchKernelGGL(b_post_kernel, dim3(batch), dim3(BNT), 0, st, mats_dev, states, active, partials,
+                           o.gate_lp_terms ? 1 : 0, act_w2, act_w3, act_yw);
+        cap_ok = G.c(T_W2, act_w2) == hipSuccess && G.c(T_W3, act_w3) == hipSuccess &&
+                 G.c(T_YW, act_yw) == hipSuccess;
+        if (!cap_ok) break;
+        hipLaunchKernelGGL(b_delta_kernel, dim3(batch), dim3(BNT), 0, st, mats_dev, states, active);
+        cap_ok = G.z(T_U + 4 * e, 0, EPI_ADD, 0, active) == hipSuccess;
+        hipLaunchKernelGGL(b_flip_kernel, dim3(small), dim3(256), 0, st, states, active, batch);
+      }
+      const hipError_t ce = hipStreamEndCapture(st, &graph);
+      if (!cap_ok || ce != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        fail(SR_EHIP);
+        break;
+      }
+      g_graph_builds++;
+      if (!owned) {
+        // kept for the next call on this thread
+        gc.key = key;
+        gc.graph = graph;
+        gc.exec = exec;
+        graph = nullptr;
+      }
     }
-    const hipError_t ce = hipStreamEndCapture(st, &graph);
-    if (!cap_ok || ce != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-      fail(SR_EHIP);
-      break;
-    }
-    int* hcount = nullptr;
-    if (hipHostMalloc((void**)&hcount, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    int* hcount = host_counter();
+    if (!hcount) {
       fail(SR_ENOMEM);
       break;
     }
@@ -691,7 +765,6 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
       }
       if (*hcount == 0) break;
     }
-    hipHostFree(hcount);
     if (rc != SR_OK) break;
     hipLaunchKernelGGL(b_finish_kernel, dim3(batch), dim3(BNT), 0, st, mats_dev, states);
     std::vector<BState> hs(batch);
@@ -724,7 +797,8 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
     // the caller's stream continues after this call's work
     if (hipEventRecord(ev, st) != hipSuccess || hipStreamWaitEvent(user, ev, 0) != hipSuccess) fail(SR_EHIP);
   } while (false);
-  if (exec) hipGraphExecDestroy(exec);
+  // a graph kept in the thread's cache is destroyed when it is replaced
+  if (exec && exec != graph_cache().exec) hipGraphExecDestroy(exec);
   if (graph) hipGraphDestroy(graph);
   hipEventDestroy(ev);
   if (owned) {
@@ -733,6 +807,9 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
   }
   return rc;
 }
+
+// Two-pass graphs captured and instantiated so far in this process.
+int sr_batched_graph_builds(void) { return g_graph_builds.load(); }
 
 // Bucket -> tile edge chosen so far (-1: not tuned yet); for reports and tests.
 int sr_batched_tile_edge(int n) {

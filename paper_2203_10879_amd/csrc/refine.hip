@@ -150,19 +150,40 @@ int read_back(hipStream_t st, const Work& w, int count, double* out, unsigned* s
   return SR_OK;
 }
 
-// Side stream for the Hermitian product Y beside the solve: one per device, created
-// on first use (non-blocking, default priority) and kept for the process.
+// Side stream for the Hermitian product Y beside the solve: one per (device,
+// caller stream), created on first use (non-blocking, default priority) and kept
+// for the process, so that calls on different streams never share one. After
+// kMaxSideStreams distinct pairs no more are made and Y runs on the caller's
+// stream (NULL return).
 constexpr int kSideYMaxN = 2048, kSideYMaxNdd = 2048;
-hipStream_t side_stream() {
+constexpr size_t kMaxSideStreams = 64;
+hipStream_t side_stream(hipStream_t caller) {
+  struct Entry {
+    int dev;
+    hipStream_t caller, side;
+  };
   static std::mutex mu;
-  static hipStream_t streams[64] = {};
+  static std::vector<Entry> tab;
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   std::lock_guard<std::mutex> lock(mu);
-  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
-    streams[dev] = nullptr;
-  return streams[dev];
+  for (const Entry& e : tab)
+    if (e.dev == dev && e.caller == caller) return e.side;
+  if (tab.size() >= kMaxSideStreams) return nullptr;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  tab.push_back({dev, caller, s});
+  return s;
 }
+
+// Events of one refinement call, released on every return path.
+struct CallEvents {
+  hipEvent_t t0 = nullptr, t1 = nullptr, fork = nullptr, join = nullptr;
+  ~CallEvents() {
+    for (hipEvent_t e : {t0, t1, fork, join})
+      if (e) hipEventDestroy(e);
+  }
+};
 
 GemmArgs gargs(int m, int n, int k, const void* A, long lda, const void* B, long ldb, void* C,
                long ldc) {
@@ -187,11 +208,12 @@ GemmArgs gargs(int m, int n, int k, const void* A, long lda, const void* B, long
   } while (0)
 
 // Optional HIP-event timing of launch groups on the call's stream:
-// category 0 = hp products, 1 = triangular solves.
+// category 0 = hp products, 1 = triangular solves, 2 = the full split products
+// with the main digit count (product kernel alone, inside a category-0 group).
 struct Timer {
   hipStream_t st = nullptr;
-  std::vector<hipEvent_t> ev[2];
-  int count[2] = {0, 0};
+  std::vector<hipEvent_t> ev[3];
+  int count[3] = {0, 0, 0};
   int herm = 0;                  // timed hp products that were Hermitian (Y)
   std::vector<char> herm_pair;   // per event pair of channel 0
   void mark(int c) {
@@ -326,7 +348,9 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
   if (w.oz_s) {
     const int S = w.oz_s;
     CK(oz_split_cols(Q, nullptr, n, n, n, S, w.sQc, w.eQc, st));
+    TIC(tm, 2);
     CK(oz_gemm(EPI_STORE, w.sA, w.eA, S, w.sQc, w.eQc, S, 0, S + 1, g, w.oz_scratch, st));
+    TOC(tm, 2);
   } else {
     CK(zgemm(0, EPI_STORE, comp, g, st));
   }
@@ -335,7 +359,9 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
     const int S = w.oz_s;
     TIC(tm, 0);
     CK(oz_split_cols(w.P, nullptr, n, n, n, S, w.sD, w.eD, st));
+    TIC(tm, 2);
     CK(oz_gemm(EPI_SPLIT, w.sQc, w.eQc, S, w.sD, w.eD, S, 1, S + 1, s, w.oz_scratch, st));
+    TOC(tm, 2);
     TOC(tm, 0);
     CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, false, false, S, S, S + 1), w.scal + 1, st));
     return SR_OK;
@@ -475,6 +501,25 @@ int get_ws(const sr_opts& o, size_t need, void** out) {
   return SR_OK;
 }
 
+// Outcome of a pass from its residual eps (-1: go on). eps1, eps2: the residuals
+// of the two passes before (-1 if none); nw_last: ||W||_F of the last update.
+// With opts.strict_stop, eps <= tol also needs an update to have been made and its
+// correction to have been negligible to second order (||W||^2 <= u, so that the
+// next one would fall below roundoff): on matrices whose entries span many orders
+// of magnitude the normwise residual reaches tol (even at the start) while the
+// small parts of Q still move. While eps <= tol waits for that, the divergence
+// and stagnation tests are not applied.
+int stop_test(const sr_opts& o, double eps, double tol, double eps1, double eps2, int updates,
+              double nw_last, double u, int n) {
+  if (eps <= tol) {
+    if (!o.strict_stop || (updates > 0 && nw_last * nw_last <= u)) return SR_OK;
+    return -1;
+  }
+  if (eps2 >= 0 && eps > eps1 && eps1 > eps2) return SR_DIVERGED;
+  if (eps1 >= 0 && eps > 0.5 * eps1 && eps < 100.0 * u * sqrt((double)n)) return SR_STAGNATED;
+  return -1;
+}
+
 void info_init(sr_info* info) {
   if (info) memset(info, 0, sizeof(*info));
 }
@@ -511,8 +556,8 @@ const char* sr_status_string(int s) {
   }
 }
 
-int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double tol,
-                 const sr_opts* opts_in, sr_info* info) {
+static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, double tol,
+                       const sr_opts* opts_in, sr_info* info) {
   info_init(info);
   if (!A_ || !Q_ || !T_ || n < 1 || iters < 1 || !(tol > 0)) {
     if (info) info->status = SR_EINVAL;
@@ -570,24 +615,23 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
   Timer timer;
   timer.st = st;
   Timer* tm = o.timing ? &timer : nullptr;
-  hipEvent_t e0, e1;
-  CK(hipEventCreate(&e0));
-  CK(hipEventCreate(&e1));
-  CK(hipEventRecord(e0, st));
+  CallEvents ev;
+  CK(hipEventCreate(&ev.t0));
+  CK(hipEventCreate(&ev.t1));
+  CK(hipEventRecord(ev.t0, st));
   CK(fill_zero(w.status, 256, st));
   CK(fro2_partials(A, (long)n * n, w.partials, 1024, st));
   CK(reduce_partials(w.partials, 1024, w.scal, st));
 
   int status = SR_NOT_CONVERGED;
   int passes = 0, updates = 0, nprod = 0;
-  double eps = 0, eps1 = -1, eps2 = -1, orth = 0;
+  double eps = 0, eps1 = -1, eps2 = -1, orth = 0, nw_last = 0;
   zc* cur = w.Qa;
   zc* other = Q;
-  hipStream_t sst = n <= kSideYMaxN ? side_stream() : nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t sst = n <= kSideYMaxN ? side_stream(st) : nullptr;
   if (sst) {
-    CK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-    CK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&ev.join, hipEventDisableTiming));
   }
   if (w.oz_s) CK(oz_split_rows(A, nullptr, n, n, n, w.oz_s, w.sA, w.eA, st));
   int su = 0;
@@ -609,16 +653,9 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
       status = SR_BREAKDOWN;
       break;
     }
-    if (eps <= tol) {
-      status = SR_OK;
-      break;
-    }
-    if (eps2 >= 0 && eps > eps1 && eps1 > eps2) {
-      status = SR_DIVERGED;
-      break;
-    }
-    if (eps1 >= 0 && eps > 0.5 * eps1 && eps < 100.0 * kU64 * sqrt((double)n)) {
-      status = SR_STAGNATED;
+    const int stop = stop_test(o, eps, tol, eps1, eps2, updates, nw_last, kU64, n);
+    if (stop >= 0) {
+      status = stop;
       break;
     }
     eps2 = eps1;
@@ -632,19 +669,19 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
     // the two run one after the other.
     const bool side = sst && n <= kSideYMaxN;
     if (side) {
-      CK(hipEventRecord(ev_fork, st));
-      CK(hipStreamWaitEvent(sst, ev_fork, 0));
+      CK(hipEventRecord(ev.fork, st));
+      CK(hipStreamWaitEvent(sst, ev.fork, 0));
       hipStream_t keep = tm ? tm->st : nullptr;
       if (tm) tm->st = sst;
       rc = ydef(cur, QH, n, comp, w, sst, tm);
       if (tm) tm->st = keep;
       if (rc != SR_OK) return rc;
-      CK(hipEventRecord(ev_join, sst));
+      CK(hipEventRecord(ev.join, sst));
     }
     TIC(tm, 1);
     CK(trisolve(w.Tlp, w.Elp, w.Llp, n, o.trunc ? 1e-5f : 0.f, w.tri, w.status, st));
     TOC(tm, 1);
-    if (side) CK(hipStreamWaitEvent(st, ev_join, 0));
+    if (side) CK(hipStreamWaitEvent(st, ev.join, 0));
     else if ((rc = ydef(cur, QH, n, comp, w, st, tm)) != SR_OK) return rc;
     CK(form_w(w.Llp, w.W, n, w.partials, st));
     CK(reduce_partials(w.partials, form_w_parts(n), w.scal + 3, st));
@@ -656,6 +693,7 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
     }
     const double ny = sqrt(nrm[2]), nw = sqrt(nrm[3]);
     orth = ny;
+    nw_last = nw;
     if (info && updates < 16) info->norm_w_hist[updates] = nw;
     if (!isfinite(ny) || !isfinite(nw)) {
       status = SR_BREAKDOWN;
@@ -671,14 +709,10 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
     updates++;
   }
   if (cur != Q) CK(hipMemcpyAsync(Q, cur, (size_t)n * n * sizeof(zc), hipMemcpyDeviceToDevice, st));
-  CK(hipEventRecord(e1, st));
-  CK(hipEventSynchronize(e1));
+  CK(hipEventRecord(ev.t1, st));
+  CK(hipEventSynchronize(ev.t1));
   float ms = 0;
-  hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  if (ev_fork) hipEventDestroy(ev_fork);
-  if (ev_join) hipEventDestroy(ev_join);
+  hipEventElapsedTime(&ms, ev.t0, ev.t1);
   if (info) {
     info->status = status;
     info->iters = passes;
@@ -694,11 +728,20 @@ int schur_refine(const void* A_, void* Q_, void* T_, int n, int iters, double to
       info->hp_gemm_herm_launches = timer.herm;
       info->ms_hp_gemm_herm = timer.total(0, 1);
       info->ms_solve = timer.total(1);
+      info->ms_oz_full = timer.total(2);
+      info->oz_full_launches = timer.count[2];
+      info->oz_full_pairs = w.oz_s ? w.oz_s * (w.oz_s + 1) / 2 : 0;
     }
   }
   return status;
 }
 
+int schur_refine(const void* A, void* Q, void* T, int n, int iters, double tol, const sr_opts* opts,
+                 sr_info* info) {
+  const int rc = refine_fp64(A, Q, T, n, iters, tol, opts, info);
+  if (rc < 0 && info) info->status = rc;
+  return rc;
+}
 
 }  // extern "C"
 
@@ -864,9 +907,9 @@ int dd_ydef(int n, const DDWork& w, hipStream_t st) {
 
 extern "C" {
 
-int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, void* T_hi,
-                    void* T_lo, int n, int iters, double tol, const sr_opts* opts_in,
-                    sr_info* info) {
+static int refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, void* T_hi,
+                     void* T_lo, int n, int iters, double tol, const sr_opts* opts_in,
+                     sr_info* info) {
   info_init(info);
   if (!A_hi || !A_lo || !Q_hi || !Q_lo || !T_hi || !T_lo || n < 1 || iters < 1 || !(tol > 0)) {
     if (info) info->status = SR_EINVAL;
@@ -924,19 +967,18 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
   Timer timer;
   timer.st = st;
   Timer* tm = o.timing ? &timer : nullptr;
-  hipEvent_t e0, e1;
-  CK(hipEventCreate(&e0));
-  CK(hipEventCreate(&e1));
-  CK(hipEventRecord(e0, st));
+  CallEvents ev;
+  CK(hipEventCreate(&ev.t0));
+  CK(hipEventCreate(&ev.t1));
+  CK(hipEventRecord(ev.t0, st));
   CK(fill_zero(w.status, 256, st));
   CK(fro2_partials(Ah, (long)n * n, w.partials, 1024, st));
   CK(reduce_partials(w.partials, 1024, w.scal, st));
   CK(oz_split_rows(Ah, Al, n, n, n, S, w.sA, w.eA, st));
-  hipStream_t sst = n <= kSideYMaxNdd ? side_stream() : nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t sst = n <= kSideYMaxNdd ? side_stream(st) : nullptr;
   if (sst) {
-    CK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-    CK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming));
+    CK(hipEventCreateWithFlags(&ev.join, hipEventDisableTiming));
   }
 
   // Newton-Schulz start from Q-hat = (Q_hi, Q_lo)
@@ -959,7 +1001,7 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
   TOC(tm, 0);
 
   int status = SR_NOT_CONVERGED, passes = 0, updates = 0, nprod = 0;
-  double eps = 0, eps1 = -1, eps2 = -1, orth = 0;
+  double eps = 0, eps1 = -1, eps2 = -1, orth = 0, nw_last = 0;
   for (int p = 0; p < iters; p++) {
     TIC(tm, 0);
     CK(oz_split_cols(curh, curl, n, n, n, S, w.sQc, w.eQc, st));
@@ -989,16 +1031,9 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
       status = SR_BREAKDOWN;
       break;
     }
-    if (eps <= tol) {
-      status = SR_OK;
-      break;
-    }
-    if (eps2 >= 0 && eps > eps1 && eps1 > eps2) {
-      status = SR_DIVERGED;
-      break;
-    }
-    if (eps1 >= 0 && eps > 0.5 * eps1 && eps < 100.0 * kUDD * sqrt((double)n)) {
-      status = SR_STAGNATED;
+    const int stop = stop_test(o, eps, tol, eps1, eps2, updates, nw_last, kUDD, n);
+    if (stop >= 0) {
+      status = stop;
       break;
     }
     eps2 = eps1;
@@ -1008,8 +1043,8 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
     // Y beside the solve on the side stream up to kSideYMaxNdd (see the FP64 tier)
     const bool side = sst && n <= kSideYMaxNdd;
     if (side) {
-      CK(hipEventRecord(ev_fork, st));
-      CK(hipStreamWaitEvent(sst, ev_fork, 0));
+      CK(hipEventRecord(ev.fork, st));
+      CK(hipStreamWaitEvent(sst, ev.fork, 0));
       hipStream_t keep = tm ? tm->st : nullptr;
       if (tm) tm->st = sst;
       TIC(tm, 0);
@@ -1017,13 +1052,13 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
       if (rc == SR_OK) TOC_HERM(tm);
       if (tm) tm->st = keep;
       if (rc != SR_OK) return rc;
-      CK(hipEventRecord(ev_join, sst));
+      CK(hipEventRecord(ev.join, sst));
     }
     TIC(tm, 1);
     CK(trisolve64(w.Tlp, w.Elp, w.L, n, w.tri, w.status, st));
     TOC(tm, 1);
     if (side) {
-      CK(hipStreamWaitEvent(st, ev_join, 0));
+      CK(hipStreamWaitEvent(st, ev.join, 0));
     } else {
       TIC(tm, 0);
       if ((rc = dd_ydef(n, w, st)) != SR_OK) return rc;
@@ -1038,6 +1073,7 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
     }
     const double ny = sqrt(nrm[2]), nw = sqrt(nrm[3]);
     orth = ny;
+    nw_last = nw;
     if (info && updates < 16) info->norm_w_hist[updates] = nw;
     if (!isfinite(ny) || !isfinite(nw)) {
       status = SR_BREAKDOWN;
@@ -1088,14 +1124,10 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
     CK(hipMemcpyAsync(Q_hi, curh, (size_t)n * n * sizeof(zc), hipMemcpyDeviceToDevice, st));
     CK(hipMemcpyAsync(Q_lo, curl, (size_t)n * n * sizeof(zc), hipMemcpyDeviceToDevice, st));
   }
-  CK(hipEventRecord(e1, st));
-  CK(hipEventSynchronize(e1));
+  CK(hipEventRecord(ev.t1, st));
+  CK(hipEventSynchronize(ev.t1));
   float ms = 0;
-  hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  if (ev_fork) hipEventDestroy(ev_fork);
-  if (ev_join) hipEventDestroy(ev_join);
+  hipEventElapsedTime(&ms, ev.t0, ev.t1);
   if (info) {
     info->status = status;
     info->iters = passes;
@@ -1114,6 +1146,13 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
     }
   }
   return status;
+}
+
+int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, void* T_hi, void* T_lo,
+                    int n, int iters, double tol, const sr_opts* opts, sr_info* info) {
+  const int rc = refine_dd(A_hi, A_lo, Q_hi, Q_lo, T_hi, T_lo, n, iters, tol, opts, info);
+  if (rc < 0 && info) info->status = rc;
+  return rc;
 }
 
 size_t sr_workspace_bytes_dd(int n, const sr_opts* opts) {

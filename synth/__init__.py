@@ -16,6 +16,7 @@ from .generator import (  # noqa: F401
     wilkinson_companion_dd,
     example3_matrix,
     batched_sizes,
+    batched_inputs,
     continuation_step_dd,
     continuation_perturbation,
     to_dd,

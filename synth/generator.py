@@ -212,6 +212,37 @@ def batched_sizes(count: int = 2000, seed: int = 3, lo: int = 16, hi: int = 256)
     return lo + np.random.default_rng(seed).integers(0, hi - lo + 1, size=count)
 
 
+def _batched_one(item):
+    n, seed = item
+    g = schur_test_matrix(n, seed=seed)
+    return g["A"], lp_schur_start(g["A"])
+
+
+def batched_inputs(sizes, seed0: int = 10000, workers: int = 16):
+    """Matrices and cgees starts of a batch: matrix i is schur_test_matrix(sizes[i],
+    seed0 + i) (gaps 0.05) with its complex64 Schur basis. Made in `workers`
+    processes (spawned, each with single-threaded BLAS: many small factorizations
+    are faster side by side than threaded one by one). Returns [(A, Q-hat)]."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ[k] = "1"
+    try:
+        items = [(int(n), seed0 + i) for i, n in enumerate(sizes)]
+        with cf.ProcessPoolExecutor(max_workers=max(1, workers), mp_context=mp.get_context("spawn")) as ex:
+            return list(ex.map(_batched_one, items, chunksize=25))
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
 def continuation_step_dd(a0: np.ndarray, a1: np.ndarray, k: int, steps: int = 64):
     """A(t_k) = A0 + (k/steps) A1 as an exact double-double pair. a1 must carry at
     most 46 significant bits so that (k/steps) * a1 is exact for k < 64."""

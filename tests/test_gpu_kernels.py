@@ -123,10 +123,34 @@ def test_residual_split_matches_quad(sr, n):
     # lp copies are the FP32 roundings of the split (up to one FP64 error)
     tl, el = host(tlp), host(elp)
     assert not np.tril(tl, -1).any() and not np.triu(el).any()
-    assert np.allclose(tl, np.triu(th).astype(np.complex64), rtol=2 * U32, atol=1e-30)
-    assert np.allclose(el, np.tril(th, -1).astype(np.complex64), rtol=1e-3, atol=1e-3 * np.abs(np.tril(th, -1)).max())
+    # E_lp is the FP32 rounding of the FP64 stril(That): per entry at most one FP32
+    # rounding of the exact value plus the FP64 product bound (carried through it)
+    e_exact = np.tril(th, -1)
+    lower = np.tril(np.ones((n, n), dtype=bool), -1)
+    e_err = np.abs(el.astype(np.complex128) - e_exact)
+    e_bound = np.sqrt(2) * U32 * np.abs(e_exact) + (1 + 2 * U32) * bound
+    assert np.all(e_err[lower] <= e_bound[lower])
+    t_err = np.abs(tl.astype(np.complex128) - np.triu(th))
+    t_bound = np.sqrt(2) * U32 * np.abs(np.triu(th)) + (1 + 2 * U32) * bound
+    upper = np.triu(np.ones((n, n), dtype=bool))
+    assert np.all(t_err[upper] <= t_bound[upper])
     ev = oracle.evaluate(a, q)
     assert abs(eps - ev["stril"]) <= 1e-6 * ev["stril"]
+
+
+def _residual_entrywise_ok(t, e, lg, u):
+    """Componentwise backward error of a substitution solve of the equation
+    stril(T L - L T) = -E (eq. (7)): every entry (i, j), i > j, of the residual
+    R = stril(T L - L T) + E satisfies |r_ij| <= c u (|T||L| + |L||T|)_ij + u |e_ij|
+    with c = sqrt(2)(n + 8) (dot products of at most n terms in any summation order,
+    complex products, the division), for a correct solve in precision u. Returns the
+    largest ratio |r_ij| / bound_ij (evaluated in FP64, far below u32 / u64 bounds)."""
+    n = t.shape[0]
+    lower = np.tril(np.ones((n, n), dtype=bool), -1)
+    r = np.abs(np.tril(t @ lg - lg @ t, -1) + e)
+    at, al = np.abs(t), np.abs(lg)
+    b = np.sqrt(2) * (n + 8) * u * (at @ al + al @ at) + u * np.abs(e)
+    return float(np.max(r[lower] / b[lower])) if lower.any() else 0.0
 
 
 def _sweep_case(n, seed, scale=1e-6):
@@ -151,8 +175,12 @@ def test_trisolve_matches_exact_solution(sr, n):
     err_gpu = np.linalg.norm(lg - lx)
     err_alg2 = np.linalg.norm(lf - lx)
     assert err_gpu <= 10 * err_alg2 + 10 * U32 * np.linalg.norm(lx)
-    res = np.linalg.norm(np.tril(t64 @ lg - lg @ t64, -1) + e64)
-    assert res <= 8 * n * U32 * (np.linalg.norm(t64) * np.linalg.norm(lg) + np.linalg.norm(e64))
+    # entry by entry: the componentwise backward error of a correct FP32 solve
+    assert _residual_entrywise_ok(t64, e64, lg, U32) <= 1.0
+    # and per column, the forward error within 10x the oracle's FP32 Algorithm 2
+    ecol_gpu = np.abs(lg - lx).max(axis=0)
+    ecol_alg2 = np.abs(lf - lx).max(axis=0)
+    assert np.all(ecol_gpu <= 10 * ecol_alg2 + 10 * U32 * np.abs(lx).max(axis=0) + 1e-300)
 
 
 def test_trisolve_32_wide_tiles(sr):
@@ -179,6 +207,7 @@ def test_trisolve_32_wide_tiles(sr):
         assert np.linalg.norm(lg - ld) <= bound
         res = np.linalg.norm(np.tril(t64 @ lg - lg @ t64, -1) + e64)
         assert res <= 8 * n * u * (nt * np.linalg.norm(lg) + np.linalg.norm(e64))
+        assert _residual_entrywise_ok(t64, e64, lg, u) <= 1.0
 
 
 def test_trisolve_one_by_one_and_breakdown(sr):
@@ -202,6 +231,40 @@ def test_trisolve_truncation(sr):
     assert np.abs(host(l)).max() <= 1e-5
 
 
+@pytest.mark.parametrize("n,ref_lp", [(70, "quad"), (600, "double"), (2100, "double")])
+def test_trisolve_truncation_as_computed_against_oracle(sr, n, ref_lp):
+    """The large-entry device of Example 4 zeroes an entry of L as it is computed,
+    so later entries see the zero. On a case whose few large entries (far above
+    1e-5) feed every later entry, the GPU takes the same zeroing decisions as the
+    oracle (the same zero pattern) and the surviving entries match the oracle's
+    truncating solve entry by entry: 16- and 32-wide tiles, ragged edges."""
+    from test_oracle_pins import truncation_case
+
+    trunc = 1e-5
+    t, e = truncation_case(n, 3)
+    t32, e32 = t.astype(np.complex64), e.astype(np.complex64)
+    t64, e64 = t32.astype(np.complex128), e32.astype(np.complex128)
+    lr, st = oracle.trisolve(t64, e64, lp=ref_lp, trunc=trunc)
+    assert st == "OK"
+    lr = lr.to_c128()
+    lower = np.tril(np.ones((n, n), dtype=bool), -1)
+    ar = np.abs(lr[lower])
+    assert np.all((ar == 0) | (ar < 0.1 * trunc))  # no decision close to the threshold
+    assert np.count_nonzero(ar == 0) >= 3
+    l = empty(n, n, True)
+    assert sr.sr_trisolve(dev(t32), dev(e32), l, sr.workspace(n), trunc=trunc) == 0
+    lg = host(l).astype(np.complex128)
+    assert np.array_equal(lg == 0, lr == 0)
+    # surviving entries: FP32 forward error, entry by entry relative to the largest
+    # entry of their column (the entries are O(1e-8), the zeroed ones left out)
+    scale = np.abs(lr).max(axis=0)[None, :]
+    assert np.all(np.abs(lg - lr) <= 1e-3 * scale + 1e-30)
+    # zeroing only after the sweep would give another L
+    full = oracle.trisolve(t64, e64, lp="double")[0].to_c128()
+    after = np.where(np.abs(full) > trunc, 0, full)
+    assert np.abs(after - lr).max() >= 10 * np.abs(lr).max()
+
+
 def test_ns_init_matches_quad(sr):
     n = 150
     g = synth.schur_test_matrix(n, seed=4)
@@ -211,6 +274,12 @@ def test_ns_init_matches_quad(sr):
     hi, lo = oracle.ns(qh).to_dd()
     err = np.linalg.norm((host(q) - hi) - lo)
     assert err <= 8 * U64 * n  # ||Q|| ~ sqrt(n); error ~ u sqrt(n) per column
+    # entry by entry: first-order bound of Q = Qh + Qh (-Y0 / 2) with Y0 = Qh^H Qh - I
+    # formed in FP64 (dot products of length n), the product Qh (Y0 / 2) and the sum
+    aq = np.abs(qh)
+    y0 = qh.conj().T @ qh - np.eye(n)
+    bound = np.sqrt(2) * (n + 8) * U64 * (aq @ (aq.conj().T @ aq) / 2 + aq @ np.abs(y0) / 2) + U64 * np.abs(hi)
+    assert np.all(np.abs((host(q) - hi) - lo) <= bound)
     # Lemma 2: the defect after the step is -3/4 Y0^2 + 1/4 Y0^3
     y0 = qh.conj().T @ qh - np.eye(n)
     y = host(q).conj().T @ host(q) - np.eye(n)
@@ -233,6 +302,7 @@ def test_update_matches_oracle_merged_step(sr):
     err = np.linalg.norm((host(qo) - hi) - lo)
     # FP64 rounding of Q + Q Delta, plus FP32 rounding of the (1e-8 sized) lp products
     assert err <= 16 * U64 * n + 1e-7 * np.linalg.norm(w @ w) * np.sqrt(n)
+    assert np.all(np.abs((host(qo) - hi) - lo) <= _update_bound(q, w, hi))
 
 
 @pytest.mark.parametrize("n", [64, 200])
@@ -254,4 +324,23 @@ def test_update_hermitian_defect(sr, n):
     # FP64 products plus FP32 lp products YW, W^2, W^3 (Y ~ 0.1, W ~ 1e-4)
     err = np.linalg.norm((host(qo) - hi) - lo)
     assert err <= 1e-9 * np.linalg.norm(hi)
+    assert np.all(np.abs((host(qo) - hi) - lo) <= _update_bound(q, w, hi))
+
+
+def _update_bound(q, w, qout):
+    """Entrywise first-order bound for the GPU form Q + Q Delta of the merged
+    update against the oracle's (float lp, binary128 hp) step: Y = Q^H Q - I in FP64
+    (length-n dot products), the FP32 products YW, W^2, W^3 and their operands
+    rounded to FP32 (operands rounded once; (W^2 - Y) W formed as one product when
+    both terms are present), Delta in FP64, the FP64 product Q Delta and the sum."""
+    n = q.shape[0]
+    aq, aw = np.abs(q), np.abs(w)
+    y = q.conj().T @ q - np.eye(n)
+    ay = np.abs(y)
+    c64 = np.sqrt(2) * (n + 8) * U64
+    c32 = np.sqrt(2) * (n + 8) * U32
+    d_y = c64 * (aq.conj().T @ aq) / 2
+    d_lp = c32 * (ay @ aw + aw @ aw + aw @ aw @ aw + (aw @ aw + ay) @ aw) + U32 * (ay + aw @ aw) @ aw
+    delta = np.abs(w) + ay / 2 + (ay @ aw + aw @ aw + aw @ aw @ aw) / 2
+    return aq @ (d_y + d_lp + 4 * U64 * delta) + c64 * (aq @ delta) + 2 * U64 * np.abs(qout)
 
