@@ -1,22 +1,23 @@
 """Benchmark: refined Schur decompositions per second on one MI355X.
 
-Default workload (the headline line): one complex128 matrix of size n = 1024 built
-as A = Q0 T0 Q0^H (Haar Q0, gap-separated complex normal eigenvalues >= 0.05
-apart, strictly upper part CN(0,1)/sqrt(n)), started from the complex64 Schur
-basis of complex64(A) (LAPACK cgees). One step is one complete refinement
-(Algorithm 4 from the Newton-Schulz start) to ||stril(Q^H A Q)||_F / ||A||_F <=
-1e-15 in the FP64 tier (FP64 MFMA products with compensated accumulation, FP32
-solve). A, the start and the workspace are resident in HBM before timing; each
-step first restores the start into Q with a device-to-device copy (inside the
-timed region).
+Default workload (the headline line): the precision comparison at n = 4096, the
+largest single-GPU configuration. One complex128 matrix A = Q0 T0 Q0^H (Haar Q0,
+complex normal eigenvalues at least 1e-3 apart, strictly upper part CN(0,1)/sqrt(n),
+seed 2), started from the complex64 Schur basis of complex64(A) (LAPACK cgees).
+One step is one complete refinement (Algorithm 4 from the Newton-Schulz start) to
+||stril(Q^H A Q)||_F / ||A||_F <= 1e-15 in the FP64 tier (FP32 solve) in one of
+three forms of the hp products: native FP64 MFMA ("fp64"), Ozaki INT8 digits for
+P = A Q, the start and Q Delta with That and Y native ("ozaki_i8"), or INT8 digits
+for every hp product ("ozaki_i8_all"). Every form is run and timed; the line's
+value is the fastest form that converges and whose binary128 residual on sampled
+rows meets the tolerance, timed over --steps refinements. A, the start and the
+workspaces are resident in HBM before timing; each step first restores the start
+into Q with a device-to-device copy (inside the timed region).
 
 Other workloads (--workload), each one JSON line of its own:
-  precision       n = 4096, eigenvalue gaps >= 1e-3, cgees start: the FP64 tier
-                  with native FP64 products, with Ozaki INT8 splits of P, the
-                  start and Q Delta (That and Y native), and with every product
-                  split; median time to 1e-15 over interleaved steps and the
-                  binary128 error on sampled rows for each; a product sweep over
-                  digit counts;
+  single          n = 1024, gaps >= 0.05, cgees start, native FP64 products (also
+                  reported as the "n1024" key of the default line);
+  precision       the n = 4096 forms plus a product sweep over digit counts;
   batched         2000 matrices, n uniform in [16, 256], each from its own seed
                   with a cgees start, refined together (schur_refine_batched;
                   a step restores all starts with one device copy);
@@ -25,10 +26,11 @@ Other workloads (--workload), each one JSON line of its own:
                   tier to 1e-28, each step warm-started from the previous one,
                   the first from the zgees Schur form of A0.
 
-Prints one JSON line. `roofline` covers the dominant kernel of the workload's hp
-products, timed with HIP events on the library's stream during the timed steps.
-`cpu_baseline` times the binary128 oracle on a bounded sample (one quad product
-A Q[:, :c]) and scales it to one refinement.
+`roofline` covers the dominant kernel of the chosen form, timed with HIP events
+on the library's stream during the timed steps: the FP64 GEMM against the FP64
+MFMA peak, or the INT8 digit product against the INT8 MFMA peak. `cpu_baseline`
+is the binary128 oracle on the host cores: a full refinement at n = 64 timed
+as it stands, and binary128 row products at n = 4096 scaled to one refinement.
 """
 from __future__ import annotations
 
@@ -46,46 +48,69 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 INT8_PEAK_TOPS = 5000.0  # MI355X dense INT8 matrix peak
 METRIC = "refined Schur decomps/sec to ||stril||/||A||<=1e-15; GEMM % MFMA peak"
-N = 1024
 TOL = 1e-15
 
 
-def cpu_baseline(a: np.ndarray, q: np.ndarray, hp_products: int, cols: int = 256) -> dict:
+def cpu_baseline(a_big: np.ndarray, q_big: np.ndarray, hp_products: int, rows: int = 16) -> dict:
+    """The binary128 oracle as it stands, on the host cores: (1) full refinements of
+    the n = 64 configuration (oracle QR start, FP32 solve, binary128 hp), timed;
+    (2) binary128 products of `rows` rows of A with Q at the benchmark's n, scaled
+    to the hp products of one refinement (the solve and the elementwise work, a few
+    percent of a refinement's flops, are not counted there)."""
     import oracle
+    import synth
 
-    n = a.shape[0]
-    qa = oracle.QMat.from_dd(a)
-    qs = oracle.QMat.from_dd(np.asfortranarray(q[:, :cols]))
-    t0 = time.perf_counter()
-    oracle.gemm(qa, qs)
-    dt = time.perf_counter() - t0
-    per_refine = dt * (n / cols) * hp_products
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    g = synth.schur_test_matrix(64, seed=0, gap=0.05)
+    z, _ = oracle.schur_qr(g["A"], lp="float")
+    reps = 0
+    t0 = time.perf_counter()
+    while reps < 3 or time.perf_counter() - t0 < 5.0:
+        r = oracle.refine(g["A"], z, lp="float", maxit=6, tol=1e-15)
+        reps += 1
+    t64 = (time.perf_counter() - t0) / reps
+    n = a_big.shape[0]
+    sel = np.sort(np.random.default_rng(11).choice(n, rows, replace=False))
+    qa = oracle.QMat.from_dd(np.asfortranarray(a_big[sel]))
+    qq = oracle.QMat.from_dd(q_big)
+    t0 = time.perf_counter()
+    oracle.gemm(qa, qq)
+    dt = time.perf_counter() - t0
+    per_refine = dt * (n / rows) * hp_products
     return {"value": 1.0 / per_refine, "unit": "decomps/s", "cores": threads, "kind": "oracle",
-            "sample": f"one binary128 complex product A @ Q[:, :{cols}] at n={n} "
-                      f"({dt:.2f} s), scaled x{n // cols} columns x {hp_products} hp products "
-                      f"per refinement; solve and elementwise work not counted"}
+            "sample": f"binary128 product of {rows} rows of A with Q at n={n} ({dt:.2f} s), scaled "
+                      f"x{n // rows} rows x {hp_products} hp products per refinement (solve and "
+                      f"elementwise work not counted); beside it a full oracle refinement at n=64",
+            "refinement_n64": {"decomps_per_s": 1.0 / t64, "s_per_refinement": t64,
+                               "passes": int(r["iters"]), "status": r["status"], "lp": "float",
+                               "hp": "binary128", "reps": reps}}
 
 
-def gemm_traffic():
-    """HBM bytes per FP64 GEMM launch from the committed rocprofv3 PMC summary, or None
-    when the GEMM sources have changed since the counters were taken."""
+def pmc_traffic(profile: str, key: str, sources, hash_key: str = "source_sha256_16") -> float | None:
+    """Bytes per launch (or per solve) from a committed rocprofv3 PMC summary under
+    profiles/, or None when the listed sources have changed since the counters were
+    taken (the summary records a hash of them)."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "refine_n1024_gemm_hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", profile)
     csrc = os.path.join(ROOT, "paper_2203_10879_amd", "csrc")
     try:
         text = open(path).read()
         h = hashlib.sha256()
-        for f in ("gemm.hip", "epilogue.hpp", "kernels.hpp", "common.hpp"):
+        for f in sources:
             h.update(open(os.path.join(csrc, f), "rb").read())
         vals = dict(line.split(":", 1) for line in text.splitlines()
-                    if line.startswith(("traffic_bytes_per_launch:", "gemm_source_sha256_16:")))
-        if vals["gemm_source_sha256_16"].split()[0] != h.hexdigest()[:16]:
+                    if line.startswith((key + ":", hash_key + ":")))
+        if vals[hash_key].split()[0] != h.hexdigest()[:16]:
             return None
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[key])
     except (OSError, KeyError, ValueError):
         return None
+
+
+GEMM_SOURCES = ("gemm.hip", "epilogue.hpp", "kernels.hpp", "common.hpp")
+OZAKI_SOURCES = ("ozaki.hip", "kernels.hpp", "common.hpp")
+SWEEP_SOURCES = ("trisolve.hip", "trisolve_tiles.inc", "kernels.hpp", "common.hpp")
 
 
 def base_record(args, value, unit, ms_per_step, dtype, config):
@@ -95,34 +120,15 @@ def base_record(args, value, unit, ms_per_step, dtype, config):
             "config": config}
 
 
-def sweep_traffic():
-    """Bytes per solve beyond L2 of the triangular-equation sweep from the committed
-    rocprofv3 PMC summary, or None when the solve sources have changed since."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", "trisolve_n1024_hbm_traffic.txt")
-    csrc = os.path.join(ROOT, "paper_2203_10879_amd", "csrc")
-    try:
-        text = open(path).read()
-        h = hashlib.sha256()
-        for f in ("trisolve.hip", "trisolve_tiles.inc", "kernels.hpp", "common.hpp"):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-        vals = dict(line.split(":", 1) for line in text.splitlines()
-                    if line.startswith(("sweep_hbm_bytes_per_solve:", "trisolve_source_sha256_16:")))
-        if vals["trisolve_source_sha256_16"].split()[0] != h.hexdigest()[:16]:
-            return None
-        return float(vals["sweep_hbm_bytes_per_solve"])
-    except (OSError, KeyError, ValueError):
-        return None
-
-
-def run_default(args) -> int:
+def single_record(args, n: int, steps: int, warmup: int):
+    """One matrix of size n (gaps >= 0.05, seed 1, cgees start), native FP64 tier:
+    `steps` timed refinements after `warmup`. Returns the record, the last info, A
+    and the start."""
     import torch
 
     import paper_2203_10879_amd as sr
     import synth
 
-    n = args.n
     g = synth.schur_test_matrix(n, seed=1, gap=0.05)
     qh = synth.lp_schur_start(g["A"])
     torch.cuda.set_device(torch.device("cuda:0"))
@@ -138,15 +144,12 @@ def run_default(args) -> int:
         Q.copy_(Q0)
         return sr.schur_refine(A, Q, T, iters=6, tol=TOL, timing=timing, **kw)
 
-    for _ in range(args.warmup):
-        info = step()
-        if info["status"] != "OK":
-            print(json.dumps({"error": "warmup refinement did not converge", "info": info}))
-            return 1
+    for _ in range(warmup):
+        step()
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         infos.append(step(timing=True))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -162,19 +165,21 @@ def run_default(args) -> int:
     avg_gemm_ms = (ms_gemm - ms_herm) / max(1, full)
     achieved = 8.0 * n ** 3 / (avg_gemm_ms * 1e-3) / 1e12
     last = infos[-1]
-    out = base_record(args, args.steps / dt if ok else 0.0, "decomps/s", 1e3 * dt / args.steps, "f64",
+    out = base_record(args, steps / dt if ok else 0.0, "decomps/s", 1e3 * dt / steps, "f64",
                       {"workload": f"single matrix n={n}, eigenvalue gaps >= 0.05, FP32 cgees start, "
                                    "FP64 tier (FP64 MFMA products, FP32 solve), tol 1e-15",
                        "n": n, "tol": TOL, "compensated": not args.no_compensated,
                        "parallelism": "1 GPU"})
-    traffic = gemm_traffic() if n == N else None
+    traffic = (pmc_traffic("refine_n1024_gemm_hbm_traffic.txt", "traffic_bytes_per_launch", GEMM_SOURCES,
+                           "gemm_source_sha256_16")
+               if n == 1024 else None)
     out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                        "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x 1.997 + WRITE_SIZE)",
                        "kernel": "complex FP64 GEMM (gemm_kernel<double,...>), full products: 8n^3 flop "
                                  "per launch",
-                       "avg_launch_ms": avg_gemm_ms, "launches_per_step": full / args.steps,
-                       "hermitian_products": {"launches_per_step": herm / args.steps,
+                       "avg_launch_ms": avg_gemm_ms, "launches_per_step": full / steps,
+                       "hermitian_products": {"launches_per_step": herm / steps,
                                               "avg_launch_ms": ms_herm / max(1, herm),
                                               "flop_per_launch": 4.0 * n * n * (n + 1)}}
     # The triangular-equation sweep: one solve per update, timed with HIP events around
@@ -182,22 +187,172 @@ def run_default(args) -> int:
     solves = sum(i["updates"] for i in infos)
     ms_solve = sum(i["ms_solve"] for i in infos) / max(1, solves)
     alg_bytes = 12.0 * n * n
-    sweep_bytes = sweep_traffic() if n == N else None
+    sweep_bytes = (pmc_traffic("trisolve_n1024_hbm_traffic.txt", "sweep_hbm_bytes_per_solve", SWEEP_SOURCES,
+                               "trisolve_source_sha256_16")
+                   if n == 1024 else None)
     out["sweep"] = {"kernel": "triangular-equation sweep (trisolve_level_kernel<float>, one launch per tile "
                               "diagonal)",
                     "bound": f"latency: {(n + 15) // 16 if n <= 2048 else (n + 31) // 32} dependent launches "
                              "(tile diagonals)",
-                    "ms_per_solve": ms_solve, "solves_per_step": solves / args.steps,
+                    "ms_per_solve": ms_solve, "solves_per_step": solves / steps,
                     "algorithmic_bytes_per_solve": alg_bytes,
                     "algorithmic_GBps": alg_bytes / (ms_solve * 1e-3) / 1e9,
                     "beyond_l2_bytes_per_solve": sweep_bytes,
                     "beyond_l2_GBps": sweep_bytes / (ms_solve * 1e-3) / 1e9 if sweep_bytes else None,
                     "hbm_peak_GBps": 8000.0}
-    out.update({"passes": last["iters"], "hp_gemms": last["hp_gemms"], "resid_hist": last["resid_hist"],
-                "ms_solve_per_step": sum(i["ms_solve"] for i in infos) / args.steps,
-                "ms_hp_gemm_per_step": ms_gemm / args.steps, "all_converged": ok})
+    out.update({"steps": steps, "warmup": warmup, "passes": last["iters"], "hp_gemms": last["hp_gemms"],
+                "resid_hist": last["resid_hist"],
+                "ms_solve_per_step": sum(i["ms_solve"] for i in infos) / steps,
+                "ms_hp_gemm_per_step": ms_gemm / steps, "all_converged": ok})
+    return out, last, g["A"], qh
+
+
+def run_single(args) -> int:
+    n = 1024 if args.n is None else args.n
+    out, last, a, qh = single_record(args, n, args.steps, args.warmup)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g["A"], qh, hp_products=last["hp_gemms"])
+        out["cpu_baseline"] = cpu_baseline(a, qh, hp_products=last["hp_gemms"])
+    print(json.dumps(out), flush=True)
+    return 0 if out["all_converged"] else 1
+
+
+HEADLINE_FORMS = ("fp64", "ozaki_i8", "ozaki_i8_all")
+
+
+def run_default(args) -> int:
+    """The headline line: n = 4096, gaps >= 1e-3, every form of the hp products."""
+    import torch
+
+    import oracle
+    import paper_2203_10879_amd as sr
+    import synth
+
+    n = 4096 if args.n is None else args.n
+    t0 = time.perf_counter()
+    g = synth.schur_test_matrix(n, seed=2, gap=1e-3)
+    qh = synth.lp_schur_start(g["A"])
+    print(f"# inputs n={n} ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.set_device(torch.device("cuda:0"))
+    A, Q0 = sr.colmajor(g["A"]), sr.colmajor(qh)
+    Q, T = sr.colmajor_empty(n, n), sr.colmajor_empty(n, n)
+    form_list = tuple(args.forms.split(",")) if args.forms else HEADLINE_FORMS
+    wss = {m: sr.workspace(n, gemm=m) for m in form_list}
+    iters = 8
+
+    def refine(m, timing=False):
+        Q.copy_(Q0)
+        return sr.schur_refine(A, Q, T, iters=iters, tol=TOL, gemm=m, timing=timing, workspace=wss[m])
+
+    # every form: untimed warmup, then refinements timed one by one with HIP events
+    # (the forms interleaved, so that clock drift falls on all alike), then the
+    # binary128 residual of its result on sampled rows
+    rows = np.sort(np.random.default_rng(7).choice(n, args.rows, replace=False))
+    reps = max(2, args.warmup)
+    for _ in range(args.warmup):
+        for m in form_list:
+            refine(m)
+    torch.cuda.synchronize()
+    ms_each = {m: [] for m in form_list}
+    last = {}
+    for _ in range(reps):
+        for m in form_list:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            last[m] = refine(m)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_each[m].append(e0.elapsed_time(e1))
+    forms = {}
+    for m in form_list:
+        refine(m)
+        torch.cuda.synchronize()
+        # --rows 0 (profiling runs): no binary128 check, the library's own residual decides
+        ev = (oracle.evaluate_rows(g["A"], sr.to_numpy(Q), rows) if args.rows > 0
+              else {"stril": float("nan"), "stril_rowmax": float("nan"), "orth": float("nan")})
+        inf = last[m]
+        meets = inf["status"] == "OK" and (args.rows == 0 or float(ev["stril"]) <= TOL)
+        forms[m] = {"status": inf["status"], "passes": inf["iters"], "ms_to_tol": float(np.median(ms_each[m])),
+                    "ms_min": float(np.min(ms_each[m])), "resid_hist": inf["resid_hist"],
+                    "update_digits": inf["update_slices_hist"] if m != "fp64" else None,
+                    "quad_stril_rows": float(ev["stril"]), "quad_stril_rowmax": float(ev["stril_rowmax"]),
+                    "quad_orth_rows": float(ev["orth"]), "meets_tol": meets}
+        print(f"# {m}: {forms[m]['ms_to_tol']:.1f} ms, {inf['iters']} passes, binary128 rows "
+              f"{ev['stril']:.2e}", file=sys.stderr, flush=True)
+    ok_forms = [m for m in form_list if forms[m]["meets_tol"]]
+    if not ok_forms:
+        print(json.dumps({"error": "no form met the tolerance", "forms": forms}), flush=True)
+        return 1
+    best = min(ok_forms, key=lambda m: forms[m]["ms_to_tol"])
+
+    # the timed region: --steps refinements of the chosen form, HIP events around its
+    # product and solve launches
+    for _ in range(args.warmup):
+        refine(best)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(refine(best, timing=True))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = all(i["status"] == "OK" for i in infos)
+    steps = args.steps
+    out = base_record(args, steps / dt if ok else 0.0, "decomps/s", 1e3 * dt / steps,
+                      "f64" if best == "fp64" else "f64+i8",
+                      {"workload": f"single matrix n={n}, eigenvalue gaps >= 1e-3 (seed 2), FP32 cgees start, "
+                                   f"FP64 tier (FP32 solve), tol 1e-15; hp products as '{best}', the fastest "
+                                   "of native FP64 / Ozaki INT8 (P, the start, Q Delta) / Ozaki INT8 (every "
+                                   "hp product) that met the tolerance",
+                       "n": n, "tol": TOL, "form": best, "parallelism": "1 GPU"})
+    if best == "fp64":
+        ms = sum(i["ms_hp_gemm"] - i["ms_hp_gemm_herm"] for i in infos)
+        cnt = sum(i["hp_gemm_launches"] - i["hp_gemm_herm_launches"] for i in infos)
+        avg = ms / max(1, cnt)
+        achieved = 8.0 * n ** 3 / (avg * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": achieved / FP64_PEAK_TFLOPS,
+                           "traffic": pmc_traffic("gemm_n4096_hbm_traffic.txt", "traffic_bytes_per_launch",
+                                                  GEMM_SOURCES),
+                           "kernel": "complex FP64 GEMM (gemm_kernel<double,...>), full products P, That, "
+                                     "Q Delta: 8n^3 flop per launch",
+                           "avg_launch_ms": avg, "launches_per_step": cnt / steps}
+    else:
+        ms = sum(i["ms_oz_full"] for i in infos)
+        cnt = sum(i["oz_full_launches"] for i in infos)
+        pairs = infos[-1]["oz_full_pairs"]
+        avg = ms / max(1, cnt)
+        achieved = pairs * 8.0 * n ** 3 / (avg * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                           "frac": achieved / INT8_PEAK_TOPS,
+                           "traffic": pmc_traffic("ozaki_allpairs_n4096_hbm_traffic.txt",
+                                                  "traffic_bytes_per_launch", OZAKI_SOURCES),
+                           "kernel": f"INT8 digit product (oz_gemm_allpairs_kernel, {pairs} slice pairs), the "
+                                     f"full products with the main digit count: {pairs} x 8n^3 int8 ops per "
+                                     "launch",
+                           "avg_launch_ms": avg, "launches_per_step": cnt / steps,
+                           "fp64_equivalent_tflops": 8.0 * n ** 3 / (avg * 1e-3) / 1e12}
+    out["roofline"]["traffic_unit"] = ("HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, "
+                                       "calibrated on a copy kernel)")
+    lastinfo = infos[-1]
+    solves = sum(i["updates"] for i in infos)
+    out.update({"passes": lastinfo["iters"], "hp_gemms": lastinfo["hp_gemms"], "resid_hist": lastinfo["resid_hist"],
+                "ms_hp_products_per_step": sum(i["ms_hp_gemm"] for i in infos) / steps,
+                "ms_solve_per_step": sum(i["ms_solve"] for i in infos) / steps,
+                "ms_per_solve": sum(i["ms_solve"] for i in infos) / max(1, solves),
+                "all_converged": ok, "forms": forms, "quad_rows": args.rows})
+    for m in ("ozaki_i8", "ozaki_i8_all"):
+        if m in forms and "fp64" in forms:
+            out[m + "_speedup_vs_fp64"] = forms["fp64"]["ms_to_tol"] / forms[m]["ms_to_tol"]
+    del wss
+    torch.cuda.empty_cache()
+    if not args.no_secondary:
+        # the n = 1024 configuration (native FP64), as a secondary key
+        n1024, _, _, _ = single_record(args, 1024, 10, 2)
+        out["n1024"] = {k: n1024[k] for k in ("value", "ms_per_step", "passes", "roofline", "sweep",
+                                              "resid_hist", "ms_solve_per_step", "ms_hp_gemm_per_step",
+                                              "all_converged", "steps")}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g["A"], qh, hp_products=lastinfo["hp_gemms"])
     print(json.dumps(out), flush=True)
     return 0 if ok else 1
 
@@ -209,7 +364,7 @@ def run_precision(args) -> int:
     import paper_2203_10879_amd as sr
     import synth
 
-    n = 4096 if args.n == N else args.n
+    n = 4096 if args.n is None else args.n
     t0 = time.perf_counter()
     g = synth.schur_test_matrix(n, seed=2, gap=1e-3)
     qh = synth.lp_schur_start(g["A"])
@@ -312,29 +467,14 @@ def run_precision(args) -> int:
     return 0 if ok else 1
 
 
-def _gen_batched(item):
-    n, seed = item
-    import synth
-
-    g = synth.schur_test_matrix(n, seed=seed)
-    return g["A"], synth.lp_schur_start(g["A"])
-
-
 def run_batched(args) -> int:
-    import concurrent.futures as cf
-    import multiprocessing as mp
-
     import synth
 
     count = args.count
     sizes = [int(x) for x in synth.batched_sizes(count, seed=3)]
     t0 = time.perf_counter()
-    # inputs are made before the GPU is touched; workers run single-threaded BLAS
-    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        os.environ[k] = "1"
-    workers = min(16, os.cpu_count() or 1)
-    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        data = list(ex.map(_gen_batched, [(n, 10000 + i) for i, n in enumerate(sizes)], chunksize=16))
+    # inputs are made before the GPU is touched
+    data = synth.batched_inputs(sizes, 10000, workers=min(16, os.cpu_count() or 1))
     print(f"# {count} inputs ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
     import torch
@@ -400,7 +540,7 @@ def run_dd_continuation(args) -> int:
     import paper_2203_10879_amd as sr
     import synth
 
-    n = 2048 if args.n == N else args.n
+    n = 2048 if args.n is None else args.n
     steps = args.cont_steps
     t0 = time.perf_counter()
     g = synth.schur_test_matrix(n, seed=4, gap=0.05)
@@ -449,13 +589,15 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=N)
+    ap.add_argument("--n", type=int, default=None, help="matrix size (default: the workload's)")
     ap.add_argument("--workload", default="default",
-                    choices=["default", "precision", "batched", "dd_continuation"])
+                    choices=["default", "single", "precision", "batched", "dd_continuation"])
     ap.add_argument("--count", type=int, default=2000, help="batched: number of matrices")
     ap.add_argument("--cont-steps", type=int, default=64, help="dd_continuation: steps")
     ap.add_argument("--rows", type=int, default=32, help="rows of the binary128 check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="default: leave out the n = 1024 key")
+    ap.add_argument("--forms", default="", help="default: comma-separated forms to run (default: all three)")
     ap.add_argument("--no-compensated", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -463,7 +605,7 @@ def main() -> int:
               "(the refinement of one matrix is not sharded across GPUs)",
               file=sys.stderr)
         return 2
-    return {"default": run_default, "precision": run_precision, "batched": run_batched,
+    return {"default": run_default, "single": run_single, "precision": run_precision, "batched": run_batched,
             "dd_continuation": run_dd_continuation}[args.workload](args)
 
 
