@@ -109,7 +109,8 @@ def pmc_traffic(profile: str, key: str, sources, hash_key: str = "source_sha256_
 
 
 GEMM_SOURCES = ("gemm.hip", "epilogue.hpp", "kernels.hpp", "common.hpp")
-OZAKI_SOURCES = ("ozaki.hip", "kernels.hpp", "common.hpp")
+OZAKI_SOURCES = ("ozaki.hip", "ozaki_layout.hpp", "epilogue.hpp", "kernels.hpp", "common.hpp")
+CRT_SOURCES = ("crt.hip", "ozaki_layout.hpp", "epilogue.hpp", "kernels.hpp", "common.hpp")
 SWEEP_SOURCES = ("trisolve.hip", "trisolve_tiles.inc", "kernels.hpp", "common.hpp")
 
 
@@ -216,7 +217,7 @@ def run_single(args) -> int:
     return 0 if out["all_converged"] else 1
 
 
-HEADLINE_FORMS = ("fp64", "ozaki_i8", "ozaki_i8_all")
+HEADLINE_FORMS = ("fp64", "ozaki_i8", "ozaki_i8_all", "ozaki_crt")
 
 
 def run_default(args) -> int:
@@ -322,13 +323,17 @@ def run_default(args) -> int:
         pairs = infos[-1]["oz_full_pairs"]
         avg = ms / max(1, cnt)
         achieved = pairs * 8.0 * n ** 3 / (avg * 1e-3) / 1e12
+        if best == "ozaki_crt":
+            kernel = (f"INT8 residue product (crt_gemm_kernel, Ozaki scheme II, {pairs} moduli), the full "
+                      f"products P and That with 55-bit integers: {pairs} x 8n^3 int8 ops per launch")
+            traffic = pmc_traffic("crt_gemm_n4096_hbm_traffic.txt", "traffic_bytes_per_launch", CRT_SOURCES)
+        else:
+            kernel = (f"INT8 digit product (oz_gemm_allpairs_kernel, {pairs} slice pairs), the full products "
+                      f"with the main digit count: {pairs} x 8n^3 int8 ops per launch")
+            traffic = pmc_traffic("ozaki_allpairs_n4096_hbm_traffic.txt", "traffic_bytes_per_launch",
+                                  OZAKI_SOURCES)
         out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                           "frac": achieved / INT8_PEAK_TOPS,
-                           "traffic": pmc_traffic("ozaki_allpairs_n4096_hbm_traffic.txt",
-                                                  "traffic_bytes_per_launch", OZAKI_SOURCES),
-                           "kernel": f"INT8 digit product (oz_gemm_allpairs_kernel, {pairs} slice pairs), the "
-                                     f"full products with the main digit count: {pairs} x 8n^3 int8 ops per "
-                                     "launch",
+                           "frac": achieved / INT8_PEAK_TOPS, "traffic": traffic, "kernel": kernel,
                            "avg_launch_ms": avg, "launches_per_step": cnt / steps,
                            "fp64_equivalent_tflops": 8.0 * n ** 3 / (avg * 1e-3) / 1e12}
     out["roofline"]["traffic_unit"] = ("HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, "
@@ -340,7 +345,7 @@ def run_default(args) -> int:
                 "ms_solve_per_step": sum(i["ms_solve"] for i in infos) / steps,
                 "ms_per_solve": sum(i["ms_solve"] for i in infos) / max(1, solves),
                 "all_converged": ok, "forms": forms, "quad_rows": args.rows})
-    for m in ("ozaki_i8", "ozaki_i8_all"):
+    for m in ("ozaki_i8", "ozaki_i8_all", "ozaki_crt"):
         if m in forms and "fp64" in forms:
             out[m + "_speedup_vs_fp64"] = forms["fp64"]["ms_to_tol"] / forms[m]["ms_to_tol"]
     del wss
@@ -376,7 +381,7 @@ def run_precision(args) -> int:
     # The forms are timed interleaved (one refinement of each per step, each timed
     # with HIP events on the current stream), so that clock drift over the run falls
     # on all of them alike.
-    modes = ("fp64", "ozaki_i8", "ozaki_i8_all")
+    modes = HEADLINE_FORMS
     wss = {m: sr.workspace(n, gemm=m) for m in modes}
     for _ in range(args.warmup):
         for m in modes:
@@ -443,6 +448,13 @@ def run_precision(args) -> int:
         sweep.append({"form": f"int8 s={sd}", "pairs": pairs, "ms": ms, "rel_err_rows": rel_err(),
                       "int8_frac_of_peak": pairs * 8.0 * n ** 3 / (ms * 1e-3) / (INT8_PEAK_TOPS * 1e12)})
     del ws_oz
+    ws_crt = torch.empty(int(sr.lib().sr_crt_ws_bytes(n, n, n, 55)), dtype=torch.uint8, device="cuda")
+    for bits in (23, 31, 39, 47, 55):
+        ms = timed(lambda: sr.sr_crt_zgemm(A, Q0, P, bits=bits, ws=ws_crt))
+        nm = int(sr.lib().sr_crt_moduli(n, bits))
+        sweep.append({"form": f"crt bits={bits}", "moduli": nm, "ms": ms, "rel_err_rows": rel_err(),
+                      "int8_frac_of_peak": nm * 8.0 * n ** 3 / (ms * 1e-3) / (INT8_PEAK_TOPS * 1e12)})
+    del ws_crt
     for comp in (False, True):
         ms = timed(lambda: sr.sr_zgemm(A, Q0, P, compensated=comp))
         sweep.append({"form": "fp64" + (" compensated" if comp else ""), "ms": ms, "rel_err_rows": rel_err(),
@@ -460,6 +472,7 @@ def run_precision(args) -> int:
     out["forms"] = forms
     out["ozaki_speedup_vs_fp64"] = fp["ms_to_tol"] / oz["ms_to_tol"]
     out["ozaki_all_speedup_vs_fp64"] = fp["ms_to_tol"] / forms["ozaki_i8_all"]["ms_to_tol"]
+    out["ozaki_crt_speedup_vs_fp64"] = fp["ms_to_tol"] / forms["ozaki_crt"]["ms_to_tol"]
     out["product_sweep"] = {"product": f"P = A Q-hat, n={n}", "error": "relative Frobenius error on 8 rows "
                             "against the binary128 product", "forms": sweep}
     out["roofline"] = None

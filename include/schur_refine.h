@@ -60,18 +60,28 @@ typedef enum {
                              residual products named for the precision comparison)     */
   SR_GEMM_OZAKI_BF16 = 2, /* Ozaki split on BF16 MFMA: not built (SR_ENOSYS); INT8
                              digits give the same exactness at twice the MFMA rate    */
-  SR_GEMM_OZAKI_I8_ALL = 3 /* as SR_GEMM_OZAKI_I8, and That and Y from digit slices too
+  SR_GEMM_OZAKI_I8_ALL = 3, /* as SR_GEMM_OZAKI_I8, and That and Y from digit slices too
                              (Y from the column slices of Q made for P); the slice
                              sums are combined in FP64                                 */
+  SR_GEMM_OZAKI_CRT = 4   /* every hp product (P, That, Y, the start, Q Delta) as an
+                             Ozaki scheme II product on INT8 MFMA: rows and columns
+                             scaled to integers of `slices` bits, their residues
+                             modulo N pairwise coprime moduli <= 256 multiplied
+                             exactly, the product recovered by the Chinese
+                             remainder theorem (N = 16 for 55 bits at n <= 4096,
+                             against 28 slice pairs for 7 digits)                   */
 } sr_gemm_mode;
 
 typedef struct {
   int gemm;               /* sr_gemm_mode for the hp products                         */
   int slices;             /* SR_GEMM_OZAKI_I8(_ALL): 8-bit digits per operand of P = A Q and
                              of the start's Gram matrix, slice pairs up to s + t =
-                             slices + 1 (0 = default 7, at most 16)                   */
+                             slices + 1 (0 = default 7, at most 16);
+                             SR_GEMM_OZAKI_CRT: bits of the scaled integers of the
+                             main products (0 = default 55, at most 55)               */
   int update_slices;      /* SR_GEMM_OZAKI_I8: digits per operand of Q * Delta
-                             (0 = chosen per update from ||Delta||_F, 2..7)           */
+                             (0 = chosen per update from ||Delta||_F, 2..7);
+                             SR_GEMM_OZAKI_CRT: bits (0 = from ||Delta||_F, 12..55)   */
   int compensated;        /* 1: chunked K accumulation with error-free (TwoSum)
                              combination in the FP64 products P, That and Y            */
   int gate_lp_terms;      /* 1: skip YW, W^2, W^3 whose Frobenius bound is below
@@ -111,8 +121,8 @@ typedef struct {
   float ms_hp_gemm;       /* with opts.timing: summed time of the hp product launches  */
   int hp_gemm_launches;   /* with opts.timing: number of hp product launches timed     */
   float ms_solve;         /* with opts.timing: summed time of the triangular solves    */
-  int update_slices_hist[16]; /* SR_GEMM_OZAKI_I8: digits used by the Newton-Schulz start
-                             (entry 0) and by updates 1..15                           */
+  int update_slices_hist[16]; /* Ozaki modes: digits (SR_GEMM_OZAKI_CRT: bits) used by
+                             the Newton-Schulz start (entry 0) and by updates 1..15   */
   int hp_gemm_herm_launches; /* with opts.timing: how many of the timed launches were
                              the Hermitian products Y = Q^H Q - I, which form only the
                              tiles on and above the diagonal (half the work)          */
@@ -123,7 +133,8 @@ typedef struct {
                              the INT8 product kernel alone (its digit splits are in
                              ms_hp_gemm only)                                          */
   int oz_full_launches;   /* number of launches timed in ms_oz_full                     */
-  int oz_full_pairs;      /* slice pairs per such launch (s + t <= slices + 1)          */
+  int oz_full_pairs;      /* slice pairs per such launch (s + t <= slices + 1), or the
+                             number of moduli with SR_GEMM_OZAKI_CRT                   */
 } sr_info;
 
 /* Default options: FP64 MFMA, compensated accumulation on, gating on, no trunc. */
@@ -318,6 +329,22 @@ int sr_ozaki_zgemm_dd(int opa, int m, int n, int k, const void* A_hi, const void
                       const void* Cin_lo, int ldcin, void* C_hi, void* C_lo, int ldc,
                       int slices_a, int slices_b, int dmax, void* ws, size_t ws_bytes,
                       void* stream);
+
+/* Ozaki scheme II product (the hp products of Section 3 from an Ozaki-type scheme,
+ * here its CRT form) on INT8 MFMA: C = op(A) B (+ Cin), complex128, arguments as
+ * sr_zgemm. Every row of op(A) and column of B is scaled by a power of two to
+ * integers of at most `bits` bits (rounded to nearest: an error of at most 2^-bits
+ * of the row / column maximum per entry); the residues of those integers modulo
+ * N = sr_crt_moduli(k, bits) pairwise coprime moduli <= 256 are multiplied exactly
+ * in int32, and each output is recovered from its N residues by the Chinese
+ * remainder theorem and rounded once to FP64. Requires k < 65536 and N <= 20
+ * (SR_EINVAL otherwise); bits <= 55 for full FP64 operands.
+ * ws: device workspace of >= sr_crt_ws_bytes(m, n, k, bits). */
+int sr_crt_moduli(int k, int bits);
+size_t sr_crt_ws_bytes(int m, int n, int k, int bits);
+int sr_crt_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+                 const void* Cin, int ldcin, void* C, int ldc, int bits, void* ws, size_t ws_bytes,
+                 void* stream);
 
 /* Diagnostic: one matrix-core instruction (kind 0: v_mfma_f64_16x16x4f64, kind 1:
  * v_mfma_f32_16x16x4f32) on a 16x4 A and a 4x16 B (row-major, host), fed and read

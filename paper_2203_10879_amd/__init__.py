@@ -25,7 +25,7 @@ _LIB = None
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "STAGNATED", 3: "BREAKDOWN", 4: "DIVERGED",
           -1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "ENOSYS"}
-GEMM_MODES = {"fp64": 0, "ozaki_i8": 1, "ozaki_bf16": 2, "ozaki_i8_all": 3}
+GEMM_MODES = {"fp64": 0, "ozaki_i8": 1, "ozaki_bf16": 2, "ozaki_i8_all": 3, "ozaki_crt": 4}
 
 
 class SrOpts(ctypes.Structure):
@@ -88,6 +88,9 @@ _SIGS = {
     "sr_ozaki_zgemm_dd": (_i, [_i, _i, _i, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i,
                                _i, _i, _i, _vp, _sz, _vp]),
     "sr_workspace_bytes_dd": (_sz, [_i, ctypes.POINTER(SrOpts)]),
+    "sr_crt_moduli": (_i, [_i, _i]),
+    "sr_crt_ws_bytes": (_sz, [_i, _i, _i, _i]),
+    "sr_crt_zgemm": (_i, [_i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _vp, _sz, _vp]),
     "sr_workspace_bytes_batched": (_sz, [_i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(SrOpts)]),
     "sr_batched_tile_edge": (_i, [_i]),
     "sr_batched_graph_builds": (_i, []),
@@ -291,6 +294,21 @@ def sr_ozaki_zgemm(A, B, C, opa: int = 0, slices_a: int = 7, slices_b: int = 7, 
                                 _ld(Cin), _mat(C, "c128"), _ld(C),
                                 int(slices_a), int(slices_b), d, ctypes.c_void_p(ws.data_ptr()),
                                 ws.numel() * ws.element_size(), _stream(stream))
+
+
+def sr_crt_zgemm(A, B, C, opa: int = 0, bits: int = 55, Cin=None, ws=None, stream=None) -> int:
+    """Ozaki scheme II (CRT) product on INT8 MFMA (see include/schur_refine.h)."""
+    import torch
+
+    m, n = C.shape
+    k = B.shape[0]
+    need = int(lib().sr_crt_ws_bytes(m, n, k, int(bits)))
+    if ws is None:
+        ws = torch.empty(max(1, need), dtype=torch.uint8, device=C.device)
+    return lib().sr_crt_zgemm(int(opa), m, n, k, _mat(A, "c128"), _ld(A), _mat(B, "c128"), _ld(B),
+                              _mat(Cin, "c128") if Cin is not None else None, _ld(Cin), _mat(C, "c128"),
+                              _ld(C), int(bits), ctypes.c_void_p(ws.data_ptr()),
+                              ws.numel() * ws.element_size(), _stream(stream))
 
 
 def sr_ozaki_zgemm_dd(A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, opa: int = 0, slices_a: int = 14,

@@ -110,6 +110,22 @@ hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t
                    int SB, int conjA, int dmax, GemmArgs g, void* scratch, hipStream_t st,
                    bool dd = false);
 
+// Ozaki scheme II (CRT) products on INT8 MFMA (complex128 operands, FP64 output):
+// rows of op(A) and columns of B scaled to integers of at most `bits` bits, their
+// residues modulo crt_moduli(K, bits) pairwise coprime moduli (the digit-plane
+// layout, one "slice" per modulus), and the product reconstructed from the
+// residues of its sums. K < 65536.
+int crt_moduli(int K, int bits);  // 0: not possible (more than 20 moduli)
+bool crt_plan_ok(int K, int bits);
+size_t crt_residue_bytes(int rows, int K, int N);
+size_t crt_scratch_bytes(int m, int n, int N);
+int crt_gemm_tiles(int m, int n, bool herm);
+hipError_t crt_split_cols(const zc* X, long ld, int K, int ncols, int bits, int8_t* out, int* exps,
+                          hipStream_t st);
+hipError_t crt_split_rows(const zc* X, long ld, int M, int K, int bits, int8_t* out, int* exps, hipStream_t st);
+hipError_t crt_gemm(int epi, const int8_t* A, const int* ta, const int8_t* B, const int* tb, int conjA, int bits,
+                    GemmArgs g, void* scratch, hipStream_t st);
+
 // Triangular matrix equation in FP32 (complex64) and in FP64 (complex128); the
 // workspace size serves both.
 size_t trisolve_ws_bytes(int n);

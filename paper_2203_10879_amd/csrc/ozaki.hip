@@ -34,43 +34,18 @@
 #include <type_traits>
 
 #include "epilogue.hpp"
+#include "ozaki_layout.hpp"
 
 namespace sr {
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int OBM = 128, OBN = 64, OBK = 64, ONT = 512, OLD = 80;
+constexpr int OBM = 128, OBN = 64, ONT = 512, OLD = 80;
 constexpr int kSplitNT = 256;
 
-__host__ __device__ inline int oz_kp(int K) { return (K + OBK - 1) / OBK * OBK; }
-
-// Slice buffers hold three parts per slice: real digits, imaginary digits and the
-// negated imaginary digits (so that a product never negates on the fly). Within a
-// part ("plane"), the digits of 16 rows x 64 K-positions form one contiguous KiB
-// (row-block major, then K-block), so a 64-lane load of 16 bytes per lane moves
-// one whole block; inside a block a row is 64 bytes whose four 16-byte chunks are
-// stored in the order chunk ^ f(row) (f below), which spreads the fragment reads of
-// consecutive rows over the LDS banks after the block is copied as it is.
-constexpr int kParts = 3;
-__host__ __device__ inline int oz_rows_pad(int rows) { return (rows + 15) / 16 * 16; }
-__host__ __device__ inline int chunk_swz(int row) { return ((row >> 1) ^ (row >> 3)) & 3; }
-__host__ __device__ inline long oz_plane_bytes(int rows, int Kp) { return (long)oz_rows_pad(rows) * Kp; }
-// byte of (row, k) inside a plane with KB = Kp / 64 K-blocks
-__device__ inline long oz_off(int row, int k, int KB) {
-  return ((long)(row >> 4) * KB + (k >> 6)) * 1024 + (row & 15) * 64 + ((((k >> 4) & 3) ^ chunk_swz(row)) << 4) +
-         (k & 15);
-}
 size_t oz_slice_bytes(int rows, int K, int S) { return (size_t)S * kParts * oz_plane_bytes(rows, oz_kp(K)); }
 
 // ------------------------------------------------------------------- splitting
 
-__host__ __device__ inline int scale_exponent(double m) {
-  if (!(m > 0)) return 0;
-  int e;
-  frexp(m, &e);  // m = f 2^e, f in [0.5, 1): m < 2^e
-  return e;
-}
 
 // Scale exponent of a row (column) with largest magnitude m: the least e with
 // 256 m / 2^e < 126 (m 256 / 126 is rounded at most twice, which keeps
@@ -550,13 +525,6 @@ constexpr int kRowBytes = 64, kPartBytes = PBM * kRowBytes;            // 8 KiB
 constexpr int kStageBytes = 5 * kPartBytes;                             // 3 A parts + 2 B parts
 constexpr int kLoadsPerWave = 5 * (PBM / 16) / (PNT / 64);              // 10 wave instructions
 
-typedef __attribute__((address_space(3))) void lds_ptr_t;
-typedef __attribute__((address_space(1))) const void gbl_ptr_t;
-
-// s_waitcnt immediates (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4,
-// lgkmcnt 11:8; a field at its maximum does not wait).
-constexpr int kWaitLgkm0 = 0xC07F;                   // lgkmcnt(0)
-constexpr int kWaitVm0 = 0x0F70;                     // vmcnt(0)
 constexpr int kWaitVmStep = 0x0F70 | kLoadsPerWave;  // vmcnt(10): one step in flight
 static_assert(kLoadsPerWave < 16, "vmcnt immediate");
 
@@ -797,8 +765,12 @@ __global__ __launch_bounds__(PNT) __attribute__((amdgpu_waves_per_eu(2))) void o
       first = false;
     }
   }
-  // the ring is free after the last segment: its first bytes hold the block reduction
-  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<PNT>(g, part, (double*)lds, bid);
+  // the ring is free once every wave is past its last fragment read: its first
+  // bytes then hold the block reduction
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) {
+    __syncthreads();
+    epi_reduce<PNT>(g, part, (double*)lds, bid);
+  }
 }
 
 // ------------------------------------------------------ all-pairs product

@@ -40,6 +40,9 @@ int partial_slots(int n) {
 // pairs up to s + t = kOzSlices + 1; the products Q Delta take between kOzMinUpd
 // and kOzMaxUpd, chosen from ||Delta||.
 constexpr int kOzSlices = 7, kOzMinUpd = 2, kOzMaxUpd = 7;
+// CRT mode (Ozaki scheme II): bits of the scaled integers of every operand of the
+// main products (2^-55 of the row maxima, as 7 digits), and the range for Q Delta.
+constexpr int kCrtBits = 55, kCrtMinUpd = 12;
 
 struct Work {
   zc *Qa, *QH, *P, *Y;
@@ -52,15 +55,37 @@ struct Work {
   // slices of Q and column slices of Delta, with their exponents.
   int8_t *sA, *sQc, *sQr, *sD;
   int *eA, *eQc, *eQr, *eD;
-  void* oz_scratch;  // FP64 partial sums of the large-tile product (may be NULL)
+  void* oz_scratch;  // FP64 partial sums of the large-tile product, or the CRT
+                     // product's residues between moduli (may be NULL)
   bool oz_all;  // Ozaki mode: That and Y from slices too
+  bool crt;     // CRT mode: the slices are residues, oz_s and the update counts bits
   int oz_s;
   size_t bytes;
 };
 
+// The split and product steps of the two split forms: digit slices (prec = digits
+// per operand, pairs up to prec + 1) or residues (prec = bits of the scaled
+// integers).
+hipError_t w_split_cols(const Work& w, const zc* X, int n, int prec, int8_t* out, int* e, hipStream_t st) {
+  return w.crt ? crt_split_cols(X, n, n, n, prec, out, e, st) : oz_split_cols(X, nullptr, n, n, n, prec, out, e, st);
+}
+hipError_t w_split_rows(const Work& w, const zc* X, int n, int prec, int8_t* out, int* e, hipStream_t st) {
+  return w.crt ? crt_split_rows(X, n, n, n, prec, out, e, st) : oz_split_rows(X, nullptr, n, n, n, prec, out, e, st);
+}
+hipError_t w_prod(const Work& w, int epi, const int8_t* A, const int* ea, const int8_t* B, const int* eb, int prec,
+                  int conjA, const GemmArgs& g, hipStream_t st) {
+  return w.crt ? crt_gemm(epi, A, ea, B, eb, conjA, prec, g, w.oz_scratch, st)
+               : oz_gemm(epi, A, ea, prec, B, eb, prec, conjA, prec + 1, g, w.oz_scratch, st);
+}
+int w_tiles(const Work& w, int n, bool herm, int prec) {
+  return w.crt ? crt_gemm_tiles(n, n, herm) : oz_gemm_tiles(n, n, n, false, herm, prec, prec, prec + 1);
+}
+
 int oz_main_slices(const sr_opts* o) {
   return (o && o->slices > 0) ? o->slices : kOzSlices;
 }
+
+int crt_main_bits(const sr_opts* o) { return (o && o->slices > 0) ? o->slices : kCrtBits; }
 
 Work carve(void* base, int n, const sr_opts* o = nullptr) {
   Work w;
@@ -93,7 +118,24 @@ Work carve(void* base, int n, const sr_opts* o = nullptr) {
   w.oz_scratch = nullptr;
   w.oz_s = 0;
   w.oz_all = false;
-  if (o && (o->gemm == SR_GEMM_OZAKI_I8 || o->gemm == SR_GEMM_OZAKI_I8_ALL)) {
+  w.crt = false;
+  if (o && o->gemm == SR_GEMM_OZAKI_CRT) {
+    // residues of A's rows, Q's columns, Q's rows and Delta's (and P's) columns
+    // for the main bit count (the update never takes more)
+    w.crt = w.oz_all = true;
+    w.oz_s = crt_main_bits(o);
+    const int N = crt_moduli(n, w.oz_s);
+    const size_t rb = align256(crt_residue_bytes(n, n, N));
+    w.sA = (int8_t*)take(rb);
+    w.sQc = (int8_t*)take(rb);
+    w.sQr = (int8_t*)take(rb);
+    w.sD = (int8_t*)take(rb);
+    w.eA = (int*)take(align256((size_t)n * sizeof(int)));
+    w.eQc = (int*)take(align256((size_t)n * sizeof(int)));
+    w.eQr = (int*)take(align256((size_t)n * sizeof(int)));
+    w.eD = (int*)take(align256((size_t)n * sizeof(int)));
+    w.oz_scratch = take(align256(crt_scratch_bytes(n, n, N)));
+  } else if (o && (o->gemm == SR_GEMM_OZAKI_I8 || o->gemm == SR_GEMM_OZAKI_I8_ALL)) {
     w.oz_all = o->gemm == SR_GEMM_OZAKI_I8_ALL;
     const int S = oz_main_slices(o);
     const int Su = o->update_slices > 0 ? o->update_slices : kOzMaxUpd;
@@ -262,14 +304,14 @@ struct Timer {
 // Ozaki mode: Qout = Q + Q D (QHout = Qout^H if given) from Su slices per operand.
 int oz_update(const zc* Q, const zc* D, zc* Qout, zc* QHout, int n, int Su, const Work& w,
               hipStream_t st) {
-  CK(oz_split_rows(Q, nullptr, n, n, n, Su, w.sQr, w.eQr, st));
-  CK(oz_split_cols(D, nullptr, n, n, n, Su, w.sD, w.eD, st));
+  CK(w_split_rows(w, Q, n, Su, w.sQr, w.eQr, st));
+  CK(w_split_cols(w, D, n, Su, w.sD, w.eD, st));
   GemmArgs u = gargs(n, n, n, nullptr, 0, nullptr, 0, Qout, n);
   u.Cin = Q;
   u.ldcin = n;
   u.CH = QHout;
   u.ldch = n;
-  CK(oz_gemm(EPI_ADD, w.sQr, w.eQr, Su, w.sD, w.eD, Su, 0, Su + 1, u, w.oz_scratch, st));
+  CK(w_prod(w, EPI_ADD, w.sQr, w.eQr, w.sD, w.eD, Su, 0, u, st));
   return SR_OK;
 }
 
@@ -279,6 +321,16 @@ int oz_update(const zc* Q, const zc* D, zc* Qout, zc* QHout, int n, int Su, cons
 // column of Delta ~||Delta||_F / sqrt(n), so the error relative to Q's entries is
 // ~2^(-8 Su) ||Delta||_F, and Su is the least count with that under 0.05 u.
 int update_slices(const sr_opts& o, double norm_delta) {
+  if (o.gemm == SR_GEMM_OZAKI_CRT) {
+    // the same rule in bits: 2^-b ||Delta||_F under 0.05 u
+    if (o.update_slices > 0) return o.update_slices;
+    const int top = crt_main_bits(&o);
+    if (!(norm_delta > 0)) return kCrtMinUpd;
+    int b = (int)ceil(log2(norm_delta / (0.05 * kU64)));
+    if (b < kCrtMinUpd) b = kCrtMinUpd;
+    if (b > top) b = top;
+    return b;
+  }
   if (o.update_slices > 0) return o.update_slices;
   if (!(norm_delta > 0)) return kOzMinUpd;
   const double bits = log2(norm_delta / (0.05 * kU64));
@@ -294,13 +346,13 @@ int ns_init(const zc* Qh, zc* Qout, zc* QHout, int n, int comp, const Work& w, h
     // The Gram matrix Qh^H Qh from the column slices of Qh, used for both operands.
     const int S = w.oz_s;
     TIC(tm, 0);
-    CK(oz_split_cols(Qh, nullptr, n, n, n, S, w.sQc, w.eQc, st));
+    CK(w_split_cols(w, Qh, n, S, w.sQc, w.eQc, st));
     GemmArgs g = gargs(n, n, n, nullptr, 0, nullptr, 0, w.Y, n);
     g.partials = w.partials;
     g.herm = 1;
-    CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, S, w.sQc, w.eQc, S, 1, S + 1, g, w.oz_scratch, st));
+    CK(w_prod(w, EPI_YDEF, w.sQc, w.eQc, w.sQc, w.eQc, S, 1, g, st));
     TOC_HERM(tm);
-    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, false, true, S, S, S + 1), w.scal + 2, st));
+    CK(reduce_partials(w.partials, w_tiles(w, n, true, S), w.scal + 2, st));
     double nrm[3];
     unsigned dst = 0;
     int rc = read_back(st, w, 3, nrm, &dst);
@@ -347,9 +399,9 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
   TIC(tm, 0);
   if (w.oz_s) {
     const int S = w.oz_s;
-    CK(oz_split_cols(Q, nullptr, n, n, n, S, w.sQc, w.eQc, st));
+    CK(w_split_cols(w, Q, n, S, w.sQc, w.eQc, st));
     TIC(tm, 2);
-    CK(oz_gemm(EPI_STORE, w.sA, w.eA, S, w.sQc, w.eQc, S, 0, S + 1, g, w.oz_scratch, st));
+    CK(w_prod(w, EPI_STORE, w.sA, w.eA, w.sQc, w.eQc, S, 0, g, st));
     TOC(tm, 2);
   } else {
     CK(zgemm(0, EPI_STORE, comp, g, st));
@@ -358,12 +410,12 @@ int residual(const zc* A, const zc* Q, const zc* QH, zc* T, int n, int comp, con
   if (w.oz_all) {
     const int S = w.oz_s;
     TIC(tm, 0);
-    CK(oz_split_cols(w.P, nullptr, n, n, n, S, w.sD, w.eD, st));
+    CK(w_split_cols(w, w.P, n, S, w.sD, w.eD, st));
     TIC(tm, 2);
-    CK(oz_gemm(EPI_SPLIT, w.sQc, w.eQc, S, w.sD, w.eD, S, 1, S + 1, s, w.oz_scratch, st));
+    CK(w_prod(w, EPI_SPLIT, w.sQc, w.eQc, w.sD, w.eD, S, 1, s, st));
     TOC(tm, 2);
     TOC(tm, 0);
-    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, false, false, S, S, S + 1), w.scal + 1, st));
+    CK(reduce_partials(w.partials, w_tiles(w, n, false, S), w.scal + 1, st));
     return SR_OK;
   }
   TIC(tm, 0);
@@ -382,9 +434,9 @@ int ydef(const zc* Q, const zc* QH, int n, int comp, const Work& w, hipStream_t 
   if (w.oz_all) {
     const int S = w.oz_s;
     TIC(tm, 0);
-    CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, S, w.sQc, w.eQc, S, 1, S + 1, g, w.oz_scratch, st));
+    CK(w_prod(w, EPI_YDEF, w.sQc, w.eQc, w.sQc, w.eQc, S, 1, g, st));
     TOC_HERM(tm);
-    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, false, true, S, S, S + 1), w.scal + 2, st));
+    CK(reduce_partials(w.partials, w_tiles(w, n, true, S), w.scal + 2, st));
     return SR_OK;
   }
   TIC(tm, 0);
@@ -566,8 +618,14 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
   sr_opts o;
   if (opts_in) o = *opts_in;
   else sr_default_opts(&o);
+  const bool crt = o.gemm == SR_GEMM_OZAKI_CRT;
   const bool ozaki = o.gemm == SR_GEMM_OZAKI_I8 || o.gemm == SR_GEMM_OZAKI_I8_ALL;
-  if (o.gemm != SR_GEMM_FP64 && !ozaki) {
+  if (crt && (o.slices < 0 || o.slices > kCrtBits || o.update_slices < 0 || o.update_slices > crt_main_bits(&o) ||
+              !crt_plan_ok(n, crt_main_bits(&o)))) {
+    if (info) info->status = SR_EINVAL;
+    return SR_EINVAL;
+  }
+  if (o.gemm != SR_GEMM_FP64 && !ozaki && !crt) {
     if (info) info->status = o.gemm == SR_GEMM_OZAKI_BF16 ? SR_ENOSYS : SR_EINVAL;
     return o.gemm == SR_GEMM_OZAKI_BF16 ? SR_ENOSYS : SR_EINVAL;
   }
@@ -633,7 +691,7 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
     CK(hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming));
     CK(hipEventCreateWithFlags(&ev.join, hipEventDisableTiming));
   }
-  if (w.oz_s) CK(oz_split_rows(A, nullptr, n, n, n, w.oz_s, w.sA, w.eA, st));
+  if (w.oz_s) CK(w_split_rows(w, A, n, w.oz_s, w.sA, w.eA, st));
   int su = 0;
   // the explicit Q^H serves the native That and Y; with oz_all they use the column
   // slices of Q instead
@@ -730,7 +788,7 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
       info->ms_solve = timer.total(1);
       info->ms_oz_full = timer.total(2);
       info->oz_full_launches = timer.count[2];
-      info->oz_full_pairs = w.oz_s ? w.oz_s * (w.oz_s + 1) / 2 : 0;
+      info->oz_full_pairs = w.crt ? crt_moduli(n, w.oz_s) : w.oz_s ? w.oz_s * (w.oz_s + 1) / 2 : 0;
     }
   }
   return status;
@@ -1204,6 +1262,41 @@ int sr_ozaki_zgemm(int opa, int m, int n, int k, const void* A, int lda, const v
   g.Cin = Cin;
   g.ldcin = ldcin;
   CK(oz_gemm(Cin ? EPI_ADD : EPI_STORE, qa, ea, slices_a, qb, eb, slices_b, opa, dmax, g, scr, st));
+  return SR_OK;
+}
+
+int sr_crt_moduli(int k, int bits) { return (k < 1 || bits < 1 || k >= 65536) ? 0 : crt_moduli(k, bits); }
+
+size_t sr_crt_ws_bytes(int m, int n, int k, int bits) {
+  const int N = sr_crt_moduli(k, bits);
+  if (m < 0 || n < 0 || !N) return 0;
+  return align256(crt_residue_bytes(m, k, N)) + align256(crt_residue_bytes(n, k, N)) +
+         align256((size_t)(m + n) * sizeof(int)) + align256(crt_scratch_bytes(m, n, N));
+}
+
+int sr_crt_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb, const void* Cin,
+                 int ldcin, void* C, int ldc, int bits, void* ws, size_t ws_bytes, void* stream) {
+  if (m < 0 || n < 0 || k < 0 || (opa != 0 && opa != 1) || !C) return SR_EINVAL;
+  if (m == 0 || n == 0) return SR_OK;
+  if (k > 0 && (!A || !B)) return SR_EINVAL;
+  if (k < 1 || !sr_crt_moduli(k, bits)) return SR_EINVAL;
+  if (lda < (opa ? k : (m > 1 ? m : 1)) || ldb < k || ldc < m) return SR_EINVAL;
+  if (Cin && ldcin < m) return SR_EINVAL;
+  if (!ws || ws_bytes < sr_crt_ws_bytes(m, n, k, bits)) return SR_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  const int N = crt_moduli(k, bits);
+  int8_t* ra = (int8_t*)ws;
+  int8_t* rb = ra + align256(crt_residue_bytes(m, k, N));
+  int* ta = (int*)(rb + align256(crt_residue_bytes(n, k, N)));
+  int* tb = ta + m;
+  void* scr = (int8_t*)ta + align256((size_t)(m + n) * sizeof(int));
+  if (opa == 0) CK(crt_split_rows((const zc*)A, lda, m, k, bits, ra, ta, st));
+  else CK(crt_split_cols((const zc*)A, lda, k, m, bits, ra, ta, st));
+  CK(crt_split_cols((const zc*)B, ldb, k, n, bits, rb, tb, st));
+  GemmArgs g = gargs(m, n, k, nullptr, 0, nullptr, 0, C, ldc);
+  g.Cin = Cin;
+  g.ldcin = ldcin;
+  CK(crt_gemm(Cin ? EPI_ADD : EPI_STORE, ra, ta, rb, tb, opa, bits, g, scr, st));
   return SR_OK;
 }
 

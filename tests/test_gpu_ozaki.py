@@ -217,3 +217,97 @@ def test_ozaki_allpairs_exact_with_digit_carries(sr, opa):
     assert sr.sr_ozaki_zgemm(dev(a), dev(b), c, opa=opa, slices_a=3, slices_b=3, dmax=4) == 0
     ref = (a.conj().T if opa else a) @ b
     assert np.array_equal(host(c), ref)
+
+
+# ------------------------------------------------------------ Ozaki scheme II (CRT)
+
+def test_crt_moduli_count(sr):
+    """N is the least count of the moduli 256, 255, 253, 251, ... whose product M
+    exceeds 8 K 2^(2 bits) (host call, no GPU work)."""
+    mods = [256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199, 197, 193, 191, 181, 179, 173]
+    for k, bits in [(4096, 55), (8192, 55), (64, 55), (1000, 30), (100, 12), (65535, 55)]:
+        n = sr.lib().sr_crt_moduli(k, bits)
+        prod = 1
+        for m in mods[:n]:
+            prod *= m
+        lk = (k - 1).bit_length()
+        assert prod >= 2 ** (2 * bits + lk + 3)
+        assert n == 1 or prod // mods[n - 1] < 2 ** (2 * bits + lk + 3)
+    assert sr.lib().sr_crt_moduli(4096, 55) == 16
+    assert sr.lib().sr_crt_moduli(65536, 55) == 0  # int32 sums would not stay exact
+    assert sr.lib().sr_crt_moduli(4096, 80) == 0  # more than 20 moduli
+
+
+@pytest.mark.parametrize("add", [False, True])
+@pytest.mark.parametrize("opa", [0, 1])
+@pytest.mark.parametrize("shape", [(130, 97, 75), (128, 128, 64), (1, 1, 1), (257, 33, 200)])
+def test_crt_exact_on_integers(sr, opa, shape, add):
+    """Gaussian integers of at most 21 bits are scaled exactly (55 bits per entry
+    hold them), so the residue products and the reconstruction give the exact
+    product, which FP64 holds (|sum| < 2^52): bit-exact, ragged tiles, op(A) = A
+    and A^H, with and without the added C."""
+    m, n, k = shape
+    rng = np.random.default_rng(3 * m + 5 * n + 7 * k + opa + 11 * add)
+    a = _gauss_int(rng, (k, m) if opa else (m, k), 2**20)
+    b = _gauss_int(rng, (k, n), 2**20)
+    c0 = _gauss_int(rng, (m, n), 2**30) if add else None
+    c = empty(m, n)
+    assert sr.sr_crt_zgemm(dev(a), dev(b), c, opa=opa, bits=55, Cin=dev(c0) if add else None) == 0
+    ref = (a.conj().T if opa else a) @ b
+    if add:
+        ref = ref + c0
+    assert np.array_equal(host(c), ref)
+
+
+def _crt_bound(a_op, b, bits):
+    """Entrywise bound of the CRT product: each entry of a row (column) is rounded to
+    a multiple of 2^t with 2^t <= 2^-bits of twice the row (column) maximum (an
+    error of 2^(t-1) in re and in im), plus the final rounding to FP64."""
+    def scale(mx):
+        e = np.where(mx > 0, np.frexp(mx)[1], 0)
+        return np.ldexp(1.0, e - bits)  # 2^t
+    ra = scale(np.maximum(np.abs(a_op.real), np.abs(a_op.imag)).max(axis=1))
+    cb = scale(np.maximum(np.abs(b.real), np.abs(b.imag)).max(axis=0))
+    da = np.sqrt(2) * 0.5 * ra[:, None] * np.ones_like(a_op.real)
+    db = np.sqrt(2) * 0.5 * cb[None, :] * np.ones_like(b.real)
+    return da @ np.abs(b) + np.abs(a_op) @ db + da @ db
+
+
+@pytest.mark.parametrize("opa", [0, 1])
+@pytest.mark.parametrize("bits", [55, 30])
+def test_crt_random_within_bound_of_quad(sr, opa, bits):
+    rng = np.random.default_rng(41 + opa + bits)
+    m, n, k = 150, 131, 260
+    a = rand_c(rng, (k, m) if opa else (m, k))
+    a[3] *= 1e-9  # rows and columns of very different scales
+    b = rand_c(rng, (k, n))
+    b[:, 7] *= 1e12
+    c = empty(m, n)
+    assert sr.sr_crt_zgemm(dev(a), dev(b), c, opa=opa, bits=bits) == 0
+    chi, clo = oracle.gemm(a, b, opa=opa).to_dd()
+    err = np.abs((host(c) - chi) - clo)
+    a_op = a.conj().T if opa else a
+    bound = _crt_bound(a_op, b, bits) + 1.01 * U64 * np.abs(chi)
+    assert np.all(err <= bound), (err / bound).max()
+    # the bound is met with little room: the error is of the order of the input rounding
+    if bits == 30:
+        assert np.median(err / bound) >= 1e-3
+
+
+def test_crt_n2048_rows_against_quad(sr):
+    """A product with 256 output tiles of 128 x 128 (every CU busy): sampled rows
+    against the binary128 product, and more accurate than native FP64."""
+    rng = np.random.default_rng(9)
+    n = 2048
+    a, b = rand_c(rng, (n, n)), rand_c(rng, (n, n))
+    c = empty(n, n)
+    assert sr.sr_crt_zgemm(dev(a), dev(b), c, bits=55) == 0
+    rows = np.sort(rng.choice(n, 6, replace=False))
+    chi, clo = oracle.gemm(np.asfortranarray(a[rows]), b).to_dd()
+    err = np.abs((host(c)[rows] - chi) - clo)
+    bound = _crt_bound(a[rows], b, 55) + 1.01 * U64 * np.abs(chi)
+    assert np.all(err <= bound)
+    cf = empty(n, n)
+    assert sr.sr_zgemm(dev(a), dev(b), cf) == 0
+    err64 = np.abs((host(cf)[rows] - chi) - clo)
+    assert np.linalg.norm(err) < np.linalg.norm(err64)
