@@ -62,6 +62,11 @@ def lib():
         L.orc_schur_qr.argtypes = [i32, i32, vp, vp, vp]
         L.orc_schur_qr.restype = i32
         L.orc_reorder.argtypes = [i32, vp, vp, f64, vp, vp]
+        L.orc_trisolve_real.argtypes = [i32, i32, vp, vp, vp, vp]
+        L.orc_trisolve_real.restype = i32
+        L.orc_refine_real.argtypes = [i32, i32, vp, vp, vp, i32, f64, vp, vp, vp, vp]
+        L.orc_refine_real.restype = i32
+        L.orc_eval_real.argtypes = [i32, vp, vp, vp, vp, vp]
         _LIB = L
     return _LIB
 
@@ -193,3 +198,45 @@ def schur_qr(a, lp: str = "float"):
     if rc != 0:
         raise RuntimeError("QR algorithm did not converge")
     return z.to_c128(), s.to_c128()
+
+
+# ------------------------------------------------------------ real Schur variant
+
+def _blk(blk, n):
+    b = np.zeros(n, dtype=np.int32) if blk is None else np.ascontiguousarray(np.asarray(blk, dtype=np.int32))
+    assert b.size == n
+    return b
+
+
+def trisolve_real(t, e, blk, lp: str = "float"):
+    """Block strictly lower L with block-stril(T L - L T) = -E (real Schur form with
+    2 x 2 blocks marked by blk), solved in lp; returns (L as QMat, status)."""
+    t, e = _q(t), _q(e)
+    n = t.n
+    b = _blk(blk, n)
+    out = QMat(n, n)
+    rc = lib().orc_trisolve_real(LP[lp], n, b.ctypes.data, t.ptr, e.ptr, out.ptr)
+    return out, STATUS.get(rc, rc)
+
+
+def refine_real(a, qh, blk, lp: str = "float", maxit: int = 6, tol: float = 1e-15) -> dict:
+    """Algorithm 4 for the real Schur form (2 x 2 blocks marked by blk)."""
+    a, qh = _q(a), _q(qh)
+    n = a.n
+    b = _blk(blk, n)
+    qo, to = QMat(n, n), QMat(n, n)
+    hist = np.zeros(maxit, dtype=np.float64)
+    it = ctypes.c_int(0)
+    rc = lib().orc_refine_real(LP[lp], n, a.ptr, qh.ptr, b.ctypes.data, int(maxit), float(tol), qo.ptr, to.ptr,
+                               hist.ctypes.data, ctypes.byref(it))
+    return {"Q": qo, "T": to, "hist": hist[: it.value].copy(), "iters": it.value, "status": STATUS.get(rc, rc)}
+
+
+def evaluate_real(a, q, t, blk) -> dict:
+    """Binary128 checks with the block strictly lower part of the real Schur form."""
+    a, q = _q(a), _q(q)
+    tq = _q(t) if t is not None else None
+    b = _blk(blk, a.n)
+    out = np.zeros(4, dtype=np.float64)
+    lib().orc_eval_real(a.n, a.ptr, q.ptr, tq.ptr if tq is not None else None, b.ctypes.data, out.ctypes.data)
+    return {"stril": out[0], "orth": out[1], "tdiff": out[2], "normA": out[3]}

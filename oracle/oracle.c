@@ -515,3 +515,183 @@ void orc_reorder(int n, const orc_qc* A, const orc_qc* Qh, double theta, orc_qc*
   free(T);
   free(P);
 }
+
+/* ------------------------------------------------------- real Schur variant */
+/* Block starts from the 2 x 2 markers: blk[i] = 1 when rows and columns i, i + 1
+ * form one diagonal block. Returns the block count, or -1 for an invalid marker
+ * (a block past the end, or overlapping blocks). */
+static int real_blocks(int n, const int* blk, int* bs)
+{
+  int nb = 0;
+  for (int i = 0; i < n;) {
+    bs[nb++] = i;
+    if (blk && blk[i]) {
+      if (i + 1 >= n || blk[i + 1]) return -1;
+      i += 2;
+    } else {
+      i += 1;
+    }
+  }
+  bs[nb] = n;
+  return nb;
+}
+
+/* whether (i, j), i > j, lies in the block strictly lower part */
+static int below_blocks(int i, int j, const int* blk) { return i > j && !(i == j + 1 && blk && blk[j]); }
+
+int orc_trisolve_real(int lp, int n, const int* blk, const orc_qc* T, const orc_qc* E, orc_qc* L)
+{
+  long nn = (long)n * n;
+  int* bs = (int*)xmalloc(sizeof(int) * (size_t)(n + 1));
+  int nb = real_blocks(n, blk, bs);
+  if (nb < 0) {
+    free(bs);
+    return ORC_BREAKDOWN;
+  }
+  int rc;
+  if (lp == ORC_LP_FLOAT) {
+    float *t = (float*)xmalloc(sizeof(float) * nn), *e = (float*)xmalloc(sizeof(float) * nn),
+          *l = (float*)xmalloc(sizeof(float) * nn);
+    for (long z = 0; z < nn; z++) {
+      t[z] = (float)T[z].re;
+      e[z] = (float)E[z].re;
+    }
+    rc = trisolve_real_f(n, nb, bs, t, e, l);
+    for (long z = 0; z < nn; z++) L[z] = qc_mk((quad)l[z], 0);
+    free(t);
+    free(e);
+    free(l);
+  } else if (lp == ORC_LP_DOUBLE) {
+    double *t = (double*)xmalloc(sizeof(double) * nn), *e = (double*)xmalloc(sizeof(double) * nn),
+           *l = (double*)xmalloc(sizeof(double) * nn);
+    for (long z = 0; z < nn; z++) {
+      t[z] = (double)T[z].re;
+      e[z] = (double)E[z].re;
+    }
+    rc = trisolve_real_d(n, nb, bs, t, e, l);
+    for (long z = 0; z < nn; z++) L[z] = qc_mk((quad)l[z], 0);
+    free(t);
+    free(e);
+    free(l);
+  } else {
+    quad *t = (quad*)xmalloc(sizeof(quad) * nn), *e = (quad*)xmalloc(sizeof(quad) * nn),
+         *l = (quad*)xmalloc(sizeof(quad) * nn);
+    memset(t, 0, sizeof(quad) * nn);
+    memset(e, 0, sizeof(quad) * nn);
+    for (long z = 0; z < nn; z++) {
+      t[z] = T[z].re;
+      e[z] = E[z].re;
+    }
+    rc = trisolve_real_q(n, nb, bs, t, e, l);
+    for (long z = 0; z < nn; z++) L[z] = qc_mk(l[z], 0);
+    free(t);
+    free(e);
+    free(l);
+  }
+  free(bs);
+  return rc;
+}
+
+int orc_refine_real(int lp, int n, const orc_qc* A, const orc_qc* Qh, const int* blk, int maxit, double tol,
+                    orc_qc* Qout, orc_qc* Tout, double* hist, int* iters)
+{
+  long nn = (long)n * n;
+  orc_qc* Q = NEWQ(nn);
+  orc_qc* Qn = NEWQ(nn);
+  orc_qc* AQ = NEWQ(nn);
+  orc_qc* Th = NEWQ(nn);
+  orc_qc* T = NEWQ(nn);
+  orc_qc* E = NEWQ(nn);
+  orc_qc* L = NEWQ(nn);
+  orc_qc* W = NEWQ(nn);
+  int status = ORC_NOT_CONVERGED, passes = 0;
+  /* real data stay real through the complex products: every imaginary part is 0 */
+  orc_ns(n, Qh, Q);
+  quad normA = sqrtq(fro2(A, nn));
+  for (int p = 0; p < maxit; p++) {
+    orc_gemm(0, n, n, n, A, Q, AQ); /* That = Q^T A Q */
+    orc_gemm(1, n, n, n, Q, AQ, Th);
+    for (int j = 0; j < n; j++) /* E = the block strictly lower part, T = That - E */
+      for (int i = 0; i < n; i++) {
+        long z = i + (long)j * n;
+        int low = below_blocks(i, j, blk);
+        E[z] = low ? Th[z] : qc_mk(0, 0);
+        T[z] = low ? qc_mk(0, 0) : Th[z];
+      }
+    quad eps = sqrtq(fro2(E, nn)) / normA;
+    hist[p] = (double)eps;
+    passes = p + 1;
+    memcpy(Tout, T, sizeof(orc_qc) * (size_t)nn);
+    if (!quad_finite(eps)) {
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    if (eps <= (quad)tol) {
+      status = ORC_OK;
+      break;
+    }
+    if (p >= 2 && hist[p] > hist[p - 1] && hist[p - 1] > hist[p - 2]) {
+      status = ORC_DIVERGED;
+      break;
+    }
+    if (p == maxit - 1) break;
+    if (orc_trisolve_real(lp, n, blk, T, E, L) != ORC_OK) {
+      status = ORC_BREAKDOWN;
+      break;
+    }
+    for (int j = 0; j < n; j++) /* W = L - L^T */
+      for (int i = 0; i < n; i++) W[i + (long)j * n] = qc_mk(L[i + (long)j * n].re - L[j + (long)i * n].re, 0);
+    orc_ns_merged(lp, n, Q, W, 0, Qn);
+    orc_qc* tmp = Q;
+    Q = Qn;
+    Qn = tmp;
+  }
+  memcpy(Qout, Q, sizeof(orc_qc) * (size_t)nn);
+  *iters = passes;
+  free(Q);
+  free(Qn);
+  free(AQ);
+  free(Th);
+  free(T);
+  free(E);
+  free(L);
+  free(W);
+  return status;
+}
+
+void orc_eval_real(int n, const orc_qc* A, const orc_qc* Q, const orc_qc* T, const int* blk, double out[4])
+{
+  long nn = (long)n * n;
+  orc_qc* AQ = NEWQ(nn);
+  orc_qc* Th = NEWQ(nn);
+  orc_qc* G = NEWQ(nn);
+  orc_gemm(0, n, n, n, A, Q, AQ);
+  orc_gemm(1, n, n, n, Q, AQ, Th);
+  orc_gemm(1, n, n, n, Q, Q, G);
+  quad s = 0, o = 0, t = 0;
+  for (int j = 0; j < n; j++)
+    for (int i = 0; i < n; i++) {
+      long z = i + (long)j * n;
+      int low = below_blocks(i, j, blk);
+      if (low) s += qc_abs2(Th[z]);
+      orc_qc g = G[z];
+      if (i == j) g.re -= 1;
+      o += qc_abs2(g);
+      if (T) {
+        orc_qc d = T[z];
+        if (!low) {
+          d.re -= Th[z].re;
+          d.im -= Th[z].im;
+        }
+        t += qc_abs2(d);
+      }
+    }
+  quad normA = sqrtq(fro2(A, nn));
+  out[0] = (double)(sqrtq(s) / normA);
+  out[1] = (double)sqrtq(o);
+  out[2] = (double)sqrtq(t);
+  out[3] = (double)normA;
+  free(AQ);
+  free(Th);
+  free(G);
+}

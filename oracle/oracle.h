@@ -125,6 +125,31 @@ int orc_schur_qr(int lp, int n, const orc_qc* A, orc_qc* Z, orc_qc* S);
  * order; and the 2 x 2 closed form. */
 void orc_reorder(int n, const orc_qc* A, const orc_qc* Qh, double theta, orc_qc* Qout, int* perm);
 
+/* Real Schur variant (Section 3: the method extended to the real Schur form, whose
+ * triangular factor has 2 x 2 diagonal blocks holding complex conjugate pairs).
+ * Matrices are real: complex records with zero imaginary parts. blk (n ints): blk[i]
+ * = 1 when rows and columns i, i + 1 form one 2 x 2 diagonal block, 0 otherwise (NULL:
+ * no 2 x 2 blocks). The block strictly lower part of a matrix is every (i, j), i > j,
+ * except the subdiagonal entry of a 2 x 2 block.
+ *
+ * orc_trisolve_real: the block form of the triangular matrix equation, block
+ * stril(T L - L T) = -E, for block strictly lower L, in lp (see trisolve_real in
+ * oracle_lp.inc). Returns ORC_OK or ORC_BREAKDOWN (a singular small equation: two
+ * blocks sharing an eigenvalue, or an invalid marker). Pinned by the scalar solve on
+ * 1 x 1 blocks and by exact rational solutions of the full Kronecker system.
+ *
+ * orc_refine_real: Algorithm 4 with the block strictly lower part as E, the block
+ * solve, W = L - L^T and the merged update (the same steps on real data).
+ * Pinned by exact real Schur forms with 2 x 2 blocks (the invariant subspaces and
+ * the block eigenvalues recovered), the FP32-lp convergence law, and agreement with
+ * the complex refinement when every block is 1 x 1.
+ *
+ * orc_eval_real: orc_eval with the block strictly lower part. */
+int orc_trisolve_real(int lp, int n, const int* blk, const orc_qc* T, const orc_qc* E, orc_qc* L);
+int orc_refine_real(int lp, int n, const orc_qc* A, const orc_qc* Qh, const int* blk, int maxit, double tol,
+                    orc_qc* Qout, orc_qc* Tout, double* hist, int* iters);
+void orc_eval_real(int n, const orc_qc* A, const orc_qc* Q, const orc_qc* T, const int* blk, double out[4]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,9 @@ from .generator import (  # noqa: F401
     example3_matrix,
     batched_sizes,
     batched_inputs,
+    real_schur_test_matrix,
+    real_blocks_of,
+    lp_real_schur_start,
     continuation_step_dd,
     continuation_perturbation,
     to_dd,

@@ -212,6 +212,79 @@ def batched_sizes(count: int = 2000, seed: int = 3, lo: int = 16, hi: int = 256)
     return lo + np.random.default_rng(seed).integers(0, hi - lo + 1, size=count)
 
 
+def real_schur_test_matrix(n: int, seed: int, gap: float = 0.05, pair_frac: float = 0.5) -> dict:
+    """Real A = Q0 T0 Q0^T with a real quasi-triangular T0 (the real Schur form).
+
+    Draws from `default_rng(seed)`: the n x n real normal matrix behind the Haar
+    orthogonal Q0 (QR with the signs of diag(R) moved into Q), then the spectrum
+    (sequential gap rejection on complex normal draws, as for the complex
+    generator; about `pair_frac` of the eigenvalues as conjugate pairs a +- ib with
+    |b| >= gap / 2, the rest real), then the strictly upper part N(0,1)/sqrt(n).
+    A pair sits in a standardized 2 x 2 block [[a, b c], [-b / c, a]] (c drawn in
+    [0.5, 2]); blk[i] = 1 marks a block at rows and columns i, i + 1."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((n, n))
+    q, r = np.linalg.qr(z)
+    q0 = np.asfortranarray(q * np.sign(np.diag(r))[None, :])
+    lam = []  # eigenvalues in block order
+    blk = np.zeros(n, dtype=np.int32)
+    t0 = np.zeros((n, n))
+    i = 0
+    while i < n:
+        pair = i + 1 < n and rng.random() < pair_frac
+        while True:
+            w = cn(rng, 1)[0]
+            cand = [complex(w.real, abs(w.imag)), complex(w.real, -abs(w.imag))] if pair else [complex(w.real, 0.0)]
+            if pair and abs(w.imag) < gap / 2:
+                continue
+            if all(min((abs(c - l) for l in lam), default=np.inf) > gap for c in cand):
+                break
+        if pair:
+            a, b = w.real, abs(w.imag)
+            c = 0.5 + 1.5 * rng.random()
+            t0[i, i] = t0[i + 1, i + 1] = a
+            t0[i, i + 1] = b * c
+            t0[i + 1, i] = -b / c
+            blk[i] = 1
+            lam += cand
+            i += 2
+        else:
+            t0[i, i] = w.real
+            lam += cand
+            i += 1
+    u = rng.standard_normal((n, n)) / math.sqrt(n)
+    for j in range(n):
+        for k in range(j):
+            if not (j == k + 1 and blk[k]):
+                t0[k, j] = u[k, j]
+    a = (q0 @ t0) @ q0.T
+    return {"A": np.asfortranarray(a), "Q0": q0, "T0": np.asfortranarray(t0), "blk": blk,
+            "lam": np.array(lam), "n": n, "seed": seed, "gap": gap}
+
+
+def real_blocks_of(t: np.ndarray) -> np.ndarray:
+    """2 x 2 block markers of a real quasi-triangular T (nonzero subdiagonal entries)."""
+    n = t.shape[0]
+    blk = np.zeros(n, dtype=np.int32)
+    i = 0
+    while i < n - 1:
+        if t[i + 1, i] != 0:
+            blk[i] = 1
+            i += 2
+        else:
+            i += 1
+    return blk
+
+
+def lp_real_schur_start(a: np.ndarray):
+    """Real Schur vectors of float32(A) from LAPACK sgees, widened to float64, and the
+    2 x 2 block markers of the float32 quasi-triangular factor."""
+    import scipy.linalg as sl
+
+    t, z = sl.schur(np.asarray(a, dtype=np.float32), output="real")
+    return np.asfortranarray(z.astype(np.float64)), real_blocks_of(t)
+
+
 def _batched_one(item):
     n, seed = item
     g = schur_test_matrix(n, seed=seed)
