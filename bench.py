@@ -24,7 +24,10 @@ Other workloads (--workload), each one JSON line of its own:
                   matrices/s and the p50 / p99 pass counts;
   dd_continuation A(t_k) = A0 + (k/64) A1, n = 2048, k = 0..63, double-double
                   tier to 1e-28, each step warm-started from the previous one,
-                  the first from the zgees Schur form of A0.
+                  the first from the zgees Schur form of A0;
+  real            the real Schur form of a real n = 2048 matrix (about sqrt(2n/pi)
+                  real eigenvalues, conjugate pairs in 2 x 2 blocks, gaps >= 0.05),
+                  sgees start, FP64 tier, real FP64 products.
 
 `roofline` covers the dominant kernel of the chosen form, timed with HIP events
 on the library's stream during the timed steps: the FP64 GEMM against the FP64
@@ -597,6 +600,105 @@ def run_dd_continuation(args) -> int:
     return 0 if ok else 1
 
 
+REAL_SOURCES = ("real.hip", "real.hpp", "epilogue.hpp", "kernels.hpp", "common.hpp")
+
+
+def run_real(args) -> int:
+    """The real Schur variant: one real matrix with the spectrum structure of a real
+    Gaussian matrix (about sqrt(2n/pi) real eigenvalues, the rest conjugate pairs in
+    2 x 2 blocks, gaps >= 0.05, seed 3), started from the real Schur vectors of
+    float32(A) (LAPACK sgees), FP64 tier to 1e-15."""
+    import torch
+
+    import oracle
+    import paper_2203_10879_amd as sr
+    import synth
+
+    n = 2048 if args.n is None else args.n
+    t0 = time.perf_counter()
+    g = synth.real_schur_test_matrix(n, seed=3, gap=0.05)
+    qh, blk = synth.lp_real_schur_start(g["A"])
+    print(f"# inputs n={n} ready in {time.perf_counter() - t0:.1f} s ({int(blk.sum())} 2x2 blocks)",
+          file=sys.stderr, flush=True)
+    torch.cuda.set_device(torch.device("cuda:0"))
+    A, Q0 = sr.colmajor(g["A"]), sr.colmajor(qh)
+    Q, T = sr.colmajor_empty(n, n, torch.float64), sr.colmajor_empty(n, n, torch.float64)
+    ws = sr.workspace_real(n)
+    stream = torch.cuda.current_stream()
+
+    def step(timing=False):
+        Q.copy_(Q0)
+        return sr.schur_refine_real(A, Q, T, blk, iters=8, tol=TOL, timing=timing, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    infos = []
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(step(timing=True))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    ok = all(i["status"] == "OK" for i in infos)
+    steps = args.steps
+    ms = sum(i["ms_hp_gemm"] - i["ms_hp_gemm_herm"] for i in infos)
+    cnt = sum(i["hp_gemm_launches"] - i["hp_gemm_herm_launches"] for i in infos)
+    herm = sum(i["hp_gemm_herm_launches"] for i in infos)
+    avg = ms / max(1, cnt)
+    achieved = 2.0 * n ** 3 / (avg * 1e-3) / 1e12
+    last = infos[-1]
+    out = base_record(args, steps / dt if ok else 0.0, "decomps/s", 1e3 * dt / steps, "f64",
+                      {"workload": f"real Schur form, single real matrix n={n} (about sqrt(2n/pi) real "
+                                   "eigenvalues, the rest conjugate pairs in 2x2 blocks, gaps >= 0.05, seed 3), "
+                                   "FP32 sgees start, FP64 tier (FP64 MFMA products, FP32 block solve), "
+                                   "tol 1e-15",
+                       "n": n, "tol": TOL, "blocks_2x2": int(blk.sum()), "parallelism": "1 GPU"})
+    out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / FP64_PEAK_TFLOPS,
+                       "traffic": pmc_traffic(f"real_gemm_n{n}_hbm_traffic.txt", "traffic_bytes_per_launch",
+                                              REAL_SOURCES),
+                       "traffic_unit": ("HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, "
+                                        "calibrated on a copy kernel)"),
+                       "kernel": "real FP64 GEMM (rgemm_kernel<double,...>), full products P, That, Q Delta: "
+                                 "2n^3 flop per launch",
+                       "avg_launch_ms": avg, "launches_per_step": cnt / steps,
+                       "symmetric_products": {"launches_per_step": herm / steps,
+                                              "avg_launch_ms": sum(i["ms_hp_gemm_herm"] for i in infos)
+                                              / max(1, herm),
+                                              "flop_per_launch": 1.0 * n * n * (n + 1)}}
+    solves = sum(i["updates"] for i in infos)
+    out.update({"passes": last["iters"], "hp_gemms": last["hp_gemms"], "resid_hist": last["resid_hist"],
+                "ms_hp_gemm_per_step": sum(i["ms_hp_gemm"] for i in infos) / steps,
+                "ms_solve_per_step": sum(i["ms_solve"] for i in infos) / steps,
+                "ms_per_solve": sum(i["ms_solve"] for i in infos) / max(1, solves),
+                "all_converged": ok})
+    if args.rows > 0:
+        # binary128 check on sampled rows: the block strictly lower entries of
+        # Q_r^T A Q and the rows of Q_r^T Q - I
+        step()
+        torch.cuda.synchronize()
+        q = sr.to_numpy(Q)
+        rows = np.sort(np.random.default_rng(8).choice(n, args.rows, replace=False))
+        qr = np.asfortranarray(q[:, rows]).astype(complex)
+        rh, rl = oracle.gemm(qr, g["A"].astype(complex), opa=1).to_dd()
+        mh, ml = oracle.gemm(np.asfortranarray(rh), q.astype(complex)).to_dd()
+        m2h, m2l = oracle.gemm(np.asfortranarray(rl), q.astype(complex)).to_dd()
+        m = (mh.real + m2h.real) + (ml.real + m2l.real)
+        mask = np.tril(np.ones((n, n), dtype=bool), -1)[rows]
+        for i in np.nonzero(blk)[0]:
+            mask[rows == i + 1, i] = False
+        stril = float(np.sqrt(np.sum(m[mask] ** 2) * n / len(rows)) / np.linalg.norm(g["A"]))
+        oh, ol = oracle.gemm(qr, q.astype(complex), opa=1).to_dd()
+        o = oh.real.copy()
+        o[np.arange(len(rows)), rows] -= 1.0
+        o += ol.real
+        out.update({"quad_stril_rows": stril, "quad_orth_rows": float(np.sqrt(np.sum(o ** 2) * n / len(rows))),
+                    "quad_rows": int(args.rows)})
+        out["all_converged"] = ok and stril <= TOL
+    print(json.dumps(out), flush=True)
+    return 0 if out["all_converged"] else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -604,7 +706,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="matrix size (default: the workload's)")
     ap.add_argument("--workload", default="default",
-                    choices=["default", "single", "precision", "batched", "dd_continuation"])
+                    choices=["default", "single", "precision", "batched", "dd_continuation", "real"])
     ap.add_argument("--count", type=int, default=2000, help="batched: number of matrices")
     ap.add_argument("--cont-steps", type=int, default=64, help="dd_continuation: steps")
     ap.add_argument("--rows", type=int, default=32, help="rows of the binary128 check")
@@ -619,7 +721,7 @@ def main() -> int:
               file=sys.stderr)
         return 2
     return {"default": run_default, "single": run_single, "precision": run_precision, "batched": run_batched,
-            "dd_continuation": run_dd_continuation}[args.workload](args)
+            "dd_continuation": run_dd_continuation, "real": run_real}[args.workload](args)
 
 
 if __name__ == "__main__":

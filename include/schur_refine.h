@@ -214,6 +214,29 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
 /* Bytes of device workspace schur_refine_dd needs for size n under `opts`. */
 size_t sr_workspace_bytes_dd(int n, const sr_opts* opts);
 
+/* Real Schur variant (Section 3 extends the method to the real Schur form: T is
+ * quasi-upper-triangular, with 2 x 2 diagonal blocks holding complex conjugate
+ * pairs). A, Q, T: real n x n, float64, column-major, leading dimension n (device).
+ * blocks (host, int[n], may be NULL = none): blocks[i] = 1 when rows and columns
+ * i, i + 1 form a 2 x 2 diagonal block of the start's quasi-triangular form (as a
+ * real Schur decomposition such as LAPACK sgees returns it), else 0; a block may not
+ * start at the last row nor overlap the next (SR_EINVAL). The structure is kept:
+ * E is the block strictly lower part of That (every entry below the diagonal except
+ * the subdiagonal entry of a 2 x 2 block), T the rest, and the correction L solves
+ * the block form of the triangular equation, T_II L_IJ - L_IJ T_JJ = -(E_IJ +
+ * sum_{K>I} T_IK L_KJ - sum_{K<J} L_IK T_KJ), I > J. FP64 tier: the products on FP64
+ * MFMA (compensated by default), the solve in FP32 (each 2 x 2 block triangularized
+ * by a 2 x 2 unitary, the complex sweep run on the result, the correction mapped
+ * back), the merged update as in schur_refine. opts->gemm must be SR_GEMM_FP64
+ * (SR_ENOSYS otherwise); opts->trunc is ignored. Outputs and statuses as for
+ * schur_refine (the residual is the block strictly lower one); T is written with its
+ * block strictly lower part zero. n = 1: T = A, Q = sign(q). */
+int schur_refine_real(const void* A, void* Q, void* T, const int* blocks, int n, int iters, double tol,
+                      const sr_opts* opts, sr_info* info);
+
+/* Bytes of device workspace schur_refine_real needs for size n. */
+size_t sr_workspace_bytes_real(int n, const sr_opts* opts);
+
 /* Static description of a status code. */
 const char* sr_status_string(int status);
 
@@ -231,6 +254,22 @@ const char* sr_status_string(int status);
  * chunked accumulation with error-free combination. C must not overlap A, B, Cin. */
 int sr_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
              const void* Cin, int ldcin, void* C, int ldc, int compensated, void* stream);
+
+/* Real products of the real Schur variant: C = op(A) B (+ Cin), float64 on FP64
+ * MFMA, op(A) = A (opa = 0) or A^T (opa = 1), other arguments as sr_zgemm. */
+int sr_dgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,
+             const void* Cin, int ldcin, void* C, int ldc, int compensated, void* stream);
+
+/* The FP32 block solve of the real variant: T_lp (float32 n x n, quasi-upper-
+ * triangular with the 2 x 2 blocks marked by `blocks`, host, as for
+ * schur_refine_real), E_lp (float32, its block strictly lower part read), L_lp
+ * (float32 out: the block strictly lower solution, zeros elsewhere). ws: device
+ * workspace of >= sr_trisolve_real_ws_bytes(n) bytes. Synchronises the stream;
+ * returns SR_BREAKDOWN when two blocks share an eigenvalue or a value is not
+ * finite, SR_EINVAL for invalid markers. */
+size_t sr_trisolve_real_ws_bytes(int n);
+int sr_trisolve_real(const void* T_lp, const void* E_lp, void* L_lp, const int* blocks, int n, void* ws,
+                     size_t ws_bytes, void* stream);
 
 /* C = A B, complex64, FP32 MFMA (the lp products YW, W^2, W^3 of Algorithm 4). */
 int sr_cgemm(int m, int n, int k, const void* A, int lda, const void* B, int ldb, void* C,

@@ -88,6 +88,11 @@ _SIGS = {
     "sr_ozaki_zgemm_dd": (_i, [_i, _i, _i, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i, _vp, _vp, _i,
                                _i, _i, _i, _vp, _sz, _vp]),
     "sr_workspace_bytes_dd": (_sz, [_i, ctypes.POINTER(SrOpts)]),
+    "schur_refine_real": (_i, [_vp, _vp, _vp, _vp, _i, _i, _d, ctypes.POINTER(SrOpts), ctypes.POINTER(SrInfo)]),
+    "sr_workspace_bytes_real": (_sz, [_i, ctypes.POINTER(SrOpts)]),
+    "sr_dgemm": (_i, [_i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _vp]),
+    "sr_trisolve_real_ws_bytes": (_sz, [_i]),
+    "sr_trisolve_real": (_i, [_vp, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
     "sr_crt_moduli": (_i, [_i, _i]),
     "sr_crt_ws_bytes": (_sz, [_i, _i, _i, _i]),
     "sr_crt_zgemm": (_i, [_i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _vp, _sz, _vp]),
@@ -144,7 +149,7 @@ def _mat(t, dtype_name: str, rows: int | None = None, cols: int | None = None):
 
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError("expected a CUDA/HIP torch tensor")
-    want = {"c128": torch.complex128, "c64": torch.complex64}[dtype_name]
+    want = {"c128": torch.complex128, "c64": torch.complex64, "f64": torch.float64, "f32": torch.float32}[dtype_name]
     if t.dtype != want:
         raise TypeError(f"expected {want}, got {t.dtype}")
     if t.dim() != 2 or (t.shape[0] > 1 and t.stride(0) != 1) or (t.shape[1] > 1 and t.stride(1) < t.shape[0]):
@@ -418,3 +423,56 @@ def sr_diag_mfma(A: np.ndarray, B: np.ndarray, kind: int = 0) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"sr_diag_mfma failed: {rc}")
     return d
+
+
+# ------------------------------------------------------------ real Schur variant
+
+def _blocks(blocks, n):
+    if blocks is None:
+        return None
+    b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32))
+    if b.size != n:
+        raise ValueError("blocks must hold n markers")
+    return b
+
+
+def workspace_real(n: int, device="cuda"):
+    import torch
+
+    return torch.empty(max(1, int(lib().sr_workspace_bytes_real(int(n), None))), dtype=torch.uint8, device=device)
+
+
+def schur_refine_real(A, Q, T, blocks, iters: int = 6, tol: float = 1e-15, **kw) -> dict:
+    """Refine the real Schur form (Q, T) of the real A in place (float64 column-major
+    tensors); blocks: the 2 x 2 block markers of the start (length n)."""
+    n = A.shape[0]
+    b = _blocks(blocks, n)
+    o = make_opts(**kw)
+    info = SrInfo()
+    rc = lib().schur_refine_real(_mat(A, "f64", n, n), _mat(Q, "f64", n, n), _mat(T, "f64", n, n),
+                                 b.ctypes.data_as(ctypes.c_void_p) if b is not None else None, n, int(iters),
+                                 float(tol), ctypes.byref(o), ctypes.byref(info))
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def sr_dgemm(A, B, C, opa: int = 0, Cin=None, compensated: bool = False, stream=None) -> int:
+    m, n = C.shape
+    k = B.shape[0]
+    return lib().sr_dgemm(int(opa), m, n, k, _mat(A, "f64"), _ld(A), _mat(B, "f64"), _ld(B),
+                          _mat(Cin, "f64") if Cin is not None else None, _ld(Cin), _mat(C, "f64"), _ld(C),
+                          int(bool(compensated)), _stream(stream))
+
+
+def sr_trisolve_real(T_lp, E_lp, L_lp, blocks, ws=None, stream=None) -> int:
+    import torch
+
+    n = T_lp.shape[0]
+    b = _blocks(blocks, n)
+    need = int(lib().sr_trisolve_real_ws_bytes(n))
+    if ws is None:
+        ws = torch.empty(max(1, need), dtype=torch.uint8, device=T_lp.device)
+    return lib().sr_trisolve_real(_mat(T_lp, "f32", n, n), _mat(E_lp, "f32", n, n), _mat(L_lp, "f32", n, n),
+                                  b.ctypes.data_as(ctypes.c_void_p) if b is not None else None, n,
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), _stream(stream))

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 SO = os.path.join(HERE, "libschurrefine.so")
-SOURCES = ["gemm.hip", "ozaki.hip", "elementwise.hip", "trisolve.hip", "refine.hip", "batched.hip", "reorder.hip", "static_solve.hip", "crt.hip"]
+SOURCES = ["gemm.hip", "ozaki.hip", "elementwise.hip", "trisolve.hip", "refine.hip", "batched.hip", "reorder.hip", "static_solve.hip", "crt.hip", "real.hip"]
 ARCH = os.environ.get("SR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are switched off for all device code.

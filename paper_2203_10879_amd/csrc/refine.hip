@@ -20,6 +20,7 @@
 
 #include "../../include/schur_refine.h"
 #include "kernels.hpp"
+#include "real.hpp"
 
 using namespace sr;
 
@@ -1216,6 +1217,339 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
 size_t sr_workspace_bytes_dd(int n, const sr_opts* opts) {
   if (n < 1) return 0;
   return carve_dd(nullptr, n, opts).bytes + 256;
+}
+
+}  // extern "C"
+
+namespace {
+// ------------------------------------------------------------------------
+// Real Schur variant: real products (FP64 MFMA, compensated by default), the block
+// strictly lower residual, the FP32 block solve, the merged update on real data.
+
+struct RealWork {
+  double *Qa, *QT, *P, *Y;
+  float *Tlp, *Elp, *Llp, *W, *W2, *W3, *YW, *Ylp;
+  int* blk;
+  double* partials;
+  double* scal;
+  unsigned* status;
+  void* tri;
+  size_t bytes;
+};
+
+int real_partial_slots(int n) {
+  int a = rgemm_tiles(n, n, false), b = rform_w_parts(n);
+  int m = a > b ? a : b;
+  return m > 1024 ? m : 1024;
+}
+
+RealWork carve_real(void* base, int n) {
+  RealWork w;
+  uintptr_t p = (uintptr_t)base;
+  const size_t d = align256((size_t)n * n * sizeof(double)), f = align256((size_t)n * n * sizeof(float));
+  auto take = [&](size_t b) {
+    void* r = (void*)p;
+    p += b;
+    return r;
+  };
+  w.Qa = (double*)take(d);
+  w.QT = (double*)take(d);
+  w.P = (double*)take(d);
+  w.Y = (double*)take(d);
+  w.Tlp = (float*)take(f);
+  w.Elp = (float*)take(f);
+  w.Llp = (float*)take(f);
+  w.W = (float*)take(f);
+  w.W2 = (float*)take(f);
+  w.W3 = (float*)take(f);
+  w.YW = (float*)take(f);
+  w.Ylp = (float*)take(f);
+  w.blk = (int*)take(align256((size_t)n * sizeof(int)));
+  w.partials = (double*)take(align256((size_t)real_partial_slots(n) * sizeof(double)));
+  w.scal = (double*)take(256);
+  w.status = (unsigned*)take(256);
+  w.tri = take(align256(trisolve_real_ws_bytes(n)));
+  w.bytes = (size_t)(p - (uintptr_t)base);
+  return w;
+}
+
+// the 2 x 2 markers as the oracle reads them: a block never starts at the last row
+// and never overlaps the next one
+bool real_blocks_valid(const int* blk, int n) {
+  if (!blk) return true;
+  for (int i = 0; i < n; i++) {
+    if (blk[i] != 0 && blk[i] != 1) return false;
+    if (blk[i] && (i + 1 >= n || blk[i + 1])) return false;
+  }
+  return true;
+}
+
+RGemmArgs rargs(int m, int n, int k, const void* A, long lda, const void* B, long ldb, void* C, long ldc) {
+  RGemmArgs g;
+  memset(&g, 0, sizeof(g));
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  g.C = C;
+  g.ldc = ldc;
+  return g;
+}
+
+int read_back_real(hipStream_t st, const RealWork& w, int count, double* out, unsigned* status) {
+  Work v;
+  memset(&v, 0, sizeof(v));
+  v.scal = w.scal;
+  v.status = w.status;
+  return read_back(st, v, count, out, status);
+}
+
+int refine_real_fp64(const void* A_, void* Q_, void* T_, const int* blocks, int n, int iters, double tol,
+                     const sr_opts* opts_in, sr_info* info) {
+  info_init(info);
+  if (!A_ || !Q_ || !T_ || n < 1 || iters < 1 || !(tol > 0) || !real_blocks_valid(blocks, n)) return SR_EINVAL;
+  sr_opts o;
+  if (opts_in) o = *opts_in;
+  else sr_default_opts(&o);
+  if (o.gemm != SR_GEMM_FP64) return SR_ENOSYS;
+  hipStream_t st = (hipStream_t)o.stream;
+  const double* A = (const double*)A_;
+  double* Q = (double*)Q_;
+  double* T = (double*)T_;
+  if (n == 1) {
+    double a, q;
+    CK(hipMemcpyAsync(&a, A, sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(&q, Q, sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (!(q != 0) || !isfinite(a)) return SR_BREAKDOWN;
+    const double qs = q > 0 ? 1.0 : -1.0;
+    CK(hipMemcpyAsync(T, &a, sizeof(double), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(Q, &qs, sizeof(double), hipMemcpyHostToDevice, st));
+    CK(hipStreamSynchronize(st));
+    if (info) {
+      info->status = SR_OK;
+      info->iters = 1;
+    }
+    return SR_OK;
+  }
+  void* base = nullptr;
+  int rc = get_ws(o, sr_workspace_bytes_real(n, &o), &base);
+  if (rc != SR_OK) return rc;
+  const RealWork w = carve_real(base, n);
+  const int comp = o.compensated ? 1 : 0;
+  Timer timer;
+  timer.st = st;
+  Timer* tm = o.timing ? &timer : nullptr;
+  CallEvents ev;
+  CK(hipEventCreate(&ev.t0));
+  CK(hipEventCreate(&ev.t1));
+  CK(hipEventRecord(ev.t0, st));
+  if (blocks) CK(hipMemcpyAsync(w.blk, blocks, (size_t)n * sizeof(int), hipMemcpyHostToDevice, st));
+  else CK(fill_zero(w.blk, (size_t)n * sizeof(int), st));
+  CK(fill_zero(w.status, 256, st));
+  CK(rfro2_partials(A, (long)n * n, w.partials, 1024, st));
+  CK(reduce_partials(w.partials, 1024, w.scal, st));
+
+  // Newton-Schulz start: Y0 = Qh^T Qh - I, Qa = Qh + Qh (-Y0 / 2), QT = Qa^T
+  {
+    RGemmArgs g = rargs(n, n, n, Q, n, Q, n, w.Y, n);
+    g.partials = w.partials;
+    g.herm = 1;
+    TIC(tm, 0);
+    CK(dgemm(1, EPI_YDEF, comp, g, st));
+    TOC_HERM(tm);
+    CK(rform_delta(nullptr, w.Y, nullptr, nullptr, nullptr, w.P, n, st));
+    RGemmArgs u = rargs(n, n, n, Q, n, w.P, n, w.Qa, n);
+    u.Cin = Q;
+    u.ldcin = n;
+    u.CT = w.QT;
+    u.ldct = n;
+    TIC(tm, 0);
+    CK(dgemm(0, EPI_ADD, 0, u, st));
+    TOC(tm, 0);
+  }
+  int status = SR_NOT_CONVERGED, passes = 0, updates = 0, nprod = 0;
+  double eps = 0, eps1 = -1, eps2 = -1, orth = 0, nw_last = 0;
+  double* cur = w.Qa;
+  double* other = Q;
+  for (int p = 0; p < iters; p++) {
+    // P = A Q; That = Q^T P split at the block structure
+    RGemmArgs g = rargs(n, n, n, A, n, cur, n, w.P, n);
+    TIC(tm, 0);
+    CK(dgemm(0, EPI_STORE, comp, g, st));
+    TOC(tm, 0);
+    RGemmArgs sg = rargs(n, n, n, w.QT, n, w.P, n, T, n);
+    sg.Tlp = w.Tlp;
+    sg.Elp = w.Elp;
+    sg.ldlp = n;
+    sg.partials = w.partials;
+    sg.blk = w.blk;
+    TIC(tm, 0);
+    CK(dgemm(0, EPI_SPLIT, comp, sg, st));
+    TOC(tm, 0);
+    CK(reduce_partials(w.partials, rgemm_tiles(n, n, false), w.scal + 1, st));
+    double s2[2];
+    unsigned dst = 0;
+    if ((rc = read_back_real(st, w, 2, s2, &dst)) != SR_OK) return rc;
+    eps = sqrt(s2[1]) / sqrt(s2[0]);
+    passes = p + 1;
+    if (info && p < 16) info->resid_hist[p] = eps;
+    if (!isfinite(eps)) {
+      status = SR_BREAKDOWN;
+      break;
+    }
+    const int stop = stop_test(o, eps, tol, eps1, eps2, updates, nw_last, kU64, n);
+    if (stop >= 0) {
+      status = stop;
+      break;
+    }
+    eps2 = eps1;
+    eps1 = eps;
+    if (p == iters - 1) break;
+
+    TIC(tm, 1);
+    CK(trisolve_real(w.Tlp, T, w.Elp, w.Llp, w.blk, n, w.tri, w.status, st));
+    TOC(tm, 1);
+    RGemmArgs yg = rargs(n, n, n, w.QT, n, cur, n, w.Y, n);
+    yg.partials = w.partials;
+    yg.herm = 1;
+    TIC(tm, 0);
+    CK(dgemm(0, EPI_YDEF, comp, yg, st));
+    TOC_HERM(tm);
+    CK(reduce_partials(w.partials, rgemm_tiles(n, n, true), w.scal + 2, st));
+    CK(rform_w(w.Llp, w.W, n, w.partials, st));
+    CK(reduce_partials(w.partials, rform_w_parts(n), w.scal + 3, st));
+    double nrm[4];
+    if ((rc = read_back_real(st, w, 4, nrm, &dst)) != SR_OK) return rc;
+    if (dst & DEV_BREAKDOWN) {
+      status = SR_BREAKDOWN;
+      break;
+    }
+    const double ny = sqrt(nrm[2]), nw = sqrt(nrm[3]);
+    orth = ny;
+    nw_last = nw;
+    if (info && updates < 16) info->norm_w_hist[updates] = nw;
+    if (!isfinite(ny) || !isfinite(nw)) {
+      status = SR_BREAKDOWN;
+      break;
+    }
+    const Gate gt = gate_terms(o.gate_lp_terms != 0, nw, ny);
+    if (gt.w2 || gt.w3) {
+      RGemmArgs a2 = rargs(n, n, n, w.W, n, w.W, n, w.W2, n);
+      a2.herm = 1;  // W is skew-symmetric: W^2 is symmetric
+      CK(sgemm(a2, st));
+      nprod++;
+    }
+    const bool both = gt.w3 && gt.yw;
+    if (both) {
+      CK(rw2_minus_y(w.W2, w.Y, w.Ylp, (long)n * n, st));
+      CK(sgemm(rargs(n, n, n, w.Ylp, n, w.W, n, w.W3, n), st));
+      nprod++;
+    } else if (gt.w3) {
+      RGemmArgs a3 = rargs(n, n, n, w.W2, n, w.W, n, w.W3, n);
+      a3.herm = -1;  // and W^3 skew-symmetric
+      CK(sgemm(a3, st));
+      nprod++;
+    } else if (gt.yw) {
+      CK(rw2_minus_y(nullptr, w.Y, w.Ylp, (long)n * n, st));
+      CK(sgemm(rargs(n, n, n, w.Ylp, n, w.W, n, w.YW, n), st));
+      nprod++;
+    }
+    CK(rform_delta(w.Llp, w.Y, gt.w2 ? w.W2 : nullptr, gt.w3 ? w.W3 : nullptr, gt.yw && !both ? w.YW : nullptr,
+                   w.P, n, st));
+    RGemmArgs u = rargs(n, n, n, cur, n, w.P, n, other, n);
+    u.Cin = cur;
+    u.ldcin = n;
+    u.CT = w.QT;
+    u.ldct = n;
+    TIC(tm, 0);
+    CK(dgemm(0, EPI_ADD, 0, u, st));
+    TOC(tm, 0);
+    double* t = cur;
+    cur = other;
+    other = t;
+    updates++;
+  }
+  if (cur != Q) CK(hipMemcpyAsync(Q, cur, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  CK(hipEventRecord(ev.t1, st));
+  CK(hipEventSynchronize(ev.t1));
+  float ms = 0;
+  hipEventElapsedTime(&ms, ev.t0, ev.t1);
+  if (info) {
+    info->status = status;
+    info->iters = passes;
+    info->updates = updates;
+    info->hp_gemms = 2 + 4 * updates + 2 * (passes - updates);
+    info->lp_products = nprod;
+    info->resid = eps;
+    info->orth = orth;
+    info->ms_total = ms;
+    if (tm) {
+      info->ms_hp_gemm = timer.total(0);
+      info->hp_gemm_launches = timer.count[0];
+      info->hp_gemm_herm_launches = timer.herm;
+      info->ms_hp_gemm_herm = timer.total(0, 1);
+      info->ms_solve = timer.total(1);
+    }
+  }
+  return status;
+}
+}  // namespace
+
+extern "C" {
+
+size_t sr_workspace_bytes_real(int n, const sr_opts* opts) {
+  (void)opts;
+  if (n < 1) return 0;
+  return carve_real(nullptr, n).bytes + 256;
+}
+
+int schur_refine_real(const void* A, void* Q, void* T, const int* blocks, int n, int iters, double tol,
+                      const sr_opts* opts, sr_info* info) {
+  const int rc = refine_real_fp64(A, Q, T, blocks, n, iters, tol, opts, info);
+  if (rc < 0 && info) info->status = rc;
+  return rc;
+}
+
+int sr_dgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb, const void* Cin,
+             int ldcin, void* C, int ldc, int compensated, void* stream) {
+  if (m < 0 || n < 0 || k < 0 || (opa != 0 && opa != 1) || !C) return SR_EINVAL;
+  if (m == 0 || n == 0) return SR_OK;
+  if (k > 0 && (!A || !B)) return SR_EINVAL;
+  if (lda < (opa ? (k > 1 ? k : 1) : (m > 1 ? m : 1)) || ldb < (k > 1 ? k : 1) || ldc < m) return SR_EINVAL;
+  if (Cin && ldcin < m) return SR_EINVAL;
+  RGemmArgs g = rargs(m, n, k, A, lda, B, ldb, C, ldc);
+  g.Cin = Cin;
+  g.ldcin = ldcin;
+  CK(dgemm(opa, Cin ? EPI_ADD : EPI_STORE, compensated ? 1 : 0, g, (hipStream_t)stream));
+  return SR_OK;
+}
+
+size_t sr_trisolve_real_ws_bytes(int n) {
+  if (n < 1) return 0;
+  return align256(trisolve_real_ws_bytes(n)) + align256((size_t)n * sizeof(int)) + 256;
+}
+
+int sr_trisolve_real(const void* T_lp, const void* E_lp, void* L_lp, const int* blocks, int n, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (!T_lp || !E_lp || !L_lp || !ws || n < 1 || !real_blocks_valid(blocks, n)) return SR_EINVAL;
+  if (ws_bytes < sr_trisolve_real_ws_bytes(n)) return SR_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  char* p = (char*)ws;
+  void* tri = p;
+  int* blk = (int*)(p + align256(trisolve_real_ws_bytes(n)));
+  unsigned* status = (unsigned*)((char*)blk + align256((size_t)n * sizeof(int)));
+  if (blocks) CK(hipMemcpyAsync(blk, blocks, (size_t)n * sizeof(int), hipMemcpyHostToDevice, st));
+  else CK(fill_zero(blk, (size_t)n * sizeof(int), st));
+  CK(fill_zero(status, sizeof(unsigned), st));
+  CK(trisolve_real((const float*)T_lp, nullptr, (const float*)E_lp, (float*)L_lp, blk, n, tri, status, st));
+  unsigned d = 0;
+  CK(hipMemcpyAsync(&d, status, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  return (d & DEV_BREAKDOWN) ? SR_BREAKDOWN : SR_OK;
 }
 
 int sr_zgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B, int ldb,

@@ -212,26 +212,34 @@ def batched_sizes(count: int = 2000, seed: int = 3, lo: int = 16, hi: int = 256)
     return lo + np.random.default_rng(seed).integers(0, hi - lo + 1, size=count)
 
 
-def real_schur_test_matrix(n: int, seed: int, gap: float = 0.05, pair_frac: float = 0.5) -> dict:
+def real_schur_test_matrix(n: int, seed: int, gap: float = 0.05, n_real: int | None = None) -> dict:
     """Real A = Q0 T0 Q0^T with a real quasi-triangular T0 (the real Schur form).
 
+    The spectrum has the structure of a real Gaussian matrix's: about sqrt(2n/pi)
+    real eigenvalues (n_real; n - n_real is made even), the rest in conjugate pairs.
     Draws from `default_rng(seed)`: the n x n real normal matrix behind the Haar
-    orthogonal Q0 (QR with the signs of diag(R) moved into Q), then the spectrum
-    (sequential gap rejection on complex normal draws, as for the complex
-    generator; about `pair_frac` of the eigenvalues as conjugate pairs a +- ib with
-    |b| >= gap / 2, the rest real), then the strictly upper part N(0,1)/sqrt(n).
-    A pair sits in a standardized 2 x 2 block [[a, b c], [-b / c, a]] (c drawn in
-    [0.5, 2]); blk[i] = 1 marks a block at rows and columns i, i + 1."""
+    orthogonal Q0 (QR with the signs of diag(R) moved into Q), the order of the 1 x 1
+    and 2 x 2 blocks (a random permutation), then the spectrum (sequential gap
+    rejection on complex normal draws, as for the complex generator: a real
+    eigenvalue is the real part of a draw, a pair a +- ib needs |b| >= gap / 2), then
+    the strictly upper part N(0,1)/sqrt(n). A pair sits in a standardized 2 x 2 block
+    [[a, b c], [-b / c, a]] (c drawn in [0.5, 2]); blk[i] = 1 marks a block at rows and
+    columns i, i + 1."""
+    if n_real is None:
+        n_real = min(n, max(1, int(round(math.sqrt(2 * n / math.pi)))))
+    if (n - n_real) % 2:
+        n_real += 1 if n_real < n else -1
     rng = np.random.default_rng(seed)
     z = rng.standard_normal((n, n))
     q, r = np.linalg.qr(z)
     q0 = np.asfortranarray(q * np.sign(np.diag(r))[None, :])
+    kinds = rng.permutation(np.array([1] * n_real + [2] * ((n - n_real) // 2)))
     lam = []  # eigenvalues in block order
     blk = np.zeros(n, dtype=np.int32)
     t0 = np.zeros((n, n))
     i = 0
-    while i < n:
-        pair = i + 1 < n and rng.random() < pair_frac
+    for kind in kinds:
+        pair = kind == 2
         while True:
             w = cn(rng, 1)[0]
             cand = [complex(w.real, abs(w.imag)), complex(w.real, -abs(w.imag))] if pair else [complex(w.real, 0.0)]

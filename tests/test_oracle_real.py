@@ -7,35 +7,10 @@ import pytest
 
 import oracle
 import synth
-
-
-def _quasi_upper(rng, sizes, dyadic=False):
-    """A real block upper triangular T with diagonal blocks of the given orders:
-    2 x 2 blocks [[a, b], [c, a]] with b c < 0 (a complex pair), distinct eigenvalues."""
-    n = sum(sizes)
-    t = np.triu(rng.standard_normal((n, n)))
-    blk = np.zeros(n, dtype=np.int32)
-    i = 0
-    for k, s in enumerate(sizes):
-        if s == 2:
-            a, b, c = float(k + 1), 0.5 + rng.random(), -(0.5 + rng.random())
-            t[i, i] = t[i + 1, i + 1] = a
-            t[i, i + 1], t[i + 1, i] = b, c
-            blk[i] = 1
-        else:
-            t[i, i] = k + 1.5
-        i += s
-    if dyadic:
-        t = np.round(t * 64) / 64
-    return t, blk
-
-
-def _block_lower_mask(n, blk):
-    m = np.tril(np.ones((n, n), dtype=bool), -1)
-    for i in range(n - 1):
-        if blk[i]:
-            m[i + 1, i] = False
-    return m
+from real_util import block_lower_mask as _block_lower_mask
+from real_util import exact_real_problem as _exact_real_problem
+from real_util import quasi_upper as _quasi_upper
+from real_util import rotated as _rotated
 
 
 def _fraction_block_solve(t, e, blk):
@@ -127,30 +102,6 @@ def test_block_solve_float_residual_and_breakdown():
     assert oracle.trisolve_real(t2.astype(complex), e2.astype(complex), blk2, lp="quad")[1] == "BREAKDOWN"
 
 
-def _exact_real_problem(n, seed):
-    """A = Q0 T0 Q0^T exact in binary: Q0 the scaled Walsh-Hadamard matrix (entries
-    +-2^-k), T0 real quasi-triangular on the grid 2^-6 with 2 x 2 blocks for complex
-    pairs; every product stays on a fine dyadic grid with few bits."""
-    rng = np.random.default_rng(seed)
-    sizes = []
-    while sum(sizes) < n:
-        sizes.append(2 if sum(sizes) + 2 <= n and rng.random() < 0.5 else 1)
-    t0, blk = _quasi_upper(rng, sizes, dyadic=True)
-    t0 = t0 * 0.25  # eigenvalues spread less
-    h = synth.hadamard_exact(n, seed=seed)["Q0"].real
-    a = (h @ t0) @ h.T
-    return a, h, t0, blk
-
-
-def _rotated(q0, seed, delta):
-    rng = np.random.default_rng(seed)
-    n = q0.shape[0]
-    x = delta * rng.standard_normal((n, n))
-    k = (x - x.T) / 2
-    w, v = np.linalg.eigh(1j * k)
-    return np.asfortranarray((q0 @ (v @ np.diag(np.exp(-1j * w)) @ v.conj().T)).real)
-
-
 @pytest.mark.parametrize("n", [16, 64])
 def test_refine_real_recovers_exact_real_schur_form(n):
     a, q0, t0, blk = _exact_real_problem(n, n + 3)
@@ -208,7 +159,7 @@ def test_refine_real_float_lp_convergence():
 def test_refine_real_equals_complex_on_real_spectrum():
     """A real matrix with a real spectrum has no 2 x 2 blocks; the real refinement is
     then the complex one on real data (same steps): the same Q to binary128 rounding."""
-    g = synth.real_schur_test_matrix(24, seed=5, pair_frac=0.0)
+    g = synth.real_schur_test_matrix(24, seed=5, n_real=24)
     assert not g["blk"].any()
     qh, blk = synth.lp_real_schur_start(g["A"])
     assert not blk.any()
