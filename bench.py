@@ -27,7 +27,9 @@ Other workloads (--workload), each one JSON line of its own:
                   the first from the zgees Schur form of A0;
   real            the real Schur form of a real n = 2048 matrix (about sqrt(2n/pi)
                   real eigenvalues, conjugate pairs in 2 x 2 blocks, gaps >= 0.05),
-                  sgees start, FP64 tier, real FP64 products.
+                  sgees start, FP64 tier, real FP64 products;
+  solvers         the FP32 solve by the tile wavefront and by the recursive block
+                  algorithm (Algorithm 3) at n = 1024, 2048, 4096.
 
 `roofline` covers the dominant kernel of the chosen form, timed with HIP events
 on the library's stream during the timed steps: the FP64 GEMM against the FP64
@@ -600,6 +602,60 @@ def run_dd_continuation(args) -> int:
     return 0 if ok else 1
 
 
+def run_solvers(args) -> int:
+    """The FP32 triangular-equation solve by the tile wavefront and by the recursive
+    block algorithm (Algorithm 3, leaves of 64 and 256 rows) on the same data: T the
+    upper triangular factor of a test matrix (gaps >= 0.05), E = 1e-6 CN(0,1) strictly
+    lower, in complex64; milliseconds per solve (HIP events around each call, which
+    ends with a synchronisation and the read of the status word)."""
+    import torch
+
+    import paper_2203_10879_amd as sr
+    import synth
+
+    sizes = [args.n] if args.n else [1024, 2048, 4096]
+    torch.cuda.set_device(torch.device("cuda:0"))
+    rows = []
+    for n in sizes:
+        g = synth.schur_test_matrix(n, seed=30 + n % 97)
+        rng = np.random.default_rng(n)
+        t = np.triu(g["T0"]).astype(np.complex64)
+        e = (1e-6 * np.tril(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)), -1)).astype(np.complex64)
+        T, E = sr.colmajor(t), sr.colmajor(e)
+        L = sr.colmajor_empty(n, n, torch.complex64)
+        ws = sr.workspace(n)
+        cases = {"wavefront": lambda: sr.sr_trisolve(T, E, L, ws)}
+        for leaf in (64, 256):
+            wr = torch.empty(int(sr.lib().sr_trisolve_rec_ws_bytes(n, leaf)), dtype=torch.uint8, device="cuda")
+            cases[f"recursive_leaf{leaf}"] = (lambda wr=wr, leaf=leaf: sr.sr_trisolve_rec(T, E, L, leaf_rows=leaf,
+                                                                                          ws=wr))
+        row = {"n": n}
+        for name, fn in cases.items():
+            for _ in range(max(2, args.warmup)):
+                assert fn() == 0
+            ms = []
+            for _ in range(args.steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                rc = fn()
+                e1.record()
+                torch.cuda.synchronize()
+                assert rc == 0
+                ms.append(e0.elapsed_time(e1))
+            row[name + "_ms"] = float(np.median(ms))
+        print(f"# n={n}: " + ", ".join(f"{k} {v:.3f}" for k, v in row.items() if k != "n"), file=sys.stderr,
+              flush=True)
+        rows.append(row)
+    best = rows[0]
+    out = base_record(args, 1e3 / best["wavefront_ms"], "solves/s", best["wavefront_ms"], "c64",
+                      {"workload": "FP32 triangular-equation solve, tile wavefront against the recursive block "
+                                   "algorithm (Algorithm 3), T from a test matrix with gaps >= 0.05, "
+                                   "E = 1e-6 CN(0,1)", "sizes": sizes})
+    out.update({"solves": rows, "roofline": None})
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 REAL_SOURCES = ("real.hip", "real.hpp", "epilogue.hpp", "kernels.hpp", "common.hpp")
 
 
@@ -706,7 +762,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="matrix size (default: the workload's)")
     ap.add_argument("--workload", default="default",
-                    choices=["default", "single", "precision", "batched", "dd_continuation", "real"])
+                    choices=["default", "single", "precision", "batched", "dd_continuation", "real", "solvers"])
     ap.add_argument("--count", type=int, default=2000, help="batched: number of matrices")
     ap.add_argument("--cont-steps", type=int, default=64, help="dd_continuation: steps")
     ap.add_argument("--rows", type=int, default=32, help="rows of the binary128 check")
@@ -721,7 +777,7 @@ def main() -> int:
               file=sys.stderr)
         return 2
     return {"default": run_default, "single": run_single, "precision": run_precision, "batched": run_batched,
-            "dd_continuation": run_dd_continuation, "real": run_real}[args.workload](args)
+            "dd_continuation": run_dd_continuation, "real": run_real, "solvers": run_solvers}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -105,7 +105,22 @@ typedef struct {
                              the normwise residual reaches tol, even at the start,
                              while small parts of Q still move.
                              0 (default): the residual alone decides                 */
+  int solver;             /* solve of the triangular equation in the FP32 tier
+                             (schur_refine): SR_SOLVER_WAVEFRONT (0, default) or
+                             SR_SOLVER_RECURSIVE (1, Algorithm 3); other entry points
+                             take only 0 (SR_ENOSYS otherwise)                        */
+  int rec_leaf;           /* SR_SOLVER_RECURSIVE: largest node solved without a split,
+                             in rows (rounded up to the 16-row tile; 0 = 64)           */
 } sr_opts;
+
+typedef enum {
+  SR_SOLVER_WAVEFRONT = 0, /* tile wavefront over the whole strictly lower part (an
+                              order of Algorithm 2 by tile anti-diagonals)             */
+  SR_SOLVER_RECURSIVE = 1  /* Algorithm 3: split at half the tiles, a triangular
+                              Sylvester equation for the lower-left block, two
+                              updates of E by FP32 MFMA products, recursion on the
+                              diagonal blocks                                         */
+} sr_solver;
 
 typedef struct {
   int status;             /* sr_status of the call                                    */
@@ -270,6 +285,20 @@ int sr_dgemm(int opa, int m, int n, int k, const void* A, int lda, const void* B
 size_t sr_trisolve_real_ws_bytes(int n);
 int sr_trisolve_real(const void* T_lp, const void* E_lp, void* L_lp, const int* blocks, int n, void* ws,
                      size_t ws_bytes, void* stream);
+
+/* The FP32 solve of sr_trisolve by the recursive block algorithm (Section 2.1,
+ * Algorithm 3 and eqs. (11)-(12)): the node of tile rows [lo, hi) splits at
+ * mid = lo + (hi - lo) / 2 (16-row tiles); the triangular Sylvester equation
+ * T22 X - X T11 = -E21 of its lower-left block is solved tile by tile in anti-diagonal
+ * order; E11 += stril(T12 X) and E22 -= stril(X T12) follow as FP32 MFMA products;
+ * the two diagonal blocks recurse, down to nodes of at most leaf_rows rows (rounded up
+ * to whole tiles; 0 = 64), solved in the same tile order. All nodes of one depth share
+ * the launches. Arguments as sr_trisolve; E_lp is not modified. ws: device workspace
+ * of >= sr_trisolve_rec_ws_bytes(n, leaf_rows) bytes (SR_ENOMEM if smaller).
+ * Synchronises the stream; SR_BREAKDOWN as sr_trisolve. */
+size_t sr_trisolve_rec_ws_bytes(int n, int leaf_rows);
+int sr_trisolve_rec(const void* T_lp, const void* E_lp, void* L_lp, int n, int leaf_rows, float trunc, void* ws,
+                    size_t ws_bytes, void* stream);
 
 /* C = A B, complex64, FP32 MFMA (the lp products YW, W^2, W^3 of Algorithm 4). */
 int sr_cgemm(int m, int n, int k, const void* A, int lda, const void* B, int ldb, void* C,

@@ -33,7 +33,7 @@ class SrOpts(ctypes.Structure):
                 ("compensated", ctypes.c_int), ("gate_lp_terms", ctypes.c_int),
                 ("trunc", ctypes.c_int), ("timing", ctypes.c_int), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
-                ("strict_stop", ctypes.c_int)]
+                ("strict_stop", ctypes.c_int), ("solver", ctypes.c_int), ("rec_leaf", ctypes.c_int)]
 
 
 class SrInfo(ctypes.Structure):
@@ -93,6 +93,8 @@ _SIGS = {
     "sr_dgemm": (_i, [_i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _vp]),
     "sr_trisolve_real_ws_bytes": (_sz, [_i]),
     "sr_trisolve_real": (_i, [_vp, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
+    "sr_trisolve_rec_ws_bytes": (_sz, [_i, _i]),
+    "sr_trisolve_rec": (_i, [_vp, _vp, _vp, _i, _i, ctypes.c_float, _vp, _sz, _vp]),
     "sr_crt_moduli": (_i, [_i, _i]),
     "sr_crt_ws_bytes": (_sz, [_i, _i, _i, _i]),
     "sr_crt_zgemm": (_i, [_i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _vp, _sz, _vp]),
@@ -177,8 +179,12 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
+SOLVERS = {"wavefront": 0, "recursive": 1}
+
+
 def make_opts(gemm="fp64", slices=0, update_slices=0, compensated=True, gate=True, trunc=False,
-              timing=False, workspace=None, stream=None, strict_stop=False) -> SrOpts:
+              timing=False, workspace=None, stream=None, strict_stop=False, solver="wavefront",
+              rec_leaf=0) -> SrOpts:
     o = SrOpts()
     lib().sr_default_opts(ctypes.byref(o))
     o.gemm = GEMM_MODES[gemm] if isinstance(gemm, str) else int(gemm)
@@ -189,6 +195,8 @@ def make_opts(gemm="fp64", slices=0, update_slices=0, compensated=True, gate=Tru
     o.trunc = int(bool(trunc))
     o.timing = int(bool(timing))
     o.strict_stop = int(bool(strict_stop))
+    o.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
+    o.rec_leaf = int(rec_leaf)
     if workspace is not None:
         o.workspace = ctypes.c_void_p(workspace.data_ptr())
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -476,3 +484,16 @@ def sr_trisolve_real(T_lp, E_lp, L_lp, blocks, ws=None, stream=None) -> int:
     return lib().sr_trisolve_real(_mat(T_lp, "f32", n, n), _mat(E_lp, "f32", n, n), _mat(L_lp, "f32", n, n),
                                   b.ctypes.data_as(ctypes.c_void_p) if b is not None else None, n,
                                   ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), _stream(stream))
+
+
+def sr_trisolve_rec(T_lp, E_lp, L_lp, leaf_rows: int = 0, trunc: float = 0.0, ws=None, stream=None) -> int:
+    """FP32 solve of stril(T L - L T) = -E by the recursive block algorithm."""
+    import torch
+
+    n = T_lp.shape[0]
+    need = int(lib().sr_trisolve_rec_ws_bytes(n, int(leaf_rows)))
+    if ws is None:
+        ws = torch.empty(max(1, need), dtype=torch.uint8, device=T_lp.device)
+    return lib().sr_trisolve_rec(_mat(T_lp, "c64", n, n), _mat(E_lp, "c64", n, n), _mat(L_lp, "c64", n, n), n,
+                                 int(leaf_rows), float(trunc), ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel() * ws.element_size(), _stream(stream))

@@ -383,6 +383,13 @@ hipError_t zgemm_grouped(int opa, int epi, int comp, int bm, const GemmArgs* arg
   return hipErrorInvalidValue;
 }
 
+hipError_t cgemm_grouped_add(int bm, const GemmArgs* args, const GTile* tiles, int ntiles, int grid,
+                             hipStream_t st) {
+  if (bm == 64) return launch_grouped<float, 0, EPI_ADD, 0, 64>(args, tiles, ntiles, nullptr, grid, st);
+  if (bm == 32) return launch_grouped<float, 0, EPI_ADD, 0, 32>(args, tiles, ntiles, nullptr, grid, st);
+  return hipErrorInvalidValue;
+}
+
 hipError_t cgemm_grouped(int bm, const GemmArgs* args, const GTile* tiles, int ntiles, const int* active,
                          int grid, hipStream_t st) {
   if (bm == 64) return launch_grouped<float, 0, EPI_STORE, 0, 64>(args, tiles, ntiles, active, grid, st);

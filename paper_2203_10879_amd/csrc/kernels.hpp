@@ -126,6 +126,12 @@ hipError_t crt_split_rows(const zc* X, long ld, int M, int K, int bits, int8_t* 
 hipError_t crt_gemm(int epi, const int8_t* A, const int* ta, const int8_t* B, const int* tb, int conjA, int bits,
                     GemmArgs g, void* scratch, hipStream_t st);
 
+// A tile task of the recursive block solve: tile (I, J) solved inside the node of
+// tile range [lo, hi) (16-wide tiles).
+struct TileTask {
+  int I, J, lo, hi;
+};
+
 // Triangular matrix equation in FP32 (complex64) and in FP64 (complex128); the
 // workspace size serves both.
 size_t trisolve_ws_bytes(int n);
@@ -133,6 +139,16 @@ hipError_t trisolve(const cc* T, const cc* E, cc* L, int n, float trunc, void* w
                     unsigned* status, hipStream_t st);
 hipError_t trisolve64(const zc* T, const zc* E, zc* L, int n, void* ws, unsigned* status,
                       hipStream_t st);
+// The same equation in FP32 by the recursive block algorithm (Algorithm 3): nodes
+// split at half their tile count down to leaves of at most leaf_tiles tiles, the
+// Sylvester block of every node and the leaves solved as tile tasks (one launch per
+// step for all nodes of a depth), the two updates of E per node as grouped FP32
+// MFMA products. E is not modified (the updates go to a copy in ws).
+size_t trisolve_rec_ws_bytes(int n, int leaf_tiles);
+hipError_t trisolve_rec(const cc* T, const cc* E, cc* L, int n, int leaf_tiles, float trunc, void* ws,
+                        unsigned* status, hipStream_t st);
+hipError_t cgemm_grouped_add(int bm, const GemmArgs* args, const GTile* tiles, int ntiles, int grid,
+                             hipStream_t st);
 // Reordering of the start: T (complex128 n x n, Q^H A Q on entry) is made upper
 // triangular and reordered by adjacent swaps in the order of Re(lambda e^{-i theta});
 // Q is updated in place; perm_out (device, may be NULL) receives the original

@@ -15,6 +15,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -88,6 +89,12 @@ int oz_main_slices(const sr_opts* o) {
 
 int crt_main_bits(const sr_opts* o) { return (o && o->slices > 0) ? o->slices : kCrtBits; }
 
+// Leaf size of the recursive solve in 16-row tiles (default 64 rows).
+int rec_leaf_tiles(const sr_opts& o) {
+  const int rows = o.rec_leaf > 0 ? o.rec_leaf : 64;
+  return (rows + 15) / 16;
+}
+
 Work carve(void* base, int n, const sr_opts* o = nullptr) {
   Work w;
   uintptr_t p = (uintptr_t)base;
@@ -113,7 +120,11 @@ Work carve(void* base, int n, const sr_opts* o = nullptr) {
   w.partials = (double*)take(align256((size_t)partial_slots(n) * sizeof(double)));
   w.scal = (double*)take(256);
   w.status = (unsigned*)take(256);
-  w.tri = take(align256(trisolve_ws_bytes(n)));
+  {
+    size_t tb = trisolve_ws_bytes(n);
+    if (o && o->solver == SR_SOLVER_RECURSIVE) tb = std::max(tb, trisolve_rec_ws_bytes(n, rec_leaf_tiles(*o)));
+    w.tri = take(align256(tb));
+  }
   w.sA = w.sQc = w.sQr = w.sD = nullptr;
   w.eA = w.eQc = w.eQr = w.eD = nullptr;
   w.oz_scratch = nullptr;
@@ -630,6 +641,10 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
     if (info) info->status = o.gemm == SR_GEMM_OZAKI_BF16 ? SR_ENOSYS : SR_EINVAL;
     return o.gemm == SR_GEMM_OZAKI_BF16 ? SR_ENOSYS : SR_EINVAL;
   }
+  if ((o.solver != SR_SOLVER_WAVEFRONT && o.solver != SR_SOLVER_RECURSIVE) || o.rec_leaf < 0) {
+    if (info) info->status = SR_EINVAL;
+    return SR_EINVAL;
+  }
   if (ozaki &&
       (o.slices < 0 || o.slices > 16 || o.update_slices < 0 || o.update_slices > kOzMaxUpd ||
        !oz_gemm_exact(n, n, n, oz_main_slices(&o), oz_main_slices(&o)))) {
@@ -738,7 +753,10 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
       CK(hipEventRecord(ev.join, sst));
     }
     TIC(tm, 1);
-    CK(trisolve(w.Tlp, w.Elp, w.Llp, n, o.trunc ? 1e-5f : 0.f, w.tri, w.status, st));
+    if (o.solver == SR_SOLVER_RECURSIVE)
+      CK(trisolve_rec(w.Tlp, w.Elp, w.Llp, n, rec_leaf_tiles(o), o.trunc ? 1e-5f : 0.f, w.tri, w.status, st));
+    else
+      CK(trisolve(w.Tlp, w.Elp, w.Llp, n, o.trunc ? 1e-5f : 0.f, w.tri, w.status, st));
     TOC(tm, 1);
     if (side) CK(hipStreamWaitEvent(st, ev.join, 0));
     else if ((rc = ydef(cur, QH, n, comp, w, st, tm)) != SR_OK) return rc;
@@ -980,6 +998,10 @@ static int refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo,
   if (o.slices < 0 || o.slices > 32 || o.update_slices < -1 || o.update_slices > 32) {
     if (info) info->status = SR_EINVAL;
     return SR_EINVAL;
+  }
+  if (o.solver != SR_SOLVER_WAVEFRONT) {
+    if (info) info->status = SR_ENOSYS;
+    return SR_ENOSYS;
   }
   hipStream_t st = (hipStream_t)o.stream;
   const zc* Ah = (const zc*)A_hi;
@@ -1314,7 +1336,7 @@ int refine_real_fp64(const void* A_, void* Q_, void* T_, const int* blocks, int 
   sr_opts o;
   if (opts_in) o = *opts_in;
   else sr_default_opts(&o);
-  if (o.gemm != SR_GEMM_FP64) return SR_ENOSYS;
+  if (o.gemm != SR_GEMM_FP64 || o.solver != SR_SOLVER_WAVEFRONT) return SR_ENOSYS;
   hipStream_t st = (hipStream_t)o.stream;
   const double* A = (const double*)A_;
   double* Q = (double*)Q_;
@@ -1722,6 +1744,27 @@ int sr_trisolve(const void* T_lp, const void* E_lp, void* L_lp, int n, float tru
 size_t sr_reorder_ws_bytes(int n) {
   if (n < 1) return 0;
   return 2 * align256((size_t)n * n * sizeof(zc)) + align256(reorder_scratch_bytes(n));
+}
+
+size_t sr_trisolve_rec_ws_bytes(int n, int leaf_rows) {
+  if (n < 1) return 0;
+  const int lt = ((leaf_rows > 0 ? leaf_rows : 64) + 15) / 16;
+  return align256(trisolve_rec_ws_bytes(n, lt)) + 256;
+}
+
+int sr_trisolve_rec(const void* T_lp, const void* E_lp, void* L_lp, int n, int leaf_rows, float trunc, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (!T_lp || !E_lp || !L_lp || !ws || n < 1 || leaf_rows < 0 || !(trunc >= 0)) return SR_EINVAL;
+  if (ws_bytes < sr_trisolve_rec_ws_bytes(n, leaf_rows)) return SR_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  const int lt = ((leaf_rows > 0 ? leaf_rows : 64) + 15) / 16;
+  unsigned* status = (unsigned*)((char*)ws + align256(trisolve_rec_ws_bytes(n, lt)));
+  CK(fill_zero(status, sizeof(unsigned), st));
+  CK(trisolve_rec((const cc*)T_lp, (const cc*)E_lp, (cc*)L_lp, n, lt, trunc, ws, status, st));
+  unsigned d = 0;
+  CK(hipMemcpyAsync(&d, status, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  return (d & DEV_BREAKDOWN) ? SR_BREAKDOWN : SR_OK;
 }
 
 int sr_reorder_start(const void* A, void* Q, int n, double theta, int* perm, void* ws, size_t ws_bytes,
