@@ -111,6 +111,15 @@ typedef struct {
                              take only 0 (SR_ENOSYS otherwise)                        */
   int rec_leaf;           /* SR_SOLVER_RECURSIVE: largest node solved without a split,
                              in rows (rounded up to the 16-row tile; 0 = 64)           */
+  int skip_orth;          /* schur_refine only (SR_ENOSYS elsewhere). 1: skip the
+                             product Y = Q^H Q - I of an update when Q (I + W) is
+                             already unitary in hp (Section 2.4, the remark after the
+                             merged update): the next ||Y|| predicted from the last
+                             computed Y and W by the Newton-Schulz identity (Lemma 2)
+                             is below u_hp and ||W||_F^2 <= u_hp; the update then takes
+                             Y = 0. Never twice in a row; if the prediction holds but
+                             ||W||^2 is larger, Y is formed after the solve. 0: off
+                             (default)                                                 */
 } sr_opts;
 
 typedef enum {

@@ -33,7 +33,8 @@ class SrOpts(ctypes.Structure):
                 ("compensated", ctypes.c_int), ("gate_lp_terms", ctypes.c_int),
                 ("trunc", ctypes.c_int), ("timing", ctypes.c_int), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
-                ("strict_stop", ctypes.c_int), ("solver", ctypes.c_int), ("rec_leaf", ctypes.c_int)]
+                ("strict_stop", ctypes.c_int), ("solver", ctypes.c_int), ("rec_leaf", ctypes.c_int),
+                ("skip_orth", ctypes.c_int)]
 
 
 class SrInfo(ctypes.Structure):
@@ -184,7 +185,7 @@ SOLVERS = {"wavefront": 0, "recursive": 1}
 
 def make_opts(gemm="fp64", slices=0, update_slices=0, compensated=True, gate=True, trunc=False,
               timing=False, workspace=None, stream=None, strict_stop=False, solver="wavefront",
-              rec_leaf=0) -> SrOpts:
+              rec_leaf=0, skip_orth=False) -> SrOpts:
     o = SrOpts()
     lib().sr_default_opts(ctypes.byref(o))
     o.gemm = GEMM_MODES[gemm] if isinstance(gemm, str) else int(gemm)
@@ -197,6 +198,7 @@ def make_opts(gemm="fp64", slices=0, update_slices=0, compensated=True, gate=Tru
     o.strict_stop = int(bool(strict_stop))
     o.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     o.rec_leaf = int(rec_leaf)
+    o.skip_orth = int(bool(skip_orth))
     if workspace is not None:
         o.workspace = ctypes.c_void_p(workspace.data_ptr())
         o.workspace_bytes = workspace.numel() * workspace.element_size()

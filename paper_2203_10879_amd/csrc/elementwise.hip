@@ -217,7 +217,7 @@ __global__ __launch_bounds__(ENT) void form_delta_kernel(const cc* __restrict__ 
           wi = u.im;
         }
       }
-      const zc y = Y[o];
+      const zc y = Y ? Y[o] : mk<double>(0, 0);
       double pr = 0, pi = 0;
       if (W2) {
         pr += W2[o].re;

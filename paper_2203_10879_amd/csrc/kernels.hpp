@@ -75,7 +75,7 @@ hipError_t reduce_partials(const double* partials, int np, double* out, hipStrea
 // W = L - L^H (complex64, strictly lower L), partials of ||W||_F^2; returns #partials.
 int form_w_parts(int n);
 hipError_t form_w(const cc* L, cc* W, int n, double* partials, hipStream_t st);
-// D = W - Y/2 + (W2 + W3 - YW)/2 with W = L - L^H (L may be NULL: W = 0; the
+// D = W - Y/2 + (W2 + W3 - YW)/2 with W = L - L^H (L may be NULL: W = 0; Y and the
 // products may be NULL: absent).
 hipError_t form_delta(const cc* L, const zc* Y, const cc* W2, const cc* W3, const cc* YW, zc* D,
                       int n, hipStream_t st);

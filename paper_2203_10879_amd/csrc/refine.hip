@@ -479,7 +479,7 @@ struct Gate {
 
 // lp products, Delta, and Qout = Q + Q Delta (QHout, if given, receives Qout^H).
 int apply_update(const zc* Q, zc* Qout, zc* QHout, int n, Gate gt, const Work& w, hipStream_t st,
-                 int* nprod, Timer* tm = nullptr, int Su = 0) {
+                 int* nprod, Timer* tm = nullptr, int Su = 0, bool no_y = false) {
   int np = 0;
   if (gt.w2 || gt.w3) {
     GemmArgs a2 = gargs(n, n, n, w.W, n, w.W, n, w.W2, n);
@@ -503,7 +503,7 @@ int apply_update(const zc* Q, zc* Qout, zc* QHout, int n, Gate gt, const Work& w
     CK(cgemm(gargs(n, n, n, w.Ylp, n, w.W, n, w.YW, n), st));
     np++;
   }
-  CK(form_delta(w.Llp, w.Y, gt.w2 ? w.W2 : nullptr, gt.w3 ? w.W3 : nullptr,
+  CK(form_delta(w.Llp, no_y ? nullptr : w.Y, gt.w2 ? w.W2 : nullptr, gt.w3 ? w.W3 : nullptr,
                 gt.yw && !both ? w.YW : nullptr, w.P, n, st));
   TIC(tm, 0);
   if (w.oz_s) {
@@ -698,8 +698,10 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
   CK(reduce_partials(w.partials, 1024, w.scal, st));
 
   int status = SR_NOT_CONVERGED;
-  int passes = 0, updates = 0, nprod = 0;
+  int passes = 0, updates = 0, nprod = 0, skips = 0;
   double eps = 0, eps1 = -1, eps2 = -1, orth = 0, nw_last = 0;
+  double y_pred = INFINITY;  // skip_orth: predicted ||Q^H Q - I|| before the next update
+  bool skipped_last = false;
   zc* cur = w.Qa;
   zc* other = Q;
   hipStream_t sst = n <= kSideYMaxN ? side_stream(st) : nullptr;
@@ -741,7 +743,9 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
     // refinement at n = 1024, +2.7% at 2048). At n = 4096 Y's blocks take the CUs the
     // solve's later levels need (the solve doubled, the pass gained 1.5%), so there
     // the two run one after the other.
-    const bool side = sst && n <= kSideYMaxN;
+    // skip_orth: Y is left out when the prediction says it would be below u_hp
+    const bool try_skip = o.skip_orth && !skipped_last && y_pred <= kU64;
+    const bool side = sst && n <= kSideYMaxN && !try_skip;
     if (side) {
       CK(hipEventRecord(ev.fork, st));
       CK(hipStreamWaitEvent(sst, ev.fork, 0));
@@ -759,7 +763,7 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
       CK(trisolve(w.Tlp, w.Elp, w.Llp, n, o.trunc ? 1e-5f : 0.f, w.tri, w.status, st));
     TOC(tm, 1);
     if (side) CK(hipStreamWaitEvent(st, ev.join, 0));
-    else if ((rc = ydef(cur, QH, n, comp, w, st, tm)) != SR_OK) return rc;
+    else if (!try_skip && (rc = ydef(cur, QH, n, comp, w, st, tm)) != SR_OK) return rc;
     CK(form_w(w.Llp, w.W, n, w.partials, st));
     CK(reduce_partials(w.partials, form_w_parts(n), w.scal + 3, st));
     double nrm[4];
@@ -768,8 +772,15 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
       status = SR_BREAKDOWN;
       break;
     }
-    const double ny = sqrt(nrm[2]), nw = sqrt(nrm[3]);
-    orth = ny;
+    double nw = sqrt(nrm[3]);
+    bool skip = try_skip && nw * nw <= kU64;
+    if (try_skip && !skip) {
+      // the prediction held but W is not small enough: form Y after all
+      if ((rc = ydef(cur, QH, n, comp, w, st, tm)) != SR_OK) return rc;
+      if ((rc = read_back(st, w, 4, nrm, &dst)) != SR_OK) return rc;
+    }
+    const double ny = skip ? 0.0 : sqrt(nrm[2]);
+    if (!skip) orth = ny;
     nw_last = nw;
     if (info && updates < 16) info->norm_w_hist[updates] = nw;
     if (!isfinite(ny) || !isfinite(nw)) {
@@ -779,7 +790,19 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
     const Gate gt = gate_terms(o.gate_lp_terms != 0, nw, ny);
     su = w.oz_s ? update_slices(o, nw + 0.5 * ny) : 0;
     if (info && updates + 1 < 16) info->update_slices_hist[updates + 1] = su;
-    if ((rc = apply_update(cur, other, QH, n, gt, w, st, &nprod, tm, su)) != SR_OK) return rc;
+    if ((rc = apply_update(cur, other, QH, n, gt, w, st, &nprod, tm, su, skip)) != SR_OK) return rc;
+    // Predicted ||Y|| after this update (its exact-arithmetic part; the rounding of
+    // the hp products adds about sqrt(n) u_hp, which no update removes). With
+    // X = (I + W)^H (I + Y) (I + W) - I, ||X|| <= ||Y|| (1 + ||W||)^2 + ||W||^2, one
+    // Newton-Schulz step leaves -3/4 X^2 + 1/4 X^3 (Lemma 2), and the dropped terms
+    // W^2 Y, W^2 Y W add about ||W||^2 ||Y||. After a skip: ||X|| itself.
+    {
+      const double yk = skip ? y_pred : ny;
+      const double x = yk * (1 + nw) * (1 + nw) + nw * nw;
+      y_pred = skip ? x : 0.75 * x * x + 0.25 * x * x * x + nw * nw * yk * (1 + nw);
+    }
+    skipped_last = skip;
+    skips += skip ? 1 : 0;
     zc* t = cur;
     cur = other;
     other = t;
@@ -794,7 +817,7 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
     info->status = status;
     info->iters = passes;
     info->updates = updates;
-    info->hp_gemms = 2 + 4 * updates + 2 * (passes - updates);
+    info->hp_gemms = 2 + 4 * updates + 2 * (passes - updates) - skips;
     info->lp_products = nprod;
     info->resid = eps;
     info->orth = orth;
@@ -999,7 +1022,7 @@ static int refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo,
     if (info) info->status = SR_EINVAL;
     return SR_EINVAL;
   }
-  if (o.solver != SR_SOLVER_WAVEFRONT) {
+  if (o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth) {
     if (info) info->status = SR_ENOSYS;
     return SR_ENOSYS;
   }
@@ -1336,7 +1359,7 @@ int refine_real_fp64(const void* A_, void* Q_, void* T_, const int* blocks, int 
   sr_opts o;
   if (opts_in) o = *opts_in;
   else sr_default_opts(&o);
-  if (o.gemm != SR_GEMM_FP64 || o.solver != SR_SOLVER_WAVEFRONT) return SR_ENOSYS;
+  if (o.gemm != SR_GEMM_FP64 || o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth) return SR_ENOSYS;
   hipStream_t st = (hipStream_t)o.stream;
   const double* A = (const double*)A_;
   double* Q = (double*)Q_;

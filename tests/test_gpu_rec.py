@@ -85,10 +85,10 @@ def test_rec_breakdown_truncation_and_arguments(sr):
     assert sr.sr_trisolve_rec(dev(t2), dev(e2), l2, leaf_rows=-1) == -1  # SR_EINVAL
 
 
-def _refine(sr, a, qh, **kw):
+def _refine(sr, a, qh, iters=6, tol=1e-15, **kw):
     n = a.shape[0]
     q, t = dev(qh), empty(n, n)
-    info = sr.schur_refine(dev(a), q, t, iters=6, tol=1e-15, **kw)
+    info = sr.schur_refine(dev(a), q, t, iters=iters, tol=tol, **kw)
     return host(q), host(t), info
 
 
@@ -119,3 +119,29 @@ def test_recursive_solver_option_scope(sr):
 
     assert sr.schur_refine_real(dev(gr["A"]), dev(qr), sr.colmajor_empty(32, 32, torch.float64), blk,
                                 solver="recursive")["rc"] == -4  # SR_ENOSYS
+
+
+@pytest.mark.parametrize("n,mode", [(257, "fp64"), (1024, "fp64"), (1024, "ozaki_crt")])
+def test_skip_orth(sr, n, mode):
+    """Section 2.4: with Q (I + W) already unitary in hp the product Y of an update can
+    be left out. Four passes with a tolerance below reach (three updates): from the
+    cgees start the first correction is ||W|| = 1e-4 .. 4e-4, so the predicted ||Y||
+    before the second update is 3/4 ||W_1||^4 (7e-17 at n = 257: skipped there, 2e-14
+    at n = 1024: formed); before the third it is below 1e-27 (skipped at n = 1024,
+    formed at n = 257 right after a skip). Either way one hp product fewer, the same
+    passes, and Q unitary to the rounding level on binary128 rows. Off by default."""
+    g = synth.schur_test_matrix(n, seed=80 + n)
+    a, qh = g["A"], synth.lp_schur_start(g["A"])
+    kw = dict(gemm=mode, iters=4, tol=1e-30)
+    q0, _, ref = _refine(sr, a, qh, **kw)
+    q1, _, info = _refine(sr, a, qh, skip_orth=True, **kw)
+    assert info["iters"] == ref["iters"] == 4 and info["status"] == ref["status"], (info, ref)
+    assert ref["hp_gemms"] == 4 * ref["iters"]
+    assert info["hp_gemms"] == ref["hp_gemms"] - 1, (info["hp_gemms"], ref["hp_gemms"], info["norm_w_hist"])
+    rows = np.random.default_rng(6).choice(n, 32, replace=False)
+    for q in (q0, q1):
+        ev = oracle.evaluate_rows(a, q, rows)
+        assert ev["stril"] <= 1e-15 and ev["orth"] <= 4 * U64 * np.sqrt(n) * 10, ev
+    ad = dev(a)
+    assert sr.schur_refine_dd(ad, dev(np.zeros_like(a)), dev(qh), dev(np.zeros_like(qh)), empty(n, n),
+                              empty(n, n), skip_orth=True)["rc"] == -4  # SR_ENOSYS
