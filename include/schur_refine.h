@@ -82,8 +82,10 @@ typedef struct {
   int update_slices;      /* SR_GEMM_OZAKI_I8: digits per operand of Q * Delta
                              (0 = chosen per update from ||Delta||_F, 2..7);
                              SR_GEMM_OZAKI_CRT: bits (0 = from ||Delta||_F, 12..55)   */
-  int compensated;        /* 1: chunked K accumulation with error-free (TwoSum)
-                             combination in the FP64 products P, That and Y            */
+  int compensated;        /* 1: two-level K accumulation in the FP64 products P, That
+                             and Y: the MFMA accumulators sum chunks of 32 K terms
+                             (16 real, for the real products), which are then added
+                             into running totals                                      */
   int gate_lp_terms;      /* 1: skip YW, W^2, W^3 whose Frobenius bound is below
                              0.1 u_hp (Section 2.4 notes the high-order terms may
                              fall below roundoff)                                      */

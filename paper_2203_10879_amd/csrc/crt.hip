@@ -419,20 +419,28 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
     const int rb = min((isA ? m0 : n0) / 16 + (qq & 7), (isA ? RBA : RBB) - 1);
     goff[j] = (int)(part * (isA ? pA : pB)) + rb * KT * 1024 + lane * 16;
   }
-  auto issue = [&](int st) {
+  const int total = N * KT;
+  // sources and stage of the loads of step st
+  struct Src {
+    const int8_t* A;
+    const int8_t* B;
+    int8_t* stage;
+  };
+  auto src = [&](int st) {
     const int k = st / KT, kt = st - k * KT;
-    const int8_t* baseA = a.A + (long)k * sA + kt * 1024;
-    const int8_t* baseB = a.B + (long)k * sB + kt * 1024;
-    int8_t* stage = lds + (st & 1) * kCStage;
-#pragma unroll
-    for (int j = 0; j < kCLoadsPerWave; j++) {
-      const int q = uwave * kCLoadsPerWave + j;
-      const bool isA = q < 24;
-      const int qq = isA ? q : q - 24;
-      const int loff = (isA ? (qq >> 3) : 3 + (qq >> 3)) * kCPart + 16 * (qq & 7) * kCRow;
-      __builtin_amdgcn_global_load_lds((gbl_ptr_t*)((isA ? baseA : baseB) + goff[j]), (lds_ptr_t*)(stage + loff),
-                                       16, 0, 0);
-    }
+    return Src{a.A + (long)k * sA + kt * 1024, a.B + (long)k * sB + kt * 1024, lds + (st & 1) * kCStage};
+  };
+  // load j of a step
+  auto issue_one = [&](const Src& sc, int j) {
+    const int8_t* baseA = sc.A;
+    const int8_t* baseB = sc.B;
+    int8_t* stage = sc.stage;
+    const int q = uwave * kCLoadsPerWave + j;
+    const bool isA = q < 24;
+    const int qq = isA ? q : q - 24;
+    const int loff = (isA ? (qq >> 3) : 3 + (qq >> 3)) * kCPart + 16 * (qq & 7) * kCRow;
+    __builtin_amdgcn_global_load_lds((gbl_ptr_t*)((isA ? baseA : baseB) + goff[j]), (lds_ptr_t*)(stage + loff),
+                                     16, 0, 0);
   };
   struct Frags {
     v4i b0[2], b1[2], a0[2], a2[2], a3[2];
@@ -456,21 +464,35 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
     }
   };
   v16i acc_re[2][2], acc_im[2][2];
-  auto mfmas = [&](const Frags& f) {
+  // the 32 MFMAs of a step (16 per K half), with the next step's loads (when nx <
+  // total) issued one after every third MFMA: spread over the step they took 6% less
+  // time at n = 4096 than issued together after the barrier
+  auto mfmas = [&](const Frags& f0, const Frags& f1, int nx) {
+    int jl = 0;
+    const bool more = nx < total;
+    const Src sc = src(more ? nx : 0);
+    auto one = [&]() {
+      if (more && jl < kCLoadsPerWave) issue_one(sc, jl);
+      jl++;
+    };
 #pragma unroll
-    for (int x = 0; x < 2; x++)
+    for (int h = 0; h < 2; h++) {
+      const Frags& f = h ? f1 : f0;
 #pragma unroll
-      for (int y = 0; y < 2; y++) {
-        acc_re[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a0[x], f.b0[y], acc_re[x][y], 0, 0, 0);
-        acc_im[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a0[x], f.b1[y], acc_im[x][y], 0, 0, 0);
-      }
+      for (int x = 0; x < 2; x++)
 #pragma unroll
-    for (int x = 0; x < 2; x++)
-#pragma unroll
-      for (int y = 0; y < 2; y++) {
-        acc_re[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a2[x], f.b1[y], acc_re[x][y], 0, 0, 0);
-        acc_im[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a3[x], f.b0[y], acc_im[x][y], 0, 0, 0);
-      }
+        for (int y = 0; y < 2; y++) {
+          const int i0 = ((h * 2 + x) * 2 + y) * 4;
+          acc_re[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a0[x], f.b0[y], acc_re[x][y], 0, 0, 0);
+          if (i0 % 3 == 1) one();
+          acc_im[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a0[x], f.b1[y], acc_im[x][y], 0, 0, 0);
+          if ((i0 + 1) % 3 == 1) one();
+          acc_re[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a2[x], f.b1[y], acc_re[x][y], 0, 0, 0);
+          if ((i0 + 2) % 3 == 1) one();
+          acc_im[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a3[x], f.b0[y], acc_im[x][y], 0, 0, 0);
+          if ((i0 + 3) % 3 == 1) one();
+        }
+    }
   };
   auto barrier = [&]() {
     __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
@@ -481,8 +503,11 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
   // outputs, lane (8 bytes)
   uint8_t* sres = a.scratch + (long)bid * N * kCScratchPerMod + (long)wave * N * (kCScratchPerMod / 4) + lane * 8;
 
-  const int total = N * KT;
-  issue(0);
+  {
+    const Src s0 = src(0);
+#pragma unroll
+    for (int j = 0; j < kCLoadsPerWave; j++) issue_one(s0, j);
+  }
   int st = 0;
   for (int k = 0; k < N; k++) {
 #pragma unroll
@@ -491,16 +516,14 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
       for (int y = 0; y < 2; y++) acc_re[x][y] = acc_im[x][y] = v16i{};
     for (int kt = 0; kt < KT; kt++, st++) {
       // wait for this step's loads, barrier (every wave's loads have landed; the
-      // other stage is no longer read), the next step's loads, then the MFMAs
+      // other stage is no longer read), then the MFMAs with the next step's loads
       __builtin_amdgcn_s_waitcnt(kWaitVm0);
       barrier();
-      if (st + 1 < total) issue(st + 1);
       const int8_t* base = lds + (st & 1) * kCStage;
       Frags f0, f1;
       load_frags(f0, base, 0);
       load_frags(f1, base, 1);
-      mfmas(f0);
-      mfmas(f1);
+      mfmas(f0, f1, st + 1);
     }
     // residues modulo m_k of this modulus' sums
     const int mo = a.c.mod[k];

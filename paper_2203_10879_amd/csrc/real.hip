@@ -16,6 +16,8 @@
 // stril(T_c L_c - L_c T_c) = -E_c (the complex sweep) gives L_c on every off-diagonal
 // block, and L = U L_c U^H there (real up to rounding; its real part is taken), 0 on
 // the diagonal blocks.
+#include <type_traits>
+
 #include "epilogue.hpp"
 #include "real.hpp"
 
@@ -209,18 +211,179 @@ __global__ __launch_bounds__(RNT) void rgemm_kernel(RGemmArgs g) {
   }
 }
 
+// Large products (at least one 128 x 128 tile per CU, FP64): a 512-thread block per
+// 128 x 128 tile, eight waves of 64 x 32 (4 x 2 blocks of 16 x 16), K-tile 16 through
+// a double-buffered LDS whose rows are permuted by XOR with 2k (the transposing
+// stores and the fragment reads then fall on distinct banks). The tile carries the
+// flop per operand byte of the complex kernel's 64 x 64 complex tile, which the 64 x 64
+// real tile has half of.
+constexpr int RBB = 128, RBNT = 512;
+__device__ inline int rbswz(int k, int c) { return c ^ (2 * k); }
+
+template <int OPA, int EPI, int COMP>
+__global__ __launch_bounds__(RBNT) void rgemm_big_kernel(RGemmArgs g) {
+  using V = typename MF<double>::v4;
+  __shared__ double As[2][RBK][RBB];
+  __shared__ double Bs[2][RBK][RBB];
+  __shared__ double red[RBNT / 64];
+  const int ntiles = gridDim.x, bid = blockIdx.x;
+  int logical = bid;
+  {
+    const int per = ntiles / kXCDs;
+    if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
+  }
+  int tm, tn;
+  if ((EPI == EPI_YDEF || EPI == EPI_STORE) && g.herm) {
+    herm_tile(logical, g.tiles_n, tm, tn);
+  } else {
+    constexpr int kGroup = 4;
+    const int group = logical / (kGroup * g.tiles_n);
+    const int first_m = group * kGroup;
+    const int gsize = min(g.tiles_m - first_m, kGroup);
+    const int within = logical - group * kGroup * g.tiles_n;
+    tm = first_m + within % gsize;
+    tn = within / gsize;
+  }
+  const int m0 = tm * RBB, n0 = tn * RBB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int WM = 4, WN = 2;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 32;
+  const double* __restrict__ Ap = (const double*)g.A;
+  const double* __restrict__ Bp = (const double*)g.B;
+
+  V acc[WM][WN], tot[WM][WN];
+#pragma unroll
+  for (int a = 0; a < WM; a++)
+#pragma unroll
+    for (int b = 0; b < WN; b++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) acc[a][b][v] = tot[a][b][v] = 0;
+
+  constexpr int kLoads = RBB * RBK / RBNT;  // 4 elements of each operand per thread
+  double ra[kLoads], rb[kLoads];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < kLoads; r++) {
+      const int idx = r * RBNT + tid;
+      int mm, kk;
+      if (OPA == 0) {
+        mm = idx & (RBB - 1);
+        kk = idx / RBB;
+      } else {
+        kk = idx & (RBK - 1);
+        mm = idx / RBK;
+      }
+      const int gm = m0 + mm, gk = k0 + kk;
+      double v = 0;
+      if (gm < g.m && gk < g.k) v = OPA == 0 ? Ap[gm + (long)gk * g.lda] : Ap[gk + (long)gm * g.lda];
+      ra[r] = v;
+      const int bk = idx & (RBK - 1), bn = idx / RBK;
+      const int gn = n0 + bn, gkb = k0 + bk;
+      double w = 0;
+      if (gn < g.n && gkb < g.k) w = Bp[gkb + (long)gn * g.ldb];
+      rb[r] = w;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < kLoads; r++) {
+      const int idx = r * RBNT + tid;
+      int mm, kk;
+      if (OPA == 0) {
+        mm = idx & (RBB - 1);
+        kk = idx / RBB;
+      } else {
+        kk = idx & (RBK - 1);
+        mm = idx / RBK;
+      }
+      As[buf][kk][rbswz(kk, mm)] = ra[r];
+      const int bk = idx & (RBK - 1);
+      Bs[buf][bk][rbswz(bk, idx / RBK)] = rb[r];
+    }
+  };
+  const int KT = (g.k + RBK - 1) / RBK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < KT; kt++) {
+    const int cur = kt & 1;
+    if (kt + 1 < KT) gload((kt + 1) * RBK);
+#pragma unroll
+    for (int kk = 0; kk < RBK; kk += 4) {
+      const int krow = kk + (lane >> 4);
+      double a[WM], b[WN];
+#pragma unroll
+      for (int x = 0; x < WM; x++) a[x] = As[cur][krow][rbswz(krow, wm + 16 * x + (lane & 15))];
+#pragma unroll
+      for (int y = 0; y < WN; y++) b[y] = Bs[cur][krow][rbswz(krow, wn + 16 * y + (lane & 15))];
+#pragma unroll
+      for (int x = 0; x < WM; x++)
+#pragma unroll
+        for (int y = 0; y < WN; y++) acc[x][y] = MF<double>::op(a[x], b[y], acc[x][y]);
+      // the next K-tile goes to the other buffer while this one's products run
+      if (kk == 4 && kt + 1 < KT) sstore(cur ^ 1);
+    }
+    if (COMP && ((kt + 1) % kRChunk == 0 || kt + 1 == KT)) {
+#pragma unroll
+      for (int x = 0; x < WM; x++)
+#pragma unroll
+        for (int y = 0; y < WN; y++) {
+          tot[x][y] += acc[x][y];
+#pragma unroll
+          for (int v = 0; v < 4; v++) acc[x][y][v] = 0;
+        }
+    }
+    __syncthreads();
+  }
+  double part = 0;
+#pragma unroll
+  for (int x = 0; x < WM; x++)
+#pragma unroll
+    for (int y = 0; y < WN; y++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int i = m0 + wm + 16 * x + MF<double>::row(lane, v);
+        const int j = n0 + wn + 16 * y + (lane & 15);
+        if (i < g.m && j < g.n) repi<EPI, double>(g, i, j, COMP ? tot[x][y][v] : acc[x][y][v], part);
+      }
+  if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    if (tid == 0) {
+      double s2 = 0;
+#pragma unroll
+      for (int w = 0; w < RBNT / 64; w++) s2 += red[w];
+      g.partials[bid] = s2;
+    }
+  }
+}
+
+// whether an FP64 product takes the 128 x 128 tile
+static bool rbig(int m, int n) { return (long)ceil_div(m, RBB) * ceil_div(n, RBB) >= kCUs; }
+
 int rgemm_tiles(int m, int n, bool herm) {
-  const int t = ceil_div(n, RBM);
-  return herm ? t * (t + 1) / 2 : ceil_div(m, RBM) * t;
+  const int e = rbig(m, n) ? RBB : RBM;
+  const int t = ceil_div(n, e);
+  return herm ? t * (t + 1) / 2 : ceil_div(m, e) * t;
 }
 
 template <typename R, int OPA, int EPI, int COMP>
 static hipError_t rlaunch(RGemmArgs g, hipStream_t st) {
-  g.tiles_m = ceil_div(g.m, RBM);
-  g.tiles_n = ceil_div(g.n, RBM);
   if (g.herm && (g.m != g.n || !(EPI == EPI_STORE || (EPI == EPI_YDEF && g.herm == 1)))) return hipErrorInvalidValue;
-  const int nt = rgemm_tiles(g.m, g.n, g.herm != 0);
+  const bool big = std::is_same<R, double>::value && rbig(g.m, g.n);
+  const int e = big ? RBB : RBM;
+  g.tiles_m = ceil_div(g.m, e);
+  g.tiles_n = ceil_div(g.n, e);
+  const int nt = g.herm ? g.tiles_n * (g.tiles_n + 1) / 2 : g.tiles_m * g.tiles_n;
   if (nt == 0) return hipSuccess;
+  if constexpr (std::is_same<R, double>::value) {
+    if (big) {
+      hipLaunchKernelGGL((rgemm_big_kernel<OPA, EPI, COMP>), dim3(nt), dim3(RBNT), 0, st, g);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((rgemm_kernel<R, OPA, EPI, COMP>), dim3(nt), dim3(RNT), 0, st, g);
   return hipGetLastError();
 }

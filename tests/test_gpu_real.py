@@ -98,6 +98,24 @@ def test_dgemm_two_level_sum_is_more_accurate(sr):
     assert errs[1] < 0.7 * errs[0], errs
 
 
+@pytest.mark.parametrize("opa", [0, 1])
+@pytest.mark.parametrize("comp", [False, True])
+def test_dgemm_large_tile_exact_on_integers(sr, opa, comp):
+    """Products with at least one 128 x 128 tile per CU take the large-tile kernel:
+    bit-exact on integers (ragged M), and with an added C."""
+    m, n, k = 2048 + 37, 2048, 300
+    rng = np.random.default_rng(90 + opa + 2 * comp)
+    a = rng.integers(-4096, 4097, (k, m) if opa else (m, k)).astype(np.float64)
+    b = rng.integers(-4096, 4097, (k, n)).astype(np.float64)
+    c0 = rng.integers(-2**20, 2**20, (m, n)).astype(np.float64)
+    c = empty(m, n)
+    assert sr.sr_dgemm(dev(a), dev(b), c, opa=opa, compensated=comp) == 0
+    ref = (a.T if opa else a) @ b
+    assert np.array_equal(host(c), ref)
+    assert sr.sr_dgemm(dev(a), dev(b), c, opa=opa, Cin=dev(c0), compensated=comp) == 0
+    assert np.array_equal(host(c), ref + c0)
+
+
 def test_dgemm_add_epilogue(sr):
     rng = np.random.default_rng(3)
     m, n, k = 70, 90, 40
@@ -287,6 +305,33 @@ def test_n1024_quad_rows(sr):
     assert np.abs(t[rows] - tt).max() <= 1e-13 * na
     lam = _block_eigs(t, blk)
     assert np.abs(np.sort_complex(lam) - np.sort_complex(g["lam"])).max() <= 1e-10
+
+
+def test_n2048_large_tiles_quad_rows(sr):
+    """n = 2048 (the real benchmark size: every FP64 product on the 128 x 128 tile
+    kernel, the symmetric Y over its upper tiles): at most 5 passes to 1e-15 and the
+    binary128 residual and orthogonality on 16 sampled rows."""
+    n = 2048
+    g = synth.real_schur_test_matrix(n, seed=3)
+    a = g["A"]
+    qh, blk = synth.lp_real_schur_start(a)
+    q, t, info = _refine_real(sr, a, qh, blk)
+    assert info["status"] == "OK" and info["iters"] <= 5, info
+    rows = np.sort(np.random.default_rng(20004).choice(n, 16, replace=False))
+    qr = np.asfortranarray(q[:, rows]).astype(complex)
+    ra_hi, ra_lo = oracle.gemm(qr, a.astype(complex), opa=1).to_dd()
+    m_hi, m_lo = oracle.gemm(np.asfortranarray(ra_hi), q.astype(complex)).to_dd()
+    m2_hi, m2_lo = oracle.gemm(np.asfortranarray(ra_lo), q.astype(complex)).to_dd()
+    m = (m_hi.real + m2_hi.real) + (m_lo.real + m2_lo.real)
+    mask = block_lower_mask(n, blk)[rows]
+    stril = np.sqrt(np.sum(m[mask] ** 2) * n / len(rows)) / np.linalg.norm(a)
+    assert stril <= 1e-15, stril
+    o_hi, o_lo = oracle.gemm(qr, q.astype(complex), opa=1).to_dd()
+    o = o_hi.real.copy()
+    o[np.arange(len(rows)), rows] -= 1.0
+    o += o_lo.real
+    assert np.sqrt(np.sum(o ** 2) * n / len(rows)) <= 4 * U64 * np.sqrt(n) * 10
+    assert np.abs(t[rows] - np.where(mask, 0.0, m)).max() <= 1e-13 * np.linalg.norm(a)
 
 
 def test_real_status_codes(sr):
