@@ -209,6 +209,26 @@ size_t sr_workspace_bytes_batched(int batch, const int* n, const sr_opts* opts);
 /* Tile edge the batched autotuner chose for matrices of size n (-1: not tuned). */
 int sr_batched_tile_edge(int n);
 
+/* Persistent blocks per CU the autotuner chose for matrices of size n (1, 2, 4 or 8;
+ * -1: not tuned). The autotuner times, once per size bucket (n <= 32, 64, 128, 192,
+ * 256, larger), the grouped product P = A Q of up to 64 of the bucket's matrices for
+ * both tile edges and grids of 1, 2, 4 and 8 blocks per CU, and keeps the fastest. */
+int sr_batched_tile_grid(int n);
+
+/* Tuning table persistence. A file holds a header line and one line per device and
+ * bucket ("<arch>/<CUs> <bucket> <edge> <blocks per CU> <ms>"). sr_tuning_save writes
+ * the current device's table (keeping other devices' lines already in the file;
+ * returns the number of entries written); sr_tuning_load reads the current device's
+ * lines into the table (returns the number read; SR_EINVAL for a missing or foreign
+ * file; loaded buckets are not timed again). With the environment variable
+ * SR_TUNING_FILE set, the file is loaded before the first tuning and written after
+ * each new one. sr_tuning_reset empties the table (and does not reload the file);
+ * sr_tuning_runs counts the buckets timed in this process. */
+int sr_tuning_save(const char* path);
+int sr_tuning_load(const char* path);
+void sr_tuning_reset(void);
+int sr_tuning_runs(void);
+
 /* Number of two-pass graphs schur_refine_batched has captured and instantiated in
  * this process. A call with a caller-owned workspace keeps its graph (per host
  * thread) and the next call on that thread replays it without a new capture when

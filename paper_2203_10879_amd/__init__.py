@@ -94,6 +94,11 @@ _SIGS = {
     "sr_dgemm": (_i, [_i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _vp]),
     "sr_trisolve_real_ws_bytes": (_sz, [_i]),
     "sr_trisolve_real": (_i, [_vp, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
+    "sr_batched_tile_grid": (_i, [_i]),
+    "sr_tuning_save": (_i, [ctypes.c_char_p]),
+    "sr_tuning_load": (_i, [ctypes.c_char_p]),
+    "sr_tuning_reset": (None, []),
+    "sr_tuning_runs": (_i, []),
     "sr_trisolve_rec_ws_bytes": (_sz, [_i, _i]),
     "sr_trisolve_rec": (_i, [_vp, _vp, _vp, _i, _i, ctypes.c_float, _vp, _sz, _vp]),
     "sr_crt_moduli": (_i, [_i, _i]),

@@ -18,12 +18,15 @@
 // once in a HIP graph and replayed until no matrix is active or the pass limit is
 // reached; the host reads one counter per replay.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/schur_refine.h"
@@ -281,13 +284,100 @@ int bucket_of(int n) {
   return 5;
 }
 
+// A tuned configuration of a bucket's products: tile edge and persistent blocks per CU.
+struct TuneChoice {
+  int edge = 64, bpc = 4;
+  float ms = 0;  // the timed grouped product (0: loaded from a file)
+};
 struct Tuner {
   std::mutex mu;
-  std::map<int, int> bm;  // bucket -> tile edge
+  std::map<int, TuneChoice> bm;  // bucket -> choice
+  int runs = 0;                  // buckets timed in this process
+  bool env_loaded = false;       // SR_TUNING_FILE read
 };
 Tuner& tuner() {
   static Tuner t;
   return t;
+}
+
+// The device a tuning file entry belongs to: architecture name and CU count.
+std::string device_key() {
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return std::string();
+  std::string a = p.gcnArchName;
+  for (char& c : a)
+    if (c == ' ') c = '_';
+  return a + "/" + std::to_string(p.multiProcessorCount);
+}
+
+// Tuning file: a header line, then one line per (device, bucket):
+//   <device> <bucket> <edge> <blocks per CU> <ms>
+constexpr const char* kTuneHeader = "schur_refine batched tuning v1";
+
+int tuning_save_locked(const char* path) {
+  const std::string dk = device_key();
+  if (dk.empty()) return SR_EHIP;
+  // keep the entries of other devices already in the file
+  std::vector<std::string> keep;
+  if (FILE* f = fopen(path, "r")) {
+    char line[512];
+    bool first = true;
+    while (fgets(line, sizeof(line), f)) {
+      if (first) {
+        first = false;
+        continue;
+      }
+      char d[256];
+      if (sscanf(line, "%255s", d) == 1 && dk != d) keep.push_back(line);
+    }
+    fclose(f);
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return SR_EINVAL;
+  fprintf(f, "%s\n", kTuneHeader);
+  for (const auto& l : keep) fputs(l.c_str(), f);
+  for (const auto& kv : tuner().bm)
+    fprintf(f, "%s %d %d %d %.4f\n", dk.c_str(), kv.first, kv.second.edge, kv.second.bpc, kv.second.ms);
+  if (fclose(f) != 0 || rename(tmp.c_str(), path) != 0) return SR_EINVAL;
+  return (int)tuner().bm.size();
+}
+
+int tuning_load_locked(const char* path) {
+  const std::string dk = device_key();
+  if (dk.empty()) return SR_EHIP;
+  FILE* f = fopen(path, "r");
+  if (!f) return SR_EINVAL;
+  char line[512];
+  int count = 0;
+  if (!fgets(line, sizeof(line), f) || strncmp(line, kTuneHeader, strlen(kTuneHeader)) != 0) {
+    fclose(f);
+    return SR_EINVAL;
+  }
+  while (fgets(line, sizeof(line), f)) {
+    char d[256];
+    int b, e, g;
+    float ms;
+    if (sscanf(line, "%255s %d %d %d %f", d, &b, &e, &g, &ms) != 5) continue;
+    if (dk != d || b < 0 || b > 5 || (e != 32 && e != 64) || !(g == 1 || g == 2 || g == 4 || g == 8)) continue;
+    TuneChoice c;
+    c.edge = e;
+    c.bpc = g;
+    c.ms = ms;
+    tuner().bm[b] = c;
+    count++;
+  }
+  fclose(f);
+  return count;
+}
+
+// SR_TUNING_FILE: read once, before the first tuning
+void tuning_env_load_locked() {
+  if (tuner().env_loaded) return;
+  tuner().env_loaded = true;
+  if (const char* p = getenv("SR_TUNING_FILE"))
+    if (*p) tuning_load_locked(p);
 }
 
 int tiles_of(int n, int bm) { return ceil_div(n, bm) * ceil_div(n, bm); }
@@ -367,19 +457,19 @@ struct Launcher {
   const GemmArgs* args_dev;  // [kArgTables][batch]
   const GTile* t64;
   const GTile* t32;
-  int n64, n32, batch, grid;
+  int n64, n32, batch, grid64, grid32;  // persistent grids of the two tile edges
   hipStream_t st;
   hipError_t z(int table, int opa, int epi, int comp, const int* active) const {
     const GemmArgs* a = args_dev + (size_t)table * batch;
-    hipError_t e = zgemm_grouped(opa, epi, comp, 64, a, t64, n64, active, grid, st);
+    hipError_t e = zgemm_grouped(opa, epi, comp, 64, a, t64, n64, active, grid64, st);
     if (e != hipSuccess) return e;
-    return zgemm_grouped(opa, epi, comp, 32, a, t32, n32, active, grid, st);
+    return zgemm_grouped(opa, epi, comp, 32, a, t32, n32, active, grid32, st);
   }
   hipError_t c(int table, const int* active) const {
     const GemmArgs* a = args_dev + (size_t)table * batch;
-    hipError_t e = cgemm_grouped(64, a, t64, n64, active, grid, st);
+    hipError_t e = cgemm_grouped(64, a, t64, n64, active, grid64, st);
     if (e != hipSuccess) return e;
-    return cgemm_grouped(32, a, t32, n32, active, grid, st);
+    return cgemm_grouped(32, a, t32, n32, active, grid32, st);
   }
 };
 
@@ -387,17 +477,23 @@ struct Launcher {
 // 10 W2, 11 W3, 12 YW.
 enum { T_NSY = 0, T_NSU = 1, T_P = 2, T_T = 3, T_Y = 4, T_U = 5, T_W2 = 10, T_W3 = 11, T_YW = 12 };
 
-// Autotuner: for a bucket seen for the first time, time the grouped P = A Q of
-// (up to 64 of) its matrices with both tile edges and keep the faster.
+// Autotuner: for a bucket seen for the first time (and not in a loaded tuning
+// file), time the grouped P = A Q of (up to 64 of) its matrices for both tile
+// edges and persistent grids of 1, 2, 4 and 8 blocks per CU, and keep the fastest.
+// With SR_TUNING_FILE set the table is written back after each new tuning.
 int tune_bucket(int bucket, const std::vector<int>& members, const int* n, const void* const* A,
-                void* const* Q, void* scratch, hipStream_t st) {
+                void* const* Q, void* scratch, hipStream_t st, TuneChoice* out) {
   {
     std::lock_guard<std::mutex> lk(tuner().mu);
+    tuning_env_load_locked();
     auto it = tuner().bm.find(bucket);
-    if (it != tuner().bm.end()) return it->second;
+    if (it != tuner().bm.end()) {
+      *out = it->second;
+      return SR_OK;
+    }
   }
   const int cnt = (int)std::min<size_t>(members.size(), 64);
-  int best = 64;
+  TuneChoice best;
   if (cnt > 0) {
     // scratch: outputs then tables
     std::vector<GemmArgs> args(cnt);
@@ -410,12 +506,13 @@ int tune_bucket(int bucket, const std::vector<int>& members, const int* n, const
     GemmArgs* args_dev = (GemmArgs*)p;
     p += a256(sizeof(GemmArgs) * cnt);
     GTile* tiles_dev = (GTile*)p;
-    float ms[2] = {0, 0};
     const int edges[2] = {64, 32};
+    const int bpcs[4] = {1, 2, 4, 8};
     hipEvent_t e0, e1;
     BCK(hipEventCreate(&e0));
     BCK(hipEventCreate(&e1));
     BCK(hipMemcpyAsync(args_dev, args.data(), sizeof(GemmArgs) * cnt, hipMemcpyHostToDevice, st));
+    float best_ms = 0;
     for (int v = 0; v < 2; v++) {
       std::vector<GTile> tl;
       for (int i = 0; i < cnt; i++) {
@@ -424,22 +521,35 @@ int tune_bucket(int bucket, const std::vector<int>& members, const int* n, const
           for (int tm = 0; tm < ceil_div(nn, edges[v]); tm++) tl.push_back({i, tm * edges[v], tn * edges[v], 0});
       }
       BCK(hipMemcpyAsync(tiles_dev, tl.data(), sizeof(GTile) * tl.size(), hipMemcpyHostToDevice, st));
-      const int grid = (int)std::min<size_t>(tl.size(), 4 * kCUs);
-      for (int rep = 0; rep < 3; rep++) {
-        if (rep == 1) BCK(hipEventRecord(e0, st));
-        BCK(zgemm_grouped(0, EPI_STORE, 1, edges[v], args_dev, tiles_dev, (int)tl.size(), nullptr, grid, st));
+      for (int gi = 0; gi < 4; gi++) {
+        const int grid = (int)std::min<size_t>(tl.size(), (size_t)bpcs[gi] * kCUs);
+        for (int rep = 0; rep < 3; rep++) {
+          if (rep == 1) BCK(hipEventRecord(e0, st));
+          BCK(zgemm_grouped(0, EPI_STORE, 1, edges[v], args_dev, tiles_dev, (int)tl.size(), nullptr, grid, st));
+        }
+        BCK(hipEventRecord(e1, st));
+        BCK(hipEventSynchronize(e1));
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms *= 0.5f;
+        if (best_ms == 0 || ms < best_ms) {
+          best_ms = ms;
+          best.edge = edges[v];
+          best.bpc = bpcs[gi];
+          best.ms = ms;
+        }
       }
-      BCK(hipEventRecord(e1, st));
-      BCK(hipEventSynchronize(e1));
-      hipEventElapsedTime(&ms[v], e0, e1);
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    best = ms[1] < ms[0] ? 32 : 64;
   }
   std::lock_guard<std::mutex> lk(tuner().mu);
   tuner().bm[bucket] = best;
-  return best;
+  tuner().runs++;
+  if (const char* p = getenv("SR_TUNING_FILE"))
+    if (*p) tuning_save_locked(p);
+  *out = best;
+  return SR_OK;
 }
 
 size_t tune_scratch_bytes(int batch, const int* n) {
@@ -470,18 +580,18 @@ int* host_counter() {
 // everything it bakes in is unchanged: the workspace address (every kernel
 // argument points into it; the per-matrix tables there are uploaded again on each
 // call, so the matrices' own addresses may change), the sizes and tile edges (the
-// grids and table offsets), the pass limit, tol and the options. Only calls with
+// table offsets), the persistent grids, the pass limit, tol and the options. Only calls with
 // a caller-owned workspace keep their graph.
 struct GraphKey {
   int dev = -1;
   const void* base = nullptr;
   std::vector<int> n, bm;
-  int iters = 0, comp = 0, gate = 0;
+  int iters = 0, comp = 0, gate = 0, grid64 = 0, grid32 = 0;
   double tol = 0;
   float trunc = 0;
   bool operator==(const GraphKey& o) const {
     return dev == o.dev && base == o.base && n == o.n && bm == o.bm && iters == o.iters && comp == o.comp &&
-           gate == o.gate && tol == o.tol && trunc == o.trunc;
+           gate == o.gate && tol == o.tol && trunc == o.trunc && grid64 == o.grid64 && grid32 == o.grid32;
   }
 };
 struct GraphCache {
@@ -567,14 +677,17 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
     for (int b = 0; b < batch; b++)
       if (n[b] >= 2) buckets[bucket_of(n[b])].push_back(b);
     std::vector<int> bm(batch, 64);
+    int bpc64 = 0, bpc32 = 0;  // the largest blocks per CU chosen for an edge
     bool bad = false;
     for (auto& kv : buckets) {
-      const int e = tune_bucket(kv.first, kv.second, n, A, Q, base, st);
-      if (e < 0) {
+      TuneChoice ch;
+      if (tune_bucket(kv.first, kv.second, n, A, Q, base, st, &ch) != SR_OK) {
         bad = true;
         break;
       }
-      for (int b : kv.second) bm[b] = e;
+      for (int b : kv.second) bm[b] = ch.edge;
+      int& g = ch.edge == 64 ? bpc64 : bpc32;
+      g = std::max(g, ch.bpc);
     }
     if (bad) {
       fail(SR_EHIP);
@@ -682,8 +795,10 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
     }
     const BMat* mats_dev = (const BMat*)(w + L.mats);
     int* counter = (int*)(w + L.counter);
+    const int grid64 = std::max(1, (int)std::min<size_t>(t64.size(), (size_t)std::max(1, bpc64) * kCUs));
+    const int grid32 = std::max(1, (int)std::min<size_t>(t32.size(), (size_t)std::max(1, bpc32) * kCUs));
     Launcher G{(const GemmArgs*)(w + L.args), tiles_dev, tiles_dev + t64.size(), (int)t64.size(),
-               (int)t32.size(), batch, 4 * kCUs, st};
+               (int)t32.size(), batch, grid64, grid32, st};
     const int small = ceil_div(batch, 256);
 
     // start: norms, state, Newton-Schulz orthogonalisation of the starts
@@ -699,6 +814,8 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
     if (hipGetDevice(&dev) != hipSuccess) { fail(SR_EHIP); break; }
     GraphKey key;
     key.dev = dev;
+    key.grid64 = grid64;
+    key.grid32 = grid32;
     key.base = base;
     key.n.assign(n, n + batch);
     key.bm = bm;
@@ -815,7 +932,37 @@ int sr_batched_graph_builds(void) { return g_graph_builds.load(); }
 int sr_batched_tile_edge(int n) {
   std::lock_guard<std::mutex> lk(tuner().mu);
   auto it = tuner().bm.find(bucket_of(n));
-  return it == tuner().bm.end() ? -1 : it->second;
+  return it == tuner().bm.end() ? -1 : it->second.edge;
+}
+
+int sr_batched_tile_grid(int n) {
+  std::lock_guard<std::mutex> lk(tuner().mu);
+  auto it = tuner().bm.find(bucket_of(n));
+  return it == tuner().bm.end() ? -1 : it->second.bpc;
+}
+
+int sr_tuning_save(const char* path) {
+  if (!path) return SR_EINVAL;
+  std::lock_guard<std::mutex> lk(tuner().mu);
+  return tuning_save_locked(path);
+}
+
+int sr_tuning_load(const char* path) {
+  if (!path) return SR_EINVAL;
+  std::lock_guard<std::mutex> lk(tuner().mu);
+  tuner().env_loaded = true;
+  return tuning_load_locked(path);
+}
+
+void sr_tuning_reset(void) {
+  std::lock_guard<std::mutex> lk(tuner().mu);
+  tuner().bm.clear();
+  tuner().env_loaded = true;  // a reset table is not refilled from SR_TUNING_FILE
+}
+
+int sr_tuning_runs(void) {
+  std::lock_guard<std::mutex> lk(tuner().mu);
+  return tuner().runs;
 }
 
 }  // extern "C"
