@@ -260,6 +260,22 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
 /* Bytes of device workspace schur_refine_dd needs for size n under `opts`. */
 size_t sr_workspace_bytes_dd(int n, const sr_opts* opts);
 
+/* Triple-double tier (more than two cells per number, Section 3 and the conclusions:
+ * hp with several doubles per entry): every hp value is a renormalized expansion of
+ * three complex128 arrays (A[0] + A[1] + A[2], likewise Q and T; column-major,
+ * leading dimension n, device memory; Q in/out, T out). hp products: Ozaki splits of
+ * the three-term operands into opts->slices 8-bit digits (0 = 22, at least 20, at
+ * most 32) on INT8 MFMA with a three-term FP64 accumulation (about 150 bits: the
+ * tolerance should stay above about 1e-44); lp = FP64 (solve and lp products) as in
+ * the double-double tier. n >= 2 (SR_EINVAL otherwise). Other outcomes as
+ * schur_refine (stagnation measured against u = 2^-150). opts->gemm must be
+ * SR_GEMM_FP64 and opts->solver, skip_orth 0 (SR_ENOSYS otherwise). */
+int schur_refine_td(const void* const* A, void* const* Q, void* const* T, int n, int iters, double tol,
+                    const sr_opts* opts, sr_info* info);
+
+/* Bytes of device workspace schur_refine_td needs for size n. */
+size_t sr_workspace_bytes_td(int n, const sr_opts* opts);
+
 /* Real Schur variant (Section 3 extends the method to the real Schur form: T is
  * quasi-upper-triangular, with 2 x 2 diagonal blocks holding complex conjugate
  * pairs). A, Q, T: real n x n, float64, column-major, leading dimension n (device).
@@ -428,6 +444,21 @@ int sr_ozaki_zgemm_dd(int opa, int m, int n, int k, const void* A_hi, const void
                       const void* Cin_lo, int ldcin, void* C_hi, void* C_lo, int ldc,
                       int slices_a, int slices_b, int dmax, void* ws, size_t ws_bytes,
                       void* stream);
+
+/* Triple-double operands and result (the hp products of the triple-double tier):
+ * C[0] + C[1] + C[2] = op(A[0] + A[1] + A[2]) (B[0] + B[1] + B[2]) (+ Cin[0] + Cin[1]
+ * + Cin[2]); each argument is an array of three device pointers to complex128
+ * column-major matrices sharing one leading dimension (terms largest first). The
+ * digits (`slices` 8-bit digits per operand, at least 1, at most 32; pairs s + t <=
+ * slices + 1) are taken from the exact three-term values, the pair sums are exact
+ * in int32 and are accumulated in a three-term FP64 expansion, so with 22 digits the
+ * result carries about 2^-150 relative to the row and column maxima. k >= 1 and every
+ * pointer of A and B set (SR_EINVAL otherwise). Cin may be NULL; when given, all
+ * three of its pointers are set. ws: device workspace of >=
+ * sr_ozaki_ws_bytes(m, n, k, slices, slices). */
+int sr_ozaki_zgemm_td(int opa, int m, int n, int k, const void* const* A, int lda, const void* const* B,
+                      int ldb, const void* const* Cin, int ldcin, void* const* C, int ldc, int slices,
+                      void* ws, size_t ws_bytes, void* stream);
 
 /* Ozaki scheme II product (the hp products of Section 3 from an Ozaki-type scheme,
  * here its CRT form) on INT8 MFMA: C = op(A) B (+ Cin), complex128, arguments as

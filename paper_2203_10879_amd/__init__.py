@@ -94,6 +94,13 @@ _SIGS = {
     "sr_dgemm": (_i, [_i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _vp, _i, _i, _vp]),
     "sr_trisolve_real_ws_bytes": (_sz, [_i]),
     "sr_trisolve_real": (_i, [_vp, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
+    "schur_refine_td": (_i, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                             ctypes.POINTER(ctypes.c_void_p), _i, _i, _d, ctypes.POINTER(SrOpts),
+                             ctypes.POINTER(SrInfo)]),
+    "sr_workspace_bytes_td": (_sz, [_i, ctypes.POINTER(SrOpts)]),
+    "sr_ozaki_zgemm_td": (_i, [_i, _i, _i, _i, ctypes.POINTER(ctypes.c_void_p), _i,
+                               ctypes.POINTER(ctypes.c_void_p), _i, ctypes.POINTER(ctypes.c_void_p), _i,
+                               ctypes.POINTER(ctypes.c_void_p), _i, _i, _vp, _sz, _vp]),
     "sr_batched_tile_grid": (_i, [_i]),
     "sr_tuning_save": (_i, [ctypes.c_char_p]),
     "sr_tuning_load": (_i, [ctypes.c_char_p]),
@@ -352,6 +359,28 @@ def sr_ozaki_zgemm_dd(A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, opa: int = 0, slices_a
         ws.numel() * ws.element_size(), _stream(stream))
 
 
+def sr_ozaki_zgemm_td(As, Bs, Cs, opa: int = 0, slices: int = 22, Cins=None, ws=None,
+                      stream=None) -> int:
+    """Triple-double Ozaki split product (see include/schur_refine.h): As, Bs, Cs
+    (and Cins) are three complex128 column-major tensors each, largest term first."""
+    import torch
+
+    m, n = Cs[0].shape
+    k = Bs[0].shape[0]
+    need = int(lib().sr_ozaki_ws_bytes(m, n, k, int(slices), int(slices)))
+    if ws is None:
+        ws = torch.empty(max(1, need), dtype=torch.uint8, device=Cs[0].device)
+    for xs in (As, Bs, Cs) + ((Cins,) if Cins is not None else ()):
+        if len(xs) != 3 or len({_ld(x) for x in xs}) != 1 or len({tuple(x.shape) for x in xs}) != 1:
+            raise ValueError("expected three terms of one shape and leading dimension")
+    arr = lambda xs: (ctypes.c_void_p * 3)(*[_mat(x, "c128").value for x in xs])
+    return lib().sr_ozaki_zgemm_td(
+        int(opa), m, n, k, arr(As), _ld(As[0]), arr(Bs), _ld(Bs[0]),
+        arr(Cins) if Cins is not None else None, _ld(Cins[0]) if Cins is not None else 1,
+        arr(Cs), _ld(Cs[0]), int(slices), ctypes.c_void_p(ws.data_ptr()),
+        ws.numel() * ws.element_size(), _stream(stream))
+
+
 def sr_cgemm(A, B, C, stream=None) -> int:
     m, n = C.shape
     k = B.shape[0]
@@ -504,3 +533,20 @@ def sr_trisolve_rec(T_lp, E_lp, L_lp, leaf_rows: int = 0, trunc: float = 0.0, ws
     return lib().sr_trisolve_rec(_mat(T_lp, "c64", n, n), _mat(E_lp, "c64", n, n), _mat(L_lp, "c64", n, n), n,
                                  int(leaf_rows), float(trunc), ctypes.c_void_p(ws.data_ptr()),
                                  ws.numel() * ws.element_size(), _stream(stream))
+
+
+# ------------------------------------------------------------ triple-double tier
+
+def schur_refine_td(As, Qs, Ts, iters: int = 6, tol: float = 1e-40, **kw) -> dict:
+    """Triple-double refinement: As, Qs, Ts are three complex128 column-major tensors
+    each (the terms of the expansions, largest first); Qs and Ts are written."""
+    n = As[0].shape[0]
+    pa = (ctypes.c_void_p * 3)(*[_mat(a, "c128", n, n).value for a in As])
+    pq = (ctypes.c_void_p * 3)(*[_mat(q, "c128", n, n).value for q in Qs])
+    pt = (ctypes.c_void_p * 3)(*[_mat(t, "c128", n, n).value for t in Ts])
+    o = make_opts(**kw)
+    info = SrInfo()
+    rc = lib().schur_refine_td(pa, pq, pt, n, int(iters), float(tol), ctypes.byref(o), ctypes.byref(info))
+    d = info.as_dict()
+    d["rc"] = rc
+    return d

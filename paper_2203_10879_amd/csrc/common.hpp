@@ -137,6 +137,32 @@ constexpr int kXCDs = 8;   // accelerator complex dies (one L2 each)
 
 __host__ __device__ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Triple-double arithmetic on renormalized expansions (x0, x1, x2), |x1| <= ulp(x0),
+// |x2| <= ulp(x1) up to small factors: renormalization by error-free sums and a sum
+// that keeps about 150 bits.
+//
+// Renormalization of three doubles of any magnitudes (a, b, c) with h + m + l = a + b
+// + c exactly: two bottom-up passes of error-free sums leave h the sum rounded to
+// double (one pass is not enough: where a and b + c cancel, the first pass's error
+// terms can exceed the sum it returns), and m the rest rounded likewise.
+__device__ inline void td_renorm(double a, double b, double c, double& h, double& m, double& l) {
+  double s, e, f, t;
+  two_sum(b, c, s, e);
+  two_sum(a, s, t, f);
+  two_sum(f, e, s, e);
+  two_sum(t, s, h, f);
+  two_sum(f, e, m, l);
+}
+__device__ inline void td_add(double a0, double a1, double a2, double b0, double b1, double b2, double& h,
+                              double& m, double& l) {
+  double s0, t0, s1, t1, s2, t2, u1, v1;
+  two_sum(a0, b0, s0, t0);
+  two_sum(a1, b1, s1, t1);
+  two_sum(a2, b2, s2, t2);
+  two_sum(t0, s1, u1, v1);
+  td_renorm(s0, u1, (t1 + s2) + (t2 + v1), h, m, l);
+}
+
 }  // namespace sr
 
 #define SR_HIP_CHECK(expr)                   \

@@ -172,6 +172,78 @@ __global__ __launch_bounds__(ENT) void form_delta_dd_kernel(
   }
 }
 
+// The triple-double Delta: W - Y/2 + (W2 + W3 - YW)/2 with Y = Y0 + Y1 + Y2 and the lp
+// terms (FP64) added as exact double-double sums.
+__global__ __launch_bounds__(ENT) void form_delta_td_kernel(
+    const zc* __restrict__ L, const zc* __restrict__ Y0, const zc* __restrict__ Y1, const zc* __restrict__ Y2,
+    const zc* __restrict__ W2, const zc* __restrict__ W3, const zc* __restrict__ YW, zc* __restrict__ D0,
+    zc* __restrict__ D1, zc* __restrict__ D2, int n) {
+  __shared__ zc lt[ET][ET + 1];
+  const int nb = ceil_div(n, ET);
+  const int bi = blockIdx.x % nb, bj = blockIdx.x / nb;
+  if (L) {
+    for (int r = threadIdx.x; r < ET * ET; r += ENT) {
+      const int a = r & (ET - 1), b = r >> 5;
+      const int gi = bj * ET + a, gj = bi * ET + b;
+      zc v = mk<double>(0, 0);
+      if (gi < n && gj < n && gi > gj) v = L[gi + (long)gj * n];
+      lt[a][b] = v;
+    }
+    __syncthreads();
+  }
+  for (int r = threadIdx.x; r < ET * ET; r += ENT) {
+    const int a = r & (ET - 1), b = r >> 5;
+    const int i = bi * ET + a, j = bj * ET + b;
+    if (i < n && j < n) {
+      const long o = i + (long)j * n;
+      double wr = 0, wi = 0;
+      if (L) {
+        if (i > j) {
+          const zc u = L[o];
+          wr = u.re;
+          wi = u.im;
+        } else if (i < j) {
+          const zc u = lt[b][a];
+          wr = -u.re;
+          wi = u.im;
+        }
+      }
+      double pr = 0, pi = 0;
+      if (W2) {
+        pr += W2[o].re;
+        pi += W2[o].im;
+      }
+      if (W3) {
+        pr += W3[o].re;
+        pi += W3[o].im;
+      }
+      if (YW) {
+        pr -= YW[o].re;
+        pi -= YW[o].im;
+      }
+      // W + (lp terms)/2 as an exact double-double, then + (-Y/2) in triple-double
+      double sr, er, si, ei;
+      two_sum(wr, 0.5 * pr, sr, er);
+      two_sum(wi, 0.5 * pi, si, ei);
+      const zc y0 = Y0[o], y1 = Y1[o], y2 = Y2[o];
+      double r0, r1, r2, q0, q1, q2;
+      td_add(-0.5 * y0.re, -0.5 * y1.re, -0.5 * y2.re, sr, er, 0.0, r0, r1, r2);
+      td_add(-0.5 * y0.im, -0.5 * y1.im, -0.5 * y2.im, si, ei, 0.0, q0, q1, q2);
+      D0[o] = mk<double>(r0, q0);
+      D1[o] = mk<double>(r1, q1);
+      D2[o] = mk<double>(r2, q2);
+    }
+  }
+}
+
+hipError_t form_delta_td(const zc* L, const zc* Y0, const zc* Y1, const zc* Y2, const zc* W2, const zc* W3,
+                         const zc* YW, zc* D0, zc* D1, zc* D2, int n, hipStream_t st) {
+  const int nb = ceil_div(n, ET);
+  hipLaunchKernelGGL(form_delta_td_kernel, dim3(nb * nb), dim3(ENT), 0, st, L, Y0, Y1, Y2, W2, W3, YW, D0, D1,
+                     D2, n);
+  return hipGetLastError();
+}
+
 hipError_t form_delta_dd(const zc* L, const zc* Yhi, const zc* Ylo, const zc* W2, const zc* W3,
                          const zc* YW, zc* Dhi, zc* Dlo, int n, hipStream_t st) {
   const int nb = ceil_div(n, ET);

@@ -104,6 +104,62 @@ __device__ inline void epi_element_dd(const GemmArgs& g, int i, int j, zc hi, zc
   }
 }
 
+// Triple-double variant: the product value is x0 + x1 + x2 (complex128 each).
+template <int EPI>
+__device__ inline void epi_element_td(const GemmArgs& g, int i, int j, zc x0, zc x1, zc x2, double& part) {
+  zc* __restrict__ C0 = (zc*)g.C;
+  zc* __restrict__ C1 = (zc*)g.Cmid;
+  zc* __restrict__ C2 = (zc*)g.Clo;
+  const long o = i + (long)j * g.ldc;
+  const zc z = mk<double>(0, 0);
+  if constexpr (EPI == EPI_STORE) {
+    C0[o] = x0;
+    C1[o] = x1;
+    C2[o] = x2;
+  } else if constexpr (EPI == EPI_ADD) {
+    const long oi = i + (long)j * g.ldcin;
+    const zc a0 = ((const zc*)g.Cin)[oi], a1 = ((const zc*)g.Cinmid)[oi], a2 = ((const zc*)g.Cinlo)[oi];
+    double r0, r1, r2, i0, i1, i2;
+    td_add(a0.re, a1.re, a2.re, x0.re, x1.re, x2.re, r0, r1, r2);
+    td_add(a0.im, a1.im, a2.im, x0.im, x1.im, x2.im, i0, i1, i2);
+    C0[o] = mk<double>(r0, i0);
+    C1[o] = mk<double>(r1, i1);
+    C2[o] = mk<double>(r2, i2);
+  } else if constexpr (EPI == EPI_SPLIT) {
+    const long ol = i + (long)j * g.ldlp;
+    if (i <= j) {
+      C0[o] = x0;
+      C1[o] = x1;
+      C2[o] = x2;
+      g.Tlp64[ol] = x0;
+      g.Elp64[ol] = z;
+    } else {
+      C0[o] = z;
+      C1[o] = z;
+      C2[o] = z;
+      g.Tlp64[ol] = z;
+      g.Elp64[ol] = x0;
+      part += x0.re * x0.re + x0.im * x0.im;
+    }
+  } else {  // EPI_YDEF
+    if (g.herm && i > j) return;  // the conjugate of (j, i) is stored there
+    double r0 = x0.re, r1 = x1.re, r2 = x2.re;
+    if (i == j) td_add(r0, r1, r2, -1.0, 0.0, 0.0, r0, r1, r2);
+    C0[o] = mk<double>(r0, x0.im);
+    C1[o] = mk<double>(r1, x1.im);
+    C2[o] = mk<double>(r2, x2.im);
+    const double p = r0 * r0 + x0.im * x0.im;
+    part += p;
+    if (g.herm && i < j) {
+      const long t = j + (long)i * g.ldc;
+      C0[t] = mk<double>(r0, -x0.im);
+      C1[t] = mk<double>(r1, -x1.im);
+      C2[t] = mk<double>(r2, -x2.im);
+      part += p;
+    }
+  }
+}
+
 // Block reduction of `part` into g.partials[slot] (fixed order).
 template <int NT>
 __device__ inline void epi_reduce(const GemmArgs& g, double part, double* red, int slot) {

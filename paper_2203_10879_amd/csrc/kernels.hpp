@@ -37,6 +37,10 @@ struct GemmArgs {
   const void* Cinlo;
   zc* Tlp64;
   zc* Elp64;
+  // triple-double outputs (windowed Ozaki product): middle terms of C and Cin (the
+  // low terms in Clo / Cinlo); C, Cmid, Clo form a renormalized expansion
+  void* Cmid;
+  const void* Cinmid;
   // EPI_YDEF (1) and EPI_STORE (1 or -1): the product is Hermitian (1) or
   // skew-Hermitian (-1), e.g. Q^H Q, W^2 and W^3 for a skew-Hermitian W. Only the
   // elements with i <= j are stored from the product, each with its conjugate
@@ -90,6 +94,10 @@ hipError_t w2_minus_y(const zc* W2, const zc* Y, zc* X, long count, hipStream_t 
 hipError_t form_w64(const zc* L, zc* W, int n, double* partials, hipStream_t st);
 hipError_t form_delta_dd(const zc* L, const zc* Yhi, const zc* Ylo, const zc* W2, const zc* W3,
                          const zc* YW, zc* Dhi, zc* Dlo, int n, hipStream_t st);
+// Triple-double tier: D = W - Y/2 + (W2 + W3 - YW)/2 with Y and D as three-term
+// expansions (Y0 + Y1 + Y2, D0 + D1 + D2); L and the lp products FP64 (may be NULL).
+hipError_t form_delta_td(const zc* L, const zc* Y0, const zc* Y1, const zc* Y2, const zc* W2, const zc* W3,
+                         const zc* YW, zc* D0, zc* D1, zc* D2, int n, hipStream_t st);
 hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
 
 // Ozaki split products on INT8 MFMA (complex128 operands, FP64 output).
@@ -98,11 +106,17 @@ hipError_t oz_split_cols(const zc* X, const zc* Xlo, long ld, int K, int ncols, 
                          int* exps, hipStream_t st);
 hipError_t oz_split_rows(const zc* X, const zc* Xlo, long ld, int M, int K, int S, int8_t* out,
                          int* exps, hipStream_t st);
+// Triple-double operands (X + Xmid + Xlo, renormalized expansions; Xmid requires Xlo).
+hipError_t oz_split_cols3(const zc* X, const zc* Xmid, const zc* Xlo, long ld, int K, int ncols, int S,
+                          int8_t* out, int* exps, hipStream_t st);
+hipError_t oz_split_rows3(const zc* X, const zc* Xmid, const zc* Xlo, long ld, int M, int K, int S,
+                          int8_t* out, int* exps, hipStream_t st);
 // Output tiles (= partial sums written) of a product; the sizes, the digit counts
 // and dd (double-double accumulation) select the kernel; herm: a Hermitian
 // product (GemmArgs::herm).
-int oz_gemm_tiles(int m, int n, int k, bool dd, bool herm, int SA, int SB, int dmax);
-// Bytes of scratch the product of an m x n output needs (0 for small FP64 outputs).
+int oz_gemm_tiles(int m, int n, int k, bool dd, bool herm, int SA, int SB, int dmax, bool td = false);
+// Bytes of scratch the product of an m x n output needs (0 for small FP64 outputs;
+// double-double and triple-double outputs use the dd size).
 size_t oz_gemm_scratch_bytes(int m, int n, bool dd = false);
 // Whether the int32 sums of a product stay exact for these sizes.
 bool oz_gemm_exact(int m, int n, int k, int SA, int SB, bool dd = false);

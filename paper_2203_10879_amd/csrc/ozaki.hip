@@ -81,6 +81,32 @@ __host__ __device__ inline int raw_digit_dd(double& rh, double& rl) {
   return (int)d;
 }
 
+// The same for a triple-double remainder (r0, r1, r2): y = 256 r exactly, d the
+// rounding of y0, and the remainder (y0 - d) + y1 + y2 renormalized by error-free
+// sums (exact), moved into [-1/2, 1/2] by one unit when the lower terms push it out.
+__host__ __device__ inline int raw_digit_td(double& r0, double& r1, double& r2) {
+  const double y0 = r0 * 256.0, y1 = r1 * 256.0, y2 = r2 * 256.0;
+  double d = rint(y0);
+  double h, e1, m, e2, h2, e3, m2, l2;
+  two_sum(y0 - d, y1, h, e1);  // y0 - d is exact, |y0 - d| <= 1/2
+  two_sum(e1, y2, m, e2);
+  two_sum(h, m, h2, e3);
+  two_sum(e3, e2, m2, l2);
+  const bool tail_pos = m2 > 0.0 || (m2 == 0.0 && l2 > 0.0);
+  const bool tail_neg = m2 < 0.0 || (m2 == 0.0 && l2 < 0.0);
+  if (h2 > 0.5 || (h2 == 0.5 && tail_pos)) {
+    d += 1.0;
+    h2 -= 1.0;  // exact: h2 is within an ulp of 1/2
+  } else if (h2 < -0.5 || (h2 == -0.5 && tail_neg)) {
+    d -= 1.0;
+    h2 += 1.0;
+  }
+  r0 = h2;
+  r1 = m2;
+  r2 = l2;
+  return (int)d;
+}
+
 // Carries of a raw digit string. Digit s (1..S) sits at bit S - s; raw 128
 // generates a carry into the digit above, raw 127 passes an incoming one on. The
 // carry into every position is that of the binary sum G + (G | P), i.e.
@@ -124,6 +150,12 @@ __host__ __device__ inline Carries value_carries_dd(double rh, double rl, int S)
   return {digit_carries(m[0], m[1]), digit_carries(m[2], m[3])};
 }
 
+__host__ __device__ inline Carries value_carries_td(double r0, double r1, double r2, int S) {
+  uint64_t m[4] = {0, 0, 0, 0};
+  for (int s = 1; s <= S; s++) note_digit(raw_digit_td(r0, r1, r2), 1ull << (S - s), m);
+  return {digit_carries(m[0], m[1]), digit_carries(m[2], m[3])};
+}
+
 // The raw digits of one value from a single pass, kept for the stores: digit s
 // (1..S) modulo 256 in byte (s - 1) mod 8 of word (s - 1) / 8, with the carry masks
 // of x and -x. (raw + carry) modulo 256 read as a signed byte is final_digit's
@@ -136,8 +168,9 @@ struct Digits {
   Carries c;
 };
 
-template <bool DD>
-__host__ __device__ inline Digits split_value(double rh, double rl, int S) {
+// NT: terms of the value (1: double, 2: double-double, 3: triple-double rh, rm, rl)
+template <int NT>
+__host__ __device__ inline Digits split_value(double rh, double rm, double rl, int S) {
   Digits d;
   uint64_t m[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -147,7 +180,7 @@ __host__ __device__ inline Digits split_value(double rh, double rl, int S) {
     for (int j = 0; j < 8; j++) {
       const int s = 8 * q + j + 1;
       if (s <= S) {
-        const int r = DD ? raw_digit_dd(rh, rl) : raw_digit(rh);
+        const int r = NT == 3 ? raw_digit_td(rh, rm, rl) : NT == 2 ? raw_digit_dd(rh, rl) : raw_digit(rh);
         note_digit(r, 1ull << (S - s), m);
         word |= (uint64_t)(uint8_t)r << (8 * j);
       }
@@ -167,6 +200,7 @@ __host__ __device__ inline int8_t byte_digit(unsigned byte, uint64_t carries, in
 // the padded count (padding columns get zero digits). These serve as B, and as
 // op(A) = X^H when the product applies the conjugation.
 __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __restrict__ X,
+                                                                 const zc* __restrict__ Xmid,
                                                                  const zc* __restrict__ Xlo, long ld,
                                                                  int K, int ncols, int S, int Kp,
                                                                  int8_t* __restrict__ out,
@@ -187,6 +221,7 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
   }
   const zc* x = X + (long)col * ld;
   const zc* xl = Xlo ? Xlo + (long)col * ld : nullptr;
+  const zc* xm = Xmid ? Xmid + (long)col * ld : nullptr;
   double m = 0;
   for (int k = threadIdx.x; k < K; k += kSplitNT) m = fmax(m, fmax(fabs(x[k].re), fabs(x[k].im)));
 #pragma unroll
@@ -209,10 +244,13 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
     if (k < K) {
       const zc v = x[k];
       const zc w = xl ? xl[k] : mk<double>(0, 0);
-      const double rh = ldexp(v.re, -e), rl = ldexp(w.re, -e);
-      const double ih = ldexp(v.im, -e), il = ldexp(w.im, -e);
-      const Digits dr = xl ? split_value<true>(rh, rl, S) : split_value<false>(rh, 0.0, S);
-      const Digits di = xl ? split_value<true>(ih, il, S) : split_value<false>(ih, 0.0, S);
+      const zc u = xm ? xm[k] : mk<double>(0, 0);
+      const double rh = ldexp(v.re, -e), rl = ldexp(w.re, -e), rm = ldexp(u.re, -e);
+      const double ih = ldexp(v.im, -e), il = ldexp(w.im, -e), im = ldexp(u.im, -e);
+      const Digits dr = xm ? split_value<3>(rh, rm, rl, S)
+                           : xl ? split_value<2>(rh, 0.0, rl, S) : split_value<1>(rh, 0.0, 0.0, S);
+      const Digits di = xm ? split_value<3>(ih, im, il, S)
+                           : xl ? split_value<2>(ih, 0.0, il, S) : split_value<1>(ih, 0.0, 0.0, S);
 #pragma unroll
       for (int q = 0; q < kMaxDigits / 8; q++)
 #pragma unroll
@@ -272,12 +310,14 @@ __global__ void oz_exp_fix_kernel(int* __restrict__ exps, int M) {
 // Slices of the rows of X; one block per 32 x 32 tile, staged through LDS so that
 // reads follow the columns and writes the rows (padding rows get zero digits).
 __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __restrict__ X,
+                                                                 const zc* __restrict__ Xmid,
                                                                  const zc* __restrict__ Xlo, long ld,
                                                                  int M, int K, int S, int Kp,
                                                                  const int* __restrict__ exps,
                                                                  int8_t* __restrict__ out) {
   __shared__ zc t[32][33];
   __shared__ zc tl[32][33];
+  __shared__ zc tmid[32][33];
   const int i0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
 #pragma unroll
   for (int r = 0; r < 4; r++) {
@@ -291,6 +331,10 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
     if (Xlo) {
       const zc w = Xlo[o];
       tl[kk][row] = mk<double>(ok ? w.re : 0.0, ok ? w.im : 0.0);
+    }
+    if (Xmid) {
+      const zc w = Xmid[o];
+      tmid[kk][row] = mk<double>(ok ? w.re : 0.0, ok ? w.im : 0.0);
     }
   }
   __syncthreads();
@@ -308,7 +352,7 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
     return;
   }
   const int e = exps[gi];
-  double rh[4], rl[4], ih[4], il[4];
+  double rh[4], rl[4], ih[4], il[4], rm[4], imd[4];
 #pragma unroll
   for (int c = 0; c < 4; c++) {
     const zc v = t[kg + c][row];
@@ -321,19 +365,30 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
     } else {
       rl[c] = il[c] = 0;
     }
+    if (Xmid) {
+      const zc w = tmid[kg + c][row];
+      rm[c] = ldexp(w.re, -e);
+      imd[c] = ldexp(w.im, -e);
+    } else {
+      rm[c] = imd[c] = 0;
+    }
   }
   Carries cr[4], ci[4];
 #pragma unroll
   for (int c = 0; c < 4; c++) {
-    cr[c] = Xlo ? value_carries_dd(rh[c], rl[c], S) : value_carries(rh[c], S);
-    ci[c] = Xlo ? value_carries_dd(ih[c], il[c], S) : value_carries(ih[c], S);
+    cr[c] = Xmid  ? value_carries_td(rh[c], rm[c], rl[c], S)
+            : Xlo ? value_carries_dd(rh[c], rl[c], S)
+                  : value_carries(rh[c], S);
+    ci[c] = Xmid  ? value_carries_td(ih[c], imd[c], il[c], S)
+            : Xlo ? value_carries_dd(ih[c], il[c], S)
+                  : value_carries(ih[c], S);
   }
   for (int s = 0; s < S; s++) {
     unsigned pr = 0, pi = 0, pn = 0;
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-      const int dr = Xlo ? raw_digit_dd(rh[c], rl[c]) : raw_digit(rh[c]);
-      const int di = Xlo ? raw_digit_dd(ih[c], il[c]) : raw_digit(ih[c]);
+      const int dr = Xmid ? raw_digit_td(rh[c], rm[c], rl[c]) : Xlo ? raw_digit_dd(rh[c], rl[c]) : raw_digit(rh[c]);
+      const int di = Xmid ? raw_digit_td(ih[c], imd[c], il[c]) : Xlo ? raw_digit_dd(ih[c], il[c]) : raw_digit(ih[c]);
       pr |= (unsigned)(uint8_t)final_digit(dr, cr[c].pos, s + 1, S) << (8 * c);
       pi |= (unsigned)(uint8_t)final_digit(di, ci[c].pos, s + 1, S) << (8 * c);
       pn |= (unsigned)(uint8_t)final_digit(-di, ci[c].neg, s + 1, S) << (8 * c);
@@ -344,17 +399,28 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
   }
 }
 
+hipError_t oz_split_cols3(const zc* X, const zc* Xmid, const zc* Xlo, long ld, int K, int ncols, int S,
+                          int8_t* out, int* exps, hipStream_t st) {
+  if (S < 1 || S > kMaxDigits || (Xmid && !Xlo)) return hipErrorInvalidValue;
+  if (ncols == 0) return hipSuccess;
+  hipLaunchKernelGGL(oz_split_cols_kernel, dim3(oz_rows_pad(ncols)), dim3(kSplitNT), 0, st, X, Xmid, Xlo, ld, K,
+                     ncols, S, oz_kp(K), out, exps);
+  return hipGetLastError();
+}
+
 hipError_t oz_split_cols(const zc* X, const zc* Xlo, long ld, int K, int ncols, int S, int8_t* out,
                          int* exps, hipStream_t st) {
-  if (S < 1 || S > kMaxDigits) return hipErrorInvalidValue;
-  if (ncols == 0) return hipSuccess;
-  hipLaunchKernelGGL(oz_split_cols_kernel, dim3(oz_rows_pad(ncols)), dim3(kSplitNT), 0, st, X, Xlo, ld, K, ncols, S,
-                     oz_kp(K), out, exps);
-  return hipGetLastError();
+  return oz_split_cols3(X, nullptr, Xlo, ld, K, ncols, S, out, exps, st);
 }
 
 hipError_t oz_split_rows(const zc* X, const zc* Xlo, long ld, int M, int K, int S, int8_t* out,
                          int* exps, hipStream_t st) {
+  return oz_split_rows3(X, nullptr, Xlo, ld, M, K, S, out, exps, st);
+}
+
+hipError_t oz_split_rows3(const zc* X, const zc* Xmid, const zc* Xlo, long ld, int M, int K, int S,
+                          int8_t* out, int* exps, hipStream_t st) {
+  if (S < 1 || S > kMaxDigits || (Xmid && !Xlo)) return hipErrorInvalidValue;
   if (M == 0) return hipSuccess;
   hipLaunchKernelGGL(oz_exp_init_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, st, exps, M);
   hipLaunchKernelGGL(oz_rowmax_kernel, dim3(ceil_div(M, 64), max(1, ceil_div(K, 256))), dim3(kSplitNT), 0,
@@ -363,8 +429,8 @@ hipError_t oz_split_rows(const zc* X, const zc* Xlo, long ld, int M, int K, int 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int Kp = oz_kp(K);
-  hipLaunchKernelGGL(oz_split_rows_kernel, dim3(ceil_div(M, 32), Kp / 32), dim3(kSplitNT), 0, st, X, Xlo,
-                     ld, M, K, S, Kp, exps, out);
+  hipLaunchKernelGGL(oz_split_rows_kernel, dim3(ceil_div(M, 32), Kp / 32), dim3(kSplitNT), 0, st, X, Xmid,
+                     Xlo, ld, M, K, S, Kp, exps, out);
   return hipGetLastError();
 }
 
@@ -1196,6 +1262,13 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           sp[v * 64] = h;
           sp[1024 + v * 64] = m;
           sp[2048 + v * 64] = l;
+        } else if (g.Cmid) {
+          // triple-double: the expansion renormalized
+          double t0, t1, t2;
+          td_renorm(h, m, l, t0, t1, t2);
+          sp[v * 64] = t0;
+          sp[1024 + v * 64] = t1;
+          sp[2048 + v * 64] = t2;
         } else {
           // to double-double, kept in the first two slots for the epilogue
           double hh, e, dh, dl;
@@ -1224,6 +1297,57 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
     }
   }
+  double* xch = (double*)lds + (quad * 16) * 64 + lane;
+  if (g.Cmid) {
+    // triple-double: the imaginary parts' three terms to the waves of the real parts,
+    // in two rounds through the stages (two terms, then the third)
+    double x0[16], x1[16], x2[16], y2[16];
+#pragma unroll
+    for (int v = 0; v < 16; v++) {
+      x0[v] = sp[v * 64];
+      x1[v] = sp[1024 + v * 64];
+      x2[v] = sp[2048 + v * 64];
+    }
+    __syncthreads();
+    if (!re_part) {
+#pragma unroll
+      for (int v = 0; v < 16; v++) {
+        xch[v * 64] = x0[v];
+        xch[4096 + v * 64] = x1[v];
+      }
+    }
+    __syncthreads();
+    double y0[16], y1[16];
+#pragma unroll
+    for (int v = 0; v < 16; v++) {
+      y0[v] = xch[v * 64];
+      y1[v] = xch[4096 + v * 64];
+    }
+    __syncthreads();
+    if (!re_part) {
+#pragma unroll
+      for (int v = 0; v < 16; v++) xch[v * 64] = x2[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 16; v++) y2[v] = xch[v * 64];
+    double part = 0;
+    if (re_part) {
+#pragma unroll
+      for (int v = 0; v < 16; v++) {
+        const int i = m0 + wm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int j = n0 + wn + (lane & 31);
+        if (i < g.m && j < g.n) {
+          const int e = a.ea[i] + a.eb[j];
+          epi_element_td<EPI>(g, i, j, mk<double>(ldexp(x0[v], e), ldexp(y0[v], e)),
+                              mk<double>(ldexp(x1[v], e), ldexp(y1[v], e)),
+                              mk<double>(ldexp(x2[v], e), ldexp(y2[v], e)), part);
+        }
+      }
+    }
+    if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) epi_reduce<ANT>(g, part, red, bid);
+    return;
+  }
   // imaginary parts (hi, lo) to the waves of the real parts
   double hi[16], lo[16];
 #pragma unroll
@@ -1231,7 +1355,6 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     hi[v] = sp[v * 64];
     lo[v] = sp[1024 + v * 64];
   }
-  double* xch = (double*)lds + (quad * 16) * 64 + lane;
   __syncthreads();
   if (!re_part) {
 #pragma unroll
@@ -1265,10 +1388,11 @@ static bool use_large_tiles(int m, int n, bool dd) {
 
 // The windowed kernel takes the double-double tier's products (S digits per
 // operand, pairs s + t <= S + 1) with a 64 x 64 tile per CU.
-static bool use_windows(int m, int n, bool dd, int SA, int SB, int dmax, int k) {
+static bool use_windows(int m, int n, bool dd, int SA, int SB, int dmax, int k, bool td = false) {
   const long span = (long)(SA + kWin) * kParts * oz_plane_bytes(m > n ? m : n, oz_kp(k));
+  // triple-double outputs: this kernel at every size (the only one that writes them)
   return dd && SA == SB && SA >= 1 && dmax == SA + 1 && span < 2147483647L &&
-         ceil_div(m, ABM) * ceil_div(n, ABM) >= kCUs;
+         (td || ceil_div(m, ABM) * ceil_div(n, ABM) >= kCUs);
 }
 
 // The all-pairs kernel takes the FP64 tier's products (S digits per operand,
@@ -1301,8 +1425,8 @@ bool oz_gemm_exact(int m, int n, int k, int SA, int SB, bool dd) {
   return pairs * (long)oz_kp(k) * 16384L < 2147483648L;
 }
 
-int oz_gemm_tiles(int m, int n, int k, bool dd, bool herm, int SA, int SB, int dmax) {
-  if (use_allpairs(m, n, dd, SA, SB, dmax, k) || use_windows(m, n, dd, SA, SB, dmax, k)) {
+int oz_gemm_tiles(int m, int n, int k, bool dd, bool herm, int SA, int SB, int dmax, bool td) {
+  if (use_allpairs(m, n, dd, SA, SB, dmax, k) || use_windows(m, n, dd, SA, SB, dmax, k, td)) {
     const int t = ceil_div(n, ABM);
     return herm ? t * (t + 1) / 2 : ceil_div(m, ABM) * t;
   }
@@ -1383,11 +1507,13 @@ hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t
       default: return hipErrorInvalidValue;
     }
   }
-  if (use_windows(g.m, g.n, dd, SA, SB, dmax, g.k)) {
+  const bool td = g.Cmid != nullptr;
+  if (td && !use_windows(g.m, g.n, dd, SA, SB, dmax, g.k, true)) return hipErrorInvalidValue;
+  if (use_windows(g.m, g.n, dd, SA, SB, dmax, g.k, td)) {
     if (!scratch) return hipErrorInvalidValue;
     g.tiles_m = ceil_div(g.m, ABM);
     g.tiles_n = ceil_div(g.n, ABM);
-    const int nt = oz_gemm_tiles(g.m, g.n, g.k, dd, g.herm != 0, SA, SB, dmax);
+    const int nt = oz_gemm_tiles(g.m, g.n, g.k, dd, g.herm != 0, SA, SB, dmax, td);
     OzArgs a{A, ea, B, eb, SA, SB, dmax, conjA, oz_kp(g.k), g, (double2*)scratch};
     switch (epi) {
       case EPI_STORE: return launch_windows<EPI_STORE>(nt, a, st);

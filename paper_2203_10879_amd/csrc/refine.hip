@@ -1259,6 +1259,306 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
   return rc;
 }
 
+}  // extern "C"
+
+namespace {
+// ------------------------------------------------------------------------
+// Triple-double tier: hp = triple-double (three-term expansions; every hp product an
+// Ozaki split product of the triple-double operands into 22 digits, the windowed
+// kernel's three-term accumulation kept to the end), lp = FP64 as in the
+// double-double tier.
+
+constexpr double kUTD = 7.006492321624085e-46;  // 2^-150: the products keep about 150 bits
+constexpr int kTDSlices = 22;
+
+struct TDWork {
+  zc* Q[3];
+  zc* P[3];
+  zc* Y[3];
+  zc* D[3];
+  zc *Tlp, *Elp, *L, *W, *W2, *W3, *YW;
+  int8_t *sA, *sQc, *sP, *sQr, *sD;
+  int *eA, *eQc, *eP, *eQr, *eD;
+  void* scratch;
+  double* partials;
+  double* scal;
+  unsigned* status;
+  void* tri;
+  int S;
+  size_t bytes;
+};
+
+int td_main_slices(const sr_opts* o) { return (o && o->slices > 0) ? o->slices : kTDSlices; }
+
+TDWork carve_td(void* base, int n, const sr_opts* o) {
+  TDWork w;
+  uintptr_t p = (uintptr_t)base;
+  auto take = [&](size_t b) {
+    void* r = (void*)p;
+    p += align256(b);
+    return r;
+  };
+  const size_t z = (size_t)n * n * sizeof(zc);
+  for (int t = 0; t < 3; t++) w.Q[t] = (zc*)take(z);
+  for (int t = 0; t < 3; t++) w.P[t] = (zc*)take(z);
+  for (int t = 0; t < 3; t++) w.Y[t] = (zc*)take(z);
+  for (int t = 0; t < 3; t++) w.D[t] = (zc*)take(z);
+  w.Tlp = (zc*)take(z);
+  w.Elp = (zc*)take(z);
+  w.L = (zc*)take(z);
+  w.W = (zc*)take(z);
+  w.W2 = (zc*)take(z);
+  w.W3 = (zc*)take(z);
+  w.YW = (zc*)take(z);
+  w.S = td_main_slices(o);
+  w.sA = (int8_t*)take(oz_slice_bytes(n, n, w.S));
+  w.sQc = (int8_t*)take(oz_slice_bytes(n, n, w.S));
+  w.sP = (int8_t*)take(oz_slice_bytes(n, n, w.S));
+  w.sQr = (int8_t*)take(oz_slice_bytes(n, n, w.S));
+  w.sD = (int8_t*)take(oz_slice_bytes(n, n, w.S));
+  w.eA = (int*)take(n * sizeof(int));
+  w.eQc = (int*)take(n * sizeof(int));
+  w.eP = (int*)take(n * sizeof(int));
+  w.eQr = (int*)take(n * sizeof(int));
+  w.eD = (int*)take(n * sizeof(int));
+  w.scratch = take(oz_gemm_scratch_bytes(n, n, true));
+  int np = oz_gemm_tiles(n, n, n, true, false, w.S, w.S, w.S + 1, true);
+  if (form_w_parts(n) > np) np = form_w_parts(n);
+  if (np < 1024) np = 1024;
+  w.partials = (double*)take((size_t)np * sizeof(double));
+  w.scal = (double*)take(256);
+  w.status = (unsigned*)take(256);
+  w.tri = take(trisolve_ws_bytes(n));
+  w.bytes = (size_t)(p - (uintptr_t)base);
+  return w;
+}
+
+int read_back_td(hipStream_t st, const TDWork& w, int count, double* out, unsigned* status) {
+  Work v;
+  memset(&v, 0, sizeof(v));
+  v.scal = w.scal;
+  v.status = w.status;
+  return read_back(st, v, count, out, status);
+}
+
+GemmArgs td_args(int n, zc* const* C) {
+  GemmArgs g = gargs(n, n, n, nullptr, 0, nullptr, 0, C[0], n);
+  g.Cmid = C[1];
+  g.Clo = C[2];
+  return g;
+}
+
+// Qout = Q + Q D (triple-double) from S digits per operand.
+int td_update(zc* const* Q, zc* const* O, int n, const TDWork& w, hipStream_t st) {
+  const int S = w.S;
+  CK(oz_split_rows3(Q[0], Q[1], Q[2], n, n, n, S, w.sQr, w.eQr, st));
+  CK(oz_split_cols3(w.D[0], w.D[1], w.D[2], n, n, n, S, w.sD, w.eD, st));
+  GemmArgs u = td_args(n, O);
+  u.Cin = Q[0];
+  u.Cinmid = Q[1];
+  u.Cinlo = Q[2];
+  u.ldcin = n;
+  CK(oz_gemm(EPI_ADD, w.sQr, w.eQr, S, w.sD, w.eD, S, 0, S + 1, u, w.scratch, st, true));
+  return SR_OK;
+}
+
+// Y = Q^H Q - I (triple-double) from the column slices of Q in w.sQc; scal[2] = ||Y||^2.
+int td_ydef(int n, const TDWork& w, hipStream_t st) {
+  GemmArgs g = td_args(n, w.Y);
+  g.partials = w.partials;
+  g.herm = 1;
+  CK(oz_gemm(EPI_YDEF, w.sQc, w.eQc, w.S, w.sQc, w.eQc, w.S, 1, w.S + 1, g, w.scratch, st, true));
+  CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, true, true, w.S, w.S, w.S + 1, true), w.scal + 2, st));
+  return SR_OK;
+}
+
+int refine_td(const void* const* A_, void* const* Q_, void* const* T_, int n, int iters, double tol,
+              const sr_opts* opts_in, sr_info* info) {
+  info_init(info);
+  if (!A_ || !Q_ || !T_ || n < 2 || iters < 1 || !(tol > 0)) return SR_EINVAL;
+  for (int t = 0; t < 3; t++)
+    if (!A_[t] || !Q_[t] || !T_[t]) return SR_EINVAL;
+  sr_opts o;
+  if (opts_in) o = *opts_in;
+  else sr_default_opts(&o);
+  if (o.slices < 0 || o.slices > 32 || (o.slices > 0 && o.slices < 20)) return SR_EINVAL;
+  if (o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth || o.gemm != SR_GEMM_FP64) return SR_ENOSYS;
+  hipStream_t st = (hipStream_t)o.stream;
+  const zc* A[3] = {(const zc*)A_[0], (const zc*)A_[1], (const zc*)A_[2]};
+  zc* Tt[3] = {(zc*)T_[0], (zc*)T_[1], (zc*)T_[2]};
+  void* base = nullptr;
+  int rc = get_ws(o, sr_workspace_bytes_td(n, &o), &base);
+  if (rc != SR_OK) return rc;
+  const TDWork w = carve_td(base, n, &o);
+  const int S = w.S;
+
+  Timer timer;
+  timer.st = st;
+  Timer* tm = o.timing ? &timer : nullptr;
+  CallEvents ev;
+  CK(hipEventCreate(&ev.t0));
+  CK(hipEventCreate(&ev.t1));
+  CK(hipEventRecord(ev.t0, st));
+  CK(fill_zero(w.status, 256, st));
+  CK(fro2_partials(A[0], (long)n * n, w.partials, 1024, st));
+  CK(reduce_partials(w.partials, 1024, w.scal, st));
+  CK(oz_split_rows3(A[0], A[1], A[2], n, n, n, S, w.sA, w.eA, st));
+
+  // Newton-Schulz start from the given Q-hat
+  zc* cur[3] = {w.Q[0], w.Q[1], w.Q[2]};
+  zc* oth[3] = {(zc*)Q_[0], (zc*)Q_[1], (zc*)Q_[2]};
+  TIC(tm, 0);
+  CK(oz_split_cols3(oth[0], oth[1], oth[2], n, n, n, S, w.sQc, w.eQc, st));
+  if ((rc = td_ydef(n, w, st)) != SR_OK) return rc;
+  TOC_HERM(tm);
+  double nrm[4] = {0, 0, 0, 0};
+  unsigned dst = 0;
+  if ((rc = read_back_td(st, w, 3, nrm, &dst)) != SR_OK) return rc;
+  CK(form_delta_td(nullptr, w.Y[0], w.Y[1], w.Y[2], nullptr, nullptr, nullptr, w.D[0], w.D[1], w.D[2], n, st));
+  TIC(tm, 0);
+  if ((rc = td_update(oth, cur, n, w, st)) != SR_OK) return rc;
+  TOC(tm, 0);
+
+  int status = SR_NOT_CONVERGED, passes = 0, updates = 0, nprod = 0;
+  double eps = 0, eps1 = -1, eps2 = -1, orth = 0, nw_last = 0;
+  for (int p = 0; p < iters; p++) {
+    TIC(tm, 0);
+    CK(oz_split_cols3(cur[0], cur[1], cur[2], n, n, n, S, w.sQc, w.eQc, st));
+    {
+      GemmArgs g = td_args(n, w.P);
+      CK(oz_gemm(EPI_STORE, w.sA, w.eA, S, w.sQc, w.eQc, S, 0, S + 1, g, w.scratch, st, true));
+    }
+    TOC(tm, 0);
+    TIC(tm, 0);
+    CK(oz_split_cols3(w.P[0], w.P[1], w.P[2], n, n, n, S, w.sP, w.eP, st));
+    {
+      GemmArgs g = td_args(n, Tt);
+      g.Tlp64 = w.Tlp;
+      g.Elp64 = w.Elp;
+      g.ldlp = n;
+      g.partials = w.partials;
+      CK(oz_gemm(EPI_SPLIT, w.sQc, w.eQc, S, w.sP, w.eP, S, 1, S + 1, g, w.scratch, st, true));
+    }
+    TOC(tm, 0);
+    CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, true, false, S, S, S + 1, true), w.scal + 1, st));
+    double s2[2];
+    if ((rc = read_back_td(st, w, 2, s2, &dst)) != SR_OK) return rc;
+    eps = sqrt(s2[1]) / sqrt(s2[0]);
+    passes = p + 1;
+    if (info && p < 16) info->resid_hist[p] = eps;
+    if (!isfinite(eps)) {
+      status = SR_BREAKDOWN;
+      break;
+    }
+    const int stop = stop_test(o, eps, tol, eps1, eps2, updates, nw_last, kUTD, n);
+    if (stop >= 0) {
+      status = stop;
+      break;
+    }
+    eps2 = eps1;
+    eps1 = eps;
+    if (p == iters - 1) break;
+
+    TIC(tm, 1);
+    CK(trisolve64(w.Tlp, w.Elp, w.L, n, w.tri, w.status, st));
+    TOC(tm, 1);
+    TIC(tm, 0);
+    if ((rc = td_ydef(n, w, st)) != SR_OK) return rc;
+    TOC_HERM(tm);
+    CK(form_w64(w.L, w.W, n, w.partials, st));
+    CK(reduce_partials(w.partials, form_w_parts(n), w.scal + 3, st));
+    if ((rc = read_back_td(st, w, 4, nrm, &dst)) != SR_OK) return rc;
+    if (dst & DEV_BREAKDOWN) {
+      status = SR_BREAKDOWN;
+      break;
+    }
+    const double ny = sqrt(nrm[2]), nw = sqrt(nrm[3]);
+    orth = ny;
+    nw_last = nw;
+    if (info && updates < 16) info->norm_w_hist[updates] = nw;
+    if (!isfinite(ny) || !isfinite(nw)) {
+      status = SR_BREAKDOWN;
+      break;
+    }
+    // lp products in FP64, gated against the triple-double roundoff
+    const double thr = 0.1 * kUTD;
+    const bool gw2 = !o.gate_lp_terms || nw * nw > thr;
+    const bool gw3 = !o.gate_lp_terms || nw * nw * nw > thr;
+    const bool gyw = !o.gate_lp_terms || ny * nw > thr;
+    if (gw2 || gw3) {
+      GemmArgs a2 = gargs(n, n, n, w.W, n, w.W, n, w.W2, n);
+      a2.herm = 1;
+      CK(zgemm(0, EPI_STORE, 0, a2, st));
+      nprod++;
+    }
+    const bool both = gw3 && gyw;
+    if (both) {
+      CK(w2_minus_y(w.W2, w.Y[0], w.YW, (long)n * n, st));
+      CK(zgemm(0, EPI_STORE, 0, gargs(n, n, n, w.YW, n, w.W, n, w.W3, n), st));
+      nprod++;
+    } else if (gw3) {
+      GemmArgs a3 = gargs(n, n, n, w.W2, n, w.W, n, w.W3, n);
+      a3.herm = -1;
+      CK(zgemm(0, EPI_STORE, 0, a3, st));
+      nprod++;
+    } else if (gyw) {
+      CK(zgemm(0, EPI_STORE, 0, gargs(n, n, n, w.Y[0], n, w.W, n, w.YW, n), st));
+      nprod++;
+    }
+    CK(form_delta_td(w.L, w.Y[0], w.Y[1], w.Y[2], gw2 ? w.W2 : nullptr, gw3 ? w.W3 : nullptr,
+                     gyw && !both ? w.YW : nullptr, w.D[0], w.D[1], w.D[2], n, st));
+    TIC(tm, 0);
+    if ((rc = td_update(cur, oth, n, w, st)) != SR_OK) return rc;
+    TOC(tm, 0);
+    for (int t = 0; t < 3; t++) {
+      zc* x = cur[t];
+      cur[t] = oth[t];
+      oth[t] = x;
+    }
+    updates++;
+  }
+  if (cur[0] != (zc*)Q_[0])
+    for (int t = 0; t < 3; t++)
+      CK(hipMemcpyAsync(Q_[t], cur[t], (size_t)n * n * sizeof(zc), hipMemcpyDeviceToDevice, st));
+  CK(hipEventRecord(ev.t1, st));
+  CK(hipEventSynchronize(ev.t1));
+  float ms = 0;
+  hipEventElapsedTime(&ms, ev.t0, ev.t1);
+  if (info) {
+    info->status = status;
+    info->iters = passes;
+    info->updates = updates;
+    info->hp_gemms = 2 + 4 * updates + 2 * (passes - updates);
+    info->lp_products = nprod;
+    info->resid = eps;
+    info->orth = orth;
+    info->ms_total = ms;
+    if (tm) {
+      info->ms_hp_gemm = timer.total(0);
+      info->hp_gemm_launches = timer.count[0];
+      info->hp_gemm_herm_launches = timer.herm;
+      info->ms_hp_gemm_herm = timer.total(0, 1);
+      info->ms_solve = timer.total(1);
+    }
+  }
+  return status;
+}
+}  // namespace
+
+extern "C" {
+
+size_t sr_workspace_bytes_td(int n, const sr_opts* opts) {
+  if (n < 1) return 0;
+  return carve_td(nullptr, n, opts).bytes + 256;
+}
+
+int schur_refine_td(const void* const* A, void* const* Q, void* const* T, int n, int iters, double tol,
+                    const sr_opts* opts, sr_info* info) {
+  const int rc = refine_td(A, Q, T, n, iters, tol, opts, info);
+  if (rc < 0 && info) info->status = rc;
+  return rc;
+}
+
 size_t sr_workspace_bytes_dd(int n, const sr_opts* opts) {
   if (n < 1) return 0;
   return carve_dd(nullptr, n, opts).bytes + 256;
@@ -1717,6 +2017,40 @@ int sr_ozaki_zgemm_dd(int opa, int m, int n, int k, const void* A_hi, const void
   }
   CK(oz_gemm(Cin_hi ? EPI_ADD : EPI_STORE, qa, ea, slices_a, qb, eb, slices_b, opa, dmax, g, scr, st,
              true));
+  return SR_OK;
+}
+
+int sr_ozaki_zgemm_td(int opa, int m, int n, int k, const void* const* A, int lda, const void* const* B,
+                      int ldb, const void* const* Cin, int ldcin, void* const* C, int ldc, int slices,
+                      void* ws, size_t ws_bytes, void* stream) {
+  if (m < 0 || n < 0 || k < 1 || (opa != 0 && opa != 1) || !C || !C[0] || !C[1] || !C[2]) return SR_EINVAL;
+  if (slices < 1 || slices > 32) return SR_EINVAL;
+  if (m == 0 || n == 0) return SR_OK;
+  if (!A || !B || !A[0] || !A[1] || !A[2] || !B[0] || !B[1] || !B[2]) return SR_EINVAL;
+  if (lda < (opa ? (k > 1 ? k : 1) : (m > 1 ? m : 1)) || ldb < (k > 1 ? k : 1) || ldc < m) return SR_EINVAL;
+  if (Cin && (!Cin[0] || !Cin[1] || !Cin[2] || ldcin < m)) return SR_EINVAL;
+  if (!ws || ws_bytes < sr_ozaki_ws_bytes(m, n, k, slices, slices)) return SR_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int8_t* qa = (int8_t*)ws;
+  int8_t* qb = qa + align256(oz_slice_bytes(m, k, slices));
+  int* ea = (int*)(qb + align256(oz_slice_bytes(n, k, slices)));
+  int* eb = ea + m;
+  void* scr = (int8_t*)ea + align256((size_t)(m + n) * sizeof(int));
+  const zc* a[3] = {(const zc*)A[0], (const zc*)A[1], (const zc*)A[2]};
+  const zc* b[3] = {(const zc*)B[0], (const zc*)B[1], (const zc*)B[2]};
+  if (opa == 0) CK(oz_split_rows3(a[0], a[1], a[2], lda, m, k, slices, qa, ea, st));
+  else CK(oz_split_cols3(a[0], a[1], a[2], lda, k, m, slices, qa, ea, st));
+  CK(oz_split_cols3(b[0], b[1], b[2], ldb, k, n, slices, qb, eb, st));
+  GemmArgs g = gargs(m, n, k, nullptr, 0, nullptr, 0, C[0], ldc);
+  g.Cmid = C[1];
+  g.Clo = C[2];
+  if (Cin) {
+    g.Cin = Cin[0];
+    g.Cinmid = Cin[1];
+    g.Cinlo = Cin[2];
+    g.ldcin = ldcin;
+  }
+  CK(oz_gemm(Cin ? EPI_ADD : EPI_STORE, qa, ea, slices, qb, eb, slices, opa, slices + 1, g, scr, st, true));
   return SR_OK;
 }
 
