@@ -29,7 +29,9 @@ Other workloads (--workload), each one JSON line of its own:
                   real eigenvalues, conjugate pairs in 2 x 2 blocks, gaps >= 0.05),
                   sgees start, FP64 tier, real FP64 products;
   solvers         the FP32 solve by the tile wavefront and by the recursive block
-                  algorithm (Algorithm 3) at n = 1024, 2048, 4096.
+                  algorithm (Algorithm 3) at n = 1024, 2048, 4096;
+  td              the triple-double tier at n = 1024 from a zgees start to 1e-42,
+                  checked exactly (Python integers) on sampled rows.
 
 `roofline` covers the dominant kernel of the chosen form, timed with HIP events
 on the library's stream during the timed steps: the FP64 GEMM against the FP64
@@ -755,6 +757,84 @@ def run_real(args) -> int:
     return 0 if out["all_converged"] else 1
 
 
+TD_TOL = 1e-42
+
+
+def run_td(args) -> int:
+    """The triple-double tier: one complex matrix (gaps >= 0.05, seed 6) from its
+    complex128 Schur basis (LAPACK zgees) to 1e-42, every hp value three complex128
+    terms, hp products from 22 INT8 digits per operand, FP64 solve and lp products."""
+    import torch
+
+    import paper_2203_10879_amd as sr
+    import synth
+    from oracle import exact
+
+    n = 1024 if args.n is None else args.n
+    t0 = time.perf_counter()
+    g = synth.schur_test_matrix(n, seed=6, gap=0.05)
+    qh = synth.hp_schur_start(g["A"])
+    print(f"# inputs n={n} ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.set_device(torch.device("cuda:0"))
+    z = np.zeros_like(g["A"])
+    As = [sr.colmajor(g["A"]), sr.colmajor(z), sr.colmajor(z)]
+    starts = [sr.colmajor(qh), sr.colmajor(z), sr.colmajor(z)]
+    Qs = [sr.colmajor_empty(n, n) for _ in range(3)]
+    Ts = [sr.colmajor_empty(n, n) for _ in range(3)]
+    ws = torch.empty(int(sr.lib().sr_workspace_bytes_td(n, None)), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(timing=False):
+        for q, q0 in zip(Qs, starts):
+            q.copy_(q0)
+        return sr.schur_refine_td(As, Qs, Ts, iters=8, tol=TD_TOL, timing=timing, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    infos = []
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(step(timing=True))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    ok = all(i["status"] == "OK" for i in infos)
+    steps = args.steps
+    ms = sum(i["ms_hp_gemm"] - i["ms_hp_gemm_herm"] for i in infos)
+    cnt = sum(i["hp_gemm_launches"] - i["hp_gemm_herm_launches"] for i in infos)
+    avg = ms / max(1, cnt)
+    slices = 22
+    pairs = slices * (slices + 1) // 2
+    achieved = pairs * 8.0 * n ** 3 / (avg * 1e-3) / 1e12
+    last = infos[-1]
+    out = base_record(args, steps / dt if ok else 0.0, "decomps/s", 1e3 * dt / steps, "td(int8)",
+                      {"workload": f"triple-double tier, single matrix n={n}, eigenvalue gaps >= 0.05 (seed 6), "
+                                   "complex128 zgees start, tol 1e-42 (three complex128 terms per hp value, "
+                                   "22 INT8 digits per operand, FP64 solve)",
+                       "n": n, "tol": TD_TOL, "parallelism": "1 GPU"})
+    out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                       "frac": achieved / INT8_PEAK_TOPS, "traffic": None,
+                       "kernel": f"triple-double product: both operand splits and the windowed INT8 product "
+                                 f"(oz_gemm_windows_kernel), {pairs} digit pairs x 8 n^3 ops per launch",
+                       "avg_launch_ms": avg, "launches_per_step": cnt / steps}
+    out.update({"passes": last["iters"], "hp_gemms": last["hp_gemms"], "resid_hist": last["resid_hist"],
+                "ms_hp_gemm_per_step": sum(i["ms_hp_gemm"] for i in infos) / steps,
+                "ms_solve_per_step": sum(i["ms_solve"] for i in infos) / steps, "all_converged": ok})
+    r = min(args.rows, 2)
+    if r > 0:
+        # exact check (Python integers) on sampled rows of the last refinement
+        step()
+        torch.cuda.synchronize()
+        rows = np.sort(np.random.default_rng(10).choice(n, r, replace=False))
+        t2 = time.perf_counter()
+        ev = exact.residual_rows([g["A"]], [sr.to_numpy(q) for q in Qs], rows)
+        print(f"# exact rows checked in {time.perf_counter() - t2:.1f} s", file=sys.stderr, flush=True)
+        out.update({"exact_stril_rows": ev["stril"], "exact_orth_rows": ev["orth"], "exact_rows": r})
+        out["all_converged"] = ok and ev["stril"] <= TD_TOL and ev["orth"] <= TD_TOL
+    print(json.dumps(out), flush=True)
+    return 0 if out["all_converged"] else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -762,7 +842,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="matrix size (default: the workload's)")
     ap.add_argument("--workload", default="default",
-                    choices=["default", "single", "precision", "batched", "dd_continuation", "real", "solvers"])
+                    choices=["default", "single", "precision", "batched", "dd_continuation", "real", "solvers",
+                             "td"])
     ap.add_argument("--count", type=int, default=2000, help="batched: number of matrices")
     ap.add_argument("--cont-steps", type=int, default=64, help="dd_continuation: steps")
     ap.add_argument("--rows", type=int, default=32, help="rows of the binary128 check")
@@ -777,7 +858,8 @@ def main() -> int:
               file=sys.stderr)
         return 2
     return {"default": run_default, "single": run_single, "precision": run_precision, "batched": run_batched,
-            "dd_continuation": run_dd_continuation, "real": run_real, "solvers": run_solvers}[args.workload](args)
+            "dd_continuation": run_dd_continuation, "real": run_real, "solvers": run_solvers,
+            "td": run_td}[args.workload](args)
 
 
 if __name__ == "__main__":

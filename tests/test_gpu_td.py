@@ -267,3 +267,41 @@ def test_td_product_arguments(sr):
     assert call(nb=need - 1) == -3  # SR_ENOMEM
     assert call(C=None) == -1
     assert call() == 0
+
+
+# ---------------------------------------------------------- sizes, checked in integers
+
+@pytest.mark.parametrize("n", [2, 3, 17, 100, 130, 256])
+def test_td_ragged_sizes_exact_rows(sr, n):
+    """Gaps 0.05 from the complex128 Schur basis (zgees): converged to 1e-42 within 5
+    passes; the exact residual and orthogonality defect (every row up to n = 130,
+    16 sampled rows above) meet it, and T's upper triangle equals Q^H A Q's there."""
+    from oracle import exact
+
+    g = synth.schur_test_matrix(n, seed=300 + n, gap=0.05)
+    a = g["A"]
+    qh = synth.hp_schur_start(a)
+    q, t, info = _refine(sr, a, qh, iters=6, tol=1e-42)
+    assert info["status"] == "OK" and info["iters"] <= 5, info
+    rows = np.arange(n) if n <= 130 else np.sort(np.random.default_rng(n).choice(n, 16, replace=False))
+    ev = exact.residual_rows([a], q, rows)
+    assert ev["stril"] <= 1e-42, ev
+    assert ev["orth"] <= 1e-42, ev
+    # T: the upper triangle of the same exact rows
+    qr, qi, eq = exact.to_ints(q)
+    ar, ai, ea = exact.to_ints([a])
+    tr, ti, et = exact.to_ints(t)
+    r = rows[: min(len(rows), 4)]
+    vr = qr[:, r].T.dot(ar) + qi[:, r].T.dot(ai)
+    vi = qr[:, r].T.dot(ai) - qi[:, r].T.dot(ar)
+    mr = vr.dot(qr) - vi.dot(qi)
+    mi = vr.dot(qi) + vi.dot(qr)
+    s = ea + 2 * eq
+    worst = 0.0
+    for k, i in enumerate(r):
+        for j in range(i, n):
+            d = abs(Fraction(int(mr[k, j]), 1 << s) - Fraction(int(tr[i, j]), 1 << et)) + \
+                abs(Fraction(int(mi[k, j]), 1 << s) - Fraction(int(ti[i, j]), 1 << et))
+            worst = max(worst, float(d))
+        assert not any(t[0][i, :i])  # T is upper triangular
+    assert worst <= 1e-44 * ev["normA"], worst
