@@ -10,6 +10,9 @@ Matrices enter as complex128 numpy arrays (column-major), or as double-double
 pairs (hi, lo). Binary128 results stay in `QMat` buffers and convert back to
 double-double on request.
 
+`oracle/exact.py` holds exact checks of multi-term results in Python integers
+(residual and orthogonality rows past binary128's reach), pinned by its own tests.
+
 Parity status: every entry point is pinned by the `-m "not gpu"` tests in
 tests/test_oracle_*.py. Per-pass residual values have no published figures, so
 they are pinned only through convergence laws, not value by value.
