@@ -260,8 +260,9 @@ int schur_refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo, 
 /* Bytes of device workspace schur_refine_dd needs for size n under `opts`. */
 size_t sr_workspace_bytes_dd(int n, const sr_opts* opts);
 
-/* Triple-double tier (more than two cells per number, Section 3 and the conclusions:
- * hp with several doubles per entry): every hp value is a renormalized expansion of
+/* Triple-double tier (more than two cells per number: Section 3 holds an hp number in
+ * several doubles, 2 for quadruple and 6 for 100 digits; Section 4 names further
+ * precision levels): every hp value is a renormalized expansion of
  * three complex128 arrays (A[0] + A[1] + A[2], likewise Q and T; column-major,
  * leading dimension n, device memory; Q in/out, T out). hp products: Ozaki splits of
  * the three-term operands into opts->slices 8-bit digits (0 = 22, at least 20, at
