@@ -227,6 +227,12 @@ def run_single(args) -> int:
 HEADLINE_FORMS = ("fp64", "ozaki_i8", "ozaki_i8_all", "ozaki_crt")
 
 
+def lp_digits_of(args, form: str) -> int:
+    """INT8 digits per operand of the lp products in a split form (--lp-digits; the
+    native form keeps them in FP32)."""
+    return 0 if form == "fp64" else int(args.lp_digits)
+
+
 def run_default(args) -> int:
     """The headline line: n = 4096, gaps >= 1e-3, every form of the hp products."""
     import torch
@@ -244,12 +250,13 @@ def run_default(args) -> int:
     A, Q0 = sr.colmajor(g["A"]), sr.colmajor(qh)
     Q, T = sr.colmajor_empty(n, n), sr.colmajor_empty(n, n)
     form_list = tuple(args.forms.split(",")) if args.forms else HEADLINE_FORMS
-    wss = {m: sr.workspace(n, gemm=m) for m in form_list}
+    wss = {m: sr.workspace(n, gemm=m, lp_digits=lp_digits_of(args, m)) for m in form_list}
     iters = 8
 
     def refine(m, timing=False):
         Q.copy_(Q0)
-        return sr.schur_refine(A, Q, T, iters=iters, tol=TOL, gemm=m, timing=timing, workspace=wss[m])
+        return sr.schur_refine(A, Q, T, iters=iters, tol=TOL, gemm=m, timing=timing, workspace=wss[m],
+                               lp_digits=lp_digits_of(args, m))
 
     # every form: untimed warmup, then refinements timed one by one with HIP events
     # (the forms interleaved, so that clock drift falls on all alike), then the
@@ -282,6 +289,8 @@ def run_default(args) -> int:
         forms[m] = {"status": inf["status"], "passes": inf["iters"], "ms_to_tol": float(np.median(ms_each[m])),
                     "ms_min": float(np.min(ms_each[m])), "resid_hist": inf["resid_hist"],
                     "update_digits": inf["update_slices_hist"] if m != "fp64" else None,
+                    "lp_products": (f"INT8, {lp_digits_of(args, m)} digits" if lp_digits_of(args, m)
+                                    else "FP32 MFMA"),
                     "quad_stril_rows": float(ev["stril"]), "quad_stril_rowmax": float(ev["stril_rowmax"]),
                     "quad_orth_rows": float(ev["orth"]), "meets_tol": meets}
         print(f"# {m}: {forms[m]['ms_to_tol']:.1f} ms, {inf['iters']} passes, binary128 rows "
@@ -310,8 +319,16 @@ def run_default(args) -> int:
                       {"workload": f"single matrix n={n}, eigenvalue gaps >= 1e-3 (seed 2), FP32 cgees start, "
                                    f"FP64 tier (FP32 solve), tol 1e-15; hp products as '{best}', the fastest "
                                    "of native FP64 / Ozaki INT8 (P, the start, Q Delta) / Ozaki INT8 (every "
-                                   "hp product) that met the tolerance",
-                       "n": n, "tol": TOL, "form": best, "parallelism": "1 GPU"})
+                                   "hp product) / Ozaki scheme II (every hp product) that met the tolerance; "
+                                   "the split forms' lp products W^2, W^3, YW from "
+                                   f"{args.lp_digits} INT8 digits per operand (native: FP32 MFMA)"
+                                   if args.lp_digits else
+                                   f"FP64 tier (FP32 solve), tol 1e-15; hp products as '{best}', the fastest "
+                                   "of native FP64 / Ozaki INT8 (P, the start, Q Delta) / Ozaki INT8 (every "
+                                   "hp product) / Ozaki scheme II (every hp product) that met the tolerance; "
+                                   "lp products in FP32 MFMA",
+                       "n": n, "tol": TOL, "form": best, "lp_digits": lp_digits_of(args, best),
+                       "parallelism": "1 GPU"})
     if best == "fp64":
         ms = sum(i["ms_hp_gemm"] - i["ms_hp_gemm_herm"] for i in infos)
         cnt = sum(i["hp_gemm_launches"] - i["hp_gemm_herm_launches"] for i in infos)
@@ -389,11 +406,11 @@ def run_precision(args) -> int:
     # with HIP events on the current stream), so that clock drift over the run falls
     # on all of them alike.
     modes = HEADLINE_FORMS
-    wss = {m: sr.workspace(n, gemm=m) for m in modes}
+    wss = {m: sr.workspace(n, gemm=m, lp_digits=lp_digits_of(args, m)) for m in modes}
     for _ in range(args.warmup):
         for m in modes:
             Q.copy_(Q0)
-            sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=m, workspace=wss[m])
+            sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=m, workspace=wss[m], lp_digits=lp_digits_of(args, m))
     torch.cuda.synchronize()
     infos = {m: [] for m in modes}
     ms_each = {m: [] for m in modes}
@@ -402,14 +419,15 @@ def run_precision(args) -> int:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             Q.copy_(Q0)
-            infos[m].append(sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=m, timing=True, workspace=wss[m]))
+            infos[m].append(sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=m, timing=True, workspace=wss[m],
+                                            lp_digits=lp_digits_of(args, m)))
             e1.record()
             torch.cuda.synchronize()
             ms_each[m].append(e0.elapsed_time(e1))
     forms = {}
     for m in modes:
         Q.copy_(Q0)
-        sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=m, workspace=wss[m])
+        sr.schur_refine(A, Q, T, iters=8, tol=TOL, gemm=m, workspace=wss[m], lp_digits=lp_digits_of(args, m))
         torch.cuda.synchronize()
         ev = oracle.evaluate_rows(g["A"], sr.to_numpy(Q), rows)
         inf, last = infos[m], infos[m][-1]
@@ -851,6 +869,8 @@ def main() -> int:
     ap.add_argument("--no-secondary", action="store_true", help="default: leave out the n = 1024 key")
     ap.add_argument("--forms", default="", help="default: comma-separated forms to run (default: all three)")
     ap.add_argument("--no-compensated", action="store_true")
+    ap.add_argument("--lp-digits", type=int, default=4,
+                    help="split forms: INT8 digits of the lp products (0: FP32 MFMA)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "

@@ -122,6 +122,18 @@ typedef struct {
                              Y = 0. Never twice in a row; if the prediction holds but
                              ||W||^2 is larger, Y is formed after the solve. 0: off
                              (default)                                                 */
+  int lp_digits;          /* schur_refine with a split form of the hp products
+                             (SR_GEMM_OZAKI_*; SR_EINVAL with SR_GEMM_FP64, SR_ENOSYS in
+                             the other entry points when nonzero): 0 (default) forms
+                             the lp products W^2, W^3, YW in FP32 on MFMA; 1..7 forms
+                             them from that many balanced 8-bit digits per operand on
+                             INT8 MFMA (pairs s + t <= lp_digits + 1), W^2 and W^3 over
+                             the tiles on and above the diagonal, rounded once to
+                             complex64. The digit error is relative to the row and
+                             column maxima of W (about k 2^(-8 lp_digits) max|w_i.|
+                             max|w_.j|), FP32's to its entries: 4 digits keep the pass
+                             counts of FP32 on the test matrices, 3 can cost a pass.
+                             Sizes below 1024 keep FP32.                               */
 } sr_opts;
 
 typedef enum {
@@ -460,6 +472,18 @@ int sr_ozaki_zgemm_dd(int opa, int m, int n, int k, const void* A_hi, const void
 int sr_ozaki_zgemm_td(int opa, int m, int n, int k, const void* const* A, int lda, const void* const* B,
                       int ldb, const void* const* Cin, int ldcin, void* const* C, int ldc, int slices,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* The lp products on INT8 digits (sr_opts.lp_digits): C = A B for complex64 A (m x
+ * k), B (k x n), C (m x n), column-major device memory, from `slices` balanced 8-bit
+ * digits per operand (1..7; pairs s + t <= slices + 1) with exact int32 pair sums
+ * folded in FP64 and rounded once to complex64. herm = 1 (-1): the product is
+ * Hermitian (skew-Hermitian), only the elements i <= j are formed and each is stored
+ * with its conjugate (negated conjugate) at (j, i); m == n required. The kernel
+ * takes at least 256 output tiles of 64 x 64 (m n >= 2^20): SR_EINVAL below that, and
+ * for other bad arguments. ws: device workspace of >= sr_ozaki_ws_bytes(m, n, k,
+ * slices, slices). */
+int sr_ozaki_cgemm(int m, int n, int k, const void* A, int lda, const void* B, int ldb, void* C, int ldc,
+                   int slices, int herm, void* ws, size_t ws_bytes, void* stream);
 
 /* Ozaki scheme II product (the hp products of Section 3 from an Ozaki-type scheme,
  * here its CRT form) on INT8 MFMA: C = op(A) B (+ Cin), complex128, arguments as

@@ -34,7 +34,7 @@ class SrOpts(ctypes.Structure):
                 ("trunc", ctypes.c_int), ("timing", ctypes.c_int), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
                 ("strict_stop", ctypes.c_int), ("solver", ctypes.c_int), ("rec_leaf", ctypes.c_int),
-                ("skip_orth", ctypes.c_int)]
+                ("skip_orth", ctypes.c_int), ("lp_digits", ctypes.c_int)]
 
 
 class SrInfo(ctypes.Structure):
@@ -98,6 +98,7 @@ _SIGS = {
                              ctypes.POINTER(ctypes.c_void_p), _i, _i, _d, ctypes.POINTER(SrOpts),
                              ctypes.POINTER(SrInfo)]),
     "sr_workspace_bytes_td": (_sz, [_i, ctypes.POINTER(SrOpts)]),
+    "sr_ozaki_cgemm": (_i, [_i, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, _i, _vp, _sz, _vp]),
     "sr_ozaki_zgemm_td": (_i, [_i, _i, _i, _i, ctypes.POINTER(ctypes.c_void_p), _i,
                                ctypes.POINTER(ctypes.c_void_p), _i, ctypes.POINTER(ctypes.c_void_p), _i,
                                ctypes.POINTER(ctypes.c_void_p), _i, _i, _vp, _sz, _vp]),
@@ -197,7 +198,7 @@ SOLVERS = {"wavefront": 0, "recursive": 1}
 
 def make_opts(gemm="fp64", slices=0, update_slices=0, compensated=True, gate=True, trunc=False,
               timing=False, workspace=None, stream=None, strict_stop=False, solver="wavefront",
-              rec_leaf=0, skip_orth=False) -> SrOpts:
+              rec_leaf=0, skip_orth=False, lp_digits=0) -> SrOpts:
     o = SrOpts()
     lib().sr_default_opts(ctypes.byref(o))
     o.gemm = GEMM_MODES[gemm] if isinstance(gemm, str) else int(gemm)
@@ -211,6 +212,7 @@ def make_opts(gemm="fp64", slices=0, update_slices=0, compensated=True, gate=Tru
     o.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     o.rec_leaf = int(rec_leaf)
     o.skip_orth = int(bool(skip_orth))
+    o.lp_digits = int(lp_digits)
     if workspace is not None:
         o.workspace = ctypes.c_void_p(workspace.data_ptr())
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -357,6 +359,21 @@ def sr_ozaki_zgemm_dd(A_hi, A_lo, B_hi, B_lo, C_hi, C_lo, opa: int = 0, slices_a
         _ld(Cin_hi), _mat(C_hi, "c128"), _mat(C_lo, "c128"),
         _ld(C_hi), int(slices_a), int(slices_b), d, ctypes.c_void_p(ws.data_ptr()),
         ws.numel() * ws.element_size(), _stream(stream))
+
+
+def sr_ozaki_cgemm(A, B, C, slices: int = 3, herm: int = 0, ws=None, stream=None) -> int:
+    """Complex64 product C = A B from INT8 digits, optionally Hermitian (1) or
+    skew-Hermitian (-1) (see include/schur_refine.h)."""
+    import torch
+
+    m, n = C.shape
+    k = B.shape[0]
+    need = int(lib().sr_ozaki_ws_bytes(m, n, k, int(slices), int(slices)))
+    if ws is None:
+        ws = torch.empty(max(1, need), dtype=torch.uint8, device=C.device)
+    return lib().sr_ozaki_cgemm(m, n, k, _mat(A, "c64"), _ld(A), _mat(B, "c64"), _ld(B), _mat(C, "c64"), _ld(C),
+                                int(slices), int(herm), ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel() * ws.element_size(), _stream(stream))
 
 
 def sr_ozaki_zgemm_td(As, Bs, Cs, opa: int = 0, slices: int = 22, Cins=None, ws=None,

@@ -638,7 +638,7 @@ int schur_refine_batched(int batch, const int* n, const void* const* A, void* co
   sr_opts o;
   if (opts_in) o = *opts_in;
   else sr_default_opts(&o);
-  if (o.gemm != SR_GEMM_FP64 || o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth) return SR_ENOSYS;
+  if (o.gemm != SR_GEMM_FP64 || o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth || o.lp_digits) return SR_ENOSYS;
   const int comp = o.compensated ? 1 : 0;
   hipStream_t user = (hipStream_t)o.stream;
   hipStream_t st = capture_stream();

@@ -41,6 +41,9 @@ struct GemmArgs {
   // low terms in Clo / Cinlo); C, Cmid, Clo form a renormalized expansion
   void* Cmid;
   const void* Cinmid;
+  // EPI_STORE of the all-pairs INT8 product: C is complex64 (each value rounded
+  // once from FP64)
+  int c64;
   // EPI_YDEF (1) and EPI_STORE (1 or -1): the product is Hermitian (1) or
   // skew-Hermitian (-1), e.g. Q^H Q, W^2 and W^3 for a skew-Hermitian W. Only the
   // elements with i <= j are stored from the product, each with its conjugate
@@ -111,6 +114,13 @@ hipError_t oz_split_cols3(const zc* X, const zc* Xmid, const zc* Xlo, long ld, i
                           int8_t* out, int* exps, hipStream_t st);
 hipError_t oz_split_rows3(const zc* X, const zc* Xmid, const zc* Xlo, long ld, int M, int K, int S,
                           int8_t* out, int* exps, hipStream_t st);
+// Complex64 operands (one term each): the lp products taken on INT8 digits.
+hipError_t oz_split_cols_c64(const cc* X, long ld, int K, int ncols, int S, int8_t* out, int* exps, hipStream_t st);
+hipError_t oz_split_rows_c64(const cc* X, long ld, int M, int K, int S, int8_t* out, int* exps, hipStream_t st);
+// Whether an m x n x k product with S digits per operand (pairs s + t <= S + 1) runs
+// on the all-pairs kernel, the one that also takes Hermitian STORE and complex64
+// outputs.
+bool oz_allpairs_ok(int m, int n, int k, int S);
 // Output tiles (= partial sums written) of a product; the sizes, the digit counts
 // and dd (double-double accumulation) select the kernel; herm: a Hermitian
 // product (GemmArgs::herm).

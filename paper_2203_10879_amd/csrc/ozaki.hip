@@ -198,10 +198,12 @@ __host__ __device__ inline int8_t byte_digit(unsigned byte, uint64_t carries, in
 
 // Slices of the columns of X (K x ncols, leading dim ld), one block per column of
 // the padded count (padding columns get zero digits). These serve as B, and as
-// op(A) = X^H when the product applies the conjugation.
-__global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __restrict__ X,
-                                                                 const zc* __restrict__ Xmid,
-                                                                 const zc* __restrict__ Xlo, long ld,
+// op(A) = X^H when the product applies the conjugation. X is complex128 (with the
+// lower terms of an expansion) or complex64 (one term; its values are exact in FP64).
+template <typename C>
+__global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const C* __restrict__ X,
+                                                                 const C* __restrict__ Xmid,
+                                                                 const C* __restrict__ Xlo, long ld,
                                                                  int K, int ncols, int S, int Kp,
                                                                  int8_t* __restrict__ out,
                                                                  int* __restrict__ exps) {
@@ -219,11 +221,11 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
     }
     return;
   }
-  const zc* x = X + (long)col * ld;
-  const zc* xl = Xlo ? Xlo + (long)col * ld : nullptr;
-  const zc* xm = Xmid ? Xmid + (long)col * ld : nullptr;
+  const C* x = X + (long)col * ld;
+  const C* xl = Xlo ? Xlo + (long)col * ld : nullptr;
+  const C* xm = Xmid ? Xmid + (long)col * ld : nullptr;
   double m = 0;
-  for (int k = threadIdx.x; k < K; k += kSplitNT) m = fmax(m, fmax(fabs(x[k].re), fabs(x[k].im)));
+  for (int k = threadIdx.x; k < K; k += kSplitNT) m = fmax(m, fmax(fabs((double)x[k].re), fabs((double)x[k].im)));
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -242,11 +244,11 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const zc* __res
     int8_t* o_im = out + plane + o;
     int8_t* o_ni = out + 2 * plane + o;
     if (k < K) {
-      const zc v = x[k];
-      const zc w = xl ? xl[k] : mk<double>(0, 0);
-      const zc u = xm ? xm[k] : mk<double>(0, 0);
-      const double rh = ldexp(v.re, -e), rl = ldexp(w.re, -e), rm = ldexp(u.re, -e);
-      const double ih = ldexp(v.im, -e), il = ldexp(w.im, -e), im = ldexp(u.im, -e);
+      const C v = x[k];
+      const C w = xl ? xl[k] : C{0, 0};
+      const C u = xm ? xm[k] : C{0, 0};
+      const double rh = ldexp((double)v.re, -e), rl = ldexp((double)w.re, -e), rm = ldexp((double)u.re, -e);
+      const double ih = ldexp((double)v.im, -e), il = ldexp((double)w.im, -e), im = ldexp((double)u.im, -e);
       const Digits dr = xm ? split_value<3>(rh, rm, rl, S)
                            : xl ? split_value<2>(rh, 0.0, rl, S) : split_value<1>(rh, 0.0, 0.0, S);
       const Digits di = xm ? split_value<3>(ih, im, il, S)
@@ -283,7 +285,8 @@ __global__ void oz_exp_init_kernel(int* __restrict__ exps, int M) {
   if (r < M) exps[r] = kNoExp;
 }
 
-__global__ __launch_bounds__(kSplitNT) void oz_rowmax_kernel(const zc* __restrict__ X, long ld, int M,
+template <typename C>
+__global__ __launch_bounds__(kSplitNT) void oz_rowmax_kernel(const C* __restrict__ X, long ld, int M,
                                                              int K, int* __restrict__ exps) {
   __shared__ double red[4][64];
   const int r = blockIdx.x * 64 + (threadIdx.x & 63), c = threadIdx.x >> 6;
@@ -291,8 +294,8 @@ __global__ __launch_bounds__(kSplitNT) void oz_rowmax_kernel(const zc* __restric
   double m = 0;
   if (r < M)
     for (int k = k0 + c; k < k1; k += 4) {
-      const zc v = X[r + (long)k * ld];
-      m = fmax(m, fmax(fabs(v.re), fabs(v.im)));
+      const C v = X[r + (long)k * ld];
+      m = fmax(m, fmax(fabs((double)v.re), fabs((double)v.im)));
     }
   red[c][threadIdx.x & 63] = m;
   __syncthreads();
@@ -309,9 +312,10 @@ __global__ void oz_exp_fix_kernel(int* __restrict__ exps, int M) {
 
 // Slices of the rows of X; one block per 32 x 32 tile, staged through LDS so that
 // reads follow the columns and writes the rows (padding rows get zero digits).
-__global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __restrict__ X,
-                                                                 const zc* __restrict__ Xmid,
-                                                                 const zc* __restrict__ Xlo, long ld,
+template <typename C>
+__global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const C* __restrict__ X,
+                                                                 const C* __restrict__ Xmid,
+                                                                 const C* __restrict__ Xlo, long ld,
                                                                  int M, int K, int S, int Kp,
                                                                  const int* __restrict__ exps,
                                                                  int8_t* __restrict__ out) {
@@ -326,15 +330,15 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const zc* __res
     const int gi = i0 + row, gk = k0 + kk;
     const bool ok = gi < M && gk < K;
     const long o = ok ? gi + (long)gk * ld : 0;
-    const zc v = X[o];
-    t[kk][row] = mk<double>(ok ? v.re : 0.0, ok ? v.im : 0.0);
+    const C v = X[o];
+    t[kk][row] = mk<double>(ok ? (double)v.re : 0.0, ok ? (double)v.im : 0.0);
     if (Xlo) {
-      const zc w = Xlo[o];
-      tl[kk][row] = mk<double>(ok ? w.re : 0.0, ok ? w.im : 0.0);
+      const C w = Xlo[o];
+      tl[kk][row] = mk<double>(ok ? (double)w.re : 0.0, ok ? (double)w.im : 0.0);
     }
     if (Xmid) {
-      const zc w = Xmid[o];
-      tmid[kk][row] = mk<double>(ok ? w.re : 0.0, ok ? w.im : 0.0);
+      const C w = Xmid[o];
+      tmid[kk][row] = mk<double>(ok ? (double)w.re : 0.0, ok ? (double)w.im : 0.0);
     }
   }
   __syncthreads();
@@ -403,8 +407,16 @@ hipError_t oz_split_cols3(const zc* X, const zc* Xmid, const zc* Xlo, long ld, i
                           int8_t* out, int* exps, hipStream_t st) {
   if (S < 1 || S > kMaxDigits || (Xmid && !Xlo)) return hipErrorInvalidValue;
   if (ncols == 0) return hipSuccess;
-  hipLaunchKernelGGL(oz_split_cols_kernel, dim3(oz_rows_pad(ncols)), dim3(kSplitNT), 0, st, X, Xmid, Xlo, ld, K,
-                     ncols, S, oz_kp(K), out, exps);
+  hipLaunchKernelGGL(oz_split_cols_kernel<zc>, dim3(oz_rows_pad(ncols)), dim3(kSplitNT), 0, st, X, Xmid, Xlo, ld,
+                     K, ncols, S, oz_kp(K), out, exps);
+  return hipGetLastError();
+}
+
+hipError_t oz_split_cols_c64(const cc* X, long ld, int K, int ncols, int S, int8_t* out, int* exps, hipStream_t st) {
+  if (S < 1 || S > kMaxDigits) return hipErrorInvalidValue;
+  if (ncols == 0) return hipSuccess;
+  hipLaunchKernelGGL(oz_split_cols_kernel<cc>, dim3(oz_rows_pad(ncols)), dim3(kSplitNT), 0, st, X,
+                     (const cc*)nullptr, (const cc*)nullptr, ld, K, ncols, S, oz_kp(K), out, exps);
   return hipGetLastError();
 }
 
@@ -418,20 +430,30 @@ hipError_t oz_split_rows(const zc* X, const zc* Xlo, long ld, int M, int K, int 
   return oz_split_rows3(X, nullptr, Xlo, ld, M, K, S, out, exps, st);
 }
 
-hipError_t oz_split_rows3(const zc* X, const zc* Xmid, const zc* Xlo, long ld, int M, int K, int S,
-                          int8_t* out, int* exps, hipStream_t st) {
+template <typename C>
+static hipError_t split_rows_any(const C* X, const C* Xmid, const C* Xlo, long ld, int M, int K, int S,
+                                 int8_t* out, int* exps, hipStream_t st) {
   if (S < 1 || S > kMaxDigits || (Xmid && !Xlo)) return hipErrorInvalidValue;
   if (M == 0) return hipSuccess;
   hipLaunchKernelGGL(oz_exp_init_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, st, exps, M);
-  hipLaunchKernelGGL(oz_rowmax_kernel, dim3(ceil_div(M, 64), max(1, ceil_div(K, 256))), dim3(kSplitNT), 0,
+  hipLaunchKernelGGL(oz_rowmax_kernel<C>, dim3(ceil_div(M, 64), max(1, ceil_div(K, 256))), dim3(kSplitNT), 0,
                      st, X, ld, M, K, exps);
   hipLaunchKernelGGL(oz_exp_fix_kernel, dim3(ceil_div(M, 256)), dim3(256), 0, st, exps, M);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int Kp = oz_kp(K);
-  hipLaunchKernelGGL(oz_split_rows_kernel, dim3(ceil_div(M, 32), Kp / 32), dim3(kSplitNT), 0, st, X, Xmid,
+  hipLaunchKernelGGL(oz_split_rows_kernel<C>, dim3(ceil_div(M, 32), Kp / 32), dim3(kSplitNT), 0, st, X, Xmid,
                      Xlo, ld, M, K, S, Kp, exps, out);
   return hipGetLastError();
+}
+
+hipError_t oz_split_rows3(const zc* X, const zc* Xmid, const zc* Xlo, long ld, int M, int K, int S,
+                          int8_t* out, int* exps, hipStream_t st) {
+  return split_rows_any<zc>(X, Xmid, Xlo, ld, M, K, S, out, exps, st);
+}
+
+hipError_t oz_split_rows_c64(const cc* X, long ld, int M, int K, int S, int8_t* out, int* exps, hipStream_t st) {
+  return split_rows_any<cc>(X, nullptr, nullptr, ld, M, K, S, out, exps, st);
 }
 
 // -------------------------------------------------------------------- product
@@ -896,7 +918,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
   }
   int tm, tn;
-  if (EPI == EPI_YDEF && g.herm) {
+  if ((EPI == EPI_YDEF || EPI == EPI_STORE) && g.herm) {
     herm_tile(logical, g.tiles_n, tm, tn);  // the upper triangle of tiles
   } else {
     // groups of kGroup tile rows, column by column within a group: the 32 blocks
@@ -1060,7 +1082,9 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int j = n0 + wn + (lane & 31);
       if (i < g.m && j < g.n) {
         const int e = a.ea[i] + a.eb[j];
-        epi_element<EPI, double>(g, i, j, mk<double>(ldexp(val[v], e), ldexp(xch[v * 64], e)), part);
+        const double re = ldexp(val[v], e), im = ldexp(xch[v * 64], e);
+        if (EPI == EPI_STORE && g.c64) epi_element<EPI, float>(g, i, j, mk<float>((float)re, (float)im), part);
+        else epi_element<EPI, double>(g, i, j, mk<double>(re, im), part);
       }
     }
   }
@@ -1404,6 +1428,8 @@ static bool use_allpairs(int m, int n, bool dd, int SA, int SB, int dmax, int k)
          ceil_div(m, ABM) * ceil_div(n, ABM) >= kCUs;
 }
 
+bool oz_allpairs_ok(int m, int n, int k, int S) { return use_allpairs(m, n, false, S, S, S + 1, k); }
+
 // Scratch for either large-tile kernel (the all-pairs one needs at most the same:
 // a 64 x 64 double2 tile per 64-tile, and only for K past one segment).
 size_t oz_gemm_scratch_bytes(int m, int n, bool dd) {
@@ -1491,8 +1517,12 @@ hipError_t oz_gemm(int epi, const int8_t* A, const int* ea, int SA, const int8_t
                    int SB, int conjA, int dmax, GemmArgs g, void* scratch, hipStream_t st,
                    bool dd) {
   if (g.m == 0 || g.n == 0) return hipSuccess;
-  if (g.herm && (epi != EPI_YDEF || g.herm != 1 || g.m != g.n)) return hipErrorInvalidValue;
-  if (use_allpairs(g.m, g.n, dd, SA, SB, dmax, g.k)) {
+  const bool ap = use_allpairs(g.m, g.n, dd, SA, SB, dmax, g.k);
+  // Hermitian / skew-Hermitian STORE and complex64 outputs: the all-pairs kernel only
+  const bool herm_store = epi == EPI_STORE && (g.herm == 1 || g.herm == -1) && g.m == g.n && ap;
+  if (g.herm && !herm_store && (epi != EPI_YDEF || g.herm != 1 || g.m != g.n)) return hipErrorInvalidValue;
+  if (g.c64 && (epi != EPI_STORE || !ap)) return hipErrorInvalidValue;
+  if (ap) {
     g.tiles_m = ceil_div(g.m, ABM);
     g.tiles_n = ceil_div(g.n, ABM);
     const int nt = oz_gemm_tiles(g.m, g.n, g.k, dd, g.herm != 0, SA, SB, dmax);

@@ -45,6 +45,7 @@ constexpr int kOzSlices = 7, kOzMinUpd = 2, kOzMaxUpd = 7;
 // CRT mode (Ozaki scheme II): bits of the scaled integers of every operand of the
 // main products (2^-55 of the row maxima, as 7 digits), and the range for Q Delta.
 constexpr int kCrtBits = 55, kCrtMinUpd = 12;
+constexpr int kLpMaxDigits = 7;  // the all-pairs kernel's digit limit
 
 struct Work {
   zc *Qa, *QH, *P, *Y;
@@ -59,6 +60,12 @@ struct Work {
   int *eA, *eQc, *eQr, *eD;
   void* oz_scratch;  // FP64 partial sums of the large-tile product, or the CRT
                      // product's residues between moduli (may be NULL)
+  // lp products on INT8 digits (sr_opts.lp_digits > 0 and the all-pairs kernel at
+  // this size; lp_s = 0 otherwise): row and column slices of W, row slices of the
+  // left operand of the second product
+  int8_t *sWr, *sWc, *sXr;
+  int *eWr, *eWc, *eXr;
+  int lp_s;
   bool oz_all;  // Ozaki mode: That and Y from slices too
   bool crt;     // CRT mode: the slices are residues, oz_s and the update counts bits
   int oz_s;
@@ -131,6 +138,21 @@ Work carve(void* base, int n, const sr_opts* o = nullptr) {
   w.oz_s = 0;
   w.oz_all = false;
   w.crt = false;
+  w.sWr = w.sWc = w.sXr = nullptr;
+  w.eWr = w.eWc = w.eXr = nullptr;
+  w.lp_s = 0;
+  if (o && o->lp_digits > 0 && o->lp_digits <= kLpMaxDigits && o->gemm != SR_GEMM_FP64 &&
+      oz_allpairs_ok(n, n, n, o->lp_digits)) {
+    w.lp_s = o->lp_digits;
+    const size_t sb = align256(oz_slice_bytes(n, n, w.lp_s));
+    const size_t eb = align256((size_t)n * sizeof(int));
+    w.sWr = (int8_t*)take(sb);
+    w.sWc = (int8_t*)take(sb);
+    w.sXr = (int8_t*)take(sb);
+    w.eWr = (int*)take(eb);
+    w.eWc = (int*)take(eb);
+    w.eXr = (int*)take(eb);
+  }
   if (o && o->gemm == SR_GEMM_OZAKI_CRT) {
     // residues of A's rows, Q's columns, Q's rows and Delta's (and P's) columns
     // for the main bit count (the update never takes more)
@@ -146,7 +168,8 @@ Work carve(void* base, int n, const sr_opts* o = nullptr) {
     w.eQc = (int*)take(align256((size_t)n * sizeof(int)));
     w.eQr = (int*)take(align256((size_t)n * sizeof(int)));
     w.eD = (int*)take(align256((size_t)n * sizeof(int)));
-    w.oz_scratch = take(align256(crt_scratch_bytes(n, n, N)));
+    // (also the all-pairs scratch of the lp products on digits)
+    w.oz_scratch = take(align256(std::max(crt_scratch_bytes(n, n, N), w.lp_s ? oz_gemm_scratch_bytes(n, n) : 0)));
   } else if (o && (o->gemm == SR_GEMM_OZAKI_I8 || o->gemm == SR_GEMM_OZAKI_I8_ALL)) {
     w.oz_all = o->gemm == SR_GEMM_OZAKI_I8_ALL;
     const int S = oz_main_slices(o);
@@ -478,31 +501,82 @@ struct Gate {
 };
 
 // lp products, Delta, and Qout = Q + Q Delta (QHout, if given, receives Qout^H).
-int apply_update(const zc* Q, zc* Qout, zc* QHout, int n, Gate gt, const Work& w, hipStream_t st,
-                 int* nprod, Timer* tm = nullptr, int Su = 0, bool no_y = false) {
-  int np = 0;
+// The lp products from INT8 digits (w.lp_s per operand, pairs s + t <= lp_s + 1):
+// C = X W with X given by its row slices (complex64 out; herm as GemmArgs::herm).
+int lp_digit_product(const int8_t* sX, const int* eX, cc* C, int herm, int n, const Work& w, hipStream_t st) {
+  GemmArgs g = gargs(n, n, n, nullptr, 0, nullptr, 0, C, n);
+  g.c64 = 1;
+  g.herm = herm;
+  CK(oz_gemm(EPI_STORE, sX, eX, w.lp_s, w.sWc, w.eWc, w.lp_s, 0, w.lp_s + 1, g, w.oz_scratch, st));
+  return SR_OK;
+}
+
+int lp_products_digits(Gate gt, bool both, int n, const Work& w, hipStream_t st, int* np) {
+  const int S = w.lp_s;
+  CK(oz_split_cols_c64(w.W, n, n, n, S, w.sWc, w.eWc, st));
+  if (gt.w2 || gt.w3) {
+    CK(oz_split_rows_c64(w.W, n, n, n, S, w.sWr, w.eWr, st));
+    const int rc = lp_digit_product(w.sWr, w.eWr, w.W2, 1, n, w, st);  // W^2: Hermitian
+    if (rc != SR_OK) return rc;
+    (*np)++;
+  }
+  const cc* X = nullptr;
+  cc* out = nullptr;
+  int herm = 0;
+  if (both) {
+    CK(w2_minus_y(w.W2, w.Y, w.Ylp, (long)n * n, st));
+    X = w.Ylp;
+    out = w.W3;
+  } else if (gt.w3) {
+    X = w.W2;
+    out = w.W3;
+    herm = -1;  // W^3: skew-Hermitian
+  } else if (gt.yw) {
+    CK(to_c64(w.Y, w.Ylp, (long)n * n, st));
+    X = w.Ylp;
+    out = w.YW;
+  }
+  if (X) {
+    CK(oz_split_rows_c64(X, n, n, n, S, w.sXr, w.eXr, st));
+    const int rc = lp_digit_product(w.sXr, w.eXr, out, herm, n, w, st);
+    if (rc != SR_OK) return rc;
+    (*np)++;
+  }
+  return SR_OK;
+}
+
+// The lp products in FP32 on MFMA.
+int lp_products_fp32(Gate gt, bool both, int n, const Work& w, hipStream_t st, int* np) {
   if (gt.w2 || gt.w3) {
     GemmArgs a2 = gargs(n, n, n, w.W, n, w.W, n, w.W2, n);
     a2.herm = 1;  // W is skew-Hermitian: W^2 is Hermitian
     CK(cgemm(a2, st));
-    np++;
+    (*np)++;
   }
-  // With both W^3 and YW, one product gives their difference: (W^2 - Y) W (into W3).
-  const bool both = gt.w3 && gt.yw;
   if (both) {
     CK(w2_minus_y(w.W2, w.Y, w.Ylp, (long)n * n, st));
     CK(cgemm(gargs(n, n, n, w.Ylp, n, w.W, n, w.W3, n), st));
-    np++;
+    (*np)++;
   } else if (gt.w3) {
     GemmArgs a3 = gargs(n, n, n, w.W2, n, w.W, n, w.W3, n);
     a3.herm = -1;  // and W^3 skew-Hermitian
     CK(cgemm(a3, st));
-    np++;
+    (*np)++;
   } else if (gt.yw) {
     CK(to_c64(w.Y, w.Ylp, (long)n * n, st));
     CK(cgemm(gargs(n, n, n, w.Ylp, n, w.W, n, w.YW, n), st));
-    np++;
+    (*np)++;
   }
+  return SR_OK;
+}
+
+int apply_update(const zc* Q, zc* Qout, zc* QHout, int n, Gate gt, const Work& w, hipStream_t st,
+                 int* nprod, Timer* tm = nullptr, int Su = 0, bool no_y = false) {
+  int np = 0;
+  // With both W^3 and YW, one product gives their difference: (W^2 - Y) W (into W3).
+  const bool both = gt.w3 && gt.yw;
+  const int lrc = w.lp_s ? lp_products_digits(gt, both, n, w, st, &np) : lp_products_fp32(gt, both, n, w, st, &np);
+  if (lrc != SR_OK) return lrc;
   CK(form_delta(w.Llp, no_y ? nullptr : w.Y, gt.w2 ? w.W2 : nullptr, gt.w3 ? w.W3 : nullptr,
                 gt.yw && !both ? w.YW : nullptr, w.P, n, st));
   TIC(tm, 0);
@@ -642,6 +716,10 @@ static int refine_fp64(const void* A_, void* Q_, void* T_, int n, int iters, dou
     return o.gemm == SR_GEMM_OZAKI_BF16 ? SR_ENOSYS : SR_EINVAL;
   }
   if ((o.solver != SR_SOLVER_WAVEFRONT && o.solver != SR_SOLVER_RECURSIVE) || o.rec_leaf < 0) {
+    if (info) info->status = SR_EINVAL;
+    return SR_EINVAL;
+  }
+  if (o.lp_digits < 0 || o.lp_digits > kLpMaxDigits || (o.lp_digits && !ozaki && !crt)) {
     if (info) info->status = SR_EINVAL;
     return SR_EINVAL;
   }
@@ -1022,7 +1100,7 @@ static int refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo,
     if (info) info->status = SR_EINVAL;
     return SR_EINVAL;
   }
-  if (o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth) {
+  if (o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth || o.lp_digits) {
     if (info) info->status = SR_ENOSYS;
     return SR_ENOSYS;
   }
@@ -1382,7 +1460,7 @@ int refine_td(const void* const* A_, void* const* Q_, void* const* T_, int n, in
   if (opts_in) o = *opts_in;
   else sr_default_opts(&o);
   if (o.slices < 0 || o.slices > 32 || (o.slices > 0 && o.slices < 20)) return SR_EINVAL;
-  if (o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth || o.gemm != SR_GEMM_FP64) return SR_ENOSYS;
+  if (o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth || o.lp_digits || o.gemm != SR_GEMM_FP64) return SR_ENOSYS;
   hipStream_t st = (hipStream_t)o.stream;
   const zc* A[3] = {(const zc*)A_[0], (const zc*)A_[1], (const zc*)A_[2]};
   zc* Tt[3] = {(zc*)T_[0], (zc*)T_[1], (zc*)T_[2]};
@@ -1659,7 +1737,7 @@ int refine_real_fp64(const void* A_, void* Q_, void* T_, const int* blocks, int 
   sr_opts o;
   if (opts_in) o = *opts_in;
   else sr_default_opts(&o);
-  if (o.gemm != SR_GEMM_FP64 || o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth) return SR_ENOSYS;
+  if (o.gemm != SR_GEMM_FP64 || o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth || o.lp_digits) return SR_ENOSYS;
   hipStream_t st = (hipStream_t)o.stream;
   const double* A = (const double*)A_;
   double* Q = (double*)Q_;
@@ -2017,6 +2095,27 @@ int sr_ozaki_zgemm_dd(int opa, int m, int n, int k, const void* A_hi, const void
   }
   CK(oz_gemm(Cin_hi ? EPI_ADD : EPI_STORE, qa, ea, slices_a, qb, eb, slices_b, opa, dmax, g, scr, st,
              true));
+  return SR_OK;
+}
+
+int sr_ozaki_cgemm(int m, int n, int k, const void* A, int lda, const void* B, int ldb, void* C, int ldc,
+                   int slices, int herm, void* ws, size_t ws_bytes, void* stream) {
+  if (m < 1 || n < 1 || k < 1 || !A || !B || !C || slices < 1 || slices > kLpMaxDigits) return SR_EINVAL;
+  if (herm < -1 || herm > 1 || (herm && m != n)) return SR_EINVAL;
+  if (lda < m || ldb < k || ldc < m || !oz_allpairs_ok(m, n, k, slices)) return SR_EINVAL;
+  if (!ws || ws_bytes < sr_ozaki_ws_bytes(m, n, k, slices, slices)) return SR_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int8_t* qa = (int8_t*)ws;
+  int8_t* qb = qa + align256(oz_slice_bytes(m, k, slices));
+  int* ea = (int*)(qb + align256(oz_slice_bytes(n, k, slices)));
+  int* eb = ea + m;
+  void* scr = (int8_t*)ea + align256((size_t)(m + n) * sizeof(int));
+  CK(oz_split_rows_c64((const cc*)A, lda, m, k, slices, qa, ea, st));
+  CK(oz_split_cols_c64((const cc*)B, ldb, k, n, slices, qb, eb, st));
+  GemmArgs g = gargs(m, n, k, nullptr, 0, nullptr, 0, C, ldc);
+  g.c64 = 1;
+  g.herm = herm;
+  CK(oz_gemm(EPI_STORE, qa, ea, slices, qb, eb, slices, 0, slices + 1, g, scr, st));
   return SR_OK;
 }
 

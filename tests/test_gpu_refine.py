@@ -97,15 +97,18 @@ def config2():
     return g["A"], synth.lp_schur_start(g["A"])
 
 
-@pytest.mark.parametrize("mode", ["fp64", "ozaki_i8", "ozaki_i8_all", "ozaki_crt"])
+@pytest.mark.parametrize("mode", ["fp64", "ozaki_i8", "ozaki_i8_all", "ozaki_crt", "ozaki_i8_all/lp4",
+                                  "ozaki_crt/lp4"])
 def test_config2_n4096_quad_rows(sr, config2, mode):
     """The precision comparison at n = 4096 in each form of the hp products (native
     FP64; INT8 digits for P, the start and Q Delta; INT8 digits for every hp
-    product): at most 5 passes to 1e-15 (the paper's count, That evaluations), and
-    the binary128 residual and orthogonality on 32 sampled rows."""
+    product; residues for every hp product; "/lp4": the lp products from 4 INT8
+    digits as well): at most 5 passes to 1e-15 (the paper's count, That evaluations),
+    and the binary128 residual and orthogonality on 32 sampled rows."""
     a, qh = config2
     n = a.shape[0]
-    q, t, info = _refine(sr, a, qh, iters=8, gemm=mode)
+    form, _, lp = mode.partition("/lp")
+    q, t, info = _refine(sr, a, qh, iters=8, gemm=form, lp_digits=int(lp or 0))
     assert info["status"] == "OK" and info["iters"] <= 5, (mode, info)
     assert info["hp_gemms"] == 4 * info["iters"]
     rows = np.random.default_rng(20002).choice(n, 32, replace=False)
