@@ -818,11 +818,11 @@ def run_td(args) -> int:
     dt = time.perf_counter() - t1
     ok = all(i["status"] == "OK" for i in infos)
     steps = args.steps
-    ms = sum(i["ms_hp_gemm"] - i["ms_hp_gemm_herm"] for i in infos)
-    cnt = sum(i["hp_gemm_launches"] - i["hp_gemm_herm_launches"] for i in infos)
+    # the product launches P = A Q and That alone (HIP events on the library's stream)
+    ms = sum(i["ms_oz_full"] for i in infos)
+    cnt = sum(i["oz_full_launches"] for i in infos)
     avg = ms / max(1, cnt)
-    slices = 22
-    pairs = slices * (slices + 1) // 2
+    pairs = infos[-1]["oz_full_pairs"]
     achieved = pairs * 8.0 * n ** 3 / (avg * 1e-3) / 1e12
     last = infos[-1]
     out = base_record(args, steps / dt if ok else 0.0, "decomps/s", 1e3 * dt / steps, "td(int8)",
@@ -832,9 +832,12 @@ def run_td(args) -> int:
                        "n": n, "tol": TD_TOL, "parallelism": "1 GPU"})
     out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                        "frac": achieved / INT8_PEAK_TOPS, "traffic": None,
-                       "kernel": f"triple-double product: both operand splits and the windowed INT8 product "
-                                 f"(oz_gemm_windows_kernel), {pairs} digit pairs x 8 n^3 ops per launch",
-                       "avg_launch_ms": avg, "launches_per_step": cnt / steps}
+                       "kernel": f"triple-double product: the windowed INT8 product with three-term outputs "
+                                 f"(oz_gemm_windows_kernel<0> P = A Q and <2> That = Q^H P), {pairs} digit pairs "
+                                 f"x 8 n^3 ops per launch",
+                       "avg_launch_ms": avg, "launches_per_step": cnt / steps,
+                       "with_splits_ms": sum(i["ms_hp_gemm"] - i["ms_hp_gemm_herm"] for i in infos)
+                       / max(1, sum(i["hp_gemm_launches"] - i["hp_gemm_herm_launches"] for i in infos))}
     out.update({"passes": last["iters"], "hp_gemms": last["hp_gemms"], "resid_hist": last["resid_hist"],
                 "ms_hp_gemm_per_step": sum(i["ms_hp_gemm"] for i in infos) / steps,
                 "ms_solve_per_step": sum(i["ms_solve"] for i in infos) / steps, "all_converged": ok})

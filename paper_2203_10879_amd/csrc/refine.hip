@@ -1504,7 +1504,9 @@ int refine_td(const void* const* A_, void* const* Q_, void* const* T_, int n, in
     CK(oz_split_cols3(cur[0], cur[1], cur[2], n, n, n, S, w.sQc, w.eQc, st));
     {
       GemmArgs g = td_args(n, w.P);
+      TIC(tm, 2);
       CK(oz_gemm(EPI_STORE, w.sA, w.eA, S, w.sQc, w.eQc, S, 0, S + 1, g, w.scratch, st, true));
+      TOC(tm, 2);
     }
     TOC(tm, 0);
     TIC(tm, 0);
@@ -1515,7 +1517,9 @@ int refine_td(const void* const* A_, void* const* Q_, void* const* T_, int n, in
       g.Elp64 = w.Elp;
       g.ldlp = n;
       g.partials = w.partials;
+      TIC(tm, 2);
       CK(oz_gemm(EPI_SPLIT, w.sQc, w.eQc, S, w.sP, w.eP, S, 1, S + 1, g, w.scratch, st, true));
+      TOC(tm, 2);
     }
     TOC(tm, 0);
     CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, true, false, S, S, S + 1, true), w.scal + 1, st));
@@ -1617,6 +1621,10 @@ int refine_td(const void* const* A_, void* const* Q_, void* const* T_, int n, in
       info->hp_gemm_herm_launches = timer.herm;
       info->ms_hp_gemm_herm = timer.total(0, 1);
       info->ms_solve = timer.total(1);
+      // the product launches P and That alone (no splits)
+      info->ms_oz_full = timer.total(2);
+      info->oz_full_launches = timer.count[2];
+      info->oz_full_pairs = S * (S + 1) / 2;
     }
   }
   return status;
