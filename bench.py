@@ -563,7 +563,8 @@ def run_batched(args) -> int:
                                    "eigenvalue gaps >= 0.05, FP32 cgees starts, FP64 tier, tol 1e-15, "
                                    "one schur_refine_batched call per step",
                        "count": count, "tol": TOL,
-                       "tile_edges": {str(b): sr.lib().sr_batched_tile_edge(b) for b in (32, 64, 128, 192, 256)}})
+                       "tile_edges": {str(b): sr.lib().sr_batched_tile_edge(b) for b in (32, 64, 128, 192, 256)},
+                       "blocks_per_cu": {str(b): sr.lib().sr_batched_tile_grid(b) for b in (32, 64, 128, 192, 256)}})
     out.update({"passes_p50": float(np.percentile(passes, 50)), "passes_p99": float(np.percentile(passes, 99)),
                 "passes_max": int(passes.max()), "hp_flops_per_step": flops,
                 "hp_tflops_effective": flops / dt / 1e12, "quad_checks": checks, "roofline": None})
