@@ -164,24 +164,13 @@ __device__ inline int crt_neg(int r, int m) {
   return s;
 }
 
-// Exponents t = E - b of the columns of X (K x ncols) and their residues; one
-// block per column of the padded count (padding columns get zero residues). Each
-// thread takes 4 consecutive K positions (one dword per part and modulus).
-__global__ __launch_bounds__(kCrtSplitNT) void crt_split_cols_kernel(const zc* __restrict__ X, long ld, int K,
-                                                                     int ncols, int Kp, int bits, CrtConst c,
-                                                                     int8_t* __restrict__ out,
-                                                                     int* __restrict__ exps) {
+// Exponents t = E - b of the columns of X (K x ncols): one block per column.
+__global__ __launch_bounds__(kCrtSplitNT) void crt_colexp_kernel(const zc* __restrict__ X, long ld, int K,
+                                                                 int bits, int* __restrict__ exps) {
   __shared__ double red[kCrtSplitNT / 64];
-  __shared__ int t_sh;
-  const int col = blockIdx.x;
-  const long plane = oz_plane_bytes(ncols, Kp);
-  const long stride = (long)kParts * plane;  // modulus k -> k + 1
-  const int KB = Kp / 64;
-  const bool live = col < ncols;
-  const zc* x = X + (long)(live ? col : 0) * ld;
+  const zc* x = X + (long)blockIdx.x * ld;
   double m = 0;
-  if (live)
-    for (int k = threadIdx.x; k < K; k += kCrtSplitNT) m = fmax(m, fmax(fabs(x[k].re), fabs(x[k].im)));
+  for (int k = threadIdx.x; k < K; k += kCrtSplitNT) m = fmax(m, fmax(fabs(x[k].re), fabs(x[k].im)));
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -189,37 +178,50 @@ __global__ __launch_bounds__(kCrtSplitNT) void crt_split_cols_kernel(const zc* _
   if (threadIdx.x == 0) {
     double t = 0;
     for (int w = 0; w < kCrtSplitNT / 64; w++) t = fmax(t, red[w]);
-    t_sh = t > 0 ? scale_exponent(t) - bits : 0;
-    if (live) exps[col] = t_sh;
+    exps[blockIdx.x] = t > 0 ? scale_exponent(t) - bits : 0;
   }
-  __syncthreads();
-  const int t = t_sh;
-  for (int k0 = 4 * threadIdx.x; k0 < Kp; k0 += 4 * kCrtSplitNT) {
-    double vr[4], vi[4];
+}
+
+// Residues of the columns of X: one block per plane block (16 columns of the padded
+// count x 64 K positions; padding columns and positions get zero residues), so that
+// every store of a wave fills 256 contiguous bytes of the block. Thread t takes
+// column 16 blockIdx.x + t / 16 at the 4 consecutive K positions 4 (t % 16) of the
+// block (one dword per part and modulus).
+__global__ __launch_bounds__(kCrtSplitNT) void crt_split_cols_kernel(const zc* __restrict__ X, long ld, int K,
+                                                                     int ncols, int Kp, CrtConst c,
+                                                                     const int* __restrict__ exps,
+                                                                     int8_t* __restrict__ out) {
+  const int col = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int k0 = blockIdx.y * 64 + (threadIdx.x & 15) * 4;
+  const long plane = oz_plane_bytes(ncols, Kp);
+  const long stride = (long)kParts * plane;  // modulus k -> k + 1
+  const bool live = col < ncols;
+  const int t = live ? exps[col] : 0;
+  const zc* x = X + (long)(live ? col : 0) * ld;
+  double vr[4], vi[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const bool ok = live && k0 + q < K;
+    const zc v = x[ok ? k0 + q : 0];
+    vr[q] = ok ? rint(ldexp(v.re, -t)) : 0.0;
+    vi[q] = ok ? rint(ldexp(v.im, -t)) : 0.0;
+  }
+  const long o = oz_off(col, k0, Kp / 64);  // 4 consecutive K positions stay in one chunk
+  for (int k = 0; k < c.N; k++) {
+    const int mo = c.mod[k];
+    const double inv = c.inv[k];
+    unsigned pr = 0, pi = 0, pn = 0;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      const bool ok = live && k0 + q < K;
-      const zc v = x[ok ? k0 + q : 0];
-      vr[q] = ok ? rint(ldexp(v.re, -t)) : 0.0;
-      vi[q] = ok ? rint(ldexp(v.im, -t)) : 0.0;
+      const int rr = crt_residue(vr[q], mo, inv), ri = crt_residue(vi[q], mo, inv);
+      pr |= (unsigned)(uint8_t)rr << (8 * q);
+      pi |= (unsigned)(uint8_t)ri << (8 * q);
+      pn |= (unsigned)(uint8_t)crt_neg(ri, mo) << (8 * q);
     }
-    const long o = oz_off(col, k0, KB);  // 4 consecutive K positions stay in one chunk
-    for (int k = 0; k < c.N; k++) {
-      const int mo = c.mod[k];
-      const double inv = c.inv[k];
-      unsigned pr = 0, pi = 0, pn = 0;
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const int rr = crt_residue(vr[q], mo, inv), ri = crt_residue(vi[q], mo, inv);
-        pr |= (unsigned)(uint8_t)rr << (8 * q);
-        pi |= (unsigned)(uint8_t)ri << (8 * q);
-        pn |= (unsigned)(uint8_t)crt_neg(ri, mo) << (8 * q);
-      }
-      int8_t* base = out + k * stride + o;
-      *(unsigned*)base = pr;
-      *(unsigned*)(base + plane) = pi;
-      *(unsigned*)(base + 2 * plane) = pn;
-    }
+    int8_t* base = out + k * stride + o;
+    *(unsigned*)base = pr;
+    *(unsigned*)(base + plane) = pi;
+    *(unsigned*)(base + 2 * plane) = pn;
   }
 }
 
@@ -600,8 +602,10 @@ hipError_t crt_split_cols(const zc* X, long ld, int K, int ncols, int bits, int8
   if (ncols == 0) return hipSuccess;
   CrtConst c;
   crt_const(N, c);
-  hipLaunchKernelGGL(crt_split_cols_kernel, dim3(oz_rows_pad(ncols)), dim3(kCrtSplitNT), 0, st, X, ld, K, ncols,
-                     oz_kp(K), bits, c, out, exps);
+  hipLaunchKernelGGL(crt_colexp_kernel, dim3(ncols), dim3(kCrtSplitNT), 0, st, X, ld, K, bits, exps);
+  const int Kp = oz_kp(K);
+  hipLaunchKernelGGL(crt_split_cols_kernel, dim3(oz_rows_pad(ncols) / 16, Kp / 64), dim3(kCrtSplitNT), 0, st, X,
+                     ld, K, ncols, Kp, c, (const int*)exps, out);
   return hipGetLastError();
 }
 
