@@ -280,7 +280,8 @@ size_t sr_workspace_bytes_dd(int n, const sr_opts* opts);
  * the three-term operands into opts->slices 8-bit digits (0 = 22, at least 20, at
  * most 32) on INT8 MFMA with a three-term FP64 accumulation (about 150 bits: the
  * tolerance should stay above about 1e-44); lp = FP64 (solve and lp products) as in
- * the double-double tier. n >= 2 (SR_EINVAL otherwise). Other outcomes as
+ * the double-double tier. n >= 2 and (slices + 4) 3 n^2 < 2^31, i.e. n <= 5200 with 22
+ * digits (the product kernel's 32-bit plane offsets; SR_EINVAL otherwise). Other outcomes as
  * schur_refine (stagnation measured against u = 2^-150). opts->gemm must be
  * SR_GEMM_FP64 and opts->solver, skip_orth 0 (SR_ENOSYS otherwise). */
 int schur_refine_td(const void* const* A, void* const* Q, void* const* T, int n, int iters, double tol,
@@ -465,8 +466,8 @@ int sr_ozaki_zgemm_dd(int opa, int m, int n, int k, const void* A_hi, const void
  * digits (`slices` 8-bit digits per operand, at least 1, at most 32; pairs s + t <=
  * slices + 1) are taken from the exact three-term values, the pair sums are exact
  * in int32 and are accumulated in a three-term FP64 expansion, so with 22 digits the
- * result carries about 2^-150 relative to the row and column maxima. k >= 1 and every
- * pointer of A and B set (SR_EINVAL otherwise). Cin may be NULL; when given, all
+ * result carries about 2^-150 relative to the row and column maxima. k >= 1, every
+ * pointer of A and B set and (slices + 4) 3 max(m, n) k < 2^31 (SR_EINVAL otherwise). Cin may be NULL; when given, all
  * three of its pointers are set. ws: device workspace of >=
  * sr_ozaki_ws_bytes(m, n, k, slices, slices). */
 int sr_ozaki_zgemm_td(int opa, int m, int n, int k, const void* const* A, int lda, const void* const* B,

@@ -121,6 +121,10 @@ hipError_t oz_split_rows_c64(const cc* X, long ld, int M, int K, int S, int8_t* 
 // on the all-pairs kernel, the one that also takes Hermitian STORE and complex64
 // outputs.
 bool oz_allpairs_ok(int m, int n, int k, int S);
+// Whether the windowed kernel, the only one with triple-double outputs, takes an
+// m x n x k product with S digits per operand (its 32-bit plane offsets bound the
+// sizes: (S + 4) 3 max(m, n) k < 2^31).
+bool oz_td_ok(int m, int n, int k, int S);
 // Output tiles (= partial sums written) of a product; the sizes, the digit counts
 // and dd (double-double accumulation) select the kernel; herm: a Hermitian
 // product (GemmArgs::herm).

@@ -1430,6 +1430,8 @@ static bool use_allpairs(int m, int n, bool dd, int SA, int SB, int dmax, int k)
 
 bool oz_allpairs_ok(int m, int n, int k, int S) { return use_allpairs(m, n, false, S, S, S + 1, k); }
 
+bool oz_td_ok(int m, int n, int k, int S) { return use_windows(m, n, true, S, S, S + 1, k, true); }
+
 // Scratch for either large-tile kernel (the all-pairs one needs at most the same:
 // a 64 x 64 double2 tile per 64-tile, and only for K past one segment).
 size_t oz_gemm_scratch_bytes(int m, int n, bool dd) {

@@ -1461,6 +1461,7 @@ int refine_td(const void* const* A_, void* const* Q_, void* const* T_, int n, in
   else sr_default_opts(&o);
   if (o.slices < 0 || o.slices > 32 || (o.slices > 0 && o.slices < 20)) return SR_EINVAL;
   if (o.solver != SR_SOLVER_WAVEFRONT || o.skip_orth || o.lp_digits || o.gemm != SR_GEMM_FP64) return SR_ENOSYS;
+  if (!oz_td_ok(n, n, n, td_main_slices(&o))) return SR_EINVAL;
   hipStream_t st = (hipStream_t)o.stream;
   const zc* A[3] = {(const zc*)A_[0], (const zc*)A_[1], (const zc*)A_[2]};
   zc* Tt[3] = {(zc*)T_[0], (zc*)T_[1], (zc*)T_[2]};
@@ -2136,6 +2137,7 @@ int sr_ozaki_zgemm_td(int opa, int m, int n, int k, const void* const* A, int ld
   if (!A || !B || !A[0] || !A[1] || !A[2] || !B[0] || !B[1] || !B[2]) return SR_EINVAL;
   if (lda < (opa ? (k > 1 ? k : 1) : (m > 1 ? m : 1)) || ldb < (k > 1 ? k : 1) || ldc < m) return SR_EINVAL;
   if (Cin && (!Cin[0] || !Cin[1] || !Cin[2] || ldcin < m)) return SR_EINVAL;
+  if (!oz_td_ok(m, n, k, slices)) return SR_EINVAL;
   if (!ws || ws_bytes < sr_ozaki_ws_bytes(m, n, k, slices, slices)) return SR_ENOMEM;
   hipStream_t st = (hipStream_t)stream;
   int8_t* qa = (int8_t*)ws;

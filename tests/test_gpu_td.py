@@ -110,6 +110,15 @@ def test_td_arguments(sr):
     Ts = [empty(8, 8), empty(8, 8), empty(8, 8)]
     assert sr.schur_refine_td(As, Qs, Ts, gemm="ozaki_i8")["rc"] == -4  # SR_ENOSYS
     assert sr.schur_refine_td(As, Qs, Ts, slices=12)["rc"] == -1  # SR_EINVAL: too few digits
+    # past the product kernel's 32-bit plane offsets (rejected before any access)
+    import ctypes
+
+    arr = lambda xs: (ctypes.c_void_p * 3)(*[x.data_ptr() for x in xs])
+    info = sr.SrInfo()
+    assert sr.lib().schur_refine_td(arr(As), arr(Qs), arr(Ts), 5300, 2, 1e-40, None, ctypes.byref(info)) == -1
+    ws = sr.lib().sr_ozaki_ws_bytes(8, 8, 8, 22, 22)
+    assert sr.lib().sr_ozaki_zgemm_td(0, 5300, 5300, 5300, arr(As), 5300, arr(As), 5300, None, 1, arr(Ts), 5300,
+                                      22, ctypes.c_void_p(Ts[0].data_ptr()), ws, None) == -1
 
 
 # ---------------------------------------------------------------- the product stage call
