@@ -782,7 +782,7 @@ TD_TOL = 1e-42
 def run_td(args) -> int:
     """The triple-double tier: one complex matrix (gaps >= 0.05, seed 6) from its
     complex128 Schur basis (LAPACK zgees) to 1e-42, every hp value three complex128
-    terms, hp products from 22 INT8 digits per operand, FP64 solve and lp products."""
+    terms, hp products from 20 INT8 digits per operand, FP64 solve and lp products."""
     import torch
 
     import paper_2203_10879_amd as sr
@@ -829,7 +829,7 @@ def run_td(args) -> int:
     out = base_record(args, steps / dt if ok else 0.0, "decomps/s", 1e3 * dt / steps, "td(int8)",
                       {"workload": f"triple-double tier, single matrix n={n}, eigenvalue gaps >= 0.05 (seed 6), "
                                    "complex128 zgees start, tol 1e-42 (three complex128 terms per hp value, "
-                                   "22 INT8 digits per operand, FP64 solve)",
+                                   "20 INT8 digits per operand, FP64 solve)",
                        "n": n, "tol": TD_TOL, "parallelism": "1 GPU"})
     out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                        "frac": achieved / INT8_PEAK_TOPS, "traffic": None,

@@ -277,10 +277,10 @@ size_t sr_workspace_bytes_dd(int n, const sr_opts* opts);
  * precision levels): every hp value is a renormalized expansion of
  * three complex128 arrays (A[0] + A[1] + A[2], likewise Q and T; column-major,
  * leading dimension n, device memory; Q in/out, T out). hp products: Ozaki splits of
- * the three-term operands into opts->slices 8-bit digits (0 = 22, at least 20, at
+ * the three-term operands into opts->slices 8-bit digits (0 = 20, at least 20, at
  * most 32) on INT8 MFMA with a three-term FP64 accumulation (about 150 bits: the
  * tolerance should stay above about 1e-44); lp = FP64 (solve and lp products) as in
- * the double-double tier. n >= 2 and (slices + 4) 3 n^2 < 2^31, i.e. n <= 5200 with 22
+ * the double-double tier. n >= 2 and (slices + 4) 3 n^2 < 2^31, i.e. n <= 5400 with 20
  * digits (the product kernel's 32-bit plane offsets; SR_EINVAL otherwise). Other outcomes as
  * schur_refine (stagnation measured against u = 2^-150). opts->gemm must be
  * SR_GEMM_FP64 and opts->solver, skip_orth 0 (SR_ENOSYS otherwise). */

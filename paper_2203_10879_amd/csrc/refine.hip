@@ -1347,7 +1347,7 @@ namespace {
 // double-double tier.
 
 constexpr double kUTD = 7.006492321624085e-46;  // 2^-150: the products keep about 150 bits
-constexpr int kTDSlices = 22;
+constexpr int kTDSlices = 20;  // 160 bits: floors near 1e-47, 15 digit windows
 
 struct TDWork {
   zc* Q[3];

@@ -115,9 +115,10 @@ def test_td_arguments(sr):
 
     arr = lambda xs: (ctypes.c_void_p * 3)(*[x.data_ptr() for x in xs])
     info = sr.SrInfo()
-    assert sr.lib().schur_refine_td(arr(As), arr(Qs), arr(Ts), 5300, 2, 1e-40, None, ctypes.byref(info)) == -1
+    # n = 6000: (20 + 4) 3 n^2 > 2^31 (20 digits), and (22 + 4) 3 n^2 too (22 digits)
+    assert sr.lib().schur_refine_td(arr(As), arr(Qs), arr(Ts), 6000, 2, 1e-40, None, ctypes.byref(info)) == -1
     ws = sr.lib().sr_ozaki_ws_bytes(8, 8, 8, 22, 22)
-    assert sr.lib().sr_ozaki_zgemm_td(0, 5300, 5300, 5300, arr(As), 5300, arr(As), 5300, None, 1, arr(Ts), 5300,
+    assert sr.lib().sr_ozaki_zgemm_td(0, 6000, 6000, 6000, arr(As), 6000, arr(As), 6000, None, 1, arr(Ts), 6000,
                                       22, ctypes.c_void_p(Ts[0].data_ptr()), ws, None) == -1
 
 
