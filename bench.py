@@ -832,7 +832,11 @@ def run_td(args) -> int:
                                    "20 INT8 digits per operand, FP64 solve)",
                        "n": n, "tol": TD_TOL, "parallelism": "1 GPU"})
     out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                       "frac": achieved / INT8_PEAK_TOPS, "traffic": None,
+                       "frac": achieved / INT8_PEAK_TOPS,
+                       "traffic": pmc_traffic(f"td_windows_n{n}_hbm_traffic.txt", "traffic_bytes_per_launch",
+                                              OZAKI_SOURCES),
+                       "traffic_unit": ("HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, "
+                                        "calibrated on a copy kernel)"),
                        "kernel": f"triple-double product: the windowed INT8 product with three-term outputs "
                                  f"(oz_gemm_windows_kernel<0> P = A Q and <2> That = Q^H P), {pairs} digit pairs "
                                  f"x 8 n^3 ops per launch",
