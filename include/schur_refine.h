@@ -223,8 +223,9 @@ int sr_batched_tile_edge(int n);
 
 /* Persistent blocks per CU the autotuner chose for matrices of size n (1, 2, 4 or 8;
  * -1: not tuned). The autotuner times, once per size bucket (n <= 32, 64, 128, 192,
- * 256, larger), the grouped product P = A Q of up to 64 of the bucket's matrices for
- * both tile edges and grids of 1, 2, 4 and 8 blocks per CU, and keeps the fastest. */
+ * 256, larger), the grouped product P = A Q of up to 256 of the bucket's matrices for
+ * both tile edges and grids of 1, 2, 4 and 8 blocks per CU, and keeps the fastest;
+ * among choices within 3% of it, the one with the most blocks per CU. */
 int sr_batched_tile_grid(int n);
 
 /* Tuning table persistence. A file holds a header line and one line per device and

@@ -478,9 +478,14 @@ struct Launcher {
 enum { T_NSY = 0, T_NSU = 1, T_P = 2, T_T = 3, T_Y = 4, T_U = 5, T_W2 = 10, T_W3 = 11, T_YW = 12 };
 
 // Autotuner: for a bucket seen for the first time (and not in a loaded tuning
-// file), time the grouped P = A Q of (up to 64 of) its matrices for both tile
-// edges and persistent grids of 1, 2, 4 and 8 blocks per CU, and keep the fastest.
-// With SR_TUNING_FILE set the table is written back after each new tuning.
+// file), time the grouped P = A Q of (up to kTuneMax of) its matrices for both tile
+// edges and persistent grids of 1, 2, 4 and 8 blocks per CU, and keep the fastest;
+// among configurations within kTuneTie of it, the one with the most blocks per CU
+// (the whole batch holds more tiles than the timed sample, and near-ties in the
+// sample are noise). With SR_TUNING_FILE set the table is written back after each
+// new tuning.
+constexpr int kTuneMax = 256;
+constexpr float kTuneTie = 1.03f;
 int tune_bucket(int bucket, const std::vector<int>& members, const int* n, const void* const* A,
                 void* const* Q, void* scratch, hipStream_t st, TuneChoice* out) {
   {
@@ -492,7 +497,7 @@ int tune_bucket(int bucket, const std::vector<int>& members, const int* n, const
       return SR_OK;
     }
   }
-  const int cnt = (int)std::min<size_t>(members.size(), 64);
+  const int cnt = (int)std::min<size_t>(members.size(), kTuneMax);
   TuneChoice best;
   if (cnt > 0) {
     // scratch: outputs then tables
@@ -512,7 +517,8 @@ int tune_bucket(int bucket, const std::vector<int>& members, const int* n, const
     BCK(hipEventCreate(&e0));
     BCK(hipEventCreate(&e1));
     BCK(hipMemcpyAsync(args_dev, args.data(), sizeof(GemmArgs) * cnt, hipMemcpyHostToDevice, st));
-    float best_ms = 0;
+    TuneChoice cand[8];
+    int nc = 0;
     for (int v = 0; v < 2; v++) {
       std::vector<GTile> tl;
       for (int i = 0; i < cnt; i++) {
@@ -531,17 +537,22 @@ int tune_bucket(int bucket, const std::vector<int>& members, const int* n, const
         BCK(hipEventSynchronize(e1));
         float ms = 0;
         hipEventElapsedTime(&ms, e0, e1);
-        ms *= 0.5f;
-        if (best_ms == 0 || ms < best_ms) {
-          best_ms = ms;
-          best.edge = edges[v];
-          best.bpc = bpcs[gi];
-          best.ms = ms;
-        }
+        cand[nc].edge = edges[v];
+        cand[nc].bpc = bpcs[gi];
+        cand[nc].ms = 0.5f * ms;
+        nc++;
       }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    float fastest = cand[0].ms;
+    for (int c = 1; c < nc; c++) fastest = std::min(fastest, cand[c].ms);
+    bool have = false;
+    for (int c = 0; c < nc; c++) {
+      if (cand[c].ms > kTuneTie * fastest) continue;
+      if (!have || cand[c].bpc > best.bpc || (cand[c].bpc == best.bpc && cand[c].ms < best.ms)) best = cand[c];
+      have = true;
+    }
   }
   std::lock_guard<std::mutex> lk(tuner().mu);
   tuner().bm[bucket] = best;
@@ -553,11 +564,11 @@ int tune_bucket(int bucket, const std::vector<int>& members, const int* n, const
 }
 
 size_t tune_scratch_bytes(int batch, const int* n) {
-  // the largest 64 matrices of any bucket fit in 64 * (256^2 * 16) + tables
+  // kTuneMax outputs of the largest size, and the tables
   size_t mx = 0;
   for (int b = 0; b < batch; b++) mx = std::max<size_t>(mx, (size_t)n[b]);
-  return 64 * a256(mx * mx * sizeof(zc)) + a256(sizeof(GemmArgs) * 64) +
-         a256(sizeof(GTile) * 64 * (size_t)ceil_div((int)mx, 32) * ceil_div((int)mx, 32));
+  return kTuneMax * a256(mx * mx * sizeof(zc)) + a256(sizeof(GemmArgs) * kTuneMax) +
+         a256(sizeof(GTile) * kTuneMax * (size_t)ceil_div((int)mx, 32) * ceil_div((int)mx, 32));
 }
 
 hipStream_t capture_stream() {
