@@ -332,6 +332,13 @@ struct CrtArgs {
   GemmArgs g;
   uint8_t* scratch;
   CrtConst c;
+  // Tiles past the last full round of block slots: the first nfull blocks take one
+  // tile each; the tiles after them are split into ksplit blocks of consecutive
+  // moduli (0: no split), whose residues meet in the tile's scratch; the last of a
+  // tile's blocks to finish (counted in counters[], zero between launches)
+  // reconstructs it.
+  int nfull, ksplit;
+  unsigned* counters;
 };
 
 // sum modulo m of a (exact) int32 sum, in [0, m)
@@ -381,11 +388,18 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
 
-  const int ntiles = gridDim.x, bid = blockIdx.x;
-  int logical = bid;
-  {
-    const int per = ntiles / kXCDs;
+  const int bid = blockIdx.x, N = a.c.N;
+  int logical = bid, k0 = 0, k1 = N, rem = -1;
+  if (bid < a.nfull) {
+    const int per = a.nfull / kXCDs;
     if (bid < per * kXCDs) logical = (bid % kXCDs) * per + bid / kXCDs;
+  } else {
+    // a share of the moduli of one of the tiles after the full rounds
+    const int it = bid - a.nfull, part = it % a.ksplit;
+    rem = it / a.ksplit;
+    logical = a.nfull + rem;
+    k0 = part * N / a.ksplit;
+    k1 = (part + 1) * N / a.ksplit;
   }
   int tm, tn;
   if (EPI == EPI_YDEF && g.herm) {
@@ -404,7 +418,7 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
   }
   const int m0 = tm * CBM, n0 = tn * CBN;
 
-  const int KT = a.Kp / OBK, N = a.c.N;
+  const int KT = a.Kp / OBK;
   const long pA = oz_plane_bytes(g.m, a.Kp), pB = oz_plane_bytes(g.n, a.Kp);
   const long sA = kParts * pA, sB = kParts * pB;
   const int pa2 = a.conjA ? 1 : 2, pa3 = a.conjA ? 2 : 1;
@@ -424,7 +438,7 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
     const int rb = min((isA ? m0 : n0) / 16 + (qq & 7), (isA ? RBA : RBB) - 1);
     goff[j] = (int)(part * (isA ? pA : pB)) + rb * KT * 1024 + lane * 16;
   }
-  const int total = N * KT;
+  const int total = k1 * KT;
   // sources and stage of the loads of step st
   struct Src {
     const int8_t* A;
@@ -504,17 +518,17 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
   };
-  // this lane's residue slots: block, wave, modulus, 32 x 32 block, group of four
+  // this lane's residue slots: tile, wave, modulus, 32 x 32 block, group of four
   // outputs, lane (8 bytes)
-  uint8_t* sres = a.scratch + (long)bid * N * kCScratchPerMod + (long)wave * N * (kCScratchPerMod / 4) + lane * 8;
+  uint8_t* sres = a.scratch + (long)logical * N * kCScratchPerMod + (long)wave * N * (kCScratchPerMod / 4) + lane * 8;
 
+  int st = k0 * KT;
   {
-    const Src s0 = src(0);
+    const Src s0 = src(st);
 #pragma unroll
     for (int j = 0; j < kCLoadsPerWave; j++) issue_one(s0, j);
   }
-  int st = 0;
-  for (int k = 0; k < N; k++) {
+  for (int k = k0; k < k1; k++) {
 #pragma unroll
     for (int x = 0; x < 2; x++)
 #pragma unroll
@@ -548,7 +562,21 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
           *(uint2*)(sres + ((long)k * 16 + (x * 2 + y) * 4 + q) * 512) = make_uint2(pr, pi);
         }
   }
-  // reconstruction and epilogue (each lane reads back only what it stored)
+  if (rem >= 0) {
+    // a share of a split tile: the residues out (release), count the shares; the
+    // last one reconstructs (acquire). The stages are free once every wave is past
+    // this barrier; their first word carries the decision.
+    __threadfence();
+    __syncthreads();
+    int* flag = (int*)lds;
+    if (tid == 0) flag[0] = atomicAdd(&a.counters[rem], 1u) == (unsigned)(a.ksplit - 1);
+    __syncthreads();
+    if (!flag[0]) return;
+    __threadfence();
+    if (tid == 0) a.counters[rem] = 0u;  // ready for the next launch
+  }
+  // reconstruction and epilogue (each lane reads back what the lanes in its place
+  // stored, in this block or in the other shares of its tile)
   double part = 0;
 #pragma unroll 1
   for (int xy = 0; xy < 4; xy++) {
@@ -578,7 +606,7 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
   }
   if constexpr (EPI == EPI_SPLIT || EPI == EPI_YDEF) {
     __syncthreads();  // every wave is past its last read of the ring
-    epi_reduce<CNT>(g, part, (double*)lds, bid);
+    epi_reduce<CNT>(g, part, (double*)lds, logical);  // one slot per tile
   }
 }
 
@@ -591,7 +619,11 @@ int crt_gemm_tiles(int m, int n, bool herm) {
   return herm ? t * (t + 1) / 2 : ceil_div(m, CBM) * t;
 }
 
-size_t crt_scratch_bytes(int m, int n, int N) { return (size_t)crt_gemm_tiles(m, n, false) * N * kCScratchPerMod; }
+// the residues of every tile between moduli, then the counters of the split tiles
+static size_t crt_residue_scratch(int m, int n, int N) {
+  return (size_t)crt_gemm_tiles(m, n, false) * N * kCScratchPerMod;
+}
+size_t crt_scratch_bytes(int m, int n, int N) { return crt_residue_scratch(m, n, N) + 256 * sizeof(unsigned); }
 
 bool crt_plan_ok(int K, int bits) { return K < 65536 && bits >= 1 && crt_moduli(K, bits) > 0; }
 
@@ -638,6 +670,26 @@ static hipError_t launch_crt(int nt, const CrtArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void crt_zero_kernel(unsigned* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Blocks per launch and the split of the tiles after the last full round of
+// kCrtSlots block slots (two blocks per CU): split when those tiles fill at most a
+// quarter of a round, into shares of the moduli that fill it.
+constexpr int kCrtSlots = 2 * kCUs, kCrtMaxRem = kCrtSlots / 4;
+static void crt_plan_split(int tiles, int N, int* nfull, int* ksplit) {
+  const int full = tiles / kCrtSlots * kCrtSlots, r = tiles - full;
+  if (full > 0 && r > 0 && r <= kCrtMaxRem) {
+    *nfull = full;
+    *ksplit = std::min(N, kCrtSlots / r);
+  } else {
+    *nfull = tiles;
+    *ksplit = 0;
+  }
+}
+
 hipError_t crt_gemm(int epi, const int8_t* A, const int* ta, const int8_t* B, const int* tb, int conjA, int bits,
                     GemmArgs g, void* scratch, hipStream_t st) {
   if (g.m == 0 || g.n == 0) return hipSuccess;
@@ -658,7 +710,15 @@ hipError_t crt_gemm(int epi, const int8_t* A, const int* ta, const int8_t* B, co
   a.g = g;
   a.scratch = (uint8_t*)scratch;
   crt_const(N, a.c);
-  const int nt = crt_gemm_tiles(g.m, g.n, g.herm != 0);
+  const int tiles = crt_gemm_tiles(g.m, g.n, g.herm != 0);
+  crt_plan_split(tiles, N, &a.nfull, &a.ksplit);
+  a.counters = (unsigned*)((uint8_t*)scratch + crt_residue_scratch(g.m, g.n, N));
+  int nt = tiles;
+  if (a.ksplit) {
+    const int r = tiles - a.nfull;  // <= kCrtMaxRem < 256 counters
+    nt = a.nfull + r * a.ksplit;
+    hipLaunchKernelGGL(crt_zero_kernel, dim3(1), dim3(256), 0, st, a.counters, r);
+  }
   switch (epi) {
     case EPI_STORE: return launch_crt<EPI_STORE>(nt, a, st);
     case EPI_ADD: return launch_crt<EPI_ADD>(nt, a, st);

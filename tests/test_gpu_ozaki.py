@@ -259,6 +259,23 @@ def test_crt_exact_on_integers(sr, opa, shape, add):
     assert np.array_equal(host(c), ref)
 
 
+@pytest.mark.parametrize("opa", [0, 1])
+@pytest.mark.parametrize("shape", [(2176, 4096, 64), (4224, 4096, 32)])
+def test_crt_split_tiles_exact_on_integers(sr, opa, shape):
+    """More output tiles of 128 x 128 than full rounds of block slots (2 per CU) take:
+    544 tiles (32 past 512) and 1056 (32 past 1024). The tiles after the full rounds
+    are split into blocks of consecutive moduli whose residues meet in the tile's
+    scratch, and the last share reconstructs; the product stays bit-exact."""
+    m, n, k = shape
+    rng = np.random.default_rng(m + n + k + opa)
+    a = _gauss_int(rng, (k, m) if opa else (m, k), 2**20)
+    b = _gauss_int(rng, (k, n), 2**20)
+    c = empty(m, n)
+    assert sr.sr_crt_zgemm(dev(a), dev(b), c, opa=opa, bits=55) == 0
+    ref = (a.conj().T if opa else a) @ b
+    assert np.array_equal(host(c), ref)
+
+
 def _crt_bound(a_op, b, bits):
     """Entrywise bound of the CRT product: each entry of a row (column) is rounded to
     a multiple of 2^t with 2^t <= 2^-bits of twice the row (column) maximum (an
