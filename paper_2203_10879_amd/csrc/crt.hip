@@ -350,17 +350,8 @@ __device__ inline int crt_reduce(int acc, int m, double inv) {
   return r;
 }
 
-// X from the residues r_k (byte `sh` of res[k]): limb sums, q, carries, double-double.
-__device__ inline double crt_value(const CrtConst& c, const unsigned* res, int sh) {
-  double S[kCrtLimbs] = {0, 0, 0, 0};
-#pragma unroll
-  for (int k = 0; k < kCrtMaxMod; k++) {
-    if (k < c.N) {
-      const double r = (double)((res[k] >> sh) & 255u);
-#pragma unroll
-      for (int l = 0; l < kCrtLimbs; l++) S[l] = fma(r, c.w[k][l], S[l]);
-    }
-  }
+// X from its limb sums S_l = sum_k r_k w_kl: q, carries, double-double.
+__device__ inline double crt_finish(const CrtConst& c, const double* S) {
   // q = rint(S / M): S / M = q + X / M with |X / M| < 1/8
   const double approx = ldexp(S[3], 120) + ldexp(S[2], 80) + ldexp(S[1], 40) + S[0];
   const double q = rint(approx / c.Mf);
@@ -591,6 +582,29 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
         rre[k] = v.x;
         rim[k] = v.y;
       }
+      // limb sums of the group's 8 values (4 outputs, re and im) in one pass over the
+      // moduli: each w_kl is read once for all 8, and the 32 sums are independent
+      // (one value at a time re-read the weights per value and waited on 4 chains:
+      // 5% slower at n = 4096)
+      double S[8][kCrtLimbs];
+#pragma unroll
+      for (int t = 0; t < 8; t++)
+#pragma unroll
+        for (int l = 0; l < kCrtLimbs; l++) S[t][l] = 0.0;
+#pragma unroll
+      for (int k = 0; k < kCrtMaxMod; k++) {
+        if (k < N) {
+#pragma unroll
+          for (int c = 0; c < 4; c++) {
+            const double r0 = (double)((rre[k] >> (8 * c)) & 255u), r1 = (double)((rim[k] >> (8 * c)) & 255u);
+#pragma unroll
+            for (int l = 0; l < kCrtLimbs; l++) {
+              S[c][l] = fma(r0, a.c.w[k][l], S[c][l]);
+              S[4 + c][l] = fma(r1, a.c.w[k][l], S[4 + c][l]);
+            }
+          }
+        }
+      }
 #pragma unroll
       for (int c = 0; c < 4; c++) {
         const int v = 4 * q + c;
@@ -598,7 +612,7 @@ __global__ __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2))) void c
         const int j = n0 + wn + y * 32 + (lane & 31);
         if (i < g.m && j < g.n) {
           const int e = a.ta[i] + a.tb[j];
-          const double re = crt_value(a.c, rre, 8 * c), im = crt_value(a.c, rim, 8 * c);
+          const double re = crt_finish(a.c, S[c]), im = crt_finish(a.c, S[4 + c]);
           epi_element<EPI, double>(g, i, j, mk<double>(ldexp(re, e), ldexp(im, e)), part);
         }
       }
