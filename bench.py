@@ -500,7 +500,21 @@ def run_precision(args) -> int:
     out["ozaki_crt_speedup_vs_fp64"] = fp["ms_to_tol"] / forms["ozaki_crt"]["ms_to_tol"]
     out["product_sweep"] = {"product": f"P = A Q-hat, n={n}", "error": "relative Frobenius error on 8 rows "
                             "against the binary128 product", "forms": sweep}
-    out["roofline"] = None
+    # the value's form: its full INT8 products P = A Q (HIP events on the library's stream)
+    inf = infos["ozaki_i8"]
+    cnt = sum(i["oz_full_launches"] for i in inf)
+    avg = sum(i["ms_oz_full"] for i in inf) / max(1, cnt)
+    npairs = inf[-1]["oz_full_pairs"]
+    achieved = npairs * 8.0 * n ** 3 / (avg * 1e-3) / 1e12 if avg > 0 else 0.0
+    out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                       "frac": achieved / INT8_PEAK_TOPS,
+                       "traffic": pmc_traffic(f"ozaki_allpairs_n{n}_hbm_traffic.txt", "traffic_bytes_per_launch",
+                                              OZAKI_SOURCES),
+                       "traffic_unit": ("HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, "
+                                        "calibrated on a copy kernel)"),
+                       "kernel": f"all-pairs INT8 product (oz_gemm_allpairs_kernel<0, S>) P = A Q, {npairs} digit "
+                                 f"pairs x 8 n^3 ops per launch",
+                       "avg_launch_ms": avg, "launches_per_step": cnt / args.steps}
     print(json.dumps(out), flush=True)
     return 0 if ok else 1
 
@@ -567,7 +581,15 @@ def run_batched(args) -> int:
                        "blocks_per_cu": {str(b): sr.lib().sr_batched_tile_grid(b) for b in (32, 64, 128, 192, 256)}})
     out.update({"passes_p50": float(np.percentile(passes, 50)), "passes_p99": float(np.percentile(passes, 99)),
                 "passes_max": int(passes.max()), "hp_flops_per_step": flops,
-                "hp_tflops_effective": flops / dt / 1e12, "quad_checks": checks, "roofline": None})
+                "hp_tflops_effective": flops / dt / 1e12, "quad_checks": checks})
+    # The products run inside one HIP graph per call, so no launch can be timed on its
+    # own: the figure is the whole step's hp flops (8 n^3 per product; the Hermitian Y
+    # counted in full though it forms the tiles on and above the diagonal only) over
+    # the step's time, a lower bound on the rate of the grouped products.
+    out["roofline"] = {"bound": "mfma", "achieved": flops / dt / 1e12, "peak": FP64_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": flops / dt / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
+                       "kernel": "grouped complex FP64 products of all matrices (gemm_grouped_kernel<double,...>)",
+                       "scope": "whole step (solves, elementwise work and the graph's gaps included)"}
     print(json.dumps(out), flush=True)
     return 0 if ok else 1
 
@@ -599,7 +621,8 @@ def run_dd_continuation(args) -> int:
         info = sr.schur_refine_dd(dev[k][0], dev[k][1], Qh, Ql, Th, Tl, iters=8, tol=1e-28, timing=True,
                                   workspace=ws, update_slices=-1)
         per.append({"k": k, "status": info["status"], "passes": info["iters"], "ms": info["ms_total"],
-                    "ms_hp": info["ms_hp_gemm"], "resid": info["resid"]})
+                    "ms_hp": info["ms_hp_gemm"], "resid": info["resid"], "ms_full": info["ms_oz_full"],
+                    "full": info["oz_full_launches"], "pairs": info["oz_full_pairs"]})
         if k % 8 == 0:
             print(f"# step {k}: {info['status']} {info['iters']} passes {info['ms_total']:.1f} ms",
                   file=sys.stderr, flush=True)
@@ -611,14 +634,27 @@ def run_dd_continuation(args) -> int:
     ev = oracle.evaluate_rows(oracle.QMat.from_dd(ah, al),
                               oracle.QMat.from_dd(sr.to_numpy(Qh), sr.to_numpy(Ql)), rows)
     hp_ms = sum(p["ms_hp"] for p in per)
-    launches = sum(4 * p["passes"] for p in per)
+    # the product launches P = A Q and That alone (HIP events on the library's stream)
+    cnt = sum(p["full"] for p in per)
+    avg = sum(p["ms_full"] for p in per) / max(1, cnt)
+    npairs = per[-1]["pairs"]
+    achieved = npairs * 8.0 * n ** 3 / (avg * 1e-3) / 1e12 if avg > 0 else 0.0
     out = base_record(args, steps / dt if ok else 0.0, "decomps/s", 1e3 * dt / steps, "dd(int8)",
                       {"workload": f"double-double continuation A0 + (k/{steps}) A1, n={n}, A1 = 1e-3 CN(0,1) "
                                    "(46-bit), tol 1e-28, warm starts, first from zgees",
                        "n": n, "steps": steps, "tol": 1e-28})
     out.update({"passes_per_step": [p["passes"] for p in per], "ms_per_step_each": [p["ms"] for p in per],
                 "hp_ms_total": hp_ms, "quad_stril_rows_last": float(ev["stril"]),
-                "quad_orth_rows_last": float(ev["orth"]), "roofline": None, "steps": steps, "warmup": 0})
+                "quad_orth_rows_last": float(ev["orth"]), "steps": steps, "warmup": 0})
+    out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                       "frac": achieved / INT8_PEAK_TOPS,
+                       "traffic": pmc_traffic(f"dd_windows_n{n}_hbm_traffic.txt", "traffic_bytes_per_launch",
+                                              OZAKI_SOURCES),
+                       "traffic_unit": ("HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, "
+                                        "calibrated on a copy kernel)"),
+                       "kernel": f"double-double product: the windowed INT8 product (oz_gemm_windows_kernel<0> "
+                                 f"P = A Q and <2> That = Q^H P), {npairs} digit pairs x 8 n^3 ops per launch",
+                       "avg_launch_ms": avg, "launches_per_step": cnt / steps}
     print(json.dumps(out), flush=True)
     return 0 if ok else 1
 
@@ -875,7 +911,7 @@ def main() -> int:
     ap.add_argument("--rows", type=int, default=32, help="rows of the binary128 check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="default: leave out the n = 1024 key")
-    ap.add_argument("--forms", default="", help="default: comma-separated forms to run (default: all three)")
+    ap.add_argument("--forms", default="", help="default: comma-separated forms to run (default: all four)")
     ap.add_argument("--no-compensated", action="store_true")
     ap.add_argument("--lp-digits", type=int, default=4,
                     help="split forms: INT8 digits of the lp products (0: FP32 MFMA)")

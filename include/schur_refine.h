@@ -168,7 +168,8 @@ typedef struct {
   float ms_oz_full;       /* with opts.timing in an Ozaki mode: time of the full n x n x n
                              split products with opts->slices digits per operand (P =
                              A Q in every pass; That too with SR_GEMM_OZAKI_I8_ALL and
-                             SR_GEMM_OZAKI_CRT, and in schur_refine_td), the INT8
+                             SR_GEMM_OZAKI_CRT, and in schur_refine_dd and
+                             schur_refine_td), the INT8
                              product kernel alone (its digit splits are in ms_hp_gemm
                              only)                                                     */
   int oz_full_launches;   /* number of launches timed in ms_oz_full                     */

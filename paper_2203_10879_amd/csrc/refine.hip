@@ -1189,7 +1189,9 @@ static int refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo,
     CK(oz_split_cols(curh, curl, n, n, n, S, w.sQc, w.eQc, st));
     {
       GemmArgs g = dd_args(n, w.Ph, w.Pl);
+      TIC(tm, 2);
       CK(oz_gemm(EPI_STORE, w.sA, w.eA, S, w.sQc, w.eQc, S, 0, S + 1, g, w.scratch, st, true));
+      TOC(tm, 2);
     }
     TOC(tm, 0);
     TIC(tm, 0);
@@ -1200,7 +1202,9 @@ static int refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo,
       g.Elp64 = w.Elp;
       g.ldlp = n;
       g.partials = w.partials;
+      TIC(tm, 2);
       CK(oz_gemm(EPI_SPLIT, w.sQc, w.eQc, S, w.sP, w.eP, S, 1, S + 1, g, w.scratch, st, true));
+      TOC(tm, 2);
     }
     TOC(tm, 0);
     CK(reduce_partials(w.partials, oz_gemm_tiles(n, n, n, true, false, w.S, w.S, w.S + 1), w.scal + 1, st));
@@ -1325,6 +1329,10 @@ static int refine_dd(const void* A_hi, const void* A_lo, void* Q_hi, void* Q_lo,
       info->hp_gemm_herm_launches = timer.herm;
       info->ms_hp_gemm_herm = timer.total(0, 1);
       info->ms_solve = timer.total(1);
+      // the product launches P and That alone (no splits)
+      info->ms_oz_full = timer.total(2);
+      info->oz_full_launches = timer.count[2];
+      info->oz_full_pairs = S * (S + 1) / 2;
     }
   }
   return status;
