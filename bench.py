@@ -708,7 +708,23 @@ def run_solvers(args) -> int:
                       {"workload": "FP32 triangular-equation solve, tile wavefront against the recursive block "
                                    "algorithm (Algorithm 3), T from a test matrix with gaps >= 0.05, "
                                    "E = 1e-6 CN(0,1)", "sizes": sizes})
-    out.update({"solves": rows, "roofline": None})
+    # The wavefront is a chain of dependent launches (one per tile diagonal): its rate
+    # against the HBM peak (algorithmic bytes: the triangles of T and E read and of L
+    # written, complex64) shows
+    # how far the chain, not bandwidth, sets its time.
+    n0 = best["n"]
+    levels = -(-n0 // (16 if n0 <= 2048 else 32))
+    alg = 12.0 * n0 * n0
+    achieved = alg / (best["wavefront_ms"] * 1e-3) / 1e9
+    out.update({"solves": rows})
+    out["roofline"] = {"bound": "latency", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                       "frac": achieved / 8000.0,
+                       "traffic": (pmc_traffic("trisolve_n1024_hbm_traffic.txt", "sweep_hbm_bytes_per_solve",
+                                               SWEEP_SOURCES, "trisolve_source_sha256_16") if n0 == 1024 else None),
+                       "traffic_unit": "HBM bytes per solve (rocprofv3 FETCH_SIZE and WRITE_SIZE)",
+                       "kernel": f"triangular-equation sweep (trisolve_level_kernel<float>), {levels} dependent "
+                                 f"launches at n = {n0}; algorithmic bytes 12 n^2 per solve",
+                       "ms_per_solve": best["wavefront_ms"]}
     print(json.dumps(out), flush=True)
     return 0
 
