@@ -633,11 +633,16 @@ int crt_gemm_tiles(int m, int n, bool herm) {
   return herm ? t * (t + 1) / 2 : ceil_div(m, CBM) * t;
 }
 
-// the residues of every tile between moduli, then the counters of the split tiles
+// block slots of one round (two blocks per CU); remainders up to a quarter of a round
+// are split after full rounds
+constexpr int kCrtSlots = 2 * kCUs, kCrtMaxRem = kCrtSlots / 4;
+
+// the residues of every tile between moduli
 static size_t crt_residue_scratch(int m, int n, int N) {
   return (size_t)crt_gemm_tiles(m, n, false) * N * kCScratchPerMod;
 }
-size_t crt_scratch_bytes(int m, int n, int N) { return crt_residue_scratch(m, n, N) + 256 * sizeof(unsigned); }
+// the residues, then one share counter per split tile (fewer than kCrtSlots)
+size_t crt_scratch_bytes(int m, int n, int N) { return crt_residue_scratch(m, n, N) + kCrtSlots * sizeof(unsigned); }
 
 bool crt_plan_ok(int K, int bits) { return K < 65536 && bits >= 1 && crt_moduli(K, bits) > 0; }
 
@@ -690,14 +695,16 @@ __global__ void crt_zero_kernel(unsigned* __restrict__ p, int n) {
 }
 
 // Blocks per launch and the split of the tiles after the last full round of
-// kCrtSlots block slots (two blocks per CU): split when those tiles fill at most a
-// quarter of a round, into shares of the moduli that fill it.
-constexpr int kCrtSlots = 2 * kCUs, kCrtMaxRem = kCrtSlots / 4;
+// kCrtSlots block slots (two blocks per CU) into shares of the moduli that fill a
+// round: when those tiles fill at most a quarter of it, or when there is no full
+// round at all (n = 2048: 256 tiles in 2 shares; n = 1024: 64 tiles in 8), as long
+// as a tile gets at least two shares.
 static void crt_plan_split(int tiles, int N, int* nfull, int* ksplit) {
   const int full = tiles / kCrtSlots * kCrtSlots, r = tiles - full;
-  if (full > 0 && r > 0 && r <= kCrtMaxRem) {
+  const int k = r > 0 ? std::min(N, kCrtSlots / r) : 0;
+  if (k >= 2 && (full == 0 || r <= kCrtMaxRem)) {
     *nfull = full;
-    *ksplit = std::min(N, kCrtSlots / r);
+    *ksplit = k;
   } else {
     *nfull = tiles;
     *ksplit = 0;
@@ -729,9 +736,9 @@ hipError_t crt_gemm(int epi, const int8_t* A, const int* ta, const int8_t* B, co
   a.counters = (unsigned*)((uint8_t*)scratch + crt_residue_scratch(g.m, g.n, N));
   int nt = tiles;
   if (a.ksplit) {
-    const int r = tiles - a.nfull;  // <= kCrtMaxRem < 256 counters
+    const int r = tiles - a.nfull;  // < kCrtSlots counters
     nt = a.nfull + r * a.ksplit;
-    hipLaunchKernelGGL(crt_zero_kernel, dim3(1), dim3(256), 0, st, a.counters, r);
+    hipLaunchKernelGGL(crt_zero_kernel, dim3(ceil_div(r, 256)), dim3(256), 0, st, a.counters, r);
   }
   switch (epi) {
     case EPI_STORE: return launch_crt<EPI_STORE>(nt, a, st);
