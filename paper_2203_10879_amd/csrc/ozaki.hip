@@ -1178,10 +1178,12 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     for (int wb = 0; wb * kWin < a.SB; wb++)
       if (kWin * (wa + wb) + 2 <= a.dmax) nwin++;
   int widx = 0;
-  v16i acc[7];
+  int nfold = 0;  // folds so far
+  const int nwa = (a.SA + kWin - 1) / kWin, nwb = (a.SB + kWin - 1) / kWin;
 
-  // one window: its K-sweep in segments, each folded into the expansions
-  auto window = [&](auto dlc, int wa, int wb) {
+  // one band of windows (the same wa + wb, hence the same diagonals d0 .. d0 + DL):
+  // their K-sweeps, accumulated into the same sums
+  auto band = [&](auto dlc, int bnd) {
     constexpr int DL = decltype(dlc)::value;
     constexpr int NS = DL < kWin - 1 ? DL + 1 : kWin;  // slices staged per operand
     constexpr int nIA = 6 * NS, nI = nIA + 4 * NS, kQ = (nI + NW - 1) / NW;
@@ -1191,9 +1193,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     constexpr int NST = kWinLds / kStB >= 4 ? 4 : 2;
     constexpr int kVmAhead = 0x0F70 | ((NST - 2) * kQ);  // vmcnt: later steps' loads may be in flight
     static_assert((NST - 2) * kQ < 16 && NST * kStB <= kWinLds, "pipeline of a window");
-    const int d0 = kWin * (wa + wb) + 2;
-    const int8_t* Aw = a.A + (long)(kWin * wa) * sA;
-    const int8_t* Bw = a.B + (long)(kWin * wb) * sB;
+    const int d0 = kWin * bnd + 2;
     int goff[kQ], loff[kQ];
 #pragma unroll
     for (int k = 0; k < kQ; k++) {
@@ -1208,117 +1208,136 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         loff[k] = (3 * NS + 2 * t + part) * kApRegion + h * 1024;
       }
     }
-    auto issue = [&](int ks, int stage, int k0, int k1) {
-      const int kbo = (ks >> 1) * 1024, kx = (ks & 1) << 5;
-      int8_t* lb = lds + stage * kStB;
+    v16i acc[DL + 1];
+    int acc_steps = 0;  // K-steps in the sums since the last fold
+    const int wa_lo = max(0, bnd - (nwb - 1)), wa_hi = min(nwa - 1, bnd);
+    for (int wa = wa_lo; wa <= wa_hi; wa++) {
+      const int wb = bnd - wa;
+      const bool last_in_band = wa == wa_hi;
+      const int8_t* Aw = a.A + (long)(kWin * wa) * sA;
+      const int8_t* Bw = a.B + (long)(kWin * wb) * sB;
+      auto issue = [&](int ks, int stage, int k0, int k1) {
+        const int kbo = (ks >> 1) * 1024, kx = (ks & 1) << 5;
+        int8_t* lb = lds + stage * kStB;
 #pragma unroll
-      for (int k = 0; k < kQ; k++) {
-        if (k >= k0 && k < k1) {
-          const int q = min(uwave + NW * k, nI - 1);
-          const int8_t* src = (q < nIA ? Aw : Bw) + kbo + (goff[k] ^ kx);
-          __builtin_amdgcn_global_load_lds((gbl_ptr_t*)src, (lds_ptr_t*)(lb + loff[k]), 16, 0, 0);
-        }
-      }
-    };
-    barrier();  // the previous window no longer reads the stages
-#pragma unroll
-    for (int j = 0; j < NST - 1; j++)
-      if (j < KS) issue(j, j, 0, kQ);
-    for (int seg0 = 0; seg0 < KS; seg0 += kApSeg) {
-      const int seg1 = min(KS, seg0 + kApSeg);
-#pragma unroll
-      for (int di = 0; di <= DL; di++) acc[di] = v16i{};
-      for (int ks = seg0; ks < seg1; ks++) {
-        // this step's loads have landed once at most the NST - 2 later steps' are
-        // in flight (all of them near the end, where fewer were issued)
-        if (ks + NST - 2 < KS) __builtin_amdgcn_s_waitcnt(kVmAhead);
-        else __builtin_amdgcn_s_waitcnt(kWaitVm0);
-        barrier();
-        const int8_t* lb = lds + (ks % NST) * kStB;
-        v4i bf[NS], bs[NS];
-#pragma unroll
-        for (int t = 0; t < NS; t++) {
-          bf[t] = *(const v4i*)(lb + (3 * NS + 2 * t + pbf) * kApRegion + fb);
-          bs[t] = *(const v4i*)(lb + (3 * NS + 2 * t + pbs) * kApRegion + fb);
-        }
-        v4i a0 = *(const v4i*)(lb + fa), ax = *(const v4i*)(lb + pax * kApRegion + fa);
-        const int nxt = ks + NST - 1;  // the step whose loads go out now
-        const bool more = nxt < KS;
-#pragma unroll
-        for (int s = 0; s < NS; s++) {
-          v4i n0, nx;
-          if (s + 1 < NS) {
-            n0 = *(const v4i*)(lb + (3 * (s + 1)) * kApRegion + fa);
-            nx = *(const v4i*)(lb + (3 * (s + 1) + pax) * kApRegion + fa);
+        for (int k = 0; k < kQ; k++) {
+          if (k >= k0 && k < k1) {
+            const int q = min(uwave + NW * k, nI - 1);
+            const int8_t* src = (q < nIA ? Aw : Bw) + kbo + (goff[k] ^ kx);
+            __builtin_amdgcn_global_load_lds((gbl_ptr_t*)src, (lds_ptr_t*)(lb + loff[k]), 16, 0, 0);
           }
-          if (more) issue(nxt, nxt % NST, s * kQ / NS, (s + 1) * kQ / NS);
+        }
+      };
+      barrier();  // the previous window no longer reads the stages
 #pragma unroll
-          for (int t = 0; t < NS && s + t <= DL; t++) {
-            acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, bf[t], acc[s + t], 0, 0, 0);
-            acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ax, bs[t], acc[s + t], 0, 0, 0);
+      for (int j = 0; j < NST - 1; j++)
+        if (j < KS) issue(j, j, 0, kQ);
+      // The windows of a band (the same wa + wb) put their pairs on the same diagonals
+      // with the same weights, so they accumulate into the same int32 sums; a fold
+      // empties them after kApSeg K-steps (at most 4 pairs per diagonal, 2^22 per step:
+      // the sums stay below 2^30) and at the end of the band. Per band one fold instead
+      // of one per window: 5 instead of 15 with 20 digits, 4 instead of 10 with 14.
+      for (int seg0 = 0; seg0 < KS;) {
+        const int seg1 = min(KS, seg0 + (kApSeg - acc_steps));
+        if (acc_steps == 0) {
+#pragma unroll
+          for (int di = 0; di <= DL; di++) acc[di] = v16i{};
+        }
+        for (int ks = seg0; ks < seg1; ks++) {
+          // this step's loads have landed once at most the NST - 2 later steps' are
+          // in flight (all of them near the end, where fewer were issued)
+          if (ks + NST - 2 < KS) __builtin_amdgcn_s_waitcnt(kVmAhead);
+          else __builtin_amdgcn_s_waitcnt(kWaitVm0);
+          barrier();
+          const int8_t* lb = lds + (ks % NST) * kStB;
+          v4i bf[NS], bs[NS];
+#pragma unroll
+          for (int t = 0; t < NS; t++) {
+            bf[t] = *(const v4i*)(lb + (3 * NS + 2 * t + pbf) * kApRegion + fb);
+            bs[t] = *(const v4i*)(lb + (3 * NS + 2 * t + pbs) * kApRegion + fb);
           }
-          a0 = n0;
-          ax = nx;
+          v4i a0 = *(const v4i*)(lb + fa), ax = *(const v4i*)(lb + pax * kApRegion + fa);
+          const int nxt = ks + NST - 1;  // the step whose loads go out now
+          const bool more = nxt < KS;
+#pragma unroll
+          for (int s = 0; s < NS; s++) {
+            v4i n0, nx;
+            if (s + 1 < NS) {
+              n0 = *(const v4i*)(lb + (3 * (s + 1)) * kApRegion + fa);
+              nx = *(const v4i*)(lb + (3 * (s + 1) + pax) * kApRegion + fa);
+            }
+            if (more) issue(nxt, nxt % NST, s * kQ / NS, (s + 1) * kQ / NS);
+#pragma unroll
+            for (int t = 0; t < NS && s + t <= DL; t++) {
+              acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, bf[t], acc[s + t], 0, 0, 0);
+              acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ax, bs[t], acc[s + t], 0, 0, 0);
+            }
+            a0 = n0;
+            ax = nx;
+          }
+        }
+        acc_steps += seg1 - seg0;
+        seg0 = seg1;
+        if (acc_steps < kApSeg && !(last_in_band && seg1 == KS)) continue;
+        // fold: x = acc 2^{-8 d} (exact) into (h, m, l) with two TwoSum steps each
+        const bool first = nfold == 0;
+        const bool final = widx == nwin - 1 && seg1 == KS;
+        nfold++;
+        acc_steps = 0;
+#pragma unroll
+        for (int v = 0; v < 16; v++) {
+          double h = 0, m = 0, l = 0;
+          if (!first) {
+            h = sp[v * 64];
+            m = sp[1024 + v * 64];
+            l = sp[2048 + v * 64];
+          }
+#pragma unroll
+          for (int di = DL; di >= 0; di--) {
+            const double x = (double)acc[di][v] * __builtin_ldexp(1.0, -8 * (d0 + di));
+            double s0, e0, s1, e1;
+            two_sum(h, x, s0, e0);
+            two_sum(m, e0, s1, e1);
+            h = s0;
+            m = s1;
+            l += e1;
+          }
+          if (!final) {
+            sp[v * 64] = h;
+            sp[1024 + v * 64] = m;
+            sp[2048 + v * 64] = l;
+          } else if (g.Cmid) {
+            // triple-double: the expansion renormalized
+            double t0, t1, t2;
+            td_renorm(h, m, l, t0, t1, t2);
+            sp[v * 64] = t0;
+            sp[1024 + v * 64] = t1;
+            sp[2048 + v * 64] = t2;
+          } else {
+            // to double-double, kept in the first two slots for the epilogue
+            double hh, e, dh, dl;
+            two_sum(h, m, hh, e);
+            e += l;
+            fast_two_sum(hh, e, dh, dl);
+            sp[v * 64] = dh;
+            sp[1024 + v * 64] = dl;
+          }
         }
       }
-      // fold: x = acc 2^{-8 d} (exact) into (h, m, l) with two TwoSum steps each
-      const bool first = widx == 0 && seg0 == 0;
-      const bool final = widx == nwin - 1 && seg1 == KS;
-#pragma unroll
-      for (int v = 0; v < 16; v++) {
-        double h = 0, m = 0, l = 0;
-        if (!first) {
-          h = sp[v * 64];
-          m = sp[1024 + v * 64];
-          l = sp[2048 + v * 64];
-        }
-#pragma unroll
-        for (int di = DL; di >= 0; di--) {
-          const double x = (double)acc[di][v] * __builtin_ldexp(1.0, -8 * (d0 + di));
-          double s0, e0, s1, e1;
-          two_sum(h, x, s0, e0);
-          two_sum(m, e0, s1, e1);
-          h = s0;
-          m = s1;
-          l += e1;
-        }
-        if (!final) {
-          sp[v * 64] = h;
-          sp[1024 + v * 64] = m;
-          sp[2048 + v * 64] = l;
-        } else if (g.Cmid) {
-          // triple-double: the expansion renormalized
-          double t0, t1, t2;
-          td_renorm(h, m, l, t0, t1, t2);
-          sp[v * 64] = t0;
-          sp[1024 + v * 64] = t1;
-          sp[2048 + v * 64] = t2;
-        } else {
-          // to double-double, kept in the first two slots for the epilogue
-          double hh, e, dh, dl;
-          two_sum(h, m, hh, e);
-          e += l;
-          fast_two_sum(hh, e, dh, dl);
-          sp[v * 64] = dh;
-          sp[1024 + v * 64] = dl;
-        }
-      }
+      widx++;
     }
-    widx++;
   };
-  for (int wa = 0; wa * kWin < a.SA; wa++) {
-    for (int wb = 0; wb * kWin < a.SB; wb++) {
-      const int d0 = kWin * (wa + wb) + 2;
-      if (d0 > a.dmax) continue;
-      switch (min(6, a.dmax - d0)) {
-        case 6: window(std::integral_constant<int, 6>{}, wa, wb); break;
-        case 5: window(std::integral_constant<int, 5>{}, wa, wb); break;
-        case 4: window(std::integral_constant<int, 4>{}, wa, wb); break;
-        case 3: window(std::integral_constant<int, 3>{}, wa, wb); break;
-        case 2: window(std::integral_constant<int, 2>{}, wa, wb); break;
-        case 1: window(std::integral_constant<int, 1>{}, wa, wb); break;
-        default: window(std::integral_constant<int, 0>{}, wa, wb); break;
-      }
+  for (int bnd = 0; bnd < nwa + nwb - 1; bnd++) {
+    const int d0 = kWin * bnd + 2;
+    if (d0 > a.dmax) break;
+    switch (min(6, a.dmax - d0)) {
+      case 6: band(std::integral_constant<int, 6>{}, bnd); break;
+      case 5: band(std::integral_constant<int, 5>{}, bnd); break;
+      case 4: band(std::integral_constant<int, 4>{}, bnd); break;
+      case 3: band(std::integral_constant<int, 3>{}, bnd); break;
+      case 2: band(std::integral_constant<int, 2>{}, bnd); break;
+      case 1: band(std::integral_constant<int, 1>{}, bnd); break;
+      default: band(std::integral_constant<int, 0>{}, bnd); break;
     }
   }
   double* xch = (double*)lds + (quad * 16) * 64 + lane;
