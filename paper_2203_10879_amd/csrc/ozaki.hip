@@ -311,8 +311,10 @@ __global__ void oz_exp_fix_kernel(int* __restrict__ exps, int M) {
 }
 
 // Slices of the rows of X; one block per 32 x 32 tile, staged through LDS so that
-// reads follow the columns and writes the rows (padding rows get zero digits).
-template <typename C>
+// reads follow the columns and writes the rows (padding rows get zero digits). NTERM:
+// the terms per value (1: X; 2: X + Xlo; 3: X + Xmid + Xlo); the LDS holds only those
+// (one term: 17 KiB, eight blocks per CU instead of three).
+template <typename C, int NTERM>
 __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const C* __restrict__ X,
                                                                  const C* __restrict__ Xmid,
                                                                  const C* __restrict__ Xlo, long ld,
@@ -320,8 +322,8 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const C* __rest
                                                                  const int* __restrict__ exps,
                                                                  int8_t* __restrict__ out) {
   __shared__ zc t[32][33];
-  __shared__ zc tl[32][33];
-  __shared__ zc tmid[32][33];
+  __shared__ zc tl[NTERM >= 2 ? 32 : 1][33];
+  __shared__ zc tmid[NTERM >= 3 ? 32 : 1][33];
   const int i0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
 #pragma unroll
   for (int r = 0; r < 4; r++) {
@@ -332,11 +334,11 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const C* __rest
     const long o = ok ? gi + (long)gk * ld : 0;
     const C v = X[o];
     t[kk][row] = mk<double>(ok ? (double)v.re : 0.0, ok ? (double)v.im : 0.0);
-    if (Xlo) {
+    if constexpr (NTERM >= 2) {
       const C w = Xlo[o];
       tl[kk][row] = mk<double>(ok ? (double)w.re : 0.0, ok ? (double)w.im : 0.0);
     }
-    if (Xmid) {
+    if constexpr (NTERM >= 3) {
       const C w = Xmid[o];
       tmid[kk][row] = mk<double>(ok ? (double)w.re : 0.0, ok ? (double)w.im : 0.0);
     }
@@ -362,14 +364,14 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const C* __rest
     const zc v = t[kg + c][row];
     rh[c] = ldexp(v.re, -e);
     ih[c] = ldexp(v.im, -e);
-    if (Xlo) {
+    if constexpr (NTERM >= 2) {
       const zc w = tl[kg + c][row];
       rl[c] = ldexp(w.re, -e);
       il[c] = ldexp(w.im, -e);
     } else {
       rl[c] = il[c] = 0;
     }
-    if (Xmid) {
+    if constexpr (NTERM >= 3) {
       const zc w = tmid[kg + c][row];
       rm[c] = ldexp(w.re, -e);
       imd[c] = ldexp(w.im, -e);
@@ -380,19 +382,21 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_rows_kernel(const C* __rest
   Carries cr[4], ci[4];
 #pragma unroll
   for (int c = 0; c < 4; c++) {
-    cr[c] = Xmid  ? value_carries_td(rh[c], rm[c], rl[c], S)
-            : Xlo ? value_carries_dd(rh[c], rl[c], S)
-                  : value_carries(rh[c], S);
-    ci[c] = Xmid  ? value_carries_td(ih[c], imd[c], il[c], S)
-            : Xlo ? value_carries_dd(ih[c], il[c], S)
-                  : value_carries(ih[c], S);
+    cr[c] = NTERM == 3   ? value_carries_td(rh[c], rm[c], rl[c], S)
+            : NTERM == 2 ? value_carries_dd(rh[c], rl[c], S)
+                         : value_carries(rh[c], S);
+    ci[c] = NTERM == 3   ? value_carries_td(ih[c], imd[c], il[c], S)
+            : NTERM == 2 ? value_carries_dd(ih[c], il[c], S)
+                         : value_carries(ih[c], S);
   }
   for (int s = 0; s < S; s++) {
     unsigned pr = 0, pi = 0, pn = 0;
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-      const int dr = Xmid ? raw_digit_td(rh[c], rm[c], rl[c]) : Xlo ? raw_digit_dd(rh[c], rl[c]) : raw_digit(rh[c]);
-      const int di = Xmid ? raw_digit_td(ih[c], imd[c], il[c]) : Xlo ? raw_digit_dd(ih[c], il[c]) : raw_digit(ih[c]);
+      const int dr = NTERM == 3 ? raw_digit_td(rh[c], rm[c], rl[c])
+                     : NTERM == 2 ? raw_digit_dd(rh[c], rl[c]) : raw_digit(rh[c]);
+      const int di = NTERM == 3 ? raw_digit_td(ih[c], imd[c], il[c])
+                     : NTERM == 2 ? raw_digit_dd(ih[c], il[c]) : raw_digit(ih[c]);
       pr |= (unsigned)(uint8_t)final_digit(dr, cr[c].pos, s + 1, S) << (8 * c);
       pi |= (unsigned)(uint8_t)final_digit(di, ci[c].pos, s + 1, S) << (8 * c);
       pn |= (unsigned)(uint8_t)final_digit(-di, ci[c].neg, s + 1, S) << (8 * c);
@@ -442,8 +446,16 @@ static hipError_t split_rows_any(const C* X, const C* Xmid, const C* Xlo, long l
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int Kp = oz_kp(K);
-  hipLaunchKernelGGL(oz_split_rows_kernel<C>, dim3(ceil_div(M, 32), Kp / 32), dim3(kSplitNT), 0, st, X, Xmid,
-                     Xlo, ld, M, K, S, Kp, exps, out);
+  const dim3 grid(ceil_div(M, 32), Kp / 32);
+  if (Xmid)
+    hipLaunchKernelGGL((oz_split_rows_kernel<C, 3>), grid, dim3(kSplitNT), 0, st, X, Xmid, Xlo, ld, M, K, S, Kp,
+                       exps, out);
+  else if (Xlo)
+    hipLaunchKernelGGL((oz_split_rows_kernel<C, 2>), grid, dim3(kSplitNT), 0, st, X, Xmid, Xlo, ld, M, K, S, Kp,
+                       exps, out);
+  else
+    hipLaunchKernelGGL((oz_split_rows_kernel<C, 1>), grid, dim3(kSplitNT), 0, st, X, Xmid, Xlo, ld, M, K, S, Kp,
+                       exps, out);
   return hipGetLastError();
 }
 
