@@ -260,12 +260,13 @@ def test_crt_exact_on_integers(sr, opa, shape, add):
 
 
 @pytest.mark.parametrize("opa", [0, 1])
-@pytest.mark.parametrize("shape", [(2176, 4096, 64), (4224, 4096, 32)])
+@pytest.mark.parametrize("shape", [(2176, 4096, 64), (4224, 4096, 32), (1024, 1024, 64), (2048, 2048, 32)])
 def test_crt_split_tiles_exact_on_integers(sr, opa, shape):
-    """More output tiles of 128 x 128 than full rounds of block slots (2 per CU) take:
-    544 tiles (32 past 512) and 1056 (32 past 1024). The tiles after the full rounds
-    are split into blocks of consecutive moduli whose residues meet in the tile's
-    scratch, and the last share reconstructs; the product stays bit-exact."""
+    """Output tiles of 128 x 128 against rounds of block slots (2 per CU): 544 tiles
+    (32 past 512) and 1056 (32 past 1024), and launches with no full round, 64 tiles
+    (n = 1024, 8 shares each) and 256 (n = 2048, 2 shares). The split tiles go to
+    blocks of consecutive moduli whose residues meet in the tile's scratch, and the
+    last share reconstructs; the product stays bit-exact."""
     m, n, k = shape
     rng = np.random.default_rng(m + n + k + opa)
     a = _gauss_int(rng, (k, m) if opa else (m, k), 2**20)
