@@ -196,34 +196,13 @@ __host__ __device__ inline int8_t byte_digit(unsigned byte, uint64_t carries, in
   return (int8_t)(uint8_t)(byte + (unsigned)((carries >> (S - s)) & 1u));
 }
 
-// Slices of the columns of X (K x ncols, leading dim ld), one block per column of
-// the padded count (padding columns get zero digits). These serve as B, and as
-// op(A) = X^H when the product applies the conjugation. X is complex128 (with the
-// lower terms of an expansion) or complex64 (one term; its values are exact in FP64).
+// Column exponents of X: the scale of each column's largest leading-term entry, one
+// block per column.
 template <typename C>
-__global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const C* __restrict__ X,
-                                                                 const C* __restrict__ Xmid,
-                                                                 const C* __restrict__ Xlo, long ld,
-                                                                 int K, int ncols, int S, int Kp,
-                                                                 int8_t* __restrict__ out,
-                                                                 int* __restrict__ exps) {
+__global__ __launch_bounds__(kSplitNT) void oz_colexp_kernel(const C* __restrict__ X, long ld, int K,
+                                                             int* __restrict__ exps) {
   __shared__ double red[kSplitNT / 64];
-  __shared__ int e_sh;
-  const int col = blockIdx.x;
-  const long plane = oz_plane_bytes(ncols, Kp);
-  const long stride = (long)kParts * plane;  // slice s -> s+1
-  const int KB = Kp / 64;
-  if (col >= ncols) {
-    for (int k = threadIdx.x; k < Kp; k += kSplitNT) {
-      const long o = oz_off(col, k, KB);
-      for (int s = 0; s < S; s++)
-        for (int p = 0; p < kParts; p++) out[s * stride + p * plane + o] = 0;
-    }
-    return;
-  }
-  const C* x = X + (long)col * ld;
-  const C* xl = Xlo ? Xlo + (long)col * ld : nullptr;
-  const C* xm = Xmid ? Xmid + (long)col * ld : nullptr;
+  const C* x = X + (long)blockIdx.x * ld;
   double m = 0;
   for (int k = threadIdx.x; k < K; k += kSplitNT) m = fmax(m, fmax(fabs((double)x[k].re), fabs((double)x[k].im)));
 #pragma unroll
@@ -233,44 +212,69 @@ __global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const C* __rest
   if (threadIdx.x == 0) {
     double t = 0;
     for (int w = 0; w < kSplitNT / 64; w++) t = fmax(t, red[w]);
-    e_sh = digit_exponent(t);
-    exps[col] = e_sh;
+    exps[blockIdx.x] = digit_exponent(t);
   }
-  __syncthreads();
-  const int e = e_sh;
-  for (int k = threadIdx.x; k < Kp; k += kSplitNT) {
-    const long o = oz_off(col, k, KB);
-    int8_t* o_re = out + o;
-    int8_t* o_im = out + plane + o;
-    int8_t* o_ni = out + 2 * plane + o;
-    if (k < K) {
-      const C v = x[k];
-      const C w = xl ? xl[k] : C{0, 0};
-      const C u = xm ? xm[k] : C{0, 0};
-      const double rh = ldexp((double)v.re, -e), rl = ldexp((double)w.re, -e), rm = ldexp((double)u.re, -e);
-      const double ih = ldexp((double)v.im, -e), il = ldexp((double)w.im, -e), im = ldexp((double)u.im, -e);
-      const Digits dr = xm ? split_value<3>(rh, rm, rl, S)
-                           : xl ? split_value<2>(rh, 0.0, rl, S) : split_value<1>(rh, 0.0, 0.0, S);
-      const Digits di = xm ? split_value<3>(ih, im, il, S)
-                           : xl ? split_value<2>(ih, 0.0, il, S) : split_value<1>(ih, 0.0, 0.0, S);
+}
+
+// Slices of the columns of X (K x ncols, leading dim ld) with the exponents of
+// oz_colexp_kernel: block (c, b) takes K positions 256 b .. 256 b + 255 of column c of
+// the padded count (padding columns and positions get zero digits), one per thread (a
+// block per whole column, each thread walking a quarter of K at n = 1024, left too few
+// blocks in flight). These serve as B, and as op(A) = X^H when the product applies the
+// conjugation. X is complex128 (with the lower terms of an expansion) or complex64 (one
+// term; its values are exact in FP64).
+template <typename C>
+__global__ __launch_bounds__(kSplitNT) void oz_split_cols_kernel(const C* __restrict__ X,
+                                                                 const C* __restrict__ Xmid,
+                                                                 const C* __restrict__ Xlo, long ld,
+                                                                 int K, int ncols, int S, int Kp,
+                                                                 int8_t* __restrict__ out,
+                                                                 const int* __restrict__ exps) {
+  const int col = blockIdx.x;
+  const int k = blockIdx.y * kSplitNT + threadIdx.x;
+  if (k >= Kp) return;
+  const long plane = oz_plane_bytes(ncols, Kp);
+  const long stride = (long)kParts * plane;  // slice s -> s+1
+  const int KB = Kp / 64;
+  const long o = oz_off(col, k, KB);
+  int8_t* o_re = out + o;
+  int8_t* o_im = out + plane + o;
+  int8_t* o_ni = out + 2 * plane + o;
+  if (col >= ncols) {
+    for (int s = 0; s < S; s++) o_re[s * stride] = o_im[s * stride] = o_ni[s * stride] = 0;
+    return;
+  }
+  const C* x = X + (long)col * ld;
+  const C* xl = Xlo ? Xlo + (long)col * ld : nullptr;
+  const C* xm = Xmid ? Xmid + (long)col * ld : nullptr;
+  const int e = exps[col];
+  if (k < K) {
+    const C v = x[k];
+    const C w = xl ? xl[k] : C{0, 0};
+    const C u = xm ? xm[k] : C{0, 0};
+    const double rh = ldexp((double)v.re, -e), rl = ldexp((double)w.re, -e), rm = ldexp((double)u.re, -e);
+    const double ih = ldexp((double)v.im, -e), il = ldexp((double)w.im, -e), im = ldexp((double)u.im, -e);
+    const Digits dr = xm ? split_value<3>(rh, rm, rl, S)
+                         : xl ? split_value<2>(rh, 0.0, rl, S) : split_value<1>(rh, 0.0, 0.0, S);
+    const Digits di = xm ? split_value<3>(ih, im, il, S)
+                         : xl ? split_value<2>(ih, 0.0, il, S) : split_value<1>(ih, 0.0, 0.0, S);
 #pragma unroll
-      for (int q = 0; q < kMaxDigits / 8; q++)
+    for (int q = 0; q < kMaxDigits / 8; q++)
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
-          const int s = 8 * q + j + 1;
-          if (s <= S) {
-            const unsigned br = (unsigned)(dr.w[q] >> (8 * j)) & 255u, bi = (unsigned)(di.w[q] >> (8 * j)) & 255u;
-            o_re[(s - 1) * stride] = byte_digit(br, dr.c.pos, s, S);
-            o_im[(s - 1) * stride] = byte_digit(bi, di.c.pos, s, S);
-            o_ni[(s - 1) * stride] = byte_digit((256u - bi) & 255u, di.c.neg, s, S);
-          }
+      for (int j = 0; j < 8; j++) {
+        const int s = 8 * q + j + 1;
+        if (s <= S) {
+          const unsigned br = (unsigned)(dr.w[q] >> (8 * j)) & 255u, bi = (unsigned)(di.w[q] >> (8 * j)) & 255u;
+          o_re[(s - 1) * stride] = byte_digit(br, dr.c.pos, s, S);
+          o_im[(s - 1) * stride] = byte_digit(bi, di.c.pos, s, S);
+          o_ni[(s - 1) * stride] = byte_digit((256u - bi) & 255u, di.c.neg, s, S);
         }
-    } else {
-      for (int s = 0; s < S; s++) {
-        o_re[s * stride] = 0;
-        o_im[s * stride] = 0;
-        o_ni[s * stride] = 0;
       }
+  } else {
+    for (int s = 0; s < S; s++) {
+      o_re[s * stride] = 0;
+      o_im[s * stride] = 0;
+      o_ni[s * stride] = 0;
     }
   }
 }
@@ -411,16 +415,20 @@ hipError_t oz_split_cols3(const zc* X, const zc* Xmid, const zc* Xlo, long ld, i
                           int8_t* out, int* exps, hipStream_t st) {
   if (S < 1 || S > kMaxDigits || (Xmid && !Xlo)) return hipErrorInvalidValue;
   if (ncols == 0) return hipSuccess;
-  hipLaunchKernelGGL(oz_split_cols_kernel<zc>, dim3(oz_rows_pad(ncols)), dim3(kSplitNT), 0, st, X, Xmid, Xlo, ld,
-                     K, ncols, S, oz_kp(K), out, exps);
+  const int Kp = oz_kp(K);
+  hipLaunchKernelGGL(oz_colexp_kernel<zc>, dim3(ncols), dim3(kSplitNT), 0, st, X, ld, K, exps);
+  hipLaunchKernelGGL(oz_split_cols_kernel<zc>, dim3(oz_rows_pad(ncols), ceil_div(Kp, kSplitNT)), dim3(kSplitNT), 0,
+                     st, X, Xmid, Xlo, ld, K, ncols, S, Kp, out, exps);
   return hipGetLastError();
 }
 
 hipError_t oz_split_cols_c64(const cc* X, long ld, int K, int ncols, int S, int8_t* out, int* exps, hipStream_t st) {
   if (S < 1 || S > kMaxDigits) return hipErrorInvalidValue;
   if (ncols == 0) return hipSuccess;
-  hipLaunchKernelGGL(oz_split_cols_kernel<cc>, dim3(oz_rows_pad(ncols)), dim3(kSplitNT), 0, st, X,
-                     (const cc*)nullptr, (const cc*)nullptr, ld, K, ncols, S, oz_kp(K), out, exps);
+  const int Kp = oz_kp(K);
+  hipLaunchKernelGGL(oz_colexp_kernel<cc>, dim3(ncols), dim3(kSplitNT), 0, st, X, ld, K, exps);
+  hipLaunchKernelGGL(oz_split_cols_kernel<cc>, dim3(oz_rows_pad(ncols), ceil_div(Kp, kSplitNT)), dim3(kSplitNT), 0,
+                     st, X, (const cc*)nullptr, (const cc*)nullptr, ld, K, ncols, S, Kp, out, exps);
   return hipGetLastError();
 }
 
